@@ -1,0 +1,409 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test checks the oracle against a closed form, an independent library routine
+(numpy.fft, scipy, transformers' audio utilities, torch dtype casts, mpmath), an invariant
+of the mathematics, or a value the paper prints.  Together they are chosen so that a
+dropped term, a wrong sign or index, or a transposed operand in the oracle fails one of
+them.  None of them needs a GPU.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ Mel scale (Eq. mel_scale)
+
+def test_mel_scale_closed_forms(orc):
+    # mu(700) = 2595 log10(2): the HTK formula at f = 700 Hz
+    assert orc.hz_to_mel(700.0) == pytest.approx(2595.0 * math.log10(2.0), rel=1e-15)
+    assert orc.hz_to_mel(0.0) == 0.0
+    # Slaney scale: linear 3 Mel per 200 Hz below 1 kHz, so 1 kHz -> 15 Mel
+    assert orc.hz_to_mel(1000.0, orc.MEL_SLANEY) == pytest.approx(15.0, rel=1e-15)
+    for f in [0.0, 80.0, 440.0, 1000.0, 3999.0, 7600.0, 8000.0, 11025.0]:
+        for form in (orc.MEL_HTK, orc.MEL_SLANEY):
+            assert orc.mel_to_hz(orc.hz_to_mel(f, form), form) == pytest.approx(f, rel=1e-13, abs=1e-10)
+
+
+def test_mel_grid_and_centres(orc):
+    g = orc.mel_grid_hz(80, 0.0, 8000.0)
+    assert g[0] == pytest.approx(0.0, abs=1e-9) and g[-1] == pytest.approx(8000.0, rel=1e-14)
+    mu = np.array([orc.hz_to_mel(f) for f in g])
+    assert np.allclose(np.diff(mu), mu[-1] / 81.0, rtol=1e-12)   # uniform in Mel
+    f = orc.melt_frequencies(80, 0.0, 8000.0)
+    assert np.array_equal(f, g[1:-1])                              # filter centres
+    # numerical value of the first centre: 700 (10^(mu_1/2595) - 1), mu_1 = mu(8000)/81
+    mu1 = 2595.0 * math.log10(1.0 + 8000.0 / 700.0) / 81.0
+    assert f[0] == pytest.approx(700.0 * (10.0 ** (mu1 / 2595.0) - 1.0), rel=1e-13)
+    lin = orc.melt_frequencies(80, 0.0, 8000.0, placement=orc.PLACE_LINSPACE)
+    assert lin[0] == pytest.approx(0.0, abs=1e-9) and lin[-1] == pytest.approx(8000.0, rel=1e-13)
+
+
+# ------------------------------------------------------------------ window, frames
+
+def test_window_matches_scipy(orc):
+    from scipy.signal import windows
+    for n in (2, 5, 16, 400, 512, 1024):
+        assert np.allclose(orc.window(n, orc.WIN_HANN_SYMMETRIC), windows.hann(n, sym=True), atol=1e-15)
+        assert np.allclose(orc.window(n, orc.WIN_HANN_PERIODIC), windows.hann(n, sym=False), atol=1e-15)
+    assert np.all(orc.window(7, orc.WIN_RECT) == 1.0)
+
+
+def test_frame_counts(orc):
+    with open(os.path.join(GOLDEN, "paper_constants.json")) as fh:
+        gold = json.load(fh)
+    c = gold["frames_1s_16k"]
+    assert orc.num_frames(c["samples"], c["n_fft"], c["hop"]) == c["frames"]
+    assert orc.num_frames(399, 400, 160) == 0
+    assert orc.num_frames(400, 400, 160) == 1
+    assert orc.num_frames(559, 400, 160) == 1
+    assert orc.num_frames(560, 400, 160) == 2
+    assert orc.num_frames(0, 400, 160) == 0
+
+
+# ------------------------------------------------------------------ MelT projection
+
+def _frame(n, seed=0):
+    return np.random.default_rng(seed).standard_normal(n).astype(np.float32)
+
+
+def test_ndft_on_bins_equals_rfft(orc):
+    """P1: at f_m = k sr / N the Mel-spaced projection is the DFT at bin k: its energy equals
+    |rfft(w x)|^2 from numpy's FFT and the oracle's own naive DFT."""
+    N, H, sr = 400, 160, 16000.0
+    x = _frame(N * 3)
+    ks = np.array([0, 1, 2, 7, 50, 123, 199, 200])
+    freqs = ks * sr / N
+    S = orc.melt_forward(x, sr=sr, n_fft=N, hop=H, freqs=freqs, out_kind=orc.OUT_POWER)
+    w = orc.window(N)
+    T = S.shape[0]
+    ref = np.stack([np.abs(np.fft.rfft(w * x[t * H:t * H + N].astype(np.float64))) ** 2 for t in range(T)])
+    assert np.allclose(S, ref[:, ks], rtol=1e-11, atol=1e-9)
+    P = orc.power_spectrum(x, n_fft=N, hop=H)
+    assert np.allclose(P, ref, rtol=1e-11, atol=1e-9)
+    # R = Re X_k and I = -Im X_k (the sign of the sin term)
+    _, R, I = orc.melt_forward(x, sr=sr, n_fft=N, hop=H, freqs=freqs, out_kind=orc.OUT_POWER, return_ri=True)
+    X0 = np.fft.rfft(w * x[:N].astype(np.float64))
+    assert np.allclose(R[0], X0.real[ks], atol=1e-10)
+    assert np.allclose(I[0], -X0.imag[ks], atol=1e-10)
+
+
+def _hann_dtft(omega, N):
+    """sum_n w[n] e^{i omega n} for the symmetric Hann window, in closed form:
+    w[n] = 1/2 - (e^{i a n} + e^{-i a n})/4, a = 2 pi/(N-1), and each term is a geometric
+    series G(v) = sum_{n<N} e^{i v n} = (e^{i v N} - 1)/(e^{i v} - 1)."""
+    a = 2.0 * np.pi / (N - 1)
+
+    def G(v):
+        z = np.exp(1j * v)
+        if abs(z - 1.0) < 1e-12:
+            return complex(N)
+        return (np.exp(1j * v * N) - 1.0) / (z - 1.0)
+
+    return 0.5 * G(omega) - 0.25 * G(omega + a) - 0.25 * G(omega - a)
+
+
+@pytest.mark.parametrize("N,sr,f_tone,f_an", [(400, 16000.0, 1234.5, 1234.5),
+                                               (400, 16000.0, 1000.0, 1107.3),
+                                               (512, 22050.0, 300.0, 4100.0),
+                                               (1024, 22050.0, 9876.5, 9876.5)])
+def test_hann_tone_closed_form(orc, N, sr, f_tone, f_an):
+    """P2: for x[n] = A cos(th_x n + phi), R - iI = sum_n w x e^{-i th n}
+    = A/2 [e^{i phi} Hw(th_x - th) + e^{-i phi} Hw(-th_x - th)] with Hw the Hann DTFT."""
+    A, phi = 0.75, 0.4
+    n = np.arange(N)
+    th_x = 2 * np.pi * f_tone / sr
+    th = 2 * np.pi * f_an / sr
+    x = (A * np.cos(th_x * n + phi)).astype(np.float32)
+    # use the float32 samples exactly: decompose the residual of the rounding separately
+    resid = x.astype(np.float64) - A * np.cos(th_x * n + phi)
+    w = orc.window(N)
+    Z = A / 2 * (np.exp(1j * phi) * _hann_dtft(th_x - th, N) + np.exp(-1j * phi) * _hann_dtft(-th_x - th, N))
+    Z += np.sum(w * resid * np.exp(-1j * th * n))     # exact contribution of the float32 rounding
+    _, R, I = orc.melt_forward(x, sr=sr, n_fft=N, hop=N, freqs=[f_an], out_kind=orc.OUT_POWER, return_ri=True)
+    assert R[0, 0] == pytest.approx(Z.real, rel=1e-10, abs=1e-10 * N)
+    assert I[0, 0] == pytest.approx(-Z.imag, rel=1e-10, abs=1e-10 * N)
+    if f_tone == f_an:
+        # on-frequency: |R - iI| ~ A/2 sum w = A (N-1)/4 (plus the small image term)
+        assert abs(Z) == pytest.approx(A * (N - 1) / 4.0, rel=0.02)
+
+
+def test_projection_linearity(orc):
+    """P3: (R, I) are linear in the frame; S scales by a^2, so the log shifts by 2 ln|a|."""
+    N, H, sr = 400, 160, 16000.0
+    f = orc.melt_frequencies(80, 0.0, 8000.0)
+    # dyadic grid (multiples of 2^-12, |v| < 4) so that a x + b y is exact in float32
+    x = (np.round(_frame(2000, 1) * 1024) / 4096).astype(np.float32)
+    y = (np.round(_frame(2000, 2) * 1024) / 4096).astype(np.float32)
+    a, b = np.float32(0.5), np.float32(-2.0)
+    z = (a * x + b * y).astype(np.float32)
+    _, Rx, Ix = orc.melt_forward(x, sr=sr, n_fft=N, hop=H, freqs=f, return_ri=True)
+    _, Ry, Iy = orc.melt_forward(y, sr=sr, n_fft=N, hop=H, freqs=f, return_ri=True)
+    Lz, Rz, Iz = orc.melt_forward(z, sr=sr, n_fft=N, hop=H, freqs=f, return_ri=True, eps=0.0)
+    assert np.allclose(Rz, a * Rx + b * Ry, rtol=1e-12, atol=1e-12)
+    assert np.allclose(Iz, a * Ix + b * Iy, rtol=1e-12, atol=1e-12)
+    L1 = orc.melt_forward(x, sr=sr, n_fft=N, hop=H, freqs=f, eps=0.0)
+    L2 = orc.melt_forward((4 * x).astype(np.float32), sr=sr, n_fft=N, hop=H, freqs=f, eps=0.0)
+    assert np.allclose(L2 - L1, 2 * math.log(4.0), atol=1e-9)
+
+
+def test_explicit_basis_matches_direct(orc):
+    """Eq. dmp_weights/dmp_projection: folding the window into the basis gives the same R, I
+    as windowing the frame (Eq. dmp_components)."""
+    N, H, sr = 512, 128, 22050.0
+    f = orc.melt_frequencies(32, 0.0, sr / 2)
+    x = _frame(3000, 3)
+    Wr, Wi = orc.melt_basis(sr=sr, n_fft=N, freqs=f)
+    # the basis itself: row m is w[n] cos / sin (2 pi f_m n / sr), checked at 50 digits
+    import mpmath
+    mpmath.mp.dps = 50
+    w = orc.window(N)
+    for (m, n) in [(0, 1), (5, 511), (31, 300), (17, 256)]:
+        arg = 2 * mpmath.pi * mpmath.mpf(f[m]) * n / mpmath.mpf(sr)
+        # an FP64 argument of size |arg| carries ~|arg| ulp of phase error
+        tol = 1e-15 * (1.0 + float(arg))
+        assert Wr[m, n] == pytest.approx(float(mpmath.cos(arg)) * w[n], abs=tol)
+        assert Wi[m, n] == pytest.approx(float(mpmath.sin(arg)) * w[n], abs=tol)
+    L1, R1, I1 = orc.melt_forward(x, sr=sr, n_fft=N, hop=H, freqs=f, return_ri=True)
+    L2, R2, I2 = orc.melt_forward_basis(x, n_fft=N, hop=H, Wr=Wr, Wi=Wi, return_ri=True)
+    assert np.allclose(R1, R2, rtol=1e-12, atol=1e-12) and np.allclose(I1, I2, rtol=1e-12, atol=1e-12)
+    assert np.allclose(L1, L2, atol=1e-10)
+
+
+def test_silence_maps_to_log_floor(orc):
+    """P4: x = 0 gives S = 0, so out = ln(eps) exactly, in both pipelines."""
+    x = np.zeros(4000, np.float32)
+    for eps in (1e-10, 1e-6):
+        L = orc.melt_forward(x, sr=16000.0, n_fft=400, hop=160, freqs=orc.melt_frequencies(80, 0, 8000), eps=eps)
+        assert np.all(L == math.log(eps))
+        L2 = orc.stft_mel_forward(x, sr=16000.0, n_fft=400, hop=160, n_mels=80, fmin=0, fmax=8000, eps=eps)
+        assert np.all(L2 == math.log(eps))
+
+
+def test_output_kinds(orc):
+    x = _frame(1000, 4)
+    f = orc.melt_frequencies(16, 0, 8000)
+    kw = dict(sr=16000.0, n_fft=400, hop=160, freqs=f, eps=1e-10)
+    S = orc.melt_forward(x, out_kind=orc.OUT_POWER, **kw)
+    assert np.allclose(orc.melt_forward(x, out_kind=orc.OUT_MAGNITUDE, **kw), np.sqrt(S), rtol=1e-14)
+    assert np.allclose(orc.melt_forward(x, out_kind=orc.OUT_LOG_POWER, **kw), np.log(S + 1e-10), rtol=1e-14)
+    assert np.allclose(orc.melt_forward(x, out_kind=orc.OUT_LOG_MAGNITUDE, **kw), np.log(np.sqrt(S) + 1e-10),
+                       rtol=1e-14)
+
+
+def test_ragged_clips_equal_separate_calls(orc):
+    """Frames never straddle clips: a batched call equals per-clip calls concatenated;
+    empty and shorter-than-N clips contribute no frames."""
+    lengths = [0, 399, 400, 1234, 5, 2000, 560]
+    wave, off = workloads.random_clips(lengths, seed=7)
+    f = orc.melt_frequencies(20, 0, 8000)
+    kw = dict(sr=16000.0, n_fft=400, hop=160, freqs=f)
+    L = orc.melt_forward(wave, off, **kw)
+    parts = [orc.melt_forward(wave[off[c]:off[c + 1]], **kw) for c in range(len(lengths))]
+    assert L.shape[0] == sum(p.shape[0] for p in parts) == sum(orc.num_frames(n, 400, 160) for n in lengths)
+    assert np.array_equal(L, np.concatenate(parts))
+
+
+# ------------------------------------------------------------------ STFT + filterbank
+
+def test_parseval(orc):
+    """P5: sum over all N bins of |X_k|^2 = N sum_n (w x)^2; the one-sided spectrum counts
+    bins 1..N/2-1 twice."""
+    for N in (400, 512, 1024, 15):
+        x = _frame(3 * N, 5)
+        P = orc.power_spectrum(x, n_fft=N, hop=N)
+        w = orc.window(N)
+        for t in range(P.shape[0]):
+            xt = w * x[t * N:(t + 1) * N].astype(np.float64)
+            full = P[t, 0] + 2 * P[t, 1:(N + 1) // 2].sum() + (P[t, N // 2] if N % 2 == 0 else 0.0)
+            assert full == pytest.approx(N * np.sum(xt * xt), rel=1e-12)
+
+
+@pytest.mark.parametrize("N,sr,M,fmin,fmax", [(400, 16000, 80, 0.0, 8000.0), (400, 16000, 80, 80.0, 7600.0),
+                                               (512, 16000, 128, 0.0, 8000.0), (1024, 22050, 128, 0.0, 11025.0),
+                                               (400, 16000, 128, 0.0, 8000.0)])
+def test_filterbank_matches_library(orc, N, sr, M, fmin, fmax):
+    """The HTK triangular filterbank equals transformers.audio_utils.mel_filter_bank
+    (a torchaudio/librosa-derived routine) with and without area normalisation."""
+    from transformers.audio_utils import mel_filter_bank
+    for norm, lib_norm in ((orc.NORM_NONE, None), (orc.NORM_SLANEY, "slaney")):
+        F = orc.mel_filterbank(n_fft=N, sr=sr, n_mels=M, fmin=fmin, fmax=fmax, norm=norm)
+        ref = mel_filter_bank(N // 2 + 1, M, fmin, fmax, sr, norm=lib_norm, mel_scale="htk").T
+        assert np.allclose(F, ref, rtol=1e-10, atol=1e-12)
+
+
+def test_filterbank_partition_of_unity(orc):
+    """P6: unnormalised triangles sum to 1 at every bin between the first and last centre,
+    and a triangle peaks at 1 on its centre."""
+    N, sr, M = 1024, 16000.0, 40
+    F = orc.mel_filterbank(n_fft=N, sr=sr, n_mels=M, fmin=0.0, fmax=8000.0)
+    g = orc.mel_grid_hz(M, 0.0, 8000.0)
+    fk = np.arange(N // 2 + 1) * sr / N
+    inner = (fk >= g[1]) & (fk <= g[M])
+    assert np.allclose(F.sum(axis=0)[inner], 1.0, atol=1e-12)
+    assert np.all(F >= 0.0)
+    # nnz bound of Eq. complexity_conv: nnz(F) <= M (N/2 + 1)
+    assert np.count_nonzero(F) <= M * (N // 2 + 1)
+
+
+def test_empty_filters_at_128_mels(orc):
+    """At 16 kHz, N=400 and 128 HTK bins over 0-8 kHz the lowest triangles are narrower than
+    the 40 Hz bin spacing; the ones that contain no bin are all-zero rows, so the comparator
+    outputs ln(eps) there."""
+    F = orc.mel_filterbank(n_fft=400, sr=16000.0, n_mels=128, fmin=0.0, fmax=8000.0)
+    empty = np.where(F.sum(axis=1) == 0.0)[0]
+    assert len(empty) >= 1 and np.all(empty < 16)
+
+
+def test_stft_mel_matches_library_pipeline(orc):
+    """The whole comparator (frame, symmetric Hann, DFT power, HTK filterbank, ln) equals
+    transformers.audio_utils.spectrogram with numpy's FFT (single-precision spectrum, so
+    the tolerance is float32-level)."""
+    from transformers.audio_utils import mel_filter_bank, spectrogram, window_function
+    cfg = workloads.config1(seed=3)
+    x = cfg["wave"]
+    N, H, sr, M = 400, 160, 16000, 80
+    fb = mel_filter_bank(N // 2 + 1, M, 0.0, 8000.0, sr, norm=None, mel_scale="htk")
+    ref = spectrogram(x, window_function(N, "hann", periodic=False), N, H, power=2.0, center=False,
+                      mel_filters=fb, mel_floor=0.0, dtype=np.float64).T
+    out = orc.stft_mel_forward(x, sr=sr, n_fft=N, hop=H, n_mels=M, fmin=0.0, fmax=8000.0,
+                               out_kind=orc.OUT_POWER)
+    assert out.shape == ref.shape == (98, 80)
+    assert np.allclose(out, ref, rtol=2e-6, atol=1e-9 * ref.max())
+    L = orc.stft_mel_forward(x, sr=sr, n_fft=N, hop=H, n_mels=M, fmin=0.0, fmax=8000.0, eps=1e-10)
+    assert np.allclose(L, np.log(out + 1e-10), rtol=1e-14)
+    mag = orc.stft_mel_forward(x, sr=sr, n_fft=N, hop=H, n_mels=M, fmin=0.0, fmax=8000.0,
+                               out_kind=orc.OUT_MAGNITUDE)
+    ref1 = spectrogram(x, window_function(N, "hann", periodic=False), N, H, power=1.0, center=False,
+                       mel_filters=fb, mel_floor=0.0, dtype=np.float64).T
+    assert np.allclose(mag, ref1, rtol=2e-6, atol=1e-9 * ref1.max())
+
+
+# ------------------------------------------------------------------ gradient
+
+def _tiny():
+    # N=16, H=4, 4 analysis frequencies, 64 samples on a dyadic grid so that x +- h is
+    # exact in float32
+    rng = np.random.default_rng(11)
+    x = (np.round(rng.uniform(-1, 1, 64) * 256) / 256).astype(np.float32)
+    return x, 16, 4
+
+
+def test_gradient_wave_central_difference(orc):
+    """P10: for the power output S is quadratic in x, so the central difference with a
+    float32-exact step is exact; for the log output it agrees to O(h^2)."""
+    x, N, H = _tiny()
+    f = np.array([1000.0, 2345.6, 4000.0, 7000.0])
+    Wr, Wi = orc.melt_basis(sr=16000.0, n_fft=N, freqs=f)
+    T = orc.num_frames(x.size, N, H)
+    g = np.random.default_rng(12).standard_normal((T, 4))
+    for kind, h, tol in ((orc.OUT_POWER, 2.0 ** -8, 1e-11), (orc.OUT_LOG_POWER, 2.0 ** -14, 2e-6)):
+        gx, _, _ = orc.melt_backward(x, n_fft=N, hop=H, Wr=Wr, Wi=Wi, grad_out=g, out_kind=kind, eps=1e-3)
+        fd = np.empty(x.size)
+        for s in range(x.size):
+            xp = x.copy(); xp[s] += np.float32(h)
+            xm = x.copy(); xm[s] -= np.float32(h)
+            op = orc.melt_forward_basis(xp, n_fft=N, hop=H, Wr=Wr, Wi=Wi, out_kind=kind, eps=1e-3)
+            om = orc.melt_forward_basis(xm, n_fft=N, hop=H, Wr=Wr, Wi=Wi, out_kind=kind, eps=1e-3)
+            fd[s] = np.sum(g * (op - om)) / (2 * h)
+        assert np.allclose(gx, fd, rtol=tol, atol=tol * np.abs(fd).max())
+    # samples after the last frame get zero gradient
+    x2 = np.concatenate([x, np.ones(3, np.float32)])
+    gx2, _, _ = orc.melt_backward(x2, n_fft=N, hop=H, Wr=Wr, Wi=Wi, grad_out=g, out_kind=orc.OUT_POWER)
+    assert np.all(gx2[-3:] == 0.0)
+
+
+def test_gradient_basis_central_difference(orc):
+    """P10: dWr, dWi against central differences of the basis entries (FP64)."""
+    x, N, H = _tiny()
+    f = np.array([500.0, 3000.0, 6500.0])
+    Wr, Wi = orc.melt_basis(sr=16000.0, n_fft=N, freqs=f)
+    T = orc.num_frames(x.size, N, H)
+    g = np.random.default_rng(13).standard_normal((T, 3))
+    _, dWr, dWi = orc.melt_backward(x, n_fft=N, hop=H, Wr=Wr, Wi=Wi, grad_out=g, eps=1e-3)
+    h = 1e-6
+    for (which, dW) in ((0, dWr), (1, dWi)):
+        for (m, n) in [(0, 0), (1, 7), (2, 15), (0, 9)]:
+            Wp = [Wr.copy(), Wi.copy()]; Wp[which][m, n] += h
+            Wm = [Wr.copy(), Wi.copy()]; Wm[which][m, n] -= h
+            op = orc.melt_forward_basis(x, n_fft=N, hop=H, Wr=Wp[0], Wi=Wp[1], eps=1e-3)
+            om = orc.melt_forward_basis(x, n_fft=N, hop=H, Wr=Wm[0], Wi=Wm[1], eps=1e-3)
+            fd = np.sum(g * (op - om)) / (2 * h)
+            assert dW[m, n] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+# ------------------------------------------------------------------ MFCCT (Eq. mfcct_matrix)
+
+def test_dct_matches_scipy(orc):
+    from scipy.fft import dct
+    M, K = 80, 40
+    D = orc.dct2_ortho(K, M)
+    eye = np.eye(M)
+    ref = dct(eye, type=2, norm="ortho", axis=0)[:K]      # columns: DCT of unit vectors
+    assert np.allclose(D, ref, atol=1e-14)
+    assert np.allclose(orc.dct2_ortho(M, M) @ orc.dct2_ortho(M, M).T, eye, atol=1e-13)
+
+
+# ------------------------------------------------------------------ operand rounding models
+
+def test_rounding_models_match_torch_casts(orc):
+    import torch
+    rng = np.random.default_rng(21)
+    v = np.concatenate([rng.standard_normal(3000) * 10.0 ** rng.uniform(-12, 3, 3000),
+                        [0.0, -0.0, 1.0, -1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 2.0 ** -130, 6.1e-5, 65504.0],
+                        # bf16 / fp16 / e4m3 halfway points (ties to even)
+                        [1 + 2 ** -8 + 2 ** -9, 1 + 2 ** -11, 1 + 3 * 2 ** -11, 1.0625, 1.1875, 2.0 ** -10,
+                         3 * 2.0 ** -10, 440.0, 447.0]]).astype(np.float32)
+    t = torch.from_numpy(v)
+    assert np.array_equal(orc.round_bf16(v), t.to(torch.bfloat16).to(torch.float64).numpy())
+    assert np.array_equal(orc.round_fp16(v), t.to(torch.float16).to(torch.float64).numpy())
+    inr = np.abs(v) < 448.0
+    assert np.array_equal(orc.round_e4m3(v[inr]), t[torch.from_numpy(inr)].to(torch.float8_e4m3fn)
+                          .to(torch.float64).numpy())
+    # saturation beyond the largest finite E4M3 value
+    assert np.array_equal(orc.round_e4m3(np.array([448.0, 460.0, 464.0, 1e6, -1e6], np.float32)),
+                          [448.0, 448.0, 448.0, 448.0, -448.0])
+
+
+def test_quant_models_are_consistent(orc):
+    """With operands already representable in the format, the operand model reduces to the
+    plain FP64 projection; BF16x3 recovers about 16 bits of every product."""
+    N, H, sr = 400, 160, 16000.0
+    f = orc.melt_frequencies(16, 0, 8000)
+    Wr, Wi = orc.melt_basis(sr=sr, n_fft=N, freqs=f)
+    x = _frame(2000, 8)
+    xb = orc.round_bf16(x).astype(np.float32)
+    Wrb, Wib = orc.round_bf16(Wr.astype(np.float32)), orc.round_bf16(Wi.astype(np.float32))
+    ref = orc.melt_forward_basis(xb, n_fft=N, hop=H, Wr=Wrb, Wi=Wib, out_kind=orc.OUT_POWER)
+    q = orc.melt_forward_quant(xb, n_fft=N, hop=H, Wr=Wrb, Wi=Wib, prec=orc.PREC_BF16, out_kind=orc.OUT_POWER)
+    assert np.allclose(q, ref, rtol=1e-13)
+    exact = orc.melt_forward_basis(x, n_fft=N, hop=H, Wr=Wr, Wi=Wi, out_kind=orc.OUT_POWER)
+    q3 = orc.melt_forward_quant(x, n_fft=N, hop=H, Wr=Wr, Wi=Wi, prec=orc.PREC_BF16X3, out_kind=orc.OUT_POWER)
+    q1 = orc.melt_forward_quant(x, n_fft=N, hop=H, Wr=Wr, Wi=Wi, prec=orc.PREC_BF16, out_kind=orc.OUT_POWER)
+    act = exact > 1e-6 * exact.max()
+    e3 = np.abs(q3[act] / exact[act] - 1).max()
+    e1 = np.abs(q1[act] / exact[act] - 1).max()
+    assert e3 < 1e-3 and e3 < e1 / 30
+    q8 = orc.melt_forward_quant(x, n_fft=N, hop=H, Wr=Wr, Wi=Wi, prec=orc.PREC_FP8_E4M3, out_kind=orc.OUT_POWER)
+    loud = exact > 1e-2 * exact.max()
+    assert np.median(np.abs(q8[loud] / exact[loud] - 1)) < 0.1
+
+
+# ------------------------------------------------------------------ values the paper prints
+
+def test_paper_log_convention(orc):
+    """The paper's equivalence margin is printed both in nats and in dB (0.244 nat = 1.06 dB),
+    which fixes the natural log in Eq. meltf and 10 log10 on power when converting to dB."""
+    with open(os.path.join(GOLDEN, "paper_constants.json")) as fh:
+        gold = json.load(fh)
+    d = gold["equivalence_margin"]
+    assert round(d["nat"] * 10.0 / math.log(10.0), 2) == d["dB"]
+    # the other candidate conventions do not reproduce the printed pair
+    assert round(d["nat"] * 20.0 / math.log(10.0), 2) != d["dB"]
+    assert round(d["nat"] * 10.0, 2) != d["dB"]
