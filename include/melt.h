@@ -1,0 +1,225 @@
+/*
+ * melt.h - C ABI of the MI355X (gfx950) MelT frontend library (libmelt.so).
+ *
+ * MelT (arXiv 2606.01009, Methodology "Matmul-Native Mel Frontends") computes, for every
+ * frame x_t of a waveform, the projections of the windowed frame onto cosines and sines at
+ * Mel-spaced frequencies f_m (Eq. dmp_components), the energy S = R^2 + I^2
+ * (Eq. dmp_energy) and log(S + eps) (Eq. meltf).  The window is folded into a fixed basis
+ * (Eq. dmp_weights) so that all frames are projected by one GEMM against the stacked
+ * cos/sin basis (Eq. dmp_projection).  The library also provides the conventional
+ * pipeline the paper compares against (STFT power on uniform bins aggregated by
+ * triangular Mel filters, then log; Methodology, Eq. complexity_conv), the gradient of
+ * the projection for learnable frontends, and a streaming interface.
+ *
+ * Conventions shared by every entry point
+ *   - All functions return melt_status (MELT_OK = 0).  Nothing aborts or throws across the
+ *     ABI; melt_last_error() gives a thread-local message for the last failure.
+ *   - Pointers documented "device" must point to memory on the plan's device that the
+ *     caller allocated and owns; pointers documented "host" are ordinary host memory.
+ *     The library never frees caller memory and keeps no pointer to it after a call
+ *     returns (except a stream state's own buffers, which it owns).
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is enqueued
+ *     asynchronously on it; the call returns before the GPU finishes.
+ *   - A batch of clips is one float32 buffer with all clips back to back, described by
+ *     `clip_offsets` (int64, n_clips + 1 entries, non-decreasing, offsets[0] may be > 0):
+ *     clip c is samples [offsets[c], offsets[c+1]).  A clip of L samples has
+ *     T_c = 1 + floor((L - n_fft) / hop) frames if L >= n_fft and none otherwise (frames
+ *     start at t*hop with no centring or padding).  Outputs are frame-major [T, n_mels]
+ *     float32 with the frames of clip 0 first, T = sum_c T_c.
+ *   - Calls that share a plan use the plan's workspace and must be issued on one stream
+ *     (or otherwise serialised); use one plan per concurrent stream.
+ */
+#ifndef MELT_H
+#define MELT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MELT_OK = 0,
+    MELT_E_INVALID_ARG = 1,  /* a NULL pointer, a bad enum, or a parameter out of range */
+    MELT_E_UNSUPPORTED = 2,  /* valid but not implemented for this configuration */
+    MELT_E_NO_MEMORY = 3,    /* a host or device allocation failed */
+    MELT_E_HIP = 4,          /* a HIP runtime call failed (detail in melt_last_error) */
+    MELT_E_SHAPE = 5         /* sizes inconsistent with the plan (e.g. too many frames) */
+} melt_status;
+
+/* Analysis window, folded into the basis.  The paper uses the symmetric Hann window
+ * w[n] = 0.5 - 0.5 cos(2 pi n / (N - 1)) (Methodology). */
+typedef enum { MELT_WIN_HANN_SYMMETRIC = 0, MELT_WIN_HANN_PERIODIC = 1, MELT_WIN_RECT = 2 } melt_window;
+
+/* Mel scale: HTK mu(f) = 2595 log10(1 + f/700) (Eq. mel_scale) or the Slaney scale. */
+typedef enum { MELT_MEL_HTK = 0, MELT_MEL_SLANEY = 1 } melt_mel_formula;
+
+/* Placement of the M analysis frequencies: the centres of the M triangular filters of the
+ * conventional filterbank (interior points of an (M+2)-point grid uniform in Mel between
+ * fmin and fmax; the reading used throughout), or M points uniform in Mel from fmin to
+ * fmax inclusive. */
+typedef enum { MELT_PLACE_FILTER_CENTRES = 0, MELT_PLACE_LINSPACE = 1 } melt_freq_placement;
+
+/* Normalisation of the comparator's triangular filters: peak 1, or unit area (Slaney). */
+typedef enum { MELT_FB_NORM_NONE = 0, MELT_FB_NORM_SLANEY = 1 } melt_fb_norm;
+
+/* Output map applied to S = R^2 + I^2 (MelT) or to the filterbank sum (comparator):
+ * ln(S + eps) (Eq. meltf), ln(sqrt(S) + eps), S, sqrt(S).  For the comparator the
+ * magnitude kinds aggregate |X_k| instead of |X_k|^2. */
+typedef enum {
+    MELT_OUT_LOG_POWER = 0, MELT_OUT_LOG_MAGNITUDE = 1, MELT_OUT_POWER = 2, MELT_OUT_MAGNITUDE = 3
+} melt_output;
+
+/* Arithmetic of the projection GEMM (all accumulate in FP32; the basis is computed in
+ * FP64 and rounded once):
+ *   FP32     - FP32 operands (v_mfma_f32_32x32x2_f32)
+ *   BF16     - bfloat16 operands
+ *   FP16     - binary16 operands
+ *   FP8_E4M3 - OCP E4M3 operands; each frame scaled by 448 / max|x_t| and each basis row by
+ *              448 / max|row| before rounding, undone in FP32 after the product
+ *   BF16X3   - split-bfloat16 compensated product xh*Wh + xh*Wl + xl*Wh */
+typedef enum {
+    MELT_PREC_FP32 = 0, MELT_PREC_BF16 = 1, MELT_PREC_FP16 = 2, MELT_PREC_FP8_E4M3 = 3, MELT_PREC_BF16X3 = 4
+} melt_precision;
+
+/* Frontend parameters (Experiments, Table "Audio frontend configuration": 16 kHz,
+ * N = 400, H = 160, M = 80).  Enumerations are stored as int32_t for a fixed layout. */
+typedef struct {
+    double  sample_rate;   /* Hz, > 0 */
+    int32_t n_fft;         /* frame length N (window length), 2 .. 4096 */
+    int32_t hop;           /* hop H, 1 .. 65536 */
+    int32_t window;        /* melt_window */
+    int32_t n_mels;        /* M, 1 .. 512 */
+    double  fmin, fmax;    /* 0 <= fmin < fmax <= sample_rate / 2 */
+    int32_t mel_formula;   /* melt_mel_formula */
+    int32_t placement;     /* melt_freq_placement */
+    int32_t output;        /* melt_output */
+    double  log_eps;       /* eps > 0 of the log kinds (default 1e-10) */
+    int32_t precision;     /* melt_precision of melt_forward */
+    int32_t fb_norm;       /* melt_fb_norm of stft_mel_forward */
+} melt_config;
+
+typedef struct melt_plan_s *melt_plan;
+typedef struct melt_stream_s *melt_stream_state;
+
+/* Fills `cfg` with the paper's spectral configuration at 16 kHz: N = 400, H = 160,
+ * M = 80, symmetric Hann, HTK, filter-centre placement, fmin 0, fmax 8000, log power,
+ * eps 1e-10, FP32, peak-1 filters.  cfg: host, caller-owned. */
+melt_status melt_config_default(melt_config *cfg);
+
+/* Number of frames of a clip of n_samples samples (see the conventions above); 0 if
+ * n_samples < n_fft; -1 if n_fft < 1 or hop < 1. */
+int64_t melt_num_frames(int64_t n_samples, int32_t n_fft, int32_t hop);
+
+/* Builds a plan on HIP device `device`: the Mel analysis frequencies (Eq. mel_scale,
+ * Eq. inverse_mel), the window-folded cos/sin basis (Eq. dmp_weights) in FP64 with exact
+ * phase reduction, rounded and packed for every precision, the comparator's triangular
+ * filterbank and FFT tables, and a small device workspace.  cfg: host, read only;
+ * *out receives the plan (owned by the caller, freed by melt_plan_destroy).  Errors:
+ * MELT_E_INVALID_ARG for out-of-range parameters, MELT_E_UNSUPPORTED for sizes the
+ * kernels do not handle, MELT_E_HIP / MELT_E_NO_MEMORY on runtime failures. */
+melt_status melt_plan_create(const melt_config *cfg, int device, melt_plan *out);
+
+/* Frees the plan and its device memory (synchronises the plan's device first).  NULL ok. */
+melt_status melt_plan_destroy(melt_plan plan);
+
+/* Copies the plan's configuration into *cfg (host). */
+melt_status melt_plan_get_config(melt_plan plan, melt_config *cfg);
+
+/* The M analysis frequencies f_m in Hz (Eq. inverse_mel), FP64, into host array
+ * freqs_hz[n_mels]. */
+melt_status melt_plan_get_frequencies(melt_plan plan, double *freqs_hz);
+
+/* The plan's current FP32 basis, in the paper's stacked order [W^(r); W^(i)]
+ * (Eq. dmp_projection): rows 0..M-1 are w[n] cos(2 pi f_m n / sr), rows M..2M-1 the sines,
+ * each n_fft long.  h_basis: host, float32 [2*n_mels, n_fft]. */
+melt_status melt_plan_get_basis(melt_plan plan, float *h_basis);
+
+/* Replaces the plan's basis (learnable frontends).  d_basis: device, float32
+ * [2*n_mels, n_fft] in the stacked order above; it is read on `stream` and re-packed into
+ * every precision's layout before later calls on that stream.  The comparator is not
+ * affected. */
+melt_status melt_plan_set_basis(melt_plan plan, const float *d_basis, void *stream);
+
+/* Device prefix sums of the frame counts: d_frame_offsets[c] = sum_{c' < c} T_c' for
+ * c = 0..n_clips.  d_clip_offsets: device int64 [n_clips + 1]; d_frame_offsets: device
+ * int64 [n_clips + 1]. */
+melt_status melt_frame_offsets(melt_plan plan, const int64_t *d_clip_offsets, int32_t n_clips,
+                               int64_t *d_frame_offsets, void *stream);
+
+/* MelT forward (Eqs. dmp_projection, dmp_matrix_energy, meltf): out[t, m] =
+ * map(R[t,m]^2 + I[t,m]^2) for all frames of all clips, in the plan's precision.
+ * One persistent launch covers the ragged batch; frames are read straight from the
+ * waveform (no frame matrix is formed).
+ *   d_wave         device float32, all clips back to back (read only)
+ *   d_clip_offsets device int64 [n_clips + 1] (read only)
+ *   n_clips        >= 0 (0 enqueues nothing)
+ *   n_frames       T, the number of rows of d_out; the sum of the clips' frame counts must
+ *                  equal it (rows past the computed total are left untouched and frames
+ *                  beyond n_frames are not written)
+ *   d_out          device float32 [n_frames, n_mels] (written)
+ * Errors: MELT_E_INVALID_ARG (NULL pointers with n_frames > 0, negative counts). */
+melt_status melt_forward(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets,
+                         int32_t n_clips, int64_t n_frames, float *d_out, void *stream);
+
+/* As melt_forward, also writing the raw projections for the backward pass:
+ * d_proj device float32 [n_frames, 2 * n_mels], row t = (R[t,0], I[t,0], R[t,1], I[t,1], ...). */
+melt_status melt_forward_proj(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets,
+                              int32_t n_clips, int64_t n_frames, float *d_out, float *d_proj,
+                              void *stream);
+
+/* Conventional comparator: per frame, the symmetric-window N-point real DFT by a
+ * hand-written mixed-radix FFT, the power |X_k|^2 (or |X_k| for the magnitude kinds) on
+ * bins k = 0..N/2, the sparse triangular Mel filterbank (Methodology; nnz bound of
+ * Eq. complexity_conv) and the output map, fused in one kernel in FP32.  Arguments as in
+ * melt_forward.  MELT_E_UNSUPPORTED if n_fft has a prime factor other than 2, 3 or 5. */
+melt_status stft_mel_forward(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets,
+                             int32_t n_clips, int64_t n_frames, float *d_out, void *stream);
+
+/* Gradient of the MelT forward (not in the paper; chain rule through Eqs. meltf,
+ * dmp_matrix_energy, dmp_projection), in FP32:
+ *   G[t, 2m]   = g[t,m] map'(S) 2 R[t,m],  G[t, 2m+1] = g[t,m] map'(S) 2 I[t,m]
+ *   d_grad_wave[s] = sum over frames t and n with start_t + n = s of (G W)[t, n]
+ *   d_grad_basis   = G^T X in the stacked order of melt_plan_get_basis
+ *   d_grad_out   device float32 [n_frames, n_mels] (read only)
+ *   d_proj       device float32 [n_frames, 2 n_mels] from melt_forward_proj, or NULL to
+ *                recompute the projections
+ *   d_grad_wave  device float32, same length as d_wave's samples up to
+ *                d_clip_offsets[n_clips] (written: samples in no frame get 0), or NULL
+ *   d_grad_basis device float32 [2 n_mels, n_fft] (written, not accumulated), or NULL
+ * Deterministic: no floating-point atomics. */
+melt_status melt_backward(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets,
+                          int32_t n_clips, int64_t n_frames, const float *d_grad_out,
+                          const float *d_proj, float *d_grad_wave, float *d_grad_basis,
+                          void *stream);
+
+/* Streaming: n_streams independent audio streams, each keeping the last n_fft - hop
+ * samples (and the phase of its next frame) in device memory owned by the state.
+ * melt_stream_push appends chunk_len new samples to every stream (d_chunk: device float32
+ * [n_streams, chunk_len]) and writes each stream's newly complete frames to
+ * d_out (device float32 [n_streams, max_frames_per_push, n_mels], frame-major per stream)
+ * and their count to d_frames_emitted (device int32 [n_streams]).  max_frames_per_push =
+ * floor((chunk_len + n_fft - 1) / hop) + 1 bounds every push.  A push is one or two kernel
+ * launches with no host synchronisation and no allocation, so it can be captured in a
+ * hipGraph and replayed with new chunk contents. */
+melt_status melt_stream_create(melt_plan plan, int32_t n_streams, int32_t chunk_len,
+                               melt_stream_state *out);
+melt_status melt_stream_destroy(melt_stream_state st);
+melt_status melt_stream_reset(melt_stream_state st, void *stream);
+int32_t     melt_stream_max_frames(melt_stream_state st);
+melt_status melt_stream_push(melt_stream_state st, const float *d_chunk, float *d_out,
+                             int32_t *d_frames_emitted, void *stream);
+
+/* Autotuning: times the candidate tile shapes of melt_forward for this plan on a
+ * synthetic batch of total_frames frames and keeps the fastest for later calls.
+ * Writes a short description of the winner to `desc` (host, may be NULL). */
+melt_status melt_autotune(melt_plan plan, int64_t total_frames, char *desc, int32_t desc_len);
+
+/* Human-readable name of a status; thread-local text of the last error. */
+const char *melt_status_string(melt_status s);
+const char *melt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MELT_H */

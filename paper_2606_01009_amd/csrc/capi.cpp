@@ -1,0 +1,242 @@
+// extern "C" entry points of libmelt (include/melt.h): argument validation, plan
+// lifecycle and dispatch to the kernels.  No call aborts or throws across the ABI.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "melt_internal.h"
+
+namespace melt {
+
+static thread_local std::string g_last_error;
+
+melt_status set_error(melt_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+melt_status hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return MELT_OK;
+    return set_error(MELT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static melt_status validate(const melt_config &c) {
+    if (!(c.sample_rate > 0.0) || !std::isfinite(c.sample_rate)) return set_error(MELT_E_INVALID_ARG, "sample_rate must be > 0");
+    if (c.n_fft < 2 || c.n_fft > 4096) return set_error(MELT_E_INVALID_ARG, "n_fft must be in [2, 4096]");
+    if (c.hop < 1 || c.hop > 65536) return set_error(MELT_E_INVALID_ARG, "hop must be in [1, 65536]");
+    if (c.n_mels < 1 || c.n_mels > 512) return set_error(MELT_E_INVALID_ARG, "n_mels must be in [1, 512]");
+    if (!(c.fmin >= 0.0) || !(c.fmax > c.fmin) || c.fmax > c.sample_rate / 2 * (1 + 1e-12))
+        return set_error(MELT_E_INVALID_ARG, "need 0 <= fmin < fmax <= sample_rate / 2");
+    if (c.window < 0 || c.window > 2) return set_error(MELT_E_INVALID_ARG, "bad window");
+    if (c.mel_formula < 0 || c.mel_formula > 1) return set_error(MELT_E_INVALID_ARG, "bad mel_formula");
+    if (c.placement < 0 || c.placement > 1) return set_error(MELT_E_INVALID_ARG, "bad placement");
+    if (c.output < 0 || c.output > 3) return set_error(MELT_E_INVALID_ARG, "bad output");
+    if (!(c.log_eps > 0.0) || !std::isfinite(c.log_eps)) return set_error(MELT_E_INVALID_ARG, "log_eps must be > 0");
+    if (c.precision < 0 || c.precision > 4) return set_error(MELT_E_INVALID_ARG, "bad precision");
+    if (c.fb_norm < 0 || c.fb_norm > 1) return set_error(MELT_E_INVALID_ARG, "bad fb_norm");
+    return MELT_OK;
+}
+
+static void free_plan(Plan *p) {
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    void *bufs[] = {p->d_basis32, p->d_pack_f32, p->d_pack_h16, p->d_pack_lo, p->d_pack_f8, p->d_rowscale,
+                    p->d_fb_w, p->d_fb_start, p->d_fb_off, p->d_twiddle, p->d_chunks, p->d_nchunks};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    delete p;
+}
+
+static melt_status alloc(void **d, size_t bytes) {
+    if (hipMalloc(d, bytes ? bytes : 4) != hipSuccess) return set_error(MELT_E_NO_MEMORY, "hipMalloc failed");
+    return MELT_OK;
+}
+
+static melt_status check_batch(Plan *p, const void *wave, const int64_t *off, int32_t n_clips, int64_t n_frames,
+                               const void *out) {
+    if (!p) return set_error(MELT_E_INVALID_ARG, "plan is NULL");
+    if (n_clips < 0 || n_frames < 0) return set_error(MELT_E_INVALID_ARG, "negative n_clips or n_frames");
+    if (n_clips > 0 && !off) return set_error(MELT_E_INVALID_ARG, "clip_offsets is NULL");
+    if (n_frames > 0 && (!wave || !out)) return set_error(MELT_E_INVALID_ARG, "wave or out is NULL");
+    if (n_frames > (int64_t(1) << 40)) return set_error(MELT_E_SHAPE, "n_frames too large");
+    return MELT_OK;
+}
+
+}  // namespace melt
+
+using namespace melt;
+
+extern "C" {
+
+melt_status melt_config_default(melt_config *cfg) {
+    if (!cfg) return set_error(MELT_E_INVALID_ARG, "cfg is NULL");
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->sample_rate = 16000.0;
+    cfg->n_fft = 400;
+    cfg->hop = 160;
+    cfg->window = MELT_WIN_HANN_SYMMETRIC;
+    cfg->n_mels = 80;
+    cfg->fmin = 0.0;
+    cfg->fmax = 8000.0;
+    cfg->mel_formula = MELT_MEL_HTK;
+    cfg->placement = MELT_PLACE_FILTER_CENTRES;
+    cfg->output = MELT_OUT_LOG_POWER;
+    cfg->log_eps = 1e-10;
+    cfg->precision = MELT_PREC_FP32;
+    cfg->fb_norm = MELT_FB_NORM_NONE;
+    return MELT_OK;
+}
+
+int64_t melt_num_frames(int64_t n_samples, int32_t n_fft, int32_t hop) {
+    if (n_fft < 1 || hop < 1) return -1;
+    if (n_samples < n_fft) return 0;
+    return 1 + (n_samples - n_fft) / hop;
+}
+
+melt_status melt_plan_create(const melt_config *cfg, int device, melt_plan *out) {
+    if (!cfg || !out) return set_error(MELT_E_INVALID_ARG, "cfg or out is NULL");
+    *out = nullptr;
+    melt_status st = validate(*cfg);
+    if (st != MELT_OK) return st;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return set_error(MELT_E_HIP, "no HIP device");
+    if (device < 0 || device >= ndev) return set_error(MELT_E_INVALID_ARG, "bad device index");
+    st = hip_check(hipSetDevice(device), "hipSetDevice");
+    if (st != MELT_OK) return st;
+    Plan *p = new (std::nothrow) Plan();
+    if (!p) return set_error(MELT_E_NO_MEMORY, "plan");
+    p->cfg = *cfg;
+    p->device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        p->cu_count = cus;
+    st = plan_build_host(*p);
+    const size_t nb = size_t(2) * p->M * p->N;
+    const size_t RT = p->row_tiles;
+    if (st == MELT_OK) st = alloc((void **)&p->d_basis32, nb * sizeof(float));
+    if (st == MELT_OK) st = alloc(&p->d_pack_f32, RT * p->geo32.n_groups * 64 * 4 * sizeof(float));
+    if (st == MELT_OK) st = alloc(&p->d_pack_h16, RT * p->geo16.n_groups * 64 * 8 * 2);
+    if (st == MELT_OK) st = alloc(&p->d_pack_lo, RT * p->geo16.n_groups * 64 * 8 * 2);
+    if (st == MELT_OK) st = alloc((void **)&p->d_nchunks, sizeof(int));
+    if (st == MELT_OK) {
+        std::vector<float> b32(nb);
+        for (size_t i = 0; i < nb; ++i) b32[i] = float(p->basis64[i]);
+        st = hip_check(hipMemcpy(p->d_basis32, b32.data(), nb * sizeof(float), hipMemcpyHostToDevice), "upload basis");
+    }
+    if (st == MELT_OK) st = pack_basis(*p, nullptr);
+    if (st == MELT_OK) st = stft_plan_build(*p);
+    if (st == MELT_OK) st = ensure_chunks(*p, 4096);
+    if (st != MELT_OK) {
+        free_plan(p);
+        return st;
+    }
+    *out = reinterpret_cast<melt_plan>(p);
+    return MELT_OK;
+}
+
+melt_status melt_plan_destroy(melt_plan plan) {
+    free_plan(reinterpret_cast<Plan *>(plan));
+    return MELT_OK;
+}
+
+melt_status melt_plan_get_config(melt_plan plan, melt_config *cfg) {
+    if (!plan || !cfg) return set_error(MELT_E_INVALID_ARG, "NULL argument");
+    *cfg = reinterpret_cast<Plan *>(plan)->cfg;
+    return MELT_OK;
+}
+
+melt_status melt_plan_get_frequencies(melt_plan plan, double *freqs_hz) {
+    if (!plan || !freqs_hz) return set_error(MELT_E_INVALID_ARG, "NULL argument");
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    std::memcpy(freqs_hz, p->freqs.data(), sizeof(double) * p->M);
+    return MELT_OK;
+}
+
+melt_status melt_plan_get_basis(melt_plan plan, float *h_basis) {
+    if (!plan || !h_basis) return set_error(MELT_E_INVALID_ARG, "NULL argument");
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    melt_status st = hip_check(hipSetDevice(p->device), "hipSetDevice");
+    if (st != MELT_OK) return st;
+    st = hip_check(hipDeviceSynchronize(), "sync");
+    if (st != MELT_OK) return st;
+    return hip_check(hipMemcpy(h_basis, p->d_basis32, sizeof(float) * 2 * p->M * p->N, hipMemcpyDeviceToHost),
+                     "download basis");
+}
+
+melt_status melt_plan_set_basis(melt_plan plan, const float *d_basis, void *stream) {
+    if (!plan || !d_basis) return set_error(MELT_E_INVALID_ARG, "NULL argument");
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    hipStream_t s = (hipStream_t)stream;
+    melt_status st = hip_check(hipSetDevice(p->device), "hipSetDevice");
+    if (st != MELT_OK) return st;
+    st = hip_check(hipMemcpyAsync(p->d_basis32, d_basis, sizeof(float) * 2 * p->M * p->N, hipMemcpyDeviceToDevice, s),
+                   "copy basis");
+    if (st != MELT_OK) return st;
+    return pack_basis(*p, s);
+}
+
+melt_status melt_frame_offsets(melt_plan plan, const int64_t *d_clip_offsets, int32_t n_clips,
+                               int64_t *d_frame_offsets, void *stream) {
+    if (!plan || !d_frame_offsets || (n_clips > 0 && !d_clip_offsets) || n_clips < 0)
+        return set_error(MELT_E_INVALID_ARG, "bad argument");
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    return launch_frame_offsets(d_clip_offsets, n_clips, p->N, p->H, d_frame_offsets, (hipStream_t)stream);
+}
+
+melt_status melt_forward(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets, int32_t n_clips,
+                         int64_t n_frames, float *d_out, void *stream) {
+    return melt_forward_proj(plan, d_wave, d_clip_offsets, n_clips, n_frames, d_out, nullptr, stream);
+}
+
+melt_status melt_forward_proj(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets, int32_t n_clips,
+                              int64_t n_frames, float *d_out, float *d_proj, void *stream) {
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    melt_status st = check_batch(p, d_wave, d_clip_offsets, n_clips, n_frames, d_out);
+    if (st != MELT_OK) return st;
+    if (n_clips == 0 || n_frames == 0) return MELT_OK;
+    st = hip_check(hipSetDevice(p->device), "hipSetDevice");
+    if (st != MELT_OK) return st;
+    const int v = p->cfg.precision == MELT_PREC_FP32 ? p->tune_f32 : p->tune_h16;
+    return launch_melt_forward(*p, d_wave, d_clip_offsets, n_clips, n_frames, d_out, d_proj, (hipStream_t)stream, v);
+}
+
+melt_status stft_mel_forward(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets, int32_t n_clips,
+                             int64_t n_frames, float *d_out, void *stream) {
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    melt_status st = check_batch(p, d_wave, d_clip_offsets, n_clips, n_frames, d_out);
+    if (st != MELT_OK) return st;
+    if (n_clips == 0 || n_frames == 0) return MELT_OK;
+    st = hip_check(hipSetDevice(p->device), "hipSetDevice");
+    if (st != MELT_OK) return st;
+    return launch_stft_mel(*p, d_wave, d_clip_offsets, n_clips, n_frames, d_out, (hipStream_t)stream);
+}
+
+melt_status melt_backward(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets, int32_t n_clips,
+                          int64_t n_frames, const float *d_grad_out, const float *d_proj, float *d_grad_wave,
+                          float *d_grad_basis, void *stream) {
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    melt_status st = check_batch(p, d_wave, d_clip_offsets, n_clips, n_frames, d_grad_out);
+    if (st != MELT_OK) return st;
+    st = hip_check(hipSetDevice(p->device), "hipSetDevice");
+    if (st != MELT_OK) return st;
+    return launch_melt_backward(*p, d_wave, d_clip_offsets, n_clips, n_frames, d_grad_out, d_proj, d_grad_wave,
+                                d_grad_basis, (hipStream_t)stream);
+}
+
+const char *melt_status_string(melt_status s) {
+    switch (s) {
+    case MELT_OK: return "MELT_OK";
+    case MELT_E_INVALID_ARG: return "MELT_E_INVALID_ARG";
+    case MELT_E_UNSUPPORTED: return "MELT_E_UNSUPPORTED";
+    case MELT_E_NO_MEMORY: return "MELT_E_NO_MEMORY";
+    case MELT_E_HIP: return "MELT_E_HIP";
+    case MELT_E_SHAPE: return "MELT_E_SHAPE";
+    default: return "MELT_E_UNKNOWN";
+    }
+}
+
+const char *melt_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,689 @@
+// MelT forward on gfx950: implicit framing in LDS + basis GEMM on MFMA + fused energy/log.
+//
+// Eq. (dmp_projection): R = X W^(r)T, I = X W^(i)T; Eq. (dmp_matrix_energy): S = R.R + I.I;
+// Eq. (meltf): out = log(S + eps).  The GEMM is computed transposed, Y^T = W X^T, so that
+// MFMA A operand = basis rows and B operand = frames, and the accumulator of one lane holds
+// one frame's values for 16 basis rows.  The basis rows of a 32-row tile are permuted so
+// that those 16 rows are the cos/sin pairs of 8 consecutive Mel bins: R^2 + I^2 is formed
+// in-lane and each lane writes 8 consecutive outputs (two 16-byte stores).
+//
+// Frames are never materialised.  A chunk of up to BF consecutive frames of one clip needs
+// the contiguous sample span [start, start + (BF - 1) H + N); it is staged once into LDS
+// as "hop-block" rows (row r = samples [rH, rH + H), padded), and frame t is the
+// concatenation of the first L_j samples of rows t + j, j = 0..J-1.  Reading the B operand
+// of k-group (j, c) for the 32 frames of a tile is then 32 rows at one column: the padded
+// row stride makes those reads bank-conflict free even though frames overlap.
+#include "melt_internal.h"
+
+namespace melt {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+struct GroupTableBig {
+    int n;
+    int lds_off[512];
+};
+
+// ------------------------------------------------------------------ schedule
+
+// One workgroup: prefix sums over the clips of frame counts and chunk counts, then the
+// chunk table.  n_chunks receives min(total, cap).
+__global__ __launch_bounds__(1024) void k_schedule(const int64_t *__restrict__ off, int n_clips, int N,
+                                                   int H, int bf, Chunk *__restrict__ tab, int64_t cap,
+                                                   int *__restrict__ n_out) {
+    __shared__ int64_t sf[1024], sc[1024];
+    __shared__ int64_t carry_f, carry_c;
+    const int tid = threadIdx.x;
+    if (tid == 0) carry_f = carry_c = 0;
+    __syncthreads();
+    for (int base = 0; base < n_clips; base += 1024) {
+        const int c = base + tid;
+        int64_t st = 0, L = 0;
+        if (c < n_clips) {
+            st = off[c];
+            L = off[c + 1] - st;
+        }
+        const int64_t T = (L >= N) ? 1 + (L - N) / H : 0;
+        const int64_t K = (T + bf - 1) / bf;
+        sf[tid] = T;
+        sc[tid] = K;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            const int64_t vf = tid >= d ? sf[tid - d] : 0;
+            const int64_t vc = tid >= d ? sc[tid - d] : 0;
+            __syncthreads();
+            sf[tid] += vf;
+            sc[tid] += vc;
+            __syncthreads();
+        }
+        const int64_t fb = carry_f + sf[tid] - T;
+        const int64_t cb = carry_c + sc[tid] - K;
+        for (int64_t k = 0; k < K; ++k) {
+            const int64_t idx = cb + k;
+            if (idx >= cap) break;
+            Chunk e;
+            e.sample_start = st + k * bf * (int64_t)H;
+            e.sample_end = st + L;
+            e.out_row = fb + k * bf;
+            e.n_frames = (int)((T - k * bf) < bf ? (T - k * bf) : bf);
+            e.clip = c;
+            tab[idx] = e;
+        }
+        __syncthreads();
+        if (tid == 1023) {
+            carry_f += sf[1023];
+            carry_c += sc[1023];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *n_out = (int)(carry_c < cap ? carry_c : cap);
+}
+
+__global__ __launch_bounds__(1024) void k_frame_offsets(const int64_t *__restrict__ off, int n_clips, int N,
+                                                        int H, int64_t *__restrict__ fo) {
+    __shared__ int64_t sf[1024];
+    __shared__ int64_t carry;
+    const int tid = threadIdx.x;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n_clips; base += 1024) {
+        const int c = base + tid;
+        int64_t L = 0;
+        if (c < n_clips) L = off[c + 1] - off[c];
+        const int64_t T = (L >= N) ? 1 + (L - N) / H : 0;
+        sf[tid] = T;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            const int64_t v = tid >= d ? sf[tid - d] : 0;
+            __syncthreads();
+            sf[tid] += v;
+            __syncthreads();
+        }
+        if (c < n_clips) fo[c] = carry + sf[tid] - T;
+        __syncthreads();
+        if (tid == 1023) carry += sf[1023];
+        __syncthreads();
+    }
+    if (tid == 0) fo[n_clips] = carry;
+}
+
+// ------------------------------------------------------------------ basis packing
+
+// Row permutation of a 32-row tile.  The 32x32 MFMA accumulator puts row
+// i = 8 g + 4 h + q (g = 0..3, h = lane / 32, q = 0..3) in register 4 g + q of lane half h.
+// Row i carries Mel bin 8 h + 2 g + q / 2 of the tile, cosine for even q, sine for odd q,
+// so register pairs (4g, 4g+1) and (4g+2, 4g+3) are (R, I) of consecutive Mel bins.
+__device__ inline void tile_row_to_mel(int i, int &mel_local, int &part) {
+    const int g = i >> 3, h = (i >> 2) & 1, q = i & 3;
+    mel_local = 8 * h + 2 * g + (q >> 1);
+    part = q & 1;
+}
+
+// Value of packed element (rt, group, lane, e): basis row (part, mel) at column
+// k = j H + c + (group_size / 2) * (lane / 32) + e, zero outside the segment / N / M.
+__device__ inline float packed_value(const float *__restrict__ b32, int M, int N, int H, int rt, int j, int c,
+                                     int half_group, int lane, int e) {
+    int mel_local, part;
+    tile_row_to_mel(lane & 31, mel_local, part);
+    const int mel = rt * 16 + mel_local;
+    const int col = c + half_group * (lane >> 5) + e;
+    const int Lj = min(H, N - j * H);
+    if (mel >= M || col >= Lj) return 0.0f;
+    return b32[(size_t)(part * M + mel) * N + j * H + col];
+}
+
+__device__ inline unsigned short f32_to_bf16_bits(float x) {
+    __bf16 b = (__bf16)x;
+    return __builtin_bit_cast(unsigned short, b);
+}
+__device__ inline unsigned short f32_to_f16_bits(float x) {
+    _Float16 h = (_Float16)x;
+    return __builtin_bit_cast(unsigned short, h);
+}
+__device__ inline float bf16_bits_to_f32(unsigned short u) {
+    return __builtin_bit_cast(float, (unsigned)u << 16);
+}
+
+// FP32 pack: [rt][group][lane][4]
+__global__ void k_pack_f32(const float *__restrict__ b32, int M, int N, int H, const int *__restrict__ seg,
+                           const int *__restrict__ col, int NG, int RT, float *__restrict__ out) {
+    const int64_t total = (int64_t)RT * NG * 64 * 4;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int e = i & 3;
+        const int lane = (i >> 2) & 63;
+        const int64_t tg = i >> 8;
+        const int g = (int)(tg % NG), rt = (int)(tg / NG);
+        out[i] = packed_value(b32, M, N, H, rt, seg[g], col[g], 4, lane, e);
+    }
+}
+
+// 16-bit pack: [rt][group][lane][8]; kind 0 = bf16, 1 = fp16, 2 = bf16 low part of the split
+__global__ void k_pack_h16(const float *__restrict__ b32, int M, int N, int H, const int *__restrict__ seg,
+                           const int *__restrict__ col, int NG, int RT, int kind, unsigned short *__restrict__ out) {
+    const int64_t total = (int64_t)RT * NG * 64 * 8;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int e = i & 7;
+        const int lane = (i >> 3) & 63;
+        const int64_t tg = i >> 9;
+        const int g = (int)(tg % NG), rt = (int)(tg / NG);
+        const float v = packed_value(b32, M, N, H, rt, seg[g], col[g], 8, lane, e);
+        unsigned short r;
+        if (kind == 0) {
+            r = f32_to_bf16_bits(v);
+        } else if (kind == 1) {
+            r = f32_to_f16_bits(v);
+        } else {
+            const float hi = bf16_bits_to_f32(f32_to_bf16_bits(v));
+            r = f32_to_bf16_bits(v - hi);
+        }
+        out[i] = r;
+    }
+}
+
+// ------------------------------------------------------------------ shared device pieces
+
+struct FwdArgs {
+    const float *wave;
+    const Chunk *chunks;
+    const int *n_chunks;
+    float *out;
+    float *proj;
+    int64_t n_frames;
+    int M, J, H, Hp, S;    // S = LDS row stride in elements
+    int row_tiles;
+    int out_kind;
+    float eps;
+};
+
+__device__ inline float out_map(float S, int kind, float eps) {
+    switch (kind) {
+    case MELT_OUT_LOG_POWER: return logf(S + eps);
+    case MELT_OUT_LOG_MAGNITUDE: return logf(sqrtf(S) + eps);
+    case MELT_OUT_POWER: return S;
+    default: return sqrtf(S);
+    }
+}
+
+// Writes one 32-frame x 16-Mel tile from the accumulator of lane `lane` (frame
+// `f_local` of the chunk).  Register pairs (4g, 4g+1), (4g+2, 4g+3) are (R, I) of Mel bins
+// 8h + 2g and 8h + 2g + 1 of the tile.
+__device__ inline void store_tile(const FwdArgs &a, const Chunk &ch, int rt, int f_local, int lane,
+                                  const f32x16 &acc) {
+    if (f_local >= ch.n_frames) return;
+    const int64_t row = ch.out_row + f_local;
+    if (row >= a.n_frames) return;
+    const int h = lane >> 5;
+    const int mel0 = rt * 16 + 8 * h;
+    if (mel0 >= a.M) return;
+    float v[8];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        v[2 * g] = out_map(acc[4 * g] * acc[4 * g] + acc[4 * g + 1] * acc[4 * g + 1], a.out_kind, a.eps);
+        v[2 * g + 1] = out_map(acc[4 * g + 2] * acc[4 * g + 2] + acc[4 * g + 3] * acc[4 * g + 3], a.out_kind, a.eps);
+    }
+    float *o = a.out + row * a.M + mel0;
+    if (mel0 + 8 <= a.M && (a.M & 3) == 0) {
+        *(f32x4 *)o = f32x4{v[0], v[1], v[2], v[3]};
+        *(f32x4 *)(o + 4) = f32x4{v[4], v[5], v[6], v[7]};
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (mel0 + e < a.M) o[e] = v[e];
+    }
+    if (a.proj) {
+        float *p = a.proj + row * (2 * a.M) + 2 * mel0;
+        if (mel0 + 8 <= a.M && (a.M & 1) == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) *(f32x4 *)(p + 4 * q) = f32x4{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                if (mel0 + e / 2 < a.M) p[e] = acc[e];
+        }
+    }
+}
+
+// Stage the chunk's sample span into LDS as padded hop-block rows of element type T.
+// Element (r, c) = x[start + r H + c] for c < H and inside the clip, else 0.
+template <class Conv>
+__device__ inline void stage_rows(const FwdArgs &a, const Chunk &ch, typename Conv::elem_t *lds, int nthreads,
+                                  int lo_off = 0) {
+    const int rows = ch.n_frames + a.J - 1;
+    const int total = rows * a.Hp;
+    for (int idx = threadIdx.x; idx < total; idx += nthreads) {
+        const int r = idx / a.Hp;
+        const int c = idx - r * a.Hp;
+        const int64_t s = ch.sample_start + (int64_t)r * a.H + c;
+        const float v = (c < a.H && s < ch.sample_end) ? a.wave[s] : 0.0f;
+        Conv::store(lds, r * a.S + c, v, lo_off);
+    }
+}
+
+struct ConvF32 {
+    typedef float elem_t;
+    __device__ static void store(float *l, int i, float v, int) { l[i] = v; }
+};
+struct ConvBF16 {
+    typedef unsigned short elem_t;
+    __device__ static void store(unsigned short *l, int i, float v, int) { l[i] = f32_to_bf16_bits(v); }
+};
+struct ConvF16 {
+    typedef unsigned short elem_t;
+    __device__ static void store(unsigned short *l, int i, float v, int) { l[i] = f32_to_f16_bits(v); }
+};
+// split-bf16: the high part at [i], the low part at [i + lo_off]
+struct ConvBF16X3 {
+    typedef unsigned short elem_t;
+    __device__ static void store(unsigned short *l, int i, float v, int lo_off) {
+        const unsigned short hb = f32_to_bf16_bits(v);
+        l[i] = hb;
+        l[i + lo_off] = f32_to_bf16_bits(v - bf16_bits_to_f32(hb));
+    }
+};
+
+// ------------------------------------------------------------------ FP32 frame-split kernel
+//
+// 4 waves; each wave owns 32 frames of the 128-frame chunk and computes all Mel bins for
+// them, in blocks of RTB row tiles (RTB accumulators of 16 registers).  The basis is
+// streamed from L2 in fragment order (one 16-byte load per row tile per 8-wide k-group,
+// shared by the 4 waves through L1) and prefetched one group ahead.
+template <int RTB>
+__global__ __launch_bounds__(256, 1) void k_melt_f32_fs(FwdArgs a, const f32x4 *__restrict__ bpack,
+                                                        GroupTableBig gt) {
+    extern __shared__ float lds[];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nch = *a.n_chunks;
+    const int NG = gt.n;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const Chunk ch = a.chunks[c];
+        __syncthreads();
+        stage_rows<ConvF32>(a, ch, lds, 256);
+        __syncthreads();
+        const int fbase = wid * 32;
+        if (fbase >= ch.n_frames) continue;
+        const float *lp = lds + (fbase + (lane & 31)) * a.S + 4 * (lane >> 5);
+        for (int rb = 0; rb < a.row_tiles; rb += RTB) {
+            f32x16 acc[RTB];
+#pragma unroll
+            for (int r = 0; r < RTB; ++r) acc[r] = f32x16{};
+            const f32x4 *bp = bpack + (size_t)rb * NG * 64 + lane;
+            f32x4 acur[RTB], anxt[RTB];
+#pragma unroll
+            for (int r = 0; r < RTB; ++r) acur[r] = (rb + r < a.row_tiles) ? bp[(size_t)r * NG * 64] : f32x4{};
+            f32x4 bcur = *(const f32x4 *)(lp + gt.lds_off[0]), bnxt;
+            for (int g = 0; g < NG; ++g) {
+                if (g + 1 < NG) {
+#pragma unroll
+                    for (int r = 0; r < RTB; ++r)
+                        anxt[r] = (rb + r < a.row_tiles) ? bp[((size_t)r * NG + g + 1) * 64] : f32x4{};
+                    bnxt = *(const f32x4 *)(lp + gt.lds_off[g + 1]);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int r = 0; r < RTB; ++r)
+                        acc[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(acur[r][i], bcur[i], acc[r], 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < RTB; ++r) acur[r] = anxt[r];
+                bcur = bnxt;
+            }
+#pragma unroll
+            for (int r = 0; r < RTB; ++r)
+                if (rb + r < a.row_tiles) store_tile(a, ch, rb + r, fbase + (lane & 31), lane, acc[r]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ 16-bit row-split kernel
+//
+// One wave per 32-row basis tile (16 Mel bins); the wave keeps its whole basis tile in
+// registers for the life of the persistent kernel (NS k-groups of 16 x 16-bit values per
+// lane = 4 VGPRs each) and sweeps every frame tile of every chunk, two tiles at a time.
+// Frames are staged in LDS already rounded to the 16-bit format.  X3 adds the low parts
+// (split-bf16: hi*hi + hi*lo + lo*hi).
+template <class Conv, int NS, bool X3, bool IS_F16>
+__global__ __launch_bounds__(512) void k_melt_h16_rs(FwdArgs a, const uint4 *__restrict__ bhi,
+                                                     const uint4 *__restrict__ blo, GroupTableBig gt, int bf) {
+    extern __shared__ unsigned short lds16[];
+    const int lane = threadIdx.x & 63, rt = threadIdx.x >> 6;
+    const int nthreads = blockDim.x;
+    uint4 A[NS];
+    uint4 Al[X3 ? NS : 1];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) A[s] = bhi[((size_t)rt * NS + s) * 64 + lane];
+    if constexpr (X3) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) Al[s] = blo[((size_t)rt * NS + s) * 64 + lane];
+    }
+    const int lo_off = a.S * (bf + a.J - 1);
+    const int nch = *a.n_chunks;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const Chunk ch = a.chunks[c];
+        __syncthreads();
+        stage_rows<Conv>(a, ch, lds16, nthreads, lo_off);
+        __syncthreads();
+        const int nft = (ch.n_frames + 31) >> 5;
+        for (int ft = 0; ft < nft; ft += 2) {
+            const bool two = ft + 1 < nft;
+            f32x16 acc0 = f32x16{}, acc1 = f32x16{};
+            const unsigned short *l0 = lds16 + (ft * 32 + (lane & 31)) * a.S + 8 * (lane >> 5);
+            const unsigned short *l1 = l0 + 32 * a.S;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int o = gt.lds_off[s];
+                const uint4 b0 = *(const uint4 *)(l0 + o);
+                const uint4 b1 = two ? *(const uint4 *)(l1 + o) : uint4{};
+                if constexpr (IS_F16) {
+                    const f16x8 av = __builtin_bit_cast(f16x8, A[s]);
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, __builtin_bit_cast(f16x8, b0), acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, __builtin_bit_cast(f16x8, b1), acc1, 0, 0, 0);
+                } else {
+                    const bf16x8 av = __builtin_bit_cast(bf16x8, A[s]);
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, b0), acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, b1), acc1, 0, 0, 0);
+                    if constexpr (X3) {
+                        const uint4 c0 = *(const uint4 *)(l0 + lo_off + o);
+                        const uint4 c1 = two ? *(const uint4 *)(l1 + lo_off + o) : uint4{};
+                        const bf16x8 al = __builtin_bit_cast(bf16x8, Al[s]);
+                        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, __builtin_bit_cast(bf16x8, b0), acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, __builtin_bit_cast(bf16x8, b1), acc1, 0, 0, 0);
+                        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, c0), acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, c1), acc1, 0, 0, 0);
+                    }
+                }
+            }
+            store_tile(a, ch, rt, ft * 32 + (lane & 31), lane, acc0);
+            if (two) store_tile(a, ch, rt, (ft + 1) * 32 + (lane & 31), lane, acc1);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ 16-bit frame-split kernel
+// Fallback for frame lengths whose basis tile does not fit in registers: as the FP32
+// frame-split kernel, one 32x32x16 MFMA per k-group.
+template <class Conv, int RTB, bool IS_F16>
+__global__ __launch_bounds__(256, 1) void k_melt_h16_fs(FwdArgs a, const uint4 *__restrict__ bpack,
+                                                        GroupTableBig gt) {
+    extern __shared__ unsigned short lds16[];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nch = *a.n_chunks;
+    const int NG = gt.n;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const Chunk ch = a.chunks[c];
+        __syncthreads();
+        stage_rows<Conv>(a, ch, lds16, 256);
+        __syncthreads();
+        const int fbase = wid * 32;
+        if (fbase >= ch.n_frames) continue;
+        const unsigned short *lp = lds16 + (fbase + (lane & 31)) * a.S + 8 * (lane >> 5);
+        for (int rb = 0; rb < a.row_tiles; rb += RTB) {
+            f32x16 acc[RTB];
+#pragma unroll
+            for (int r = 0; r < RTB; ++r) acc[r] = f32x16{};
+            const uint4 *bp = bpack + (size_t)rb * NG * 64 + lane;
+            for (int g = 0; g < NG; ++g) {
+                const uint4 b = *(const uint4 *)(lp + gt.lds_off[g]);
+#pragma unroll
+                for (int r = 0; r < RTB; ++r) {
+                    if (rb + r >= a.row_tiles) continue;
+                    const uint4 av = bp[((size_t)r * NG + g) * 64];
+                    if constexpr (IS_F16)
+                        acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, av),
+                                                                        __builtin_bit_cast(f16x8, b), acc[r], 0, 0, 0);
+                    else
+                        acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
+                                                                         __builtin_bit_cast(bf16x8, b), acc[r], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < RTB; ++r)
+                if (rb + r < a.row_tiles) store_tile(a, ch, rb + r, fbase + (lane & 31), lane, acc[r]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host side
+
+namespace {
+
+int lds_stride(int Hp, int esize) {
+    // row stride (elements) whose dword count is an odd multiple of 4, so that the 16-byte
+    // reads of 8 consecutive rows at one column fall in 8 distinct 4-bank groups
+    const int per_dword = 4 / esize;
+    int dw = (Hp + per_dword - 1) / per_dword;
+    dw = ((dw + 3) / 4) * 4;
+    if ((dw / 4) % 2 == 0) dw += 4;
+    return dw * per_dword;
+}
+
+GroupTableBig make_table(const Geometry &g, int S) {
+    GroupTableBig t{};
+    t.n = g.n_groups;
+    for (int i = 0; i < g.n_groups && i < 512; ++i) t.lds_off[i] = g.seg_of_group[i] * S + g.col_of_group[i];
+    return t;
+}
+
+FwdArgs make_args(Plan &p, const Geometry &g, int S, const float *wave, float *out, float *proj,
+                  int64_t n_frames) {
+    FwdArgs a;
+    a.wave = wave;
+    a.chunks = p.d_chunks;
+    a.n_chunks = p.d_nchunks;
+    a.out = out;
+    a.proj = proj;
+    a.n_frames = n_frames;
+    a.M = p.M;
+    a.J = g.J;
+    a.H = p.H;
+    a.Hp = g.Hp;
+    a.S = S;
+    a.row_tiles = p.row_tiles;
+    a.out_kind = p.cfg.output;
+    a.eps = (float)p.cfg.log_eps;
+    return a;
+}
+
+melt_status upload_ints(const std::vector<int> &v, int **d) {
+    if (hipMalloc(d, sizeof(int) * (v.size() + 1)) != hipSuccess) return set_error(MELT_E_NO_MEMORY, "hipMalloc");
+    return hip_check(hipMemcpy(*d, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice), "hipMemcpy");
+}
+
+constexpr int kBF32 = 128;   // frames per chunk, frame-split kernels (4 waves x 32)
+constexpr int kMaxLds = 160 * 1024;
+
+template <class K>
+void allow_lds(K kern) {
+    (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+}
+
+// row-split variants: number of k-groups with a compiled register tile
+bool rs_supported(int NS) { return NS == 25 || NS == 32 || NS == 20 || NS == 16 || NS == 10; }
+
+}  // namespace
+
+melt_status pack_basis(Plan &p, hipStream_t s) {
+    melt_status st;
+    // per-group segment/column tables for the pack kernels (temporary device copies)
+    auto pack_one = [&](const Geometry &g, auto launch) -> melt_status {
+        int *dseg = nullptr, *dcol = nullptr;
+        melt_status r = upload_ints(g.seg_of_group, &dseg);
+        if (r == MELT_OK) r = upload_ints(g.col_of_group, &dcol);
+        if (r == MELT_OK) {
+            launch(dseg, dcol);
+            r = hip_check(hipGetLastError(), "pack kernel");
+        }
+        if (r == MELT_OK) r = hip_check(hipStreamSynchronize(s), "pack sync");
+        (void)hipFree(dseg);
+        (void)hipFree(dcol);
+        return r;
+    };
+    const int RT = p.row_tiles;
+    st = pack_one(p.geo32, [&](int *seg, int *col) {
+        k_pack_f32<<<256, 256, 0, s>>>(p.d_basis32, p.M, p.N, p.H, seg, col, p.geo32.n_groups, RT,
+                                       (float *)p.d_pack_f32);
+    });
+    if (st != MELT_OK) return st;
+    const int kind_hi = (p.cfg.precision == MELT_PREC_FP16) ? 1 : 0;
+    st = pack_one(p.geo16, [&](int *seg, int *col) {
+        k_pack_h16<<<256, 256, 0, s>>>(p.d_basis32, p.M, p.N, p.H, seg, col, p.geo16.n_groups, RT, kind_hi,
+                                       (unsigned short *)p.d_pack_h16);
+        k_pack_h16<<<256, 256, 0, s>>>(p.d_basis32, p.M, p.N, p.H, seg, col, p.geo16.n_groups, RT, 2,
+                                       (unsigned short *)p.d_pack_lo);
+    });
+    return st;
+}
+
+melt_status ensure_chunks(Plan &p, int64_t needed) {
+    if (needed <= p.chunk_cap) return MELT_OK;
+    int64_t cap = std::max<int64_t>(needed, 2 * p.chunk_cap);
+    Chunk *d = nullptr;
+    if (hipMalloc(&d, sizeof(Chunk) * cap) != hipSuccess) return set_error(MELT_E_NO_MEMORY, "chunk table");
+    if (p.d_chunks) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(p.d_chunks);
+    }
+    p.d_chunks = d;
+    p.chunk_cap = cap;
+    return MELT_OK;
+}
+
+melt_status launch_schedule(Plan &p, const int64_t *d_off, int n_clips, int bf, int64_t n_frames, hipStream_t s) {
+    const int64_t need = n_frames / bf + n_clips + 1;
+    melt_status st = ensure_chunks(p, need);
+    if (st != MELT_OK) return st;
+    k_schedule<<<1, 1024, 0, s>>>(d_off, n_clips, p.N, p.H, bf, p.d_chunks, p.chunk_cap, p.d_nchunks);
+    return hip_check(hipGetLastError(), "schedule launch");
+}
+
+melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H, int64_t *d_fo, hipStream_t s) {
+    k_frame_offsets<<<1, 1024, 0, s>>>(d_off, n_clips, N, H, d_fo);
+    return hip_check(hipGetLastError(), "frame offsets launch");
+}
+
+// Variant list.  0 = default for the plan's precision.
+//   FP32: 0 = frame-split (RTB = row tiles, up to 8)
+//   BF16/FP16/BF16X3: 0 = row-split (register basis) when the tile fits, 1 = frame-split
+int forward_variants(const Plan &p) {
+    if (p.cfg.precision == MELT_PREC_FP32) return 1;
+    if (p.cfg.precision == MELT_PREC_BF16X3) return 1;
+    return rs_supported(p.geo16.n_groups) && p.row_tiles <= 8 ? 2 : 1;
+}
+
+const char *forward_variant_name(const Plan &p, int v) {
+    if (p.cfg.precision == MELT_PREC_FP32) return "f32-frame-split";
+    if (rs_supported(p.geo16.n_groups) && p.row_tiles <= 8 && v == 0) return "h16-row-split";
+    return "h16-frame-split";
+}
+
+template <int RTB>
+static melt_status launch_f32_rtb(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid,
+                                  hipStream_t s) {
+    allow_lds(k_melt_f32_fs<RTB>);
+    k_melt_f32_fs<RTB><<<grid, 256, lds, s>>>(a, (const f32x4 *)p.d_pack_f32, gt);
+    return hip_check(hipGetLastError(), "melt f32 launch");
+}
+
+template <class Conv, bool F16, int RTB>
+static melt_status launch_h16fs_rtb(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid,
+                                    hipStream_t s) {
+    allow_lds(k_melt_h16_fs<Conv, RTB, F16>);
+    k_melt_h16_fs<Conv, RTB, F16><<<grid, 256, lds, s>>>(a, (const uint4 *)p.d_pack_h16, gt);
+    return hip_check(hipGetLastError(), "melt h16 fs launch");
+}
+
+template <class Conv, int NS, bool X3, bool F16>
+static melt_status launch_rs_ns(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+                                hipStream_t s) {
+    allow_lds(k_melt_h16_rs<Conv, NS, X3, F16>);
+    k_melt_h16_rs<Conv, NS, X3, F16><<<grid, 64 * p.row_tiles, lds, s>>>(
+        a, (const uint4 *)p.d_pack_h16, (const uint4 *)p.d_pack_lo, gt, bf);
+    return hip_check(hipGetLastError(), "melt h16 rs launch");
+}
+
+template <class Conv, bool X3, bool F16>
+static melt_status launch_rs(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+                             hipStream_t s) {
+    switch (p.geo16.n_groups) {
+    case 10: return launch_rs_ns<Conv, 10, X3, F16>(p, a, gt, lds, grid, bf, s);
+    case 16: return launch_rs_ns<Conv, 16, X3, F16>(p, a, gt, lds, grid, bf, s);
+    case 20: return launch_rs_ns<Conv, 20, X3, F16>(p, a, gt, lds, grid, bf, s);
+    case 25: return launch_rs_ns<Conv, 25, X3, F16>(p, a, gt, lds, grid, bf, s);
+    case 32: return launch_rs_ns<Conv, 32, X3, F16>(p, a, gt, lds, grid, bf, s);
+    default: return set_error(MELT_E_UNSUPPORTED, "no register tile for this frame length");
+    }
+}
+
+melt_status launch_melt_forward(Plan &p, const float *d_wave, const int64_t *d_off, int n_clips, int64_t n_frames,
+                                float *d_out, float *d_proj, hipStream_t s, int variant) {
+    const int prec = p.cfg.precision;
+    if (prec == MELT_PREC_FP32) {
+        const Geometry &g = p.geo32;
+        const int S = lds_stride(g.Hp, 4);
+        const size_t lds = (size_t)(kBF32 + g.J - 1) * S * 4;
+        if (lds > (size_t)kMaxLds || g.n_groups > 512)
+            return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS for FP32 kernel");
+        melt_status st = launch_schedule(p, d_off, n_clips, kBF32, n_frames, s);
+        if (st != MELT_OK) return st;
+        const FwdArgs a = make_args(p, g, S, d_wave, d_out, d_proj, n_frames);
+        const GroupTableBig gt = make_table(g, S);
+        const int64_t est = n_frames / kBF32 + n_clips + 1;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, p.cu_count));
+        switch (std::min(p.row_tiles, 8)) {
+        case 1: return launch_f32_rtb<1>(p, a, gt, lds, grid, s);
+        case 2: return launch_f32_rtb<2>(p, a, gt, lds, grid, s);
+        case 3: return launch_f32_rtb<3>(p, a, gt, lds, grid, s);
+        case 4: return launch_f32_rtb<4>(p, a, gt, lds, grid, s);
+        case 5: return launch_f32_rtb<5>(p, a, gt, lds, grid, s);
+        case 6: return launch_f32_rtb<6>(p, a, gt, lds, grid, s);
+        case 7: return launch_f32_rtb<7>(p, a, gt, lds, grid, s);
+        default: return launch_f32_rtb<8>(p, a, gt, lds, grid, s);
+        }
+    }
+    if (prec == MELT_PREC_BF16 || prec == MELT_PREC_FP16 || prec == MELT_PREC_BF16X3) {
+        const Geometry &g = p.geo16;
+        const int S = lds_stride(g.Hp, 2);
+        const bool f16 = prec == MELT_PREC_FP16;
+        const bool x3 = prec == MELT_PREC_BF16X3;
+        const bool rs = rs_supported(g.n_groups) && p.row_tiles <= 8 && (variant == 0 || x3);
+        if (g.n_groups > 512) return set_error(MELT_E_UNSUPPORTED, "frame too long");
+        if (rs) {
+            const int bf = 128;
+            const size_t lds = (size_t)(bf + g.J - 1) * S * 2 * (x3 ? 2 : 1);
+            if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
+            melt_status st = launch_schedule(p, d_off, n_clips, bf, n_frames, s);
+            if (st != MELT_OK) return st;
+            const FwdArgs a = make_args(p, g, S, d_wave, d_out, d_proj, n_frames);
+            const GroupTableBig gt = make_table(g, S);
+            const int per_cu = std::max(1, (int)(kMaxLds / lds));
+            const int64_t est = n_frames / bf + n_clips + 1;
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, (int64_t)p.cu_count * std::min(per_cu, 2)));
+            if (x3) return launch_rs<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, s);
+            if (f16) return launch_rs<ConvF16, false, true>(p, a, gt, lds, grid, bf, s);
+            return launch_rs<ConvBF16, false, false>(p, a, gt, lds, grid, bf, s);
+        }
+        if (x3) return set_error(MELT_E_UNSUPPORTED, "BF16X3 needs the register-tile kernel (frame too long)");
+        const size_t lds = (size_t)(kBF32 + g.J - 1) * S * 2;
+        if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
+        melt_status st = launch_schedule(p, d_off, n_clips, kBF32, n_frames, s);
+        if (st != MELT_OK) return st;
+        const FwdArgs a = make_args(p, g, S, d_wave, d_out, d_proj, n_frames);
+        const GroupTableBig gt = make_table(g, S);
+        const int64_t est = n_frames / kBF32 + n_clips + 1;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, (int64_t)p.cu_count * 2));
+        switch (std::min(p.row_tiles, 8)) {
+        case 1: return f16 ? launch_h16fs_rtb<ConvF16, true, 1>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 1>(p, a, gt, lds, grid, s);
+        case 2: return f16 ? launch_h16fs_rtb<ConvF16, true, 2>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 2>(p, a, gt, lds, grid, s);
+        case 4: return f16 ? launch_h16fs_rtb<ConvF16, true, 4>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 4>(p, a, gt, lds, grid, s);
+        case 3:
+        case 5:
+        case 6: return f16 ? launch_h16fs_rtb<ConvF16, true, 6>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 6>(p, a, gt, lds, grid, s);
+        default: return f16 ? launch_h16fs_rtb<ConvF16, true, 8>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 8>(p, a, gt, lds, grid, s);
+        }
+    }
+    return set_error(MELT_E_UNSUPPORTED, "precision not implemented");
+}
+
+}  // namespace melt

@@ -1,0 +1,107 @@
+// Internal declarations of libmelt: the plan object, the chunk schedule and the
+// kernel launchers.  Nothing here is part of the C ABI (include/melt.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/melt.h"
+
+namespace melt {
+
+// ---------------------------------------------------------------- chunk schedule
+// A chunk is up to `bf` consecutive frames of one clip; the persistent kernels walk a
+// table of chunks so that a ragged batch is one launch.
+struct Chunk {
+    int64_t sample_start;  // first sample of the chunk's first frame
+    int64_t sample_end;    // end of its clip (exclusive): samples at or past it read as 0
+    int64_t out_row;       // output row of the chunk's first frame
+    int32_t n_frames;      // frames in this chunk (1..bf)
+    int32_t clip;          // clip index
+};
+static_assert(sizeof(Chunk) == 32, "Chunk layout");
+
+// Hop-block geometry: a frame of N samples starting at t*H is the concatenation of
+// segments j = 0..J-1 of length L_j = min(H, N - jH), segment j being the first L_j
+// samples of hop-block row t + j (row r = samples [rH, rH + H)).  Each segment is padded
+// to a multiple of the k-group of the GEMM (8 for FP32, 16 for 16-bit, 64 for FP8) with
+// zero basis columns, so a k-group never straddles two rows.
+struct Geometry {
+    int N, H, J;         // frame length, hop, hop-block segments per frame
+    int group;           // k-group size
+    int Hp;              // padded row length used in LDS (multiple of `group`)
+    int n_groups;        // total k-groups over all segments
+    std::vector<int> seg_of_group, col_of_group;  // segment and first column of each group
+};
+Geometry make_geometry(int N, int H, int group);
+
+// per-launch descriptor of the k-groups, passed by value (kernel argument)
+constexpr int kMaxGroups = 160;
+struct GroupTable {
+    int n;                   // number of groups
+    int lds_off[kMaxGroups]; // element offset in LDS of group g relative to a frame's row
+};
+
+// ---------------------------------------------------------------- plan
+struct Plan {
+    melt_config cfg{};
+    int device = 0;
+    int M = 0, N = 0, H = 0;
+    int row_tiles = 0;                 // ceil(M / 16): 16 Mel bins (32 basis rows) per tile
+    std::vector<double> freqs;         // f_m, Hz
+    std::vector<double> basis64;       // stacked [2M][N]: cos rows then sin rows (FP64)
+    // device memory (owned)
+    float *d_basis32 = nullptr;        // stacked [2M][N] FP32 (the learnable parameter)
+    void *d_pack_f32 = nullptr;        // FP32 fragment-packed basis (frame-split kernel)
+    void *d_pack_h16 = nullptr;        // 16-bit packed basis (BF16 or FP16)
+    void *d_pack_lo = nullptr;         // BF16x3 low part
+    void *d_pack_f8 = nullptr;         // FP8 E4M3 packed basis
+    float *d_rowscale = nullptr;       // FP8 per-row scales (packed row order)
+    Geometry geo32, geo16, geo8;
+    // comparator (FFT + CSR filterbank)
+    float *d_fb_w = nullptr;           // filter weights, concatenated per Mel bin
+    int *d_fb_start = nullptr;         // first bin of each filter
+    int *d_fb_off = nullptr;           // offset of each filter's weights [M+1]
+    int fb_nnz = 0;
+    float2 *d_twiddle = nullptr;       // exp(-2 pi i j / N), j < N
+    // workspace (schedule)
+    Chunk *d_chunks = nullptr;
+    int *d_nchunks = nullptr;
+    int64_t chunk_cap = 0;
+    // tuning
+    int cu_count = 256;
+    int tune_f32 = 0, tune_h16 = 0, tune_f8 = 0;   // index of the chosen kernel variant
+    std::string last_tune;
+};
+
+// status plumbing (capi.cpp)
+melt_status set_error(melt_status s, const std::string &msg);
+melt_status hip_check(hipError_t e, const char *what);
+
+// plan construction (plan.cpp)
+melt_status plan_build_host(Plan &p);
+void mel_frequencies(const melt_config &cfg, std::vector<double> &f);
+
+// kernels (melt_fwd.hip, stft_mel.hip, melt_bwd.hip)
+melt_status pack_basis(Plan &p, hipStream_t s);
+melt_status ensure_chunks(Plan &p, int64_t needed);
+melt_status launch_schedule(Plan &p, const int64_t *d_off, int n_clips, int bf, int64_t n_frames,
+                            hipStream_t s);
+melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H, int64_t *d_fo,
+                                 hipStream_t s);
+melt_status launch_melt_forward(Plan &p, const float *d_wave, const int64_t *d_off, int n_clips,
+                                int64_t n_frames, float *d_out, float *d_proj, hipStream_t s,
+                                int variant);
+int forward_variants(const Plan &p);
+const char *forward_variant_name(const Plan &p, int variant);
+melt_status launch_stft_mel(Plan &p, const float *d_wave, const int64_t *d_off, int n_clips,
+                            int64_t n_frames, float *d_out, hipStream_t s);
+melt_status stft_plan_build(Plan &p);
+melt_status launch_melt_backward(Plan &p, const float *d_wave, const int64_t *d_off, int n_clips,
+                                 int64_t n_frames, const float *d_gout, const float *d_proj,
+                                 float *d_gwave, float *d_gbasis, hipStream_t s);
+
+}  // namespace melt

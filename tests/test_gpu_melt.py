@@ -1,0 +1,197 @@
+"""GPU parity of the MelT forward (melt_forward / melt_forward_proj) against the FP64 oracle.
+
+FP32: against the plain FP64 oracle (direct NDFT summation).  BF16 / FP16 / split-BF16x3:
+against the oracle's operand model of the same precision (operands rounded exactly as the
+format defines, products and sums exact), so the only difference left is FP32
+accumulation.  The pass condition is the per-bin bound of tests/parity.py; the dB error
+against the plain FP64 oracle is reported for every precision.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def melt():
+    import paper_2606_01009_amd as m
+    m.load_library()
+    return m
+
+
+def _gpu_forward(torch, melt, plan, wave, off, proj=False):
+    T = melt.total_frames(off, plan.n_fft, plan.hop)
+    d_wave = torch.from_numpy(np.ascontiguousarray(wave)).cuda()
+    d_off = torch.from_numpy(np.asarray(off, np.int64)).cuda()
+    out = torch.full((T, plan.n_mels), float("nan"), dtype=torch.float32, device="cuda")
+    P = torch.full((T, 2 * plan.n_mels), float("nan"), dtype=torch.float32, device="cuda") if proj else None
+    plan.forward(d_wave, d_off, T, out=out, proj=P)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), (P.cpu().numpy() if proj else None)
+
+
+def _oracle_fp32(orc, plan, wave, off, eps):
+    f = plan.frequencies()
+    Wr, Wi = orc.melt_basis(sr=plan.cfg.sample_rate, n_fft=plan.n_fft, freqs=f)
+    _, R, I = orc.melt_forward_basis(wave, off, n_fft=plan.n_fft, hop=plan.hop, Wr=Wr, Wi=Wi, eps=eps,
+                                     return_ri=True)
+    _, Ar, Ai = orc.melt_forward_basis(np.abs(wave), off, n_fft=plan.n_fft, hop=plan.hop, Wr=np.abs(Wr),
+                                       Wi=np.abs(Wi), eps=eps, return_ri=True)
+    return R, I, Ar, Ai, Wr, Wi
+
+
+def _check(orc, melt, plan, L, wave, off, prec, eps=1e-10, label=""):
+    R, I, Ar, Ai, Wr, Wi = _oracle_fp32(orc, plan, wave, off, eps)
+    N = plan.n_fft
+    if prec == "fp32":
+        st = parity.check_log_power(L, R, I, Ar, Ai, N, eps, extra_rel=1.0, label=label)
+    else:
+        code = {"bf16": orc.PREC_BF16, "fp16": orc.PREC_FP16, "bf16x3": orc.PREC_BF16X3}[prec]
+        _, Rq, Iq = orc.melt_forward_quant(wave, off, n_fft=N, hop=plan.hop, Wr=Wr, Wi=Wi, prec=code, eps=eps,
+                                           return_ri=True)
+        if prec == "bf16x3":
+            Aq_r, Aq_i, nt = Ar * 1.01, Ai * 1.01, 3 * N
+        else:
+            _, Aq_r, Aq_i = orc.melt_forward_quant(np.abs(wave), off, n_fft=N, hop=plan.hop, Wr=np.abs(Wr),
+                                                   Wi=np.abs(Wi), prec=code, eps=eps, return_ri=True)
+            nt = N
+        parity.check_log_power(L, Rq, Iq, Aq_r, Aq_i, nt, eps, extra_rel=0.0, label=label)
+        st = parity.db_stats(L, np.log(R * R + I * I + eps), R * R + I * I)
+    print(f"{label}: dB error vs FP64 oracle on active bins: max {st['max_db']:.3g} rms {st['rms_db']:.3g}")
+    return st
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3"])
+def test_config1_tiny(torch, melt, orc, prec):
+    """One 1 s clip at 16 kHz, N=400, H=160, 80 HTK bins, 0-8 kHz: 98 frames."""
+    cfg = workloads.config1()
+    plan = melt.MeltPlan(sample_rate=cfg["sr"], n_fft=400, hop=160, n_mels=80, fmin=0, fmax=8000, precision=prec)
+    L, _ = _gpu_forward(torch, melt, plan, cfg["wave"], cfg["offsets"])
+    assert L.shape == (98, 80)
+    st = _check(orc, melt, plan, L, cfg["wave"], cfg["offsets"], prec, label=f"config1 {prec}")
+    if prec == "fp32":
+        assert st["max_db"] < 0.02 and st["rms_db"] < 2e-3
+    if prec == "bf16x3":
+        # reported, not a pass condition: the split product keeps ~16 significant bits per
+        # term, so quiet bins carry about 2^8 times the FP32 error
+        assert st["max_db"] < 0.5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
+@pytest.mark.parametrize("n_mels", [80, 128])
+def test_config2_reduced(torch, melt, orc, prec, n_mels):
+    """Config-2 signals at reduced size (4 clips x 2.5 s = 4 x 248 frames: two full 128-frame
+    chunks and a ragged tail per clip)."""
+    cfg = workloads.config2(n_mels=n_mels, n_clips=4, seconds=2.5)
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=n_mels, fmin=0, fmax=8000, precision=prec)
+    L, _ = _gpu_forward(torch, melt, plan, cfg["wave"], cfg["offsets"])
+    _check(orc, melt, plan, L, cfg["wave"], cfg["offsets"], prec, label=f"config2-reduced M={n_mels} {prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_ragged_edge_cases(torch, melt, orc, prec):
+    """Empty clips, clips shorter than a frame, exactly one frame, one sample more, and
+    lengths that end chunks at every residue."""
+    lengths = [0, 399, 400, 401, 559, 560, 0, 3, 20479, 20480, 20641, 7777, 400]
+    wave, off = workloads.random_clips(lengths, seed=5)
+    off = off + 0   # offsets start at 0 here; a non-zero base is covered below
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80, precision=prec)
+    L, _ = _gpu_forward(torch, melt, plan, wave, off)
+    assert L.shape[0] == sum(melt.melt_num_frames(n, 400, 160) for n in lengths)
+    _check(orc, melt, plan, L, wave, off, prec, label=f"ragged {prec}")
+    # a batch that starts part-way into the buffer: only clips 2.. of the same buffer
+    L2, _ = _gpu_forward(torch, melt, plan, wave, off[2:])
+    assert np.array_equal(L2, L[-L2.shape[0]:])
+
+
+@pytest.mark.parametrize("geom", [(16000, 512, 128, 128), (22050, 1024, 256, 128), (16000, 400, 100, 40),
+                                  (8000, 256, 80, 24)])
+def test_other_geometries(torch, melt, orc, geom):
+    sr, N, H, M = geom
+    lengths = [N - 1, N, 5 * N + 7, 31 * H + N, 2 * 128 * H + N + 3]
+    wave, off = workloads.random_clips(lengths, seed=9)
+    for prec in ("fp32", "bf16"):
+        plan = melt.MeltPlan(sample_rate=sr, n_fft=N, hop=H, n_mels=M, precision=prec)
+        L, _ = _gpu_forward(torch, melt, plan, wave, off)
+        _check(orc, melt, plan, L, wave, off, prec, label=f"geometry {geom} {prec}")
+
+
+def test_silence_is_log_eps(torch, melt):
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80)
+    wave = np.zeros(16000, np.float32)
+    L, P = _gpu_forward(torch, melt, plan, wave, np.array([0, 16000]), proj=True)
+    # every bin is the device's logf((float)eps), bit for bit, within 2 ulp of ln(1e-10)
+    assert np.all(L == L[0, 0])
+    assert abs(float(L[0, 0]) - np.log(1e-10)) <= 2 * np.spacing(np.float32(23.0))
+    assert np.all(P == 0.0)
+
+
+def test_projection_output(torch, melt, orc):
+    """melt_forward_proj writes (R, I) per Mel bin, interleaved."""
+    cfg = workloads.config1(seed=4)
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80)
+    L, P = _gpu_forward(torch, melt, plan, cfg["wave"], cfg["offsets"], proj=True)
+    R, I, Ar, Ai, _, _ = _oracle_fp32(orc, plan, cfg["wave"], cfg["offsets"], 1e-10)
+    tol = (400 + 1) * parity.U32 * 1.01
+    assert np.all(np.abs(P[:, 0::2] - R) <= tol * Ar + 1e-30)
+    assert np.all(np.abs(P[:, 1::2] - I) <= tol * Ai + 1e-30)
+    L2, _ = _gpu_forward(torch, melt, plan, cfg["wave"], cfg["offsets"])
+    assert np.array_equal(L, L2)
+
+
+def test_output_kinds(torch, melt, orc):
+    cfg = workloads.config1(seed=6)
+    P_plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80, output=melt.MELT_OUT_POWER)
+    S, _ = _gpu_forward(torch, melt, P_plan, cfg["wave"], cfg["offsets"])
+    R, I, Ar, Ai, _, _ = _oracle_fp32(orc, P_plan, cfg["wave"], cfg["offsets"], 1e-10)
+    S_ref = R * R + I * I
+    g = 402 * parity.U32
+    dS = 2 * np.abs(R) * g * Ar + 2 * np.abs(I) * g * Ai + (g * Ar) ** 2 + (g * Ai) ** 2 + 3 * parity.U32 * S_ref
+    assert np.all(np.abs(S - S_ref) <= dS * 1.01 + 1e-30)
+    for kind, fn in ((melt.MELT_OUT_MAGNITUDE, np.sqrt), (melt.MELT_OUT_LOG_MAGNITUDE, lambda s: np.log(np.sqrt(s) + 1e-10))):
+        plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80, output=kind)
+        out, _ = _gpu_forward(torch, melt, plan, cfg["wave"], cfg["offsets"])
+        loud = S_ref > 1e-4 * S_ref.max()      # within 40 dB of the peak: relative error < 1e-4
+        assert np.allclose(out[loud], fn(S_ref[loud]), rtol=1e-4, atol=0)
+        if kind == melt.MELT_OUT_MAGNITUDE:       # everywhere: out^2 obeys the power bound
+            assert np.all(np.abs(out.astype(np.float64) ** 2 - S_ref) <= dS * 1.02 + 8 * parity.U32 * S_ref + 1e-30)
+
+
+def test_empty_calls(torch, melt):
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80)
+    d_off = torch.zeros(1, dtype=torch.int64, device="cuda")
+    d_wave = torch.zeros(10, dtype=torch.float32, device="cuda")
+    out = torch.zeros((0, 80), dtype=torch.float32, device="cuda")
+    plan.forward(d_wave, d_off, 0, out=out)            # n_clips = 0
+    d_off2 = torch.tensor([0, 10], dtype=torch.int64, device="cuda")
+    plan.forward(d_wave, d_off2, 0, out=out)           # one clip shorter than a frame
+    torch.cuda.synchronize()
+    with pytest.raises(melt.MeltError):
+        melt.melt_forward(plan.handle, None, d_off2, 5, out)
+
+
+def test_config2_full_size_sampled(torch, melt, orc):
+    """The benchmark's workload and launch: 64 clips x 30 s (191 872 frames, M=80), FP32.
+    256 frames sampled across the batch (first/last of every clip included) are checked
+    against the oracle evaluated on exactly those frames."""
+    cfg = workloads.config2(n_mels=80)
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80, precision="fp32")
+    L, _ = _gpu_forward(torch, melt, plan, cfg["wave"], cfg["offsets"])
+    assert L.shape == (191872, 80)
+    assert np.all(np.isfinite(L))
+    rng = np.random.default_rng(77)
+    ids = np.unique(np.concatenate([rng.integers(0, L.shape[0], 128), np.arange(0, 191872, 2998),
+                                    np.arange(2997, 191872, 2998)]))
+    sub, off = parity.frames_as_clips(cfg["wave"], cfg["offsets"], 400, 160, ids)
+    _check(orc, melt, plan, L[ids], sub, off, "fp32", label="config2 full sampled fp32")
