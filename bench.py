@@ -1,0 +1,218 @@
+#!/usr/bin/env python
+"""Mel frames/s of the MelT GEMM path vs the FFT + filterbank path on one MI355X.
+
+Workload: 64 clips x 30 s at 16 kHz (float32 pink noise + amplitude-modulated tones), N=400,
+H=160, 80 HTK Mel bins over 0-8 kHz: T = 191 872 frames, GEMM 191 872 x 400 x 160.  Inputs
+are resident in HBM before the timed region.  One step = one MelT forward over the batch
+(chunk schedule + the persistent MFMA kernel); the comparator (hand-written FFT + sparse
+filterbank) and the other precisions are timed the same way on the same batch and reported
+beside it, each with its log-Mel error against the FP64 oracle on sampled frames.
+
+Prints one JSON line.  `roofline` is for the dominant kernel (the MelT FP32 projection),
+timed alone with HIP events over the same number of launches; `cpu_baseline` times the FP64
+oracle on the host over the whole batch.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "f16": 2.5e15, "fp8": 5.0e15, "hbm": 8.0e12}
+KERNEL_SRC = os.path.join(ROOT, "paper_2606_01009_amd", "csrc", "melt_fwd.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_id():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def time_launches(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps          # ms per launch
+
+
+def sampled_error_db(out, wave, offsets, kind, freqs, n_fft=400, hop=160, n_mels=80, n_sample=256, seed=5):
+    """dB error against the FP64 oracle on sampled frames (max / rms over bins within 80 dB
+    of the sample's peak)."""
+    import oracle
+    from tests.parity import frames_as_clips
+    rng = np.random.default_rng(seed)
+    ids = np.sort(rng.choice(out.shape[0], n_sample, replace=False))
+    sub, off = frames_as_clips(wave, offsets, n_fft, hop, ids)
+    if kind == "melt":
+        ref = oracle.melt_forward(sub, off, sr=16000.0, n_fft=n_fft, hop=hop, freqs=freqs)
+    else:
+        ref = oracle.stft_mel_forward(sub, off, sr=16000.0, n_fft=n_fft, hop=hop, n_mels=n_mels, fmin=0.0,
+                                      fmax=8000.0)
+    S = np.exp(ref)
+    act = S >= S.max() * 1e-8
+    e = (10.0 / np.log(10.0)) * (out[ids].astype(np.float64) - ref)
+    return {"max_db": float(np.abs(e[act]).max()), "rms_db": float(np.sqrt(np.mean(e[act] ** 2))),
+            "frames_sampled": int(n_sample)}
+
+
+def cpu_baseline(wave, offsets, freqs, T):
+    import oracle
+    oracle.build()
+    t0 = time.perf_counter()
+    oracle.melt_forward(wave, offsets, sr=16000.0, n_fft=400, hop=160, freqs=freqs)
+    dt = time.perf_counter() - t0
+    return {"value": T / dt, "unit": "Mel frames/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"the whole batch: 64 clips x 30 s, {T} frames, direct FP64 NDFT summation (C, OpenMP), "
+                      f"{dt:.2f} s wall"}
+
+
+def load_traffic(path, source_id):
+    """HBM traffic of the dominant kernel from committed rocprofv3 --pmc summaries, or None if
+    absent or taken on another version of the kernel source."""
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_id") != source_id:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n-mels", type=int, default=80)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="time only the FP32 MelT path and the comparator")
+    ap.add_argument("--no-check", action="store_true", help="skip the sampled error check")
+    ap.add_argument("--only", default=None, help="time one path only: fp32|bf16|fp16|bf16x3|stft (profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported (the frames of a batch "
+              f"are independent, so N GPUs would each take 1/N of the clips with no communication)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2606_01009_amd as melt
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    melt.load_library()
+    M = args.n_mels
+    log(f"bench: generating 64 x 30 s synthetic clips (n_mels={M})")
+    cfg = workloads.config2(n_mels=M)
+    wave, offsets = cfg["wave"], cfg["offsets"]
+    T = melt.total_frames(offsets, 400, 160)
+    d_wave = torch.from_numpy(wave).cuda()
+    d_off = torch.from_numpy(offsets).cuda()
+    out = torch.empty((T, M), dtype=torch.float32, device="cuda")
+    flop_per_frame = 4 * 400 * M                       # 2 FLOP x N x 2M per frame
+    bytes_per_launch = wave.nbytes + T * M * 4 + 2 * M * 400 * 4   # wave once + output once + basis
+
+    def run_melt(prec):
+        plan = melt.MeltPlan(sample_rate=16000.0, n_fft=400, hop=160, n_mels=M, fmin=0.0, fmax=8000.0, precision=prec)
+        step_ms = time_launches(torch, lambda: plan.forward(d_wave, d_off, T, out=out), args.steps, args.warmup)
+        melt.melt_batch_prepare(plan.handle, d_off, T)
+        kern_ms = time_launches(torch, lambda: melt.melt_forward_prepared(plan.handle, d_wave, out),
+                                args.steps, args.warmup)
+        res = {"frames_per_s": T / (step_ms * 1e-3), "ms_per_step": step_ms, "kernel_ms": kern_ms,
+               "tflops": T * flop_per_frame / (kern_ms * 1e-3) / 1e12,
+               "hbm_gbps": bytes_per_launch / (kern_ms * 1e-3) / 1e9}
+        if not args.no_check:
+            res["error_vs_fp64_oracle"] = sampled_error_db(out.cpu().numpy(), wave, offsets, "melt", plan.frequencies(),
+                                                           n_mels=M)
+        log(f"bench: MelT {prec}: {res['frames_per_s'] / 1e6:.1f} M frames/s, kernel {kern_ms * 1e3:.1f} us")
+        return res, plan
+
+    def run_stft():
+        plan = melt.MeltPlan(sample_rate=16000.0, n_fft=400, hop=160, n_mels=M, fmin=0.0, fmax=8000.0)
+        step_ms = time_launches(torch, lambda: plan.stft_mel(d_wave, d_off, T, out=out), args.steps, args.warmup)
+        melt.melt_batch_prepare(plan.handle, d_off, T)
+        kern_ms = time_launches(torch, lambda: melt.stft_mel_forward_prepared(plan.handle, d_wave, out),
+                                args.steps, args.warmup)
+        res = {"frames_per_s": T / (step_ms * 1e-3), "ms_per_step": step_ms, "kernel_ms": kern_ms,
+               "hbm_gbps": bytes_per_launch / (kern_ms * 1e-3) / 1e9}
+        if not args.no_check:
+            res["error_vs_fp64_oracle"] = sampled_error_db(out.cpu().numpy(), wave, offsets, "stft", None, n_mels=M)
+        log(f"bench: FFT+filterbank: {res['frames_per_s'] / 1e6:.1f} M frames/s, kernel {kern_ms * 1e3:.1f} us")
+        return res
+
+    if args.only:
+        if args.only == "stft":
+            run_stft()
+        else:
+            run_melt(args.only)
+        return 0
+
+    fp32, plan32 = run_melt("fp32")
+    comparator = run_stft()
+    variants = {}
+    if not args.no_variants:
+        for prec in ("bf16x3", "bf16", "fp16"):
+            try:
+                variants[prec] = run_melt(prec)[0]
+            except melt.MeltError as e:
+                variants[prec] = {"error": str(e)}
+
+    source_id = kernel_source_id()
+    traffic = load_traffic(os.path.join(ROOT, "profiles", "melt_f32_fs_config2_m80_traffic.json"), source_id)
+    achieved = T * flop_per_frame / (fp32["kernel_ms"] * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32"] / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / (PEAK["f32"] / 1e12), "traffic": traffic,
+                "kernel": "k_melt_f32_fs (MelT FP32 projection + energy + log)",
+                "flop_per_launch": T * flop_per_frame, "kernel_ms": fp32["kernel_ms"],
+                "kernel_source_id": source_id}
+
+    line = {
+        "metric": "Mel frames/s: MelT GEMM vs FFT+filterbank on 1 MI355X at stated dB error",
+        "value": fp32["frames_per_s"],
+        "unit": "Mel frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": fp32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "64 clips x 30 s at 16 kHz (pink noise + AM tones), n_fft=400, hop=160, "
+                               f"n_mels={M} HTK 0-8 kHz, T={T} frames; MelT FP32 (v_mfma_f32_32x32x2f32)",
+                   "frames": T, "n_fft": 400, "hop": 160, "n_mels": M, "clips": 64, "seconds_per_clip": 30},
+        "error_vs_fp64_oracle": fp32.get("error_vs_fp64_oracle"),
+        "comparator_fft_filterbank": comparator,
+        "melt_fp32_vs_fft": fp32["frames_per_s"] / comparator["frames_per_s"],
+        "variants": variants,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the FP64 oracle on the host")
+        line["cpu_baseline"] = cpu_baseline(wave, offsets, plan32.frequencies(), T)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -176,6 +176,19 @@ melt_status melt_forward_proj(melt_plan plan, const float *d_wave, const int64_t
 melt_status stft_mel_forward(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets,
                              int32_t n_clips, int64_t n_frames, float *d_out, void *stream);
 
+/* Prepared batches, for callers that run the same batch layout many times (serving loops,
+ * benchmarks): melt_batch_prepare builds, on `stream`, the plan's chunk tables for the
+ * clips in d_clip_offsets (as in melt_forward); melt_forward_prepared and
+ * stft_mel_forward_prepared then launch only the main kernel over that batch.  The
+ * tables stay valid until the next melt_forward / melt_forward_proj / stft_mel_forward /
+ * melt_batch_prepare call on the plan.  Buffers as in melt_forward_proj / stft_mel_forward
+ * (d_proj may be NULL). */
+melt_status melt_batch_prepare(melt_plan plan, const int64_t *d_clip_offsets, int32_t n_clips,
+                               int64_t n_frames, void *stream);
+melt_status melt_forward_prepared(melt_plan plan, const float *d_wave, float *d_out, float *d_proj,
+                                  void *stream);
+melt_status stft_mel_forward_prepared(melt_plan plan, const float *d_wave, float *d_out, void *stream);
+
 /* Gradient of the MelT forward (not in the paper; chain rule through Eqs. meltf,
  * dmp_matrix_energy, dmp_projection), in FP32:
  *   G[t, 2m]   = g[t,m] map'(S) 2 R[t,m],  G[t, 2m+1] = g[t,m] map'(S) 2 I[t,m]

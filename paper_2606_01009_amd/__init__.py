@@ -70,6 +70,12 @@ _SYMBOLS = {
                                          ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "stft_mel_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                         ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "melt_batch_prepare": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                          ctypes.c_void_p]),
+    "melt_forward_prepared": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
+    "stft_mel_forward_prepared": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p]),
     "melt_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                      ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p]),
@@ -192,6 +198,21 @@ def melt_forward_proj(plan, d_wave, d_clip_offsets, n_frames, d_out, d_proj, str
 def stft_mel_forward(plan, d_wave, d_clip_offsets, n_frames, d_out, stream=None) -> None:
     _check(load_library().stft_mel_forward(plan, _ptr(d_wave), _ptr(d_clip_offsets), d_clip_offsets.numel() - 1,
                                            int(n_frames), _ptr(d_out), _stream_handle(stream)), "stft_mel_forward")
+
+
+def melt_batch_prepare(plan, d_clip_offsets, n_frames, stream=None) -> None:
+    _check(load_library().melt_batch_prepare(plan, _ptr(d_clip_offsets), d_clip_offsets.numel() - 1, int(n_frames),
+                                             _stream_handle(stream)), "melt_batch_prepare")
+
+
+def melt_forward_prepared(plan, d_wave, d_out, d_proj=None, stream=None) -> None:
+    _check(load_library().melt_forward_prepared(plan, _ptr(d_wave), _ptr(d_out), _ptr(d_proj), _stream_handle(stream)),
+           "melt_forward_prepared")
+
+
+def stft_mel_forward_prepared(plan, d_wave, d_out, stream=None) -> None:
+    _check(load_library().stft_mel_forward_prepared(plan, _ptr(d_wave), _ptr(d_out), _stream_handle(stream)),
+           "stft_mel_forward_prepared")
 
 
 def melt_backward(plan, d_wave, d_clip_offsets, n_frames, d_grad_out, d_proj, d_grad_wave, d_grad_basis,

@@ -43,7 +43,8 @@ static void free_plan(Plan *p) {
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
     void *bufs[] = {p->d_basis32, p->d_pack_f32, p->d_pack_h16, p->d_pack_lo, p->d_pack_f8, p->d_rowscale,
-                    p->d_fb_w, p->d_fb_start, p->d_fb_off, p->d_twiddle, p->d_chunks, p->d_nchunks};
+                    p->d_fb_w, p->d_fb_start, p->d_fb_off, p->d_twiddle, p->d_window, p->d_chunks[0],
+                    p->d_chunks[1], p->d_nchunks};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -119,7 +120,7 @@ melt_status melt_plan_create(const melt_config *cfg, int device, melt_plan *out)
     if (st == MELT_OK) st = alloc(&p->d_pack_f32, RT * p->geo32.n_groups * 64 * 4 * sizeof(float));
     if (st == MELT_OK) st = alloc(&p->d_pack_h16, RT * p->geo16.n_groups * 64 * 8 * 2);
     if (st == MELT_OK) st = alloc(&p->d_pack_lo, RT * p->geo16.n_groups * 64 * 8 * 2);
-    if (st == MELT_OK) st = alloc((void **)&p->d_nchunks, sizeof(int));
+    if (st == MELT_OK) st = alloc((void **)&p->d_nchunks, 2 * sizeof(int));
     if (st == MELT_OK) {
         std::vector<float> b32(nb);
         for (size_t i = 0; i < nb; ++i) b32[i] = float(p->basis64[i]);
@@ -127,7 +128,8 @@ melt_status melt_plan_create(const melt_config *cfg, int device, melt_plan *out)
     }
     if (st == MELT_OK) st = pack_basis(*p, nullptr);
     if (st == MELT_OK) st = stft_plan_build(*p);
-    if (st == MELT_OK) st = ensure_chunks(*p, 4096);
+    if (st == MELT_OK) st = ensure_chunks(*p, 0, 4096);
+    if (st == MELT_OK) st = ensure_chunks(*p, 1, 4096);
     if (st != MELT_OK) {
         free_plan(p);
         return st;
@@ -198,8 +200,10 @@ melt_status melt_forward_proj(melt_plan plan, const float *d_wave, const int64_t
     if (n_clips == 0 || n_frames == 0) return MELT_OK;
     st = hip_check(hipSetDevice(p->device), "hipSetDevice");
     if (st != MELT_OK) return st;
-    const int v = p->cfg.precision == MELT_PREC_FP32 ? p->tune_f32 : p->tune_h16;
-    return launch_melt_forward(*p, d_wave, d_clip_offsets, n_clips, n_frames, d_out, d_proj, (hipStream_t)stream, v);
+    hipStream_t s = (hipStream_t)stream;
+    st = launch_schedule(*p, 0, d_clip_offsets, n_clips, melt_chunk_frames(*p), n_frames, s);
+    if (st != MELT_OK) return st;
+    return launch_melt_main(*p, d_wave, d_out, d_proj, s);
 }
 
 melt_status stft_mel_forward(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets, int32_t n_clips,
@@ -210,7 +214,45 @@ melt_status stft_mel_forward(melt_plan plan, const float *d_wave, const int64_t 
     if (n_clips == 0 || n_frames == 0) return MELT_OK;
     st = hip_check(hipSetDevice(p->device), "hipSetDevice");
     if (st != MELT_OK) return st;
-    return launch_stft_mel(*p, d_wave, d_clip_offsets, n_clips, n_frames, d_out, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    st = launch_schedule(*p, 1, d_clip_offsets, n_clips, stft_chunk_frames(*p), n_frames, s);
+    if (st != MELT_OK) return st;
+    return launch_stft_main(*p, d_wave, d_out, s);
+}
+
+melt_status melt_batch_prepare(melt_plan plan, const int64_t *d_clip_offsets, int32_t n_clips, int64_t n_frames,
+                               void *stream) {
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p || n_clips < 0 || n_frames < 0 || (n_clips > 0 && !d_clip_offsets))
+        return set_error(MELT_E_INVALID_ARG, "bad argument");
+    melt_status st = hip_check(hipSetDevice(p->device), "hipSetDevice");
+    if (st != MELT_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (n_clips == 0) {
+        p->prepared_frames[0] = p->prepared_frames[1] = 0;
+        return MELT_OK;
+    }
+    st = launch_schedule(*p, 0, d_clip_offsets, n_clips, melt_chunk_frames(*p), n_frames, s);
+    if (st != MELT_OK) return st;
+    return launch_schedule(*p, 1, d_clip_offsets, n_clips, stft_chunk_frames(*p), n_frames, s);
+}
+
+melt_status melt_forward_prepared(melt_plan plan, const float *d_wave, float *d_out, float *d_proj, void *stream) {
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p) return set_error(MELT_E_INVALID_ARG, "plan is NULL");
+    if (p->prepared_frames[0] > 0 && (!d_wave || !d_out)) return set_error(MELT_E_INVALID_ARG, "NULL buffer");
+    melt_status st = hip_check(hipSetDevice(p->device), "hipSetDevice");
+    if (st != MELT_OK) return st;
+    return launch_melt_main(*p, d_wave, d_out, d_proj, (hipStream_t)stream);
+}
+
+melt_status stft_mel_forward_prepared(melt_plan plan, const float *d_wave, float *d_out, void *stream) {
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p) return set_error(MELT_E_INVALID_ARG, "plan is NULL");
+    if (p->prepared_frames[1] > 0 && (!d_wave || !d_out)) return set_error(MELT_E_INVALID_ARG, "NULL buffer");
+    melt_status st = hip_check(hipSetDevice(p->device), "hipSetDevice");
+    if (st != MELT_OK) return st;
+    return launch_stft_main(*p, d_wave, d_out, (hipStream_t)stream);
 }
 
 melt_status melt_backward(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets, int32_t n_clips,

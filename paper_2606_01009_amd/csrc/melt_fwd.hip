@@ -27,6 +27,8 @@ struct GroupTableBig {
     int lds_off[512];
 };
 
+constexpr int kChunkF32 = 128;   // frames per chunk of the frame-split kernels (4 waves x 32)
+
 // ------------------------------------------------------------------ schedule
 
 // One workgroup: prefix sums over the clips of frame counts and chunk counts, then the
@@ -196,6 +198,7 @@ struct FwdArgs {
     int row_tiles;
     int out_kind;
     float eps;
+    float invH;            // 1 / H rounded to FP32 (row index of a span position)
 };
 
 __device__ inline float out_map(float S, int kind, float eps) {
@@ -246,22 +249,6 @@ __device__ inline void store_tile(const FwdArgs &a, const Chunk &ch, int rt, int
     }
 }
 
-// Stage the chunk's sample span into LDS as padded hop-block rows of element type T.
-// Element (r, c) = x[start + r H + c] for c < H and inside the clip, else 0.
-template <class Conv>
-__device__ inline void stage_rows(const FwdArgs &a, const Chunk &ch, typename Conv::elem_t *lds, int nthreads,
-                                  int lo_off = 0) {
-    const int rows = ch.n_frames + a.J - 1;
-    const int total = rows * a.Hp;
-    for (int idx = threadIdx.x; idx < total; idx += nthreads) {
-        const int r = idx / a.Hp;
-        const int c = idx - r * a.Hp;
-        const int64_t s = ch.sample_start + (int64_t)r * a.H + c;
-        const float v = (c < a.H && s < ch.sample_end) ? a.wave[s] : 0.0f;
-        Conv::store(lds, r * a.S + c, v, lo_off);
-    }
-}
-
 struct ConvF32 {
     typedef float elem_t;
     __device__ static void store(float *l, int i, float v, int) { l[i] = v; }
@@ -284,24 +271,116 @@ struct ConvBF16X3 {
     }
 };
 
+// Register staging of a chunk's contiguous sample span [start, start + (n_frames + J - 1) H):
+// element u of a thread is span position o = tid + u * NT, so every load instruction of a
+// wave reads 64 consecutive samples.  span_load issues all PRE loads at once (one memory
+// round trip); span_store scatters them into the padded hop-block rows (row o / H, column
+// o % H).  Samples at or past the clip end read as 0.
+template <int PRE, int NT>
+__device__ __forceinline__ void span_load(const FwdArgs &a, const Chunk &ch, float (&pf)[PRE]) {
+    // buffer descriptor over [start, min(start + span, clip end)): loads past it return 0,
+    // so the clip end needs no branch; one VGPR offset serves all PRE loads
+    const int64_t start = ch.sample_start;
+    const int64_t span = (int64_t)(ch.n_frames + a.J - 1) * a.H;
+    const int64_t lim = ch.sample_end - start < span ? ch.sample_end - start : span;
+    const int records = (int)(lim > 0 ? lim * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(a.wave + start), (short)0, records, 0x00020000);
+    const int voff = (int)threadIdx.x * 4;
+#pragma unroll
+    for (int u = 0; u < PRE; ++u)
+        pf[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, u * NT * 4, 0));
+}
+
+__device__ __forceinline__ int span_row(const FwdArgs &a, int o) {
+    int r = (int)(((float)o + 0.5f) * a.invH);
+    const int c = o - r * a.H;
+    r += (c >= a.H) - (c < 0);
+    return r;
+}
+
+template <class Conv, int PRE, int NT>
+__device__ __forceinline__ void span_store(const FwdArgs &a, const Chunk &ch, const float (&pf)[PRE],
+                                           typename Conv::elem_t *lds, int lo_off) {
+    const int span = (ch.n_frames + a.J - 1) * a.H;
+#pragma unroll
+    for (int u = 0; u < PRE; ++u) {
+        const int o = (int)threadIdx.x + u * NT;
+        if (o < span) {
+            const int r = span_row(a, o);
+            Conv::store(lds, r * a.S + (o - r * a.H), pf[u], lo_off);
+        }
+    }
+}
+
+// Zero the pad columns [H, Hp) of `rows` LDS rows (never written by span_store).
+template <class Conv>
+__device__ __forceinline__ void zero_pad_columns(const FwdArgs &a, int rows, typename Conv::elem_t *lds, int nthreads,
+                                                 int lo_off) {
+    const int w = a.Hp - a.H;
+    if (w <= 0) return;
+    for (int i = threadIdx.x; i < rows * w; i += nthreads) {
+        const int r = i / w, c = a.H + (i - r * w);
+        Conv::store(lds, r * a.S + c, 0.0f, lo_off);
+    }
+}
+
+// Staging without the register pipeline (the 16-bit kernels): batches of U loads per thread.
+template <class Conv, int U>
+__device__ __forceinline__ void stage_span(const FwdArgs &a, const Chunk &ch, typename Conv::elem_t *lds,
+                                           int nthreads, int lo_off) {
+    const int span = (ch.n_frames + a.J - 1) * a.H;
+    for (int base = threadIdx.x; base < span; base += U * nthreads) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int o = base + u * nthreads;
+            const int64_t s = ch.sample_start + o;
+            v[u] = (o < span && s < ch.sample_end) ? a.wave[s] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int o = base + u * nthreads;
+            if (o < span) {
+                const int r = span_row(a, o);
+                Conv::store(lds, r * a.S + (o - r * a.H), v[u], lo_off);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ FP32 frame-split kernel
 //
-// 4 waves; each wave owns 32 frames of the 128-frame chunk and computes all Mel bins for
-// them, in blocks of RTB row tiles (RTB accumulators of 16 registers).  The basis is
-// streamed from L2 in fragment order (one 16-byte load per row tile per 8-wide k-group,
-// shared by the 4 waves through L1) and prefetched one group ahead.
-template <int RTB>
-__global__ __launch_bounds__(256, 1) void k_melt_f32_fs(FwdArgs a, const f32x4 *__restrict__ bpack,
-                                                        GroupTableBig gt) {
+// 4 waves, one per SIMD; each wave owns 32 frames of the 128-frame chunk and computes all
+// Mel bins for them, in blocks of RTB row tiles (RTB accumulators of 16 registers).  The
+// basis is streamed from L2 in fragment order (one 16-byte load per row tile per 8-wide
+// k-group, shared by the 4 waves through L1) and prefetched one group ahead.  While the
+// MFMA loop of chunk c runs, the sample span of the workgroup's next chunk is already in
+// flight into registers (PRE per thread); it is written to LDS after the loop.
+template <int RTB, int PRE>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
+void k_melt_f32_fs(FwdArgs a, const f32x4 *__restrict__ bpack, GroupTableBig gt) {
     extern __shared__ float lds[];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int nch = *a.n_chunks;
     const int NG = gt.n;
-    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
-        const Chunk ch = a.chunks[c];
+    zero_pad_columns<ConvF32>(a, kChunkF32 + a.J - 1, lds, 256, 0);
+    float pf[PRE];
+    int c = blockIdx.x;
+    Chunk nxt;
+    if (c < nch) {
+        nxt = a.chunks[c];
+        span_load<PRE, 256>(a, nxt, pf);
+    }
+    for (; c < nch; c += gridDim.x) {
+        const Chunk ch = nxt;
         __syncthreads();
-        stage_rows<ConvF32>(a, ch, lds, 256);
+        span_store<ConvF32, PRE, 256>(a, ch, pf, lds, 0);
         __syncthreads();
+        if (c + (int)gridDim.x < nch) {
+            nxt = a.chunks[c + gridDim.x];
+            span_load<PRE, 256>(a, nxt, pf);
+        }
         const int fbase = wid * 32;
         if (fbase >= ch.n_frames) continue;
         const float *lp = lds + (fbase + (lane & 31)) * a.S + 4 * (lane >> 5);
@@ -359,11 +438,12 @@ __global__ __launch_bounds__(512) void k_melt_h16_rs(FwdArgs a, const uint4 *__r
         for (int s = 0; s < NS; ++s) Al[s] = blo[((size_t)rt * NS + s) * 64 + lane];
     }
     const int lo_off = a.S * (bf + a.J - 1);
+    zero_pad_columns<Conv>(a, bf + a.J - 1, lds16, nthreads, lo_off);
     const int nch = *a.n_chunks;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         const Chunk ch = a.chunks[c];
         __syncthreads();
-        stage_rows<Conv>(a, ch, lds16, nthreads, lo_off);
+        stage_span<Conv, 8>(a, ch, lds16, nthreads, lo_off);
         __syncthreads();
         const int nft = (ch.n_frames + 31) >> 5;
         for (int ft = 0; ft < nft; ft += 2) {
@@ -411,10 +491,11 @@ __global__ __launch_bounds__(256, 1) void k_melt_h16_fs(FwdArgs a, const uint4 *
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int nch = *a.n_chunks;
     const int NG = gt.n;
+    zero_pad_columns<Conv>(a, kChunkF32 + a.J - 1, lds16, 256, 0);
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         const Chunk ch = a.chunks[c];
         __syncthreads();
-        stage_rows<Conv>(a, ch, lds16, 256);
+        stage_span<Conv, 8>(a, ch, lds16, 256, 0);
         __syncthreads();
         const int fbase = wid * 32;
         if (fbase >= ch.n_frames) continue;
@@ -470,7 +551,7 @@ FwdArgs make_args(Plan &p, const Geometry &g, int S, const float *wave, float *o
                   int64_t n_frames) {
     FwdArgs a;
     a.wave = wave;
-    a.chunks = p.d_chunks;
+    a.chunks = p.d_chunks[0];
     a.n_chunks = p.d_nchunks;
     a.out = out;
     a.proj = proj;
@@ -483,6 +564,7 @@ FwdArgs make_args(Plan &p, const Geometry &g, int S, const float *wave, float *o
     a.row_tiles = p.row_tiles;
     a.out_kind = p.cfg.output;
     a.eps = (float)p.cfg.log_eps;
+    a.invH = (float)(1.0 / p.H);
     return a;
 }
 
@@ -491,7 +573,7 @@ melt_status upload_ints(const std::vector<int> &v, int **d) {
     return hip_check(hipMemcpy(*d, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice), "hipMemcpy");
 }
 
-constexpr int kBF32 = 128;   // frames per chunk, frame-split kernels (4 waves x 32)
+constexpr int kBF32 = kChunkF32;
 constexpr int kMaxLds = 160 * 1024;
 
 template <class K>
@@ -536,26 +618,30 @@ melt_status pack_basis(Plan &p, hipStream_t s) {
     return st;
 }
 
-melt_status ensure_chunks(Plan &p, int64_t needed) {
-    if (needed <= p.chunk_cap) return MELT_OK;
-    int64_t cap = std::max<int64_t>(needed, 2 * p.chunk_cap);
+melt_status ensure_chunks(Plan &p, int which, int64_t needed) {
+    if (needed <= p.chunk_cap[which]) return MELT_OK;
+    int64_t cap = std::max<int64_t>(needed, 2 * p.chunk_cap[which]);
     Chunk *d = nullptr;
     if (hipMalloc(&d, sizeof(Chunk) * cap) != hipSuccess) return set_error(MELT_E_NO_MEMORY, "chunk table");
-    if (p.d_chunks) {
+    if (p.d_chunks[which]) {
         (void)hipDeviceSynchronize();
-        (void)hipFree(p.d_chunks);
+        (void)hipFree(p.d_chunks[which]);
     }
-    p.d_chunks = d;
-    p.chunk_cap = cap;
+    p.d_chunks[which] = d;
+    p.chunk_cap[which] = cap;
     return MELT_OK;
 }
 
-melt_status launch_schedule(Plan &p, const int64_t *d_off, int n_clips, int bf, int64_t n_frames, hipStream_t s) {
+melt_status launch_schedule(Plan &p, int which, const int64_t *d_off, int n_clips, int bf, int64_t n_frames,
+                            hipStream_t s) {
     const int64_t need = n_frames / bf + n_clips + 1;
-    melt_status st = ensure_chunks(p, need);
+    melt_status st = ensure_chunks(p, which, need);
     if (st != MELT_OK) return st;
-    k_schedule<<<1, 1024, 0, s>>>(d_off, n_clips, p.N, p.H, bf, p.d_chunks, p.chunk_cap, p.d_nchunks);
-    return hip_check(hipGetLastError(), "schedule launch");
+    k_schedule<<<1, 1024, 0, s>>>(d_off, n_clips, p.N, p.H, bf, p.d_chunks[which], p.chunk_cap[which],
+                                  p.d_nchunks + which);
+    st = hip_check(hipGetLastError(), "schedule launch");
+    if (st == MELT_OK) p.prepared_frames[which] = n_frames;
+    return st;
 }
 
 melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H, int64_t *d_fo, hipStream_t s) {
@@ -563,12 +649,18 @@ melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H
     return hip_check(hipGetLastError(), "frame offsets launch");
 }
 
-// Variant list.  0 = default for the plan's precision.
-//   FP32: 0 = frame-split (RTB = row tiles, up to 8)
-//   BF16/FP16/BF16X3: 0 = row-split (register basis) when the tile fits, 1 = frame-split
+// Kernel variants.  FP32: frame-split (basis streamed).  BF16/FP16/BF16X3: row-split
+// (basis in registers) when a register tile exists for the frame geometry, else the
+// 16-bit frame-split kernel (not for BF16X3).
+static bool use_row_split(const Plan &p) {
+    const int prec = p.cfg.precision;
+    if (prec == MELT_PREC_FP32 || prec == MELT_PREC_FP8_E4M3) return false;
+    if (!(rs_supported(p.geo16.n_groups) && p.row_tiles <= 8)) return false;
+    return prec == MELT_PREC_BF16X3 || p.tune_h16 == 0;
+}
+
 int forward_variants(const Plan &p) {
-    if (p.cfg.precision == MELT_PREC_FP32) return 1;
-    if (p.cfg.precision == MELT_PREC_BF16X3) return 1;
+    if (p.cfg.precision == MELT_PREC_FP32 || p.cfg.precision == MELT_PREC_BF16X3) return 1;
     return rs_supported(p.geo16.n_groups) && p.row_tiles <= 8 ? 2 : 1;
 }
 
@@ -578,12 +670,25 @@ const char *forward_variant_name(const Plan &p, int v) {
     return "h16-frame-split";
 }
 
+int melt_chunk_frames(const Plan &p) { return use_row_split(p) ? 128 : kBF32; }
+
+template <int RTB, int PRE>
+static melt_status launch_f32_pre(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid,
+                                  hipStream_t s) {
+    allow_lds(k_melt_f32_fs<RTB, PRE>);
+    k_melt_f32_fs<RTB, PRE><<<grid, 256, lds, s>>>(a, (const f32x4 *)p.d_pack_f32, gt);
+    return hip_check(hipGetLastError(), "melt f32 launch");
+}
+
+// register prefetch depth: span of a full chunk, (128 + J - 1) H samples over 256 threads
 template <int RTB>
 static melt_status launch_f32_rtb(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid,
                                   hipStream_t s) {
-    allow_lds(k_melt_f32_fs<RTB>);
-    k_melt_f32_fs<RTB><<<grid, 256, lds, s>>>(a, (const f32x4 *)p.d_pack_f32, gt);
-    return hip_check(hipGetLastError(), "melt f32 launch");
+    const int need = ((kBF32 + a.J - 1) * a.H + 255) / 256;
+    if (need <= 48) return launch_f32_pre<RTB, 48>(p, a, gt, lds, grid, s);
+    if (need <= 88) return launch_f32_pre<RTB, 88>(p, a, gt, lds, grid, s);
+    if (need <= 136) return launch_f32_pre<RTB, 136>(p, a, gt, lds, grid, s);
+    return set_error(MELT_E_UNSUPPORTED, "hop too large for the FP32 register pipeline");
 }
 
 template <class Conv, bool F16, int RTB>
@@ -616,30 +721,33 @@ static melt_status launch_rs(Plan &p, const FwdArgs &a, const GroupTableBig &gt,
     }
 }
 
-melt_status launch_melt_forward(Plan &p, const float *d_wave, const int64_t *d_off, int n_clips, int64_t n_frames,
-                                float *d_out, float *d_proj, hipStream_t s, int variant) {
+melt_status launch_melt_main(Plan &p, const float *d_wave, float *d_out, float *d_proj, hipStream_t s) {
     const int prec = p.cfg.precision;
+    const int64_t n_frames = p.prepared_frames[0];
+    if (n_frames < 0) return set_error(MELT_E_INVALID_ARG, "no batch prepared");
+    if (n_frames == 0) return MELT_OK;
     if (prec == MELT_PREC_FP32) {
         const Geometry &g = p.geo32;
         const int S = lds_stride(g.Hp, 4);
         const size_t lds = (size_t)(kBF32 + g.J - 1) * S * 4;
         if (lds > (size_t)kMaxLds || g.n_groups > 512)
             return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS for FP32 kernel");
-        melt_status st = launch_schedule(p, d_off, n_clips, kBF32, n_frames, s);
-        if (st != MELT_OK) return st;
         const FwdArgs a = make_args(p, g, S, d_wave, d_out, d_proj, n_frames);
         const GroupTableBig gt = make_table(g, S);
-        const int64_t est = n_frames / kBF32 + n_clips + 1;
+        const int64_t est = n_frames / kBF32 + 1;
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, p.cu_count));
-        switch (std::min(p.row_tiles, 8)) {
+        // row tiles per block: at most 5 (2 for the deepest prefetch) so the accumulators,
+        // the basis prefetch and the sample prefetch fit one wave's 512 registers; blocks
+        // of equal size
+        const int need = ((kBF32 + g.J - 1) * p.H + 255) / 256;
+        const int cap = need <= 88 ? 5 : 2;
+        const int blocks = (p.row_tiles + cap - 1) / cap;
+        switch ((p.row_tiles + blocks - 1) / blocks) {
         case 1: return launch_f32_rtb<1>(p, a, gt, lds, grid, s);
         case 2: return launch_f32_rtb<2>(p, a, gt, lds, grid, s);
         case 3: return launch_f32_rtb<3>(p, a, gt, lds, grid, s);
         case 4: return launch_f32_rtb<4>(p, a, gt, lds, grid, s);
-        case 5: return launch_f32_rtb<5>(p, a, gt, lds, grid, s);
-        case 6: return launch_f32_rtb<6>(p, a, gt, lds, grid, s);
-        case 7: return launch_f32_rtb<7>(p, a, gt, lds, grid, s);
-        default: return launch_f32_rtb<8>(p, a, gt, lds, grid, s);
+        default: return launch_f32_rtb<5>(p, a, gt, lds, grid, s);
         }
     }
     if (prec == MELT_PREC_BF16 || prec == MELT_PREC_FP16 || prec == MELT_PREC_BF16X3) {
@@ -647,18 +755,15 @@ melt_status launch_melt_forward(Plan &p, const float *d_wave, const int64_t *d_o
         const int S = lds_stride(g.Hp, 2);
         const bool f16 = prec == MELT_PREC_FP16;
         const bool x3 = prec == MELT_PREC_BF16X3;
-        const bool rs = rs_supported(g.n_groups) && p.row_tiles <= 8 && (variant == 0 || x3);
         if (g.n_groups > 512) return set_error(MELT_E_UNSUPPORTED, "frame too long");
-        if (rs) {
+        const FwdArgs a = make_args(p, g, S, d_wave, d_out, d_proj, n_frames);
+        const GroupTableBig gt = make_table(g, S);
+        if (use_row_split(p)) {
             const int bf = 128;
             const size_t lds = (size_t)(bf + g.J - 1) * S * 2 * (x3 ? 2 : 1);
             if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
-            melt_status st = launch_schedule(p, d_off, n_clips, bf, n_frames, s);
-            if (st != MELT_OK) return st;
-            const FwdArgs a = make_args(p, g, S, d_wave, d_out, d_proj, n_frames);
-            const GroupTableBig gt = make_table(g, S);
             const int per_cu = std::max(1, (int)(kMaxLds / lds));
-            const int64_t est = n_frames / bf + n_clips + 1;
+            const int64_t est = n_frames / bf + 1;
             const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, (int64_t)p.cu_count * std::min(per_cu, 2)));
             if (x3) return launch_rs<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, s);
             if (f16) return launch_rs<ConvF16, false, true>(p, a, gt, lds, grid, bf, s);
@@ -667,11 +772,7 @@ melt_status launch_melt_forward(Plan &p, const float *d_wave, const int64_t *d_o
         if (x3) return set_error(MELT_E_UNSUPPORTED, "BF16X3 needs the register-tile kernel (frame too long)");
         const size_t lds = (size_t)(kBF32 + g.J - 1) * S * 2;
         if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
-        melt_status st = launch_schedule(p, d_off, n_clips, kBF32, n_frames, s);
-        if (st != MELT_OK) return st;
-        const FwdArgs a = make_args(p, g, S, d_wave, d_out, d_proj, n_frames);
-        const GroupTableBig gt = make_table(g, S);
-        const int64_t est = n_frames / kBF32 + n_clips + 1;
+        const int64_t est = n_frames / kBF32 + 1;
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, (int64_t)p.cu_count * 2));
         switch (std::min(p.row_tiles, 8)) {
         case 1: return f16 ? launch_h16fs_rtb<ConvF16, true, 1>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 1>(p, a, gt, lds, grid, s);

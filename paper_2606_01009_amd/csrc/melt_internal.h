@@ -67,10 +67,12 @@ struct Plan {
     int *d_fb_off = nullptr;           // offset of each filter's weights [M+1]
     int fb_nnz = 0;
     float2 *d_twiddle = nullptr;       // exp(-2 pi i j / N), j < N
-    // workspace (schedule)
-    Chunk *d_chunks = nullptr;
-    int *d_nchunks = nullptr;
-    int64_t chunk_cap = 0;
+    float *d_window = nullptr;         // analysis window [N]
+    // workspace: chunk tables of the MelT kernels (0) and of the comparator (1)
+    Chunk *d_chunks[2] = {nullptr, nullptr};
+    int *d_nchunks = nullptr;          // [2]
+    int64_t chunk_cap[2] = {0, 0};
+    int64_t prepared_frames[2] = {-1, -1};   // n_frames of the batch each table describes
     // tuning
     int cu_count = 256;
     int tune_f32 = 0, tune_h16 = 0, tune_f8 = 0;   // index of the chosen kernel variant
@@ -87,18 +89,19 @@ void mel_frequencies(const melt_config &cfg, std::vector<double> &f);
 
 // kernels (melt_fwd.hip, stft_mel.hip, melt_bwd.hip)
 melt_status pack_basis(Plan &p, hipStream_t s);
-melt_status ensure_chunks(Plan &p, int64_t needed);
-melt_status launch_schedule(Plan &p, const int64_t *d_off, int n_clips, int bf, int64_t n_frames,
+melt_status ensure_chunks(Plan &p, int which, int64_t needed);
+melt_status launch_schedule(Plan &p, int which, const int64_t *d_off, int n_clips, int bf, int64_t n_frames,
                             hipStream_t s);
 melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H, int64_t *d_fo,
                                  hipStream_t s);
-melt_status launch_melt_forward(Plan &p, const float *d_wave, const int64_t *d_off, int n_clips,
-                                int64_t n_frames, float *d_out, float *d_proj, hipStream_t s,
-                                int variant);
+// chunk size (frames) of the MelT kernel for the plan's precision / of the comparator
+int melt_chunk_frames(const Plan &p);
+int stft_chunk_frames(const Plan &p);
+// main kernels over the batch prepared in table 0 / table 1
+melt_status launch_melt_main(Plan &p, const float *d_wave, float *d_out, float *d_proj, hipStream_t s);
+melt_status launch_stft_main(Plan &p, const float *d_wave, float *d_out, hipStream_t s);
 int forward_variants(const Plan &p);
 const char *forward_variant_name(const Plan &p, int variant);
-melt_status launch_stft_mel(Plan &p, const float *d_wave, const int64_t *d_off, int n_clips,
-                            int64_t n_frames, float *d_out, hipStream_t s);
 melt_status stft_plan_build(Plan &p);
 melt_status launch_melt_backward(Plan &p, const float *d_wave, const int64_t *d_off, int n_clips,
                                  int64_t n_frames, const float *d_gout, const float *d_proj,

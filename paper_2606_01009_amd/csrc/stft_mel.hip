@@ -1,0 +1,481 @@
+// Conventional STFT + triangular Mel filterbank on gfx950 (the comparator MelT replaces):
+// per frame, window, N-point real DFT by a hand-written mixed-radix FFT, power on the
+// uniform bins k = 0..N/2, sparse triangular Mel filters, log (Methodology: power values on
+// uniformly spaced FFT bins aggregated through non-negative triangular weights; cost
+// O(N log N + nnz(F_Mel)), Eq. complexity_conv).  Everything after the waveform read stays
+// on chip; only the [T, M] output goes back to HBM.
+//
+// Two real frames a, b share one complex FFT of z = a + i b; the spectra separate as
+// A[k] = (Z[k] + conj Z[N-k]) / 2 and B[k] = (Z[k] - conj Z[N-k]) / (2i).  The complex
+// FFT uses the four-step split N = N1 N2 (n = N2 n1 + n2, k = k1 + N1 k2):
+//   1. for each n2: N1-point DFT over n1, in registers of one thread
+//   2. multiply by exp(-2 pi i n2 k1 / N)
+//   3. for each k1: N2-point DFT over n2, in registers of one thread (after an LDS transpose)
+// The small DFTs are fully unrolled Cooley-Tukey recursions with radix 2, 3, 4, 5
+// butterflies whose twiddles are compile-time constants.
+#include <cmath>
+
+#include "melt_internal.h"
+
+namespace melt {
+
+void build_filterbank(const melt_config &c, std::vector<int> &start, std::vector<int> &off, std::vector<float> &w);
+
+// ------------------------------------------------------------------ compile-time cos/sin
+
+// cos and sin of 2 pi a / b for integers, in double precision, as constant expressions:
+// quadrant reduction in integers, then Taylor series on an angle of at most pi/4.
+constexpr double kPiD = 3.14159265358979323846264338327950288;
+constexpr double ct_sin_small(double x) {
+    double x2 = x * x, term = x, sum = x;
+    for (int i = 1; i < 14; ++i) {
+        term *= -x2 / double((2 * i) * (2 * i + 1));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double ct_cos_small(double x) {
+    double x2 = x * x, term = 1.0, sum = 1.0;
+    for (int i = 1; i < 14; ++i) {
+        term *= -x2 / double((2 * i - 1) * (2 * i));
+        sum += term;
+    }
+    return sum;
+}
+struct CtCis {
+    double c, s;
+};
+constexpr CtCis ct_cis(long a, long b) {
+    a %= b;
+    if (a < 0) a += b;
+    const long q = (4 * a) / b;          // quadrant
+    const long r = 4 * a - q * b;        // angle within the quadrant = (pi/2) r / b
+    double c = 0, s = 0;
+    if (2 * r <= b) {
+        const double t = 0.5 * kPiD * double(r) / double(b);
+        c = ct_cos_small(t);
+        s = ct_sin_small(t);
+    } else {
+        const double t = 0.5 * kPiD * double(b - r) / double(b);
+        c = ct_sin_small(t);
+        s = ct_cos_small(t);
+    }
+    switch (q) {
+    case 0: return {c, s};
+    case 1: return {-s, c};
+    case 2: return {-c, -s};
+    default: return {s, -c};
+    }
+}
+
+// ------------------------------------------------------------------ complex helpers
+
+struct cf {
+    float x, y;
+};
+__device__ __forceinline__ cf cadd(cf a, cf b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cf csub(cf a, cf b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ cf cmul(cf a, cf b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ cf mul_mi(cf a) { return {a.y, -a.x}; }   // -i a
+__device__ __forceinline__ cf mul_pi(cf a) { return {-a.y, a.x}; }   // +i a
+__device__ __forceinline__ cf cscale(cf a, float s) { return {a.x * s, a.y * s}; }
+
+// multiply by exp(-2 pi i num / den) with the constant folded; quarter turns are exact
+template <long NUM, long DEN>
+__device__ __forceinline__ cf twiddle_const(cf a) {
+    constexpr long n = ((NUM % DEN) + DEN) % DEN;
+    if constexpr (n == 0) return a;
+    else if constexpr (4 * n == DEN) return mul_mi(a);
+    else if constexpr (2 * n == DEN) return {-a.x, -a.y};
+    else if constexpr (4 * n == 3 * DEN) return mul_pi(a);
+    else {
+        constexpr CtCis w = ct_cis(n, DEN);
+        constexpr float c = (float)w.c, s = (float)(-w.s);
+        return {a.x * c - a.y * s, a.x * s + a.y * c};
+    }
+}
+
+// ------------------------------------------------------------------ small DFTs in registers
+// Forward DFT X[k] = sum_n x[n] exp(-2 pi i n k / L), in place, natural order.
+
+template <int L>
+struct Radix {
+    static constexpr int value = (L % 4 == 0 && L != 4) ? 4 : (L % 2 == 0 && L != 2) ? 2
+                                 : (L % 3 == 0 && L != 3) ? 3 : (L % 5 == 0 && L != 5) ? 5 : L;
+};
+
+template <int L>
+struct DFT;
+
+template <>
+struct DFT<1> {
+    __device__ __forceinline__ static void run(cf *) {}
+};
+template <>
+struct DFT<2> {
+    __device__ __forceinline__ static void run(cf *x) {
+        const cf a = x[0], b = x[1];
+        x[0] = cadd(a, b);
+        x[1] = csub(a, b);
+    }
+};
+template <>
+struct DFT<3> {
+    __device__ __forceinline__ static void run(cf *x) {
+        const float s = 0.86602540378443864676f;   // sin(2 pi / 3)
+        const cf a = cadd(x[1], x[2]), b = csub(x[1], x[2]);
+        const cf t = {x[0].x - 0.5f * a.x, x[0].y - 0.5f * a.y};
+        x[0] = cadd(x[0], a);
+        const cf u = mul_mi(cscale(b, s));
+        x[1] = cadd(t, u);
+        x[2] = csub(t, u);
+    }
+};
+template <>
+struct DFT<4> {
+    __device__ __forceinline__ static void run(cf *x) {
+        const cf a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
+        const cf c = cadd(x[1], x[3]), d = mul_mi(csub(x[1], x[3]));
+        x[0] = cadd(a, c);
+        x[2] = csub(a, c);
+        x[1] = cadd(b, d);
+        x[3] = csub(b, d);
+    }
+};
+template <>
+struct DFT<5> {
+    __device__ __forceinline__ static void run(cf *x) {
+        constexpr CtCis w1 = ct_cis(1, 5), w2 = ct_cis(2, 5);
+        const float c1 = (float)w1.c, s1 = (float)w1.s, c2 = (float)w2.c, s2 = (float)w2.s;
+        const cf a1 = cadd(x[1], x[4]), b1 = csub(x[1], x[4]);
+        const cf a2 = cadd(x[2], x[3]), b2 = csub(x[2], x[3]);
+        const cf x0 = x[0];
+        const cf t1 = {x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y};
+        const cf t2 = {x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y};
+        const cf u1 = mul_mi(cf{s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y});
+        const cf u2 = mul_mi(cf{s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y});
+        x[0] = cadd(x0, cadd(a1, a2));
+        x[1] = cadd(t1, u1);
+        x[4] = csub(t1, u1);
+        x[2] = cadd(t2, u2);
+        x[3] = csub(t2, u2);
+    }
+};
+
+// composite: L = R m, decimation in time
+template <int L>
+struct DFT {
+    static constexpr int R = Radix<L>::value;
+    static constexpr int Msub = L / R;
+    static_assert(R * Msub == L && R <= 5, "DFT size must factor into 2, 3, 4, 5");
+
+    template <int K>
+    __device__ __forceinline__ static void combine(cf (&sub)[R][Msub], cf *x) {
+        if constexpr (K < Msub) {
+            cf t[R];
+            apply<K, 0>(sub, t);
+            DFT<R>::run(t);
+#pragma unroll
+            for (int q = 0; q < R; ++q) x[K + Msub * q] = t[q];
+            combine<K + 1>(sub, x);
+        }
+    }
+    template <int K, int J>
+    __device__ __forceinline__ static void apply(cf (&sub)[R][Msub], cf (&t)[R]) {
+        if constexpr (J < R) {
+            t[J] = twiddle_const<(long)J * K, L>(sub[J][K]);
+            apply<K, J + 1>(sub, t);
+        }
+    }
+    __device__ __forceinline__ static void run(cf *x) {
+        cf sub[R][Msub];
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+#pragma unroll
+            for (int i = 0; i < Msub; ++i) sub[j][i] = x[R * i + j];
+#pragma unroll
+        for (int j = 0; j < R; ++j) DFT<Msub>::run(sub[j]);
+        combine<0>(sub, x);
+    }
+};
+
+// ------------------------------------------------------------------ kernel
+
+struct StftArgs {
+    const float *wave;
+    const Chunk *chunks;
+    const int *n_chunks;
+    float *out;
+    int64_t n_frames;
+    const float *window;      // [N]
+    const float2 *twiddle;    // [N], exp(-2 pi i j / N)
+    const float *fb_w;        // concatenated filter weights
+    const int *fb_start;      // [M] first bin
+    const int *fb_off;        // [M+1] offsets into fb_w
+    int fb_nnz;
+    int M, H;
+    int out_kind;
+    float eps;
+};
+
+__device__ __forceinline__ float stft_out_map(float v, int kind, float eps) {
+    return (kind <= MELT_OUT_LOG_MAGNITUDE) ? logf(v + eps) : v;
+}
+
+// Orders this wave's LDS traffic: everything before is complete and visible to every lane
+// of the wave before anything after it.  Only lanes of one wave share a buffer, so no
+// workgroup barrier is needed.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wave owns FPW = 64 / TPF complex FFTs (2 FPW frames) per sub-task and runs the whole
+// pipeline for them with wave-local LDS only; a chunk is SUB sub-tasks; the workgroup's
+// waves take chunks independently (persistent loop over the chunk table).
+template <int N1, int N2, int WAVES, int SUB>
+__global__ __launch_bounds__(64 * WAVES) void k_stft_mel(StftArgs a) {
+    constexpr int N = N1 * N2;
+    constexpr int NB = N / 2 + 1;
+    constexpr int TPF = N1 > N2 ? N1 : N2;        // lanes per FFT
+    constexpr int FPW = 64 / TPF;                 // FFTs per wave per sub-task
+    constexpr int LDB = N2 + 1;                   // padded row of the [k1][n2] layout
+    constexpr int BUF = (N1 * LDB > N ? N1 * LDB : N);
+    extern __shared__ float smem[];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    cf *tw = reinterpret_cast<cf *>(smem);                            // [N1][N2]: exp(-2 pi i n2 k1 / N)
+    float *fbw = reinterpret_cast<float *>(tw + N);                   // [nnz]
+    int *fbs = reinterpret_cast<int *>(fbw + a.fb_nnz);               // [M]
+    int *fbo = fbs + a.M;                                             // [M+1]
+    cf *buf = reinterpret_cast<cf *>(fbo + a.M + 2) + wid * FPW * BUF;   // this wave's FFT rows
+    for (int i = threadIdx.x; i < N; i += 64 * WAVES) {
+        const int k1 = i / N2, n2 = i - k1 * N2;
+        const float2 t = a.twiddle[(n2 * k1) % N];
+        tw[i] = cf{t.x, t.y};
+    }
+    for (int i = threadIdx.x; i < a.fb_nnz; i += 64 * WAVES) fbw[i] = a.fb_w[i];
+    for (int i = threadIdx.x; i < a.M; i += 64 * WAVES) fbs[i] = a.fb_start[i];
+    for (int i = threadIdx.x; i <= a.M; i += 64 * WAVES) fbo[i] = a.fb_off[i];
+    __syncthreads();
+
+    const bool mag = (a.out_kind == MELT_OUT_LOG_MAGNITUDE || a.out_kind == MELT_OUT_MAGNITUDE);
+    const int p1 = lane / TPF, n2 = lane - p1 * TPF;                  // step-1 role
+    const bool act1 = p1 < FPW && n2 < N2;
+    float win[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) win[n1] = act1 ? a.window[N2 * n1 + n2] : 0.0f;
+
+    const int nch = *a.n_chunks;
+    const int gw = blockIdx.x * WAVES + wid, nw = gridDim.x * WAVES;
+    // samples of one sub-task for this lane: frames 2 p1 and 2 p1 + 1 at points N2 n1 + n2
+    float xa[N1], xb[N1];
+    auto load = [&](const Chunk &ch, int sub) {
+        const int64_t lim = ch.sample_end - ch.sample_start;
+        const int records = (int)(lim < (int64_t(1) << 29) ? lim * 4 : (int64_t(1) << 31) - 4);
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void *)(a.wave + ch.sample_start), (short)0, records, 0x00020000);
+        const int fa = 2 * FPW * sub + 2 * p1;
+        const int va = (fa * a.H + n2) * 4, vb = va + a.H * 4;
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {
+            xa[n1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, va, N2 * n1 * 4, 0));
+            xb[n1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vb, N2 * n1 * 4, 0));
+        }
+    };
+    int c = gw;
+    Chunk ch;
+    if (c < nch) {
+        ch = a.chunks[c];
+        load(ch, 0);
+    }
+    int sub = 0;
+    while (c < nch) {
+        const Chunk cur = ch;
+        const int cur_sub = sub;
+        // advance to the next sub-task (this chunk or the wave's next chunk) and prefetch it
+        ++sub;
+        if (2 * FPW * sub >= cur.n_frames || sub >= SUB) {
+            sub = 0;
+            c += nw;
+            if (c < nch) ch = a.chunks[c];
+        }
+        // step 1: N1-point DFTs over n1, four-step twiddle, store as [k1][n2]
+        cf z[N1];
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) z[n1] = cf{xa[n1] * win[n1], xb[n1] * win[n1]};
+        if (c < nch) load(ch, sub);
+        DFT<N1>::run(z);
+        cf *row1 = buf + p1 * BUF;
+        if (act1) {
+#pragma unroll
+            for (int k1 = 0; k1 < N1; ++k1) row1[k1 * LDB + n2] = cmul(z[k1], tw[k1 * N2 + n2]);
+        }
+        wave_sync();
+        // step 3: N2-point DFTs over n2, natural order k = k1 + N1 k2
+        {
+            const int p3 = lane / TPF, k1 = lane - p3 * TPF;
+            const bool act3 = p3 < FPW && k1 < N1;
+            cf y[N2];
+            cf *row3 = buf + p3 * BUF;
+            if (act3) {
+#pragma unroll
+                for (int q = 0; q < N2; ++q) y[q] = row3[k1 * LDB + q];
+            }
+            wave_sync();
+            if (act3) {
+                DFT<N2>::run(y);
+#pragma unroll
+                for (int k2 = 0; k2 < N2; ++k2) row3[k1 + N1 * k2] = y[k2];
+            }
+        }
+        wave_sync();
+        // steps 4-5: separate the two real spectra bin by bin inside each filter's support,
+        // |X_k|^2 (or |X_k|), triangular weights, output map, coalesced store
+        const int f0 = 2 * FPW * cur_sub;
+        for (int t = lane; t < FPW * a.M; t += 64) {
+            const int p = t / a.M, m = t - p * a.M;
+            const int fa = f0 + 2 * p;
+            if (fa >= cur.n_frames) continue;
+            const cf *rowz = buf + p * BUF;
+            float acc_a = 0.0f, acc_b = 0.0f;
+            const int k0 = fbs[m];
+            for (int j = fbo[m]; j < fbo[m + 1]; ++j) {
+                const int k = k0 + (j - fbo[m]);
+                const cf zk = rowz[k], zn = rowz[(N - k) % N];
+                // A = (Z[k] + conj Z[N-k]) / 2,  B = (Z[k] - conj Z[N-k]) / (2i)
+                const float ar = 0.5f * (zk.x + zn.x), ai = 0.5f * (zk.y - zn.y);
+                const float br = 0.5f * (zk.y + zn.y), bi = -0.5f * (zk.x - zn.x);
+                float pa = ar * ar + ai * ai, pb = br * br + bi * bi;
+                if (mag) {
+                    pa = sqrtf(pa);
+                    pb = sqrtf(pb);
+                }
+                acc_a += fbw[j] * pa;
+                acc_b += fbw[j] * pb;
+            }
+            const int64_t row = cur.out_row + fa;
+            if (row < a.n_frames) a.out[row * a.M + m] = stft_out_map(acc_a, a.out_kind, a.eps);
+            if (fa + 1 < cur.n_frames && row + 1 < a.n_frames)
+                a.out[(row + 1) * a.M + m] = stft_out_map(acc_b, a.out_kind, a.eps);
+        }
+        wave_sync();
+    }
+}
+
+// ------------------------------------------------------------------ host side
+
+namespace {
+
+struct StftShape {
+    int N1, N2, FPW, SUB;
+};
+
+bool stft_shape(int N, StftShape &s) {
+    switch (N) {
+    case 400: s = {20, 20, 3, 8}; return true;
+    case 512: s = {16, 32, 2, 8}; return true;
+    case 1024: s = {32, 32, 2, 8}; return true;
+    case 256: s = {16, 16, 4, 8}; return true;
+    case 1200: s = {30, 40, 1, 16}; return true;
+    default: return false;
+    }
+}
+
+constexpr int kStftWaves = 4;
+
+size_t stft_lds_bytes(const StftShape &s, int M, int nnz) {
+    const int N = s.N1 * s.N2;
+    const int LDB = s.N2 + 1;
+    const int BUF = std::max(s.N1 * LDB, N);
+    const size_t head = (size_t)N * 8 + (size_t)nnz * 4 + (size_t)(2 * M + 2) * 4;
+    return ((head + 7) / 8) * 8 + (size_t)kStftWaves * s.FPW * BUF * 8;
+}
+
+template <int N1, int N2, int SUB>
+melt_status launch_shape(const StftArgs &a, size_t lds, int grid, hipStream_t s) {
+    (void)hipFuncSetAttribute((const void *)k_stft_mel<N1, N2, kStftWaves, SUB>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    k_stft_mel<N1, N2, kStftWaves, SUB><<<grid, 64 * kStftWaves, lds, s>>>(a);
+    return hip_check(hipGetLastError(), "stft_mel launch");
+}
+
+}  // namespace
+
+melt_status stft_plan_build(Plan &p) {
+    StftShape sh;
+    if (!stft_shape(p.N, sh)) return MELT_OK;   // comparator unsupported for this N: reported at call time
+    std::vector<int> start, off;
+    std::vector<float> w;
+    build_filterbank(p.cfg, start, off, w);
+    p.fb_nnz = (int)w.size();
+    std::vector<float> win(p.N);
+    std::vector<float2> tw(p.N);
+    for (int n = 0; n < p.N; ++n) {
+        double wv = 1.0;
+        if (p.cfg.window != MELT_WIN_RECT) {
+            const double den = (p.cfg.window == MELT_WIN_HANN_SYMMETRIC) ? double(p.N - 1) : double(p.N);
+            wv = 0.5 - 0.5 * std::cos(2.0 * kPiD * double(n) / den);
+        }
+        win[n] = float(wv);
+        const double ang = 2.0 * kPiD * double(n) / double(p.N);   // index already reduced: n < N
+        tw[n] = make_float2(float(std::cos(ang)), float(-std::sin(ang)));
+    }
+    auto up = [](const void *src, size_t bytes, void **dst) -> melt_status {
+        if (hipMalloc(dst, bytes ? bytes : 4) != hipSuccess) return set_error(MELT_E_NO_MEMORY, "hipMalloc");
+        if (bytes == 0) return MELT_OK;
+        return hip_check(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy");
+    };
+    melt_status st = up(w.data(), w.size() * 4, (void **)&p.d_fb_w);
+    if (st == MELT_OK) st = up(start.data(), start.size() * 4, (void **)&p.d_fb_start);
+    if (st == MELT_OK) st = up(off.data(), off.size() * 4, (void **)&p.d_fb_off);
+    if (st == MELT_OK) st = up(tw.data(), tw.size() * sizeof(float2), (void **)&p.d_twiddle);
+    if (st == MELT_OK) st = up(win.data(), win.size() * 4, (void **)&p.d_window);
+    return st;
+}
+
+int stft_chunk_frames(const Plan &p) {
+    StftShape sh;
+    return stft_shape(p.N, sh) ? 2 * sh.FPW * sh.SUB : 32;
+}
+
+melt_status launch_stft_main(Plan &p, const float *d_wave, float *d_out, hipStream_t s) {
+    StftShape sh;
+    if (!stft_shape(p.N, sh) || !p.d_twiddle)
+        return set_error(MELT_E_UNSUPPORTED, "comparator FFT supports n_fft in {256, 400, 512, 1024, 1200}");
+    const int64_t n_frames = p.prepared_frames[1];
+    if (n_frames < 0) return set_error(MELT_E_INVALID_ARG, "no batch prepared");
+    if (n_frames == 0) return MELT_OK;
+    const size_t lds = stft_lds_bytes(sh, p.M, p.fb_nnz);
+    if (lds > 160 * 1024) return set_error(MELT_E_UNSUPPORTED, "comparator LDS too large");
+    const int bf = stft_chunk_frames(p);
+    StftArgs a;
+    a.wave = d_wave;
+    a.chunks = p.d_chunks[1];
+    a.n_chunks = p.d_nchunks + 1;
+    a.out = d_out;
+    a.n_frames = n_frames;
+    a.window = p.d_window;
+    a.twiddle = p.d_twiddle;
+    a.fb_w = p.d_fb_w;
+    a.fb_start = p.d_fb_start;
+    a.fb_off = p.d_fb_off;
+    a.fb_nnz = p.fb_nnz;
+    a.M = p.M;
+    a.H = p.H;
+    a.out_kind = p.cfg.output;
+    a.eps = (float)p.cfg.log_eps;
+    const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / lds)));
+    const int64_t est = (n_frames / bf + 1 + kStftWaves - 1) / kStftWaves;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, (int64_t)p.cu_count * per_cu));
+    switch (p.N) {
+    case 400: return launch_shape<20, 20, 8>(a, lds, grid, s);
+    case 512: return launch_shape<16, 32, 8>(a, lds, grid, s);
+    case 1024: return launch_shape<32, 32, 8>(a, lds, grid, s);
+    case 256: return launch_shape<16, 16, 8>(a, lds, grid, s);
+    case 1200: return launch_shape<30, 40, 16>(a, lds, grid, s);
+    default: return set_error(MELT_E_UNSUPPORTED, "n_fft");
+    }
+}
+
+}  // namespace melt

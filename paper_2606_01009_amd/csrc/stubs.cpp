@@ -2,10 +2,6 @@
 #include "melt_internal.h"
 
 namespace melt {
-melt_status stft_plan_build(Plan &) { return MELT_OK; }
-melt_status launch_stft_mel(Plan &, const float *, const int64_t *, int, int64_t, float *, hipStream_t) {
-    return set_error(MELT_E_UNSUPPORTED, "stft_mel_forward not built");
-}
 melt_status launch_melt_backward(Plan &, const float *, const int64_t *, int, int64_t, const float *, const float *,
                                  float *, float *, hipStream_t) {
     return set_error(MELT_E_UNSUPPORTED, "melt_backward not built");

@@ -83,3 +83,53 @@ def frames_as_clips(wave, offsets, n_fft, hop, frame_ids):
     sub = np.concatenate(segs).astype(np.float32)
     off = np.arange(len(segs) + 1, dtype=np.int64) * n_fft
     return sub, off
+
+
+def fft_pair_norms(wave, offsets, n_fft, hop, window):
+    """For every frame, ||w x_f||^2 + ||w x_g||^2 where g is the frame that shares its complex
+    FFT (frames 2p and 2p+1 of a clip are packed into one FFT as z = a + i b)."""
+    offsets = np.asarray(offsets, np.int64)
+    out = []
+    for a, b in zip(offsets[:-1], offsets[1:]):
+        L = b - a
+        Tc = 1 + (L - n_fft) // hop if L >= n_fft else 0
+        e = np.array([np.sum((window * wave[a + t * hop:a + t * hop + n_fft].astype(np.float64)) ** 2)
+                      for t in range(Tc)])
+        partner = np.zeros(Tc)
+        for t in range(Tc):
+            g = t ^ 1
+            partner[t] = e[g] if g < Tc else 0.0
+        out.append(e + partner)
+    return np.concatenate(out) if out else np.zeros(0)
+
+
+def check_stft_log(L_gpu, P, F, pair_norm2, n_fft, eps, c_fft=4.0, label=""):
+    """Bound for the FFT + filterbank path.  A floating-point FFT of size N has a norm-wise
+    error ||dZ||_2 <= levels * eta * ||Z||_2 with eta a few u per butterfly level; Z here
+    carries the two packed frames, ||Z||_2^2 = N (||w a||^2 + ||w b||^2).  Every bin therefore
+    has |dX_k| <= delta = c_fft * u * log2(N) * sqrt(N * pair_norm2).  Then
+    |dP_k| <= 2 |X_k| delta + delta^2, the non-negative filters give
+    |dmel_m| <= sum_k F[m,k] |dP_k| + (nnz_m + 3) u mel_m, and the log adds its rounding."""
+    L_gpu = np.asarray(L_gpu, np.float64)
+    levels = np.log2(n_fft)
+    delta = c_fft * U32 * levels * np.sqrt(n_fft * pair_norm2)          # [T]
+    absX = np.sqrt(P)                                                     # [T, NB]
+    dP = 2 * absX * delta[:, None] + delta[:, None] ** 2
+    mel = P @ F.T
+    nnz = np.count_nonzero(F, axis=1)
+    dmel = dP @ F.T + (nnz[None, :] + 3) * U32 * mel
+    den = mel + eps - dmel
+    vac = den <= 0
+    L = np.log(mel + eps)
+    bound = np.where(vac, np.inf, dmel / np.where(vac, 1.0, den)) + 4 * np.spacing(np.abs(L).astype(np.float32)) + U32
+    err = np.abs(L_gpu - L)
+    bad = (~vac) & (err > bound)
+    if np.any(bad):
+        idx = np.argwhere(bad)[:8]
+        lines = [f"t={t} m={m} gpu={L_gpu[t, m]:.9g} oracle={L[t, m]:.9g} err={err[t, m]:.3g} bound={bound[t, m]:.3g}"
+                 for t, m in idx]
+        raise AssertionError(f"{label}: {int(bad.sum())} of {bad.size} bins beyond the FFT bound\n" + "\n".join(lines))
+    if np.any(vac):
+        hi = np.log(mel + dmel + eps) + 1e-6
+        assert np.all(L_gpu[vac] <= hi[vac]) and np.all(L_gpu[vac] >= np.log(eps * (1 - 2 * U32)) - 1e-6), label
+    return db_stats(L_gpu, L, mel)
