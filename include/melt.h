@@ -206,26 +206,39 @@ melt_status melt_backward(melt_plan plan, const float *d_wave, const int64_t *d_
                           const float *d_proj, float *d_grad_wave, float *d_grad_basis,
                           void *stream);
 
-/* Streaming: n_streams independent audio streams, each keeping the last n_fft - hop
- * samples (and the phase of its next frame) in device memory owned by the state.
- * melt_stream_push appends chunk_len new samples to every stream (d_chunk: device float32
- * [n_streams, chunk_len]) and writes each stream's newly complete frames to
- * d_out (device float32 [n_streams, max_frames_per_push, n_mels], frame-major per stream)
- * and their count to d_frames_emitted (device int32 [n_streams]).  max_frames_per_push =
- * floor((chunk_len + n_fft - 1) / hop) + 1 bounds every push.  A push is one or two kernel
- * launches with no host synchronisation and no allocation, so it can be captured in a
- * hipGraph and replayed with new chunk contents. */
-melt_status melt_stream_create(melt_plan plan, int32_t n_streams, int32_t chunk_len,
+/* Streaming: n_streams independent audio streams over the plan (same frontend, same
+ * precision).  Each stream keeps in device memory owned by the state the samples that
+ * no complete frame has consumed yet (fewer than n_fft), so frames come out exactly as
+ * melt_forward would produce them for the concatenated stream.
+ *   melt_stream_create   n_streams >= 1, 1 <= max_chunk_len <= 1 << 20; allocates the
+ *                        state (carry buffers, assembly buffers, a private chunk table)
+ *   melt_stream_reset    empties every stream (enqueued on `stream`)
+ *   melt_stream_max_frames  frames one push can emit per stream:
+ *                        floor((max_chunk_len + n_fft - 1 - n_fft) / hop) + 1
+ *   melt_stream_push     appends chunk_len (1..max_chunk_len) samples to every stream:
+ *                        d_chunk device float32 [n_streams, chunk_len] (row-major);
+ *                        writes stream s's new frames to d_out (device float32
+ *                        [n_streams, max_frames, n_mels]) rows [s * max_frames, + k) and
+ *                        k to d_frames_emitted[s] (device int32 [n_streams]).
+ * A push is three kernel launches (assemble, project, keep the tail) with no host
+ * synchronisation and no allocation: it can be captured in a hipGraph and replayed with
+ * new chunk contents (one graph per chunk length).  Pushes on one state must be ordered
+ * (one stream). */
+melt_status melt_stream_create(melt_plan plan, int32_t n_streams, int32_t max_chunk_len,
                                melt_stream_state *out);
 melt_status melt_stream_destroy(melt_stream_state st);
 melt_status melt_stream_reset(melt_stream_state st, void *stream);
 int32_t     melt_stream_max_frames(melt_stream_state st);
-melt_status melt_stream_push(melt_stream_state st, const float *d_chunk, float *d_out,
+melt_status melt_stream_push(melt_stream_state st, const float *d_chunk, int32_t chunk_len, float *d_out,
                              int32_t *d_frames_emitted, void *stream);
 
-/* Autotuning: times the candidate tile shapes of melt_forward for this plan on a
- * synthetic batch of total_frames frames and keeps the fastest for later calls.
- * Writes a short description of the winner to `desc` (host, may be NULL). */
+/* Autotuning: times every kernel variant and launch size of melt_forward that applies to
+ * this plan on a synthetic batch of total_frames frames (allocated and freed inside the
+ * call; synchronises the device), keeps the fastest for later calls on the plan, and
+ * records it in the JSON cache file named by the environment variable
+ * MELT_AUTOTUNE_CACHE if set (entries keyed by precision, n_fft, hop, n_mels and device
+ * name; melt_plan_create applies a matching entry).  Writes a one-line description of
+ * the winner to `desc` (host, desc_len bytes, may be NULL). */
 melt_status melt_autotune(melt_plan plan, int64_t total_frames, char *desc, int32_t desc_len);
 
 /* Human-readable name of a status; thread-local text of the last error. */

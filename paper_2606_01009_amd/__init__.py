@@ -84,8 +84,8 @@ _SYMBOLS = {
     "melt_stream_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "melt_stream_reset": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "melt_stream_max_frames": (ctypes.c_int32, [ctypes.c_void_p]),
-    "melt_stream_push": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                        ctypes.c_void_p]),
+    "melt_stream_push": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
     "melt_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_char_p, ctypes.c_int32]),
     "melt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "melt_last_error": (ctypes.c_char_p, []),
@@ -222,9 +222,9 @@ def melt_backward(plan, d_wave, d_clip_offsets, n_frames, d_grad_out, d_proj, d_
                                         _ptr(d_grad_basis), _stream_handle(stream)), "melt_backward")
 
 
-def melt_stream_create(plan, n_streams: int, chunk_len: int) -> ctypes.c_void_p:
+def melt_stream_create(plan, n_streams: int, max_chunk_len: int) -> ctypes.c_void_p:
     h = ctypes.c_void_p()
-    _check(load_library().melt_stream_create(plan, n_streams, chunk_len, ctypes.byref(h)), "melt_stream_create")
+    _check(load_library().melt_stream_create(plan, n_streams, max_chunk_len, ctypes.byref(h)), "melt_stream_create")
     return h
 
 
@@ -241,8 +241,9 @@ def melt_stream_max_frames(st) -> int:
 
 
 def melt_stream_push(st, d_chunk, d_out, d_frames_emitted, stream=None) -> None:
-    _check(load_library().melt_stream_push(st, _ptr(d_chunk), _ptr(d_out), _ptr(d_frames_emitted),
-                                           _stream_handle(stream)), "melt_stream_push")
+    """d_chunk: [n_streams, chunk_len] float32 CUDA tensor; chunk_len is its second dimension."""
+    _check(load_library().melt_stream_push(st, _ptr(d_chunk), int(d_chunk.shape[-1]), _ptr(d_out),
+                                           _ptr(d_frames_emitted), _stream_handle(stream)), "melt_stream_push")
 
 
 def melt_autotune(plan, total_frames: int) -> str:
@@ -276,6 +277,40 @@ def make_config(sample_rate=16000.0, n_fft=400, hop=160, n_mels=80, fmin=0.0, fm
 def total_frames(clip_offsets, n_fft: int, hop: int) -> int:
     off = np.asarray(clip_offsets, np.int64)
     return int(sum(melt_num_frames(int(b - a), n_fft, hop) for a, b in zip(off[:-1], off[1:])))
+
+
+class MeltStream:
+    """Owns a streaming state over a MeltPlan; push() takes a [n_streams, chunk_len] tensor and
+    returns (frames [n_streams, max_frames, n_mels], counts [n_streams]) device tensors (reused
+    between pushes)."""
+
+    def __init__(self, plan: "MeltPlan", n_streams: int, max_chunk_len: int):
+        import torch
+        self.plan = plan
+        self.n_streams = n_streams
+        self.handle = melt_stream_create(plan.handle, n_streams, max_chunk_len)
+        self.max_frames = melt_stream_max_frames(self.handle)
+        dev = f"cuda:{plan.device}"
+        self.out = torch.zeros((n_streams, self.max_frames, plan.n_mels), dtype=torch.float32, device=dev)
+        self.count = torch.zeros(n_streams, dtype=torch.int32, device=dev)
+
+    def push(self, chunk):
+        melt_stream_push(self.handle, chunk, self.out, self.count)
+        return self.out, self.count
+
+    def reset(self):
+        melt_stream_reset(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            melt_stream_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class MeltPlan:

@@ -44,7 +44,7 @@ static void free_plan(Plan *p) {
     (void)hipDeviceSynchronize();
     void *bufs[] = {p->d_basis32, p->d_pack_f32, p->d_pack_h16, p->d_pack_lo, p->d_pack_f8, p->d_rowscale,
                     p->d_fb_w, p->d_fb_start, p->d_fb_off, p->d_twiddle, p->d_window, p->d_chunks[0],
-                    p->d_chunks[1], p->d_nchunks};
+                    p->d_chunks[1], p->d_nchunks, p->d_pack_dx, p->d_bwd_ws, p->d_bwd_rows};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -130,6 +130,7 @@ melt_status melt_plan_create(const melt_config *cfg, int device, melt_plan *out)
     if (st == MELT_OK) st = stft_plan_build(*p);
     if (st == MELT_OK) st = ensure_chunks(*p, 0, 4096);
     if (st == MELT_OK) st = ensure_chunks(*p, 1, 4096);
+    if (st == MELT_OK) apply_tune_cache(*p);
     if (st != MELT_OK) {
         free_plan(p);
         return st;

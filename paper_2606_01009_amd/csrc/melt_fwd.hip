@@ -548,11 +548,11 @@ GroupTableBig make_table(const Geometry &g, int S) {
 }
 
 FwdArgs make_args(Plan &p, const Geometry &g, int S, const float *wave, float *out, float *proj,
-                  int64_t n_frames) {
+                  int64_t n_frames, const Chunk *tab, const int *n_tab) {
     FwdArgs a;
     a.wave = wave;
-    a.chunks = p.d_chunks[0];
-    a.n_chunks = p.d_nchunks;
+    a.chunks = tab;
+    a.n_chunks = n_tab;
     a.out = out;
     a.proj = proj;
     a.n_frames = n_frames;
@@ -580,6 +580,9 @@ template <class K>
 void allow_lds(K kern) {
     (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
 }
+
+// workgroups per CU of a persistent launch: the tuned value, else the default
+int grid_mult(const Plan &p, int dflt) { return p.tune_grid > 0 ? p.tune_grid : dflt; }
 
 // row-split variants: number of k-groups with a compiled register tile
 bool rs_supported(int NS) { return NS == 25 || NS == 32 || NS == 20 || NS == 16 || NS == 10; }
@@ -615,7 +618,8 @@ melt_status pack_basis(Plan &p, hipStream_t s) {
         k_pack_h16<<<256, 256, 0, s>>>(p.d_basis32, p.M, p.N, p.H, seg, col, p.geo16.n_groups, RT, 2,
                                        (unsigned short *)p.d_pack_lo);
     });
-    return st;
+    if (st != MELT_OK) return st;
+    return pack_basis_dx(p, s);
 }
 
 melt_status ensure_chunks(Plan &p, int which, int64_t needed) {
@@ -722,20 +726,26 @@ static melt_status launch_rs(Plan &p, const FwdArgs &a, const GroupTableBig &gt,
 }
 
 melt_status launch_melt_main(Plan &p, const float *d_wave, float *d_out, float *d_proj, hipStream_t s) {
-    const int prec = p.cfg.precision;
     const int64_t n_frames = p.prepared_frames[0];
     if (n_frames < 0) return set_error(MELT_E_INVALID_ARG, "no batch prepared");
     if (n_frames == 0) return MELT_OK;
+    return launch_melt_table(p, p.d_chunks[0], p.d_nchunks, n_frames / melt_chunk_frames(p) + 1, n_frames, d_wave,
+                             d_out, d_proj, s);
+}
+
+melt_status launch_melt_table(Plan &p, const Chunk *tab, const int *n_tab, int64_t est_chunks, int64_t n_frames,
+                              const float *d_wave, float *d_out, float *d_proj, hipStream_t s) {
+    const int prec = p.cfg.precision;
     if (prec == MELT_PREC_FP32) {
         const Geometry &g = p.geo32;
         const int S = lds_stride(g.Hp, 4);
         const size_t lds = (size_t)(kBF32 + g.J - 1) * S * 4;
         if (lds > (size_t)kMaxLds || g.n_groups > 512)
             return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS for FP32 kernel");
-        const FwdArgs a = make_args(p, g, S, d_wave, d_out, d_proj, n_frames);
+        const FwdArgs a = make_args(p, g, S, d_wave, d_out, d_proj, n_frames, tab, n_tab);
         const GroupTableBig gt = make_table(g, S);
-        const int64_t est = n_frames / kBF32 + 1;
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, p.cu_count));
+        const int64_t est = est_chunks;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, (int64_t)p.cu_count * grid_mult(p, 1)));
         // row tiles per block: at most 5 (2 for the deepest prefetch) so the accumulators,
         // the basis prefetch and the sample prefetch fit one wave's 512 registers; blocks
         // of equal size
@@ -756,15 +766,15 @@ melt_status launch_melt_main(Plan &p, const float *d_wave, float *d_out, float *
         const bool f16 = prec == MELT_PREC_FP16;
         const bool x3 = prec == MELT_PREC_BF16X3;
         if (g.n_groups > 512) return set_error(MELT_E_UNSUPPORTED, "frame too long");
-        const FwdArgs a = make_args(p, g, S, d_wave, d_out, d_proj, n_frames);
+        const FwdArgs a = make_args(p, g, S, d_wave, d_out, d_proj, n_frames, tab, n_tab);
         const GroupTableBig gt = make_table(g, S);
         if (use_row_split(p)) {
             const int bf = 128;
             const size_t lds = (size_t)(bf + g.J - 1) * S * 2 * (x3 ? 2 : 1);
             if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
             const int per_cu = std::max(1, (int)(kMaxLds / lds));
-            const int64_t est = n_frames / bf + 1;
-            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, (int64_t)p.cu_count * std::min(per_cu, 2)));
+            const int64_t est = est_chunks;
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, (int64_t)p.cu_count * grid_mult(p, std::min(per_cu, 2))));
             if (x3) return launch_rs<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, s);
             if (f16) return launch_rs<ConvF16, false, true>(p, a, gt, lds, grid, bf, s);
             return launch_rs<ConvBF16, false, false>(p, a, gt, lds, grid, bf, s);
@@ -772,8 +782,8 @@ melt_status launch_melt_main(Plan &p, const float *d_wave, float *d_out, float *
         if (x3) return set_error(MELT_E_UNSUPPORTED, "BF16X3 needs the register-tile kernel (frame too long)");
         const size_t lds = (size_t)(kBF32 + g.J - 1) * S * 2;
         if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
-        const int64_t est = n_frames / kBF32 + 1;
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, (int64_t)p.cu_count * 2));
+        const int64_t est = est_chunks;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, (int64_t)p.cu_count * grid_mult(p, 2)));
         switch (std::min(p.row_tiles, 8)) {
         case 1: return f16 ? launch_h16fs_rtb<ConvF16, true, 1>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 1>(p, a, gt, lds, grid, s);
         case 2: return f16 ? launch_h16fs_rtb<ConvF16, true, 2>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 2>(p, a, gt, lds, grid, s);

@@ -73,9 +73,17 @@ struct Plan {
     int *d_nchunks = nullptr;          // [2]
     int64_t chunk_cap[2] = {0, 0};
     int64_t prepared_frames[2] = {-1, -1};   // n_frames of the batch each table describes
+    // backward: dx basis layout and workspaces (grown on demand)
+    void *d_pack_dx = nullptr;
+    size_t pack_dx_cap = 0;
+    void *d_bwd_ws = nullptr;
+    size_t bwd_ws_cap = 0;
+    void *d_bwd_rows = nullptr;
+    size_t bwd_rows_cap = 0;
     // tuning
     int cu_count = 256;
     int tune_f32 = 0, tune_h16 = 0, tune_f8 = 0;   // index of the chosen kernel variant
+    int tune_grid = 0;                             // workgroups per CU (0 = kernel default)
     std::string last_tune;
 };
 
@@ -89,6 +97,7 @@ void mel_frequencies(const melt_config &cfg, std::vector<double> &f);
 
 // kernels (melt_fwd.hip, stft_mel.hip, melt_bwd.hip)
 melt_status pack_basis(Plan &p, hipStream_t s);
+melt_status pack_basis_dx(Plan &p, hipStream_t s);
 melt_status ensure_chunks(Plan &p, int which, int64_t needed);
 melt_status launch_schedule(Plan &p, int which, const int64_t *d_off, int n_clips, int bf, int64_t n_frames,
                             hipStream_t s);
@@ -100,7 +109,11 @@ int stft_chunk_frames(const Plan &p);
 // main kernels over the batch prepared in table 0 / table 1
 melt_status launch_melt_main(Plan &p, const float *d_wave, float *d_out, float *d_proj, hipStream_t s);
 melt_status launch_stft_main(Plan &p, const float *d_wave, float *d_out, hipStream_t s);
+// main MelT kernel over an explicit chunk table (streaming); est_chunks sizes the grid
+melt_status launch_melt_table(Plan &p, const Chunk *tab, const int *n_tab, int64_t est_chunks, int64_t n_frames,
+                              const float *d_wave, float *d_out, float *d_proj, hipStream_t s);
 int forward_variants(const Plan &p);
+void apply_tune_cache(Plan &p);          // stream.hip: apply a MELT_AUTOTUNE_CACHE entry
 const char *forward_variant_name(const Plan &p, int variant);
 melt_status stft_plan_build(Plan &p);
 melt_status launch_melt_backward(Plan &p, const float *d_wave, const int64_t *d_off, int n_clips,
