@@ -120,6 +120,8 @@ melt_status melt_plan_create(const melt_config *cfg, int device, melt_plan *out)
     if (st == MELT_OK) st = alloc(&p->d_pack_f32, RT * p->geo32.n_groups * 64 * 4 * sizeof(float));
     if (st == MELT_OK) st = alloc(&p->d_pack_h16, RT * p->geo16.n_groups * 64 * 8 * 2);
     if (st == MELT_OK) st = alloc(&p->d_pack_lo, RT * p->geo16.n_groups * 64 * 8 * 2);
+    if (st == MELT_OK) st = alloc(&p->d_pack_f8, RT * ((p->N + 63) / 64) * 64 * 32);
+    if (st == MELT_OK) st = alloc((void **)&p->d_rowscale, RT * 32 * sizeof(float));
     if (st == MELT_OK) st = alloc((void **)&p->d_nchunks, 2 * sizeof(int));
     if (st == MELT_OK) {
         std::vector<float> b32(nb);

@@ -297,7 +297,7 @@ melt_status grow(void **p, size_t *cap, size_t need) {
 template <int CT>
 melt_status launch_dx(Plan &p, const float *G, float *dx, int S, size_t lds, int grid, hipStream_t s) {
     (void)hipFuncSetAttribute((const void *)k_bwd_dx<CT>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    k_bwd_dx<CT><<<grid, 256, lds, s>>>((const RowChunk *)p.d_bwd_rows, p.d_nchunks, G, (const f32x4 *)p.d_pack_dx,
+    k_bwd_dx<CT><<<grid, 256, lds, s>>>((const RowChunk *)p.d_bwd_rows, p.d_nchunks + 1, G, (const f32x4 *)p.d_pack_dx,
                                         p.M, p.H, p.geo32.J, S, p.prepared_frames[0], dx);
     return hip_check(hipGetLastError(), "bwd dx launch");
 }

@@ -481,6 +481,162 @@ __global__ __launch_bounds__(512) void k_melt_h16_rs(FwdArgs a, const uint4 *__r
     }
 }
 
+// ------------------------------------------------------------------ FP8 E4M3 row-split kernel
+//
+// Per-frame scaling needs one quantised copy of every frame (a sample belongs to ~N/H
+// frames with different scales), so the chunk's FP32 span is staged as hop-block rows, the
+// maximum |x| of every frame is formed from per-row maxima, and each frame is quantised
+// with s_t = 448 / max|x_t| into a frame-major E4M3 image in LDS (K = n padded to 64).
+// One wave per 32-row basis tile keeps its E4M3 rows (pre-scaled by r_j = 448 / max|W_j|)
+// in registers; v_mfma_scale_f32_32x32x64_f8f6f4 with unit block scales multiplies; the
+// epilogue divides by s_t r_j in FP32 before R^2 + I^2.
+
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned fp8x4(float a, float b, float c, float d) {
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+    return (unsigned)w;
+}
+
+// E4M3 pack of the basis: [rt][group of 64][lane][32 bytes]; lane half h holds k = 64 g + 32 h + byte.
+// Row scales r_j = 448 / max_n |W_j| (FP32); rinv[rt][i] = 1 / r_j of tile row i.
+__global__ void k_pack_f8(const float *__restrict__ b32, int M, int N, int NG, int RT, unsigned *__restrict__ out,
+                          float *__restrict__ rinv) {
+    __shared__ float rmax[32];
+    const int rt = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 32) {
+        int ml, part;
+        tile_row_to_mel(threadIdx.x, ml, part);
+        const int mel = rt * 16 + ml;
+        float mx = 0.0f;
+        if (mel < M)
+            for (int n = 0; n < N; ++n) mx = fmaxf(mx, fabsf(b32[(size_t)(part * M + mel) * N + n]));
+        rmax[threadIdx.x] = mx;
+        rinv[rt * 32 + threadIdx.x] = mx > 0.0f ? 1.0f / __fdiv_rn(448.0f, mx) : 1.0f;
+    }
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
+    int ml, part;
+    tile_row_to_mel(lane & 31, ml, part);
+    const int mel = rt * 16 + ml;
+    const float mx = rmax[lane & 31];
+    const float sc = mx > 0.0f ? __fdiv_rn(448.0f, mx) : 1.0f;
+    for (int g = 0; g < NG; ++g)
+        for (int w = 0; w < 8; ++w) {
+            float v[4];
+            for (int e = 0; e < 4; ++e) {
+                const int k = g * 64 + 32 * (lane >> 5) + 4 * w + e;
+                v[e] = (mel < M && k < N) ? __fmul_rn(b32[(size_t)(part * M + mel) * N + k], sc) : 0.0f;
+            }
+            out[(((size_t)rt * NG + g) * 64 + lane) * 8 + w] = fp8x4(v[0], v[1], v[2], v[3]);
+        }
+}
+
+template <int NG>
+__global__ __launch_bounds__(512) void k_melt_f8_rs(FwdArgs a, const i32x8 *__restrict__ bq, const float *__restrict__ rinv_g,
+                                                    int N, int bf) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & 63, rt = threadIdx.x >> 6, nthreads = blockDim.x, nw = nthreads >> 6;
+    constexpr int KP = NG * 64;             // padded frame length in the E4M3 image
+    constexpr int SQ = KP + 16;             // row stride (bytes): 4 x odd dwords -> conflict-free 16-byte reads
+    const int rows_max = bf + a.J - 1;
+    float *xs = lds;                                                 // FP32 hop-block rows
+    unsigned char *xq = reinterpret_cast<unsigned char *>(lds + rows_max * a.S);   // [bf][SQ] E4M3
+    float *sinv = reinterpret_cast<float *>(xq + bf * SQ);           // [bf] 1 / s_t
+    float *mfull = sinv + bf;                                        // [rows] max over the row
+    float *mpre = mfull + rows_max;                                  // [rows] max over the last segment's prefix
+    const int Llast = N - (a.J - 1) * a.H;                           // length of the last segment
+    i32x8 A[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) A[g] = bq[((size_t)rt * NG + g) * 64 + lane];
+    float rinv[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) rinv[r] = rinv_g[rt * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)];
+    zero_pad_columns<ConvF32>(a, rows_max, xs, nthreads, 0);
+    const int nch = *a.n_chunks;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const Chunk ch = a.chunks[c];
+        __syncthreads();
+        stage_span<ConvF32, 8>(a, ch, xs, nthreads, 0);
+        __syncthreads();
+        // per-row maxima (whole row, and the prefix the last segment uses)
+        const int rows = ch.n_frames + a.J - 1;
+        for (int r = rt; r < rows; r += nw) {
+            float mf = 0.0f, mp = 0.0f;
+            for (int col = lane; col < a.H; col += 64) {
+                const float v = fabsf(xs[r * a.S + col]);
+                mf = fmaxf(mf, v);
+                if (col < Llast) mp = fmaxf(mp, v);
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                mf = fmaxf(mf, __shfl_xor(mf, o));
+                mp = fmaxf(mp, __shfl_xor(mp, o));
+            }
+            if (lane == 0) {
+                mfull[r] = mf;
+                mpre[r] = mp;
+            }
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < ch.n_frames; t += nthreads) {
+            float mx = mpre[t + a.J - 1];
+            for (int j = 0; j + 1 < a.J; ++j) mx = fmaxf(mx, mfull[t + j]);
+            const float s = mx > 0.0f ? __fdiv_rn(448.0f, mx) : 1.0f;
+            sinv[t] = s;                       // scale itself; inverted in the epilogue
+        }
+        __syncthreads();
+        // quantise: frame t, samples n = 4u..4u+3 -> one 32-bit LDS word
+        for (int i = threadIdx.x; i < ch.n_frames * (KP / 4); i += nthreads) {
+            const int t = i / (KP / 4), u = i - t * (KP / 4);
+            const float s = sinv[t];
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int n = 4 * u + e;
+                float x = 0.0f;
+                if (n < N) {
+                    const int j = n / a.H, col = n - j * a.H;
+                    x = xs[(t + j) * a.S + col];
+                }
+                v[e] = __fmul_rn(x, s);
+            }
+            *reinterpret_cast<unsigned *>(xq + t * SQ + 4 * u) = fp8x4(v[0], v[1], v[2], v[3]);
+        }
+        __syncthreads();
+        const int nft = (ch.n_frames + 31) >> 5;
+        for (int ft = 0; ft < nft; ft += 2) {
+            const bool two = ft + 1 < nft;
+            f32x16 acc0 = f32x16{}, acc1 = f32x16{};
+            const unsigned char *q0 = xq + (ft * 32 + (lane & 31)) * SQ + 32 * (lane >> 5);
+            const unsigned char *q1 = q0 + 32 * SQ;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const uint4 b0l = *(const uint4 *)(q0 + 64 * g), b0h = *(const uint4 *)(q0 + 64 * g + 16);
+                i32x8 B0 = {(int)b0l.x, (int)b0l.y, (int)b0l.z, (int)b0l.w, (int)b0h.x, (int)b0h.y, (int)b0h.z, (int)b0h.w};
+                acc0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[g], B0, acc0, 0, 0, 0, 127, 0, 127);
+                if (two) {
+                    const uint4 b1l = *(const uint4 *)(q1 + 64 * g), b1h = *(const uint4 *)(q1 + 64 * g + 16);
+                    i32x8 B1 = {(int)b1l.x, (int)b1l.y, (int)b1l.z, (int)b1l.w, (int)b1h.x, (int)b1h.y, (int)b1h.z, (int)b1h.w};
+                    acc1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[g], B1, acc1, 0, 0, 0, 127, 0, 127);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (u == 1 && !two) break;
+                f32x16 &acc = u ? acc1 : acc0;
+                const int f = (ft + u) * 32 + (lane & 31);
+                const float is = f < ch.n_frames ? 1.0f / sinv[f] : 0.0f;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[r] = acc[r] * (is * rinv[r]);
+                store_tile(a, ch, rt, f, lane, acc);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ 16-bit frame-split kernel
 // Fallback for frame lengths whose basis tile does not fit in registers: as the FP32
 // frame-split kernel, one 32x32x16 MFMA per k-group.
@@ -619,6 +775,10 @@ melt_status pack_basis(Plan &p, hipStream_t s) {
                                        (unsigned short *)p.d_pack_lo);
     });
     if (st != MELT_OK) return st;
+    const int ng8 = (p.N + 63) / 64;
+    k_pack_f8<<<RT, 64, 0, s>>>(p.d_basis32, p.M, p.N, ng8, RT, (unsigned *)p.d_pack_f8, p.d_rowscale);
+    st = hip_check(hipGetLastError(), "pack f8");
+    if (st != MELT_OK) return st;
     return pack_basis_dx(p, s);
 }
 
@@ -664,12 +824,15 @@ static bool use_row_split(const Plan &p) {
 }
 
 int forward_variants(const Plan &p) {
-    if (p.cfg.precision == MELT_PREC_FP32 || p.cfg.precision == MELT_PREC_BF16X3) return 1;
+    if (p.cfg.precision == MELT_PREC_FP32 || p.cfg.precision == MELT_PREC_BF16X3 ||
+        p.cfg.precision == MELT_PREC_FP8_E4M3)
+        return 1;
     return rs_supported(p.geo16.n_groups) && p.row_tiles <= 8 ? 2 : 1;
 }
 
 const char *forward_variant_name(const Plan &p, int v) {
     if (p.cfg.precision == MELT_PREC_FP32) return "f32-frame-split";
+    if (p.cfg.precision == MELT_PREC_FP8_E4M3) return "f8-row-split";
     if (rs_supported(p.geo16.n_groups) && p.row_tiles <= 8 && v == 0) return "h16-row-split";
     return "h16-frame-split";
 }
@@ -710,6 +873,13 @@ static melt_status launch_rs_ns(Plan &p, const FwdArgs &a, const GroupTableBig &
     k_melt_h16_rs<Conv, NS, X3, F16><<<grid, 64 * p.row_tiles, lds, s>>>(
         a, (const uint4 *)p.d_pack_h16, (const uint4 *)p.d_pack_lo, gt, bf);
     return hip_check(hipGetLastError(), "melt h16 rs launch");
+}
+
+template <int NG>
+static melt_status launch_f8(Plan &p, const FwdArgs &a, size_t lds, int grid, int bf, hipStream_t s) {
+    allow_lds(k_melt_f8_rs<NG>);
+    k_melt_f8_rs<NG><<<grid, 64 * p.row_tiles, lds, s>>>(a, (const i32x8 *)p.d_pack_f8, p.d_rowscale, p.N, bf);
+    return hip_check(hipGetLastError(), "melt f8 launch");
 }
 
 template <class Conv, bool X3, bool F16>
@@ -792,6 +962,25 @@ melt_status launch_melt_table(Plan &p, const Chunk *tab, const int *n_tab, int64
         case 5:
         case 6: return f16 ? launch_h16fs_rtb<ConvF16, true, 6>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 6>(p, a, gt, lds, grid, s);
         default: return f16 ? launch_h16fs_rtb<ConvF16, true, 8>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 8>(p, a, gt, lds, grid, s);
+        }
+    }
+    if (prec == MELT_PREC_FP8_E4M3) {
+        const Geometry &g = p.geo32;
+        const int S = lds_stride(g.Hp, 4);
+        const int ng8 = (p.N + 63) / 64;
+        const int bf = kBF32;
+        const int rows_max = bf + g.J - 1;
+        const size_t lds = (size_t)rows_max * S * 4 + (size_t)bf * (ng8 * 64 + 16) + (size_t)bf * 4 + 2 * (size_t)rows_max * 4;
+        if (lds > (size_t)kMaxLds || p.row_tiles > 8)
+            return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS for the FP8 kernel");
+        const FwdArgs a = make_args(p, g, S, d_wave, d_out, d_proj, n_frames, tab, n_tab);
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est_chunks, (int64_t)p.cu_count * grid_mult(p, 1)));
+        switch (ng8) {
+        case 4: return launch_f8<4>(p, a, lds, grid, bf, s);
+        case 7: return launch_f8<7>(p, a, lds, grid, bf, s);
+        case 8: return launch_f8<8>(p, a, lds, grid, bf, s);
+        case 16: return launch_f8<16>(p, a, lds, grid, bf, s);
+        default: return set_error(MELT_E_UNSUPPORTED, "FP8 kernel supports n_fft in (192, 256], (384, 512], (960, 1024]");
         }
     }
     return set_error(MELT_E_UNSUPPORTED, "precision not implemented");

