@@ -106,7 +106,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="time only the FP32 MelT path and the comparator")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled error check")
-    ap.add_argument("--only", default=None, help="time one path only: fp32|bf16|fp16|bf16x3|stft (profiling)")
+    ap.add_argument("--only", default=None, help="time one path only: fp32|bf16|fp16|bf16x3|fp8|stft (profiling)")
+    ap.add_argument("--sweep", action="store_true", help="time every kernel variant of every precision and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported (the frames of a batch "
@@ -159,6 +160,13 @@ def main():
         log(f"bench: FFT+filterbank: {res['frames_per_s'] / 1e6:.1f} M frames/s, kernel {kern_ms * 1e3:.1f} us")
         return res
 
+    if args.sweep:
+        for prec in ("fp32", "bf16", "fp16", "bf16x3", "fp8"):
+            plan = melt.MeltPlan(sample_rate=16000.0, n_fft=400, hop=160, n_mels=M, precision=prec)
+            desc = melt.melt_autotune(plan.handle, T)
+            log(f"bench: autotune {prec}: {desc}")
+        return 0
+
     if args.only:
         if args.only == "stft":
             run_stft()
@@ -170,7 +178,7 @@ def main():
     comparator = run_stft()
     variants = {}
     if not args.no_variants:
-        for prec in ("bf16x3", "bf16", "fp16"):
+        for prec in ("bf16x3", "bf16", "fp16", "fp8"):
             try:
                 variants[prec] = run_melt(prec)[0]
             except melt.MeltError as e:

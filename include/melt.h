@@ -241,6 +241,19 @@ melt_status melt_stream_push(melt_stream_state st, const float *d_chunk, int32_t
  * the winner to `desc` (host, desc_len bytes, may be NULL). */
 melt_status melt_autotune(melt_plan plan, int64_t total_frames, char *desc, int32_t desc_len);
 
+/* Kernel variants of melt_forward for this plan's precision and geometry (the kernels that
+ * can run it: staging scheme, frames per chunk).  melt_variant_count returns how many
+ * there are (at least 1); melt_variant_name names variant v ("none" if v is out of
+ * range; thread-local text, valid until the thread's next call); melt_set_variant pins variant v with grid_per_cu
+ * workgroups per compute unit (0 = the kernel's default) for later forward, backward and
+ * prepare calls on the plan.  Variant 0 with the default grid is chosen at plan creation;
+ * melt_autotune overrides it.  A batch prepared before the change keeps the variant it was
+ * prepared with, and so does a streaming state.  Error: MELT_E_INVALID_ARG for a v or
+ * grid_per_cu out of range. */
+int32_t     melt_variant_count(melt_plan plan);
+const char *melt_variant_name(melt_plan plan, int32_t v);
+melt_status melt_set_variant(melt_plan plan, int32_t v, int32_t grid_per_cu);
+
 /* Human-readable name of a status; thread-local text of the last error. */
 const char *melt_status_string(melt_status s);
 const char *melt_last_error(void);

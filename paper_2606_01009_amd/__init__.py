@@ -87,6 +87,9 @@ _SYMBOLS = {
     "melt_stream_push": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p]),
     "melt_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_char_p, ctypes.c_int32]),
+    "melt_variant_count": (ctypes.c_int32, [ctypes.c_void_p]),
+    "melt_variant_name": (ctypes.c_char_p, [ctypes.c_void_p, ctypes.c_int32]),
+    "melt_set_variant": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "melt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "melt_last_error": (ctypes.c_char_p, []),
 }
@@ -250,6 +253,18 @@ def melt_autotune(plan, total_frames: int) -> str:
     buf = ctypes.create_string_buffer(256)
     _check(load_library().melt_autotune(plan, int(total_frames), buf, 256), "melt_autotune")
     return buf.value.decode()
+
+
+def melt_variant_count(plan) -> int:
+    return int(load_library().melt_variant_count(plan))
+
+
+def melt_variant_name(plan, v: int) -> str:
+    return load_library().melt_variant_name(plan, int(v)).decode()
+
+
+def melt_set_variant(plan, v: int, grid_per_cu: int = 0) -> None:
+    _check(load_library().melt_set_variant(plan, int(v), int(grid_per_cu)), "melt_set_variant")
 
 
 # ------------------------------------------------------------------ convenience layer

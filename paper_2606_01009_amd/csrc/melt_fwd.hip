@@ -187,6 +187,23 @@ __global__ void k_pack_h16(const float *__restrict__ b32, int M, int N, int H, c
 
 // ------------------------------------------------------------------ shared device pieces
 
+// A chunk-table entry read into scalar registers (every lane of a workgroup uses the same
+// chunk, so buffer descriptors built from it need no waterfall loop).
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return (int64_t)(((uint64_t)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ Chunk read_chunk(const Chunk *tab, int c) {
+    Chunk e = tab[c];
+    e.sample_start = uniform64(e.sample_start);
+    e.sample_end = uniform64(e.sample_end);
+    e.out_row = uniform64(e.out_row);
+    e.n_frames = __builtin_amdgcn_readfirstlane(e.n_frames);
+    e.clip = __builtin_amdgcn_readfirstlane(e.clip);
+    return e;
+}
+
 struct FwdArgs {
     const float *wave;
     const Chunk *chunks;
@@ -249,17 +266,30 @@ __device__ inline void store_tile(const FwdArgs &a, const Chunk &ch, int rt, int
     }
 }
 
+// Operand formats of the staged frames.  store writes one element; store4 writes four
+// consecutive ones (i a multiple of 4).
+__device__ __forceinline__ unsigned pack2(unsigned short lo, unsigned short hi) { return lo | ((unsigned)hi << 16); }
+
 struct ConvF32 {
     typedef float elem_t;
     __device__ static void store(float *l, int i, float v, int) { l[i] = v; }
+    __device__ static void store4(float *l, int i, f32x4 v, int) { *(f32x4 *)(l + i) = v; }
 };
 struct ConvBF16 {
     typedef unsigned short elem_t;
     __device__ static void store(unsigned short *l, int i, float v, int) { l[i] = f32_to_bf16_bits(v); }
+    __device__ static void store4(unsigned short *l, int i, f32x4 v, int) {
+        *(uint2 *)(l + i) = uint2{pack2(f32_to_bf16_bits(v[0]), f32_to_bf16_bits(v[1])),
+                                  pack2(f32_to_bf16_bits(v[2]), f32_to_bf16_bits(v[3]))};
+    }
 };
 struct ConvF16 {
     typedef unsigned short elem_t;
     __device__ static void store(unsigned short *l, int i, float v, int) { l[i] = f32_to_f16_bits(v); }
+    __device__ static void store4(unsigned short *l, int i, f32x4 v, int) {
+        *(uint2 *)(l + i) = uint2{pack2(f32_to_f16_bits(v[0]), f32_to_f16_bits(v[1])),
+                                  pack2(f32_to_f16_bits(v[2]), f32_to_f16_bits(v[3]))};
+    }
 };
 // split-bf16: the high part at [i], the low part at [i + lo_off]
 struct ConvBF16X3 {
@@ -268,6 +298,16 @@ struct ConvBF16X3 {
         const unsigned short hb = f32_to_bf16_bits(v);
         l[i] = hb;
         l[i + lo_off] = f32_to_bf16_bits(v - bf16_bits_to_f32(hb));
+    }
+    __device__ static void store4(unsigned short *l, int i, f32x4 v, int lo_off) {
+        unsigned short h[4], r[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            h[e] = f32_to_bf16_bits(v[e]);
+            r[e] = f32_to_bf16_bits(v[e] - bf16_bits_to_f32(h[e]));
+        }
+        *(uint2 *)(l + i) = uint2{pack2(h[0], h[1]), pack2(h[2], h[3])};
+        *(uint2 *)(l + i + lo_off) = uint2{pack2(r[0], r[1]), pack2(r[2], r[3])};
     }
 };
 
@@ -303,6 +343,15 @@ template <class Conv, int PRE, int NT>
 __device__ __forceinline__ void span_store(const FwdArgs &a, const Chunk &ch, const float (&pf)[PRE],
                                            typename Conv::elem_t *lds, int lo_off) {
     const int span = (ch.n_frames + a.J - 1) * a.H;
+    if (span >= PRE * NT) {         // whole register tile valid: no per-element branch
+#pragma unroll
+        for (int u = 0; u < PRE; ++u) {
+            const int o = (int)threadIdx.x + u * NT;
+            const int r = span_row(a, o);
+            Conv::store(lds, r * a.S + (o - r * a.H), pf[u], lo_off);
+        }
+        return;
+    }
 #pragma unroll
     for (int u = 0; u < PRE; ++u) {
         const int o = (int)threadIdx.x + u * NT;
@@ -349,6 +398,82 @@ __device__ __forceinline__ void stage_span(const FwdArgs &a, const Chunk &ch, ty
     }
 }
 
+// ------------------------------------------------------------------ direct-to-LDS staging
+// The chunk's contiguous sample span is copied HBM -> LDS by global_load_lds_dword: each
+// wave instruction moves 64 consecutive samples straight into LDS with no registers, so
+// the copy of chunk c+1 runs while the MFMAs of chunk c execute.  Positions at or past
+// `valid` (the span clipped to the clip end) are not loaded; consumers read them as 0.
+__device__ __forceinline__ int span_valid(const FwdArgs &a, const Chunk &ch) {
+    const int span = (ch.n_frames + a.J - 1) * a.H;
+    int64_t lim = ch.sample_end - ch.sample_start;
+    lim = lim < 0 ? 0 : lim;
+    return (int)(lim < span ? lim : span);
+}
+
+// The copies are issued with inline assembly: the compiler does not track them, so it adds no
+// wait for them before the LDS reads of the MFMA loop (which never touch the scratch area);
+// async_wait and a barrier order them before the scratch is read.  M0 holds the wave's LDS
+// destination; one wait state separates its write from the copy.
+__device__ __forceinline__ unsigned lds_addr(const void *p) {
+    return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+
+__device__ __forceinline__ void lds_dma_x4(const float *g, unsigned lds) {
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds) : "memory", "m0");
+}
+
+__device__ __forceinline__ void lds_dma_x1(const float *g, unsigned lds) {
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dword %0, off" ::"v"(g), "s"(lds) : "memory", "m0");
+}
+
+// 16-byte copies (256 samples per wave instruction) over the whole blocks of the valid span,
+// then 4-byte copies over its last partial block, so no lane reads past the clip end.
+__device__ __forceinline__ void async_span(const FwdArgs &a, const Chunk &ch, float *scratch) {
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
+    const int valid = span_valid(a, ch);
+    const float *src = a.wave + ch.sample_start;
+    const unsigned base = __builtin_amdgcn_readfirstlane(lds_addr(scratch));
+    const int nfull = valid >> 8;
+    for (int b = wid; b < nfull; b += nw) lds_dma_x4(src + b * 256 + 4 * lane, base + b * 1024);
+    for (int b = 4 * nfull + wid; b * 64 < valid; b += nw) {
+        const int o = b * 64 + lane;
+        if (o < valid) lds_dma_x1(src + o, base + b * 256);
+    }
+}
+
+__device__ __forceinline__ void async_wait() {
+    __builtin_amdgcn_s_waitcnt(0);     // this wave's direct-to-LDS copies have landed
+}
+
+// scratch (contiguous span) -> padded hop-block rows in the kernel's operand format.  With
+// H a multiple of 4, four consecutive samples never straddle a row: one 16-byte LDS read and
+// one vector write per thread and step.
+template <class Conv>
+__device__ __forceinline__ void convert_span(const FwdArgs &a, const Chunk &ch, const float *scratch,
+                                             typename Conv::elem_t *rows, int lo_off) {
+    const int span = (ch.n_frames + a.J - 1) * a.H;
+    const int valid = span_valid(a, ch);
+    if ((a.H & 3) == 0) {
+        for (int o = 4 * (int)threadIdx.x; o < span; o += 4 * (int)blockDim.x) {
+            f32x4 v = *(const f32x4 *)(scratch + o);
+            if (o + 4 > valid) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (o + e >= valid) v[e] = 0.0f;
+            }
+            const int r = span_row(a, o);
+            Conv::store4(rows, r * a.S + (o - r * a.H), v, lo_off);
+        }
+        return;
+    }
+    for (int o = threadIdx.x; o < span; o += blockDim.x) {
+        const float v = o < valid ? scratch[o] : 0.0f;
+        const int r = span_row(a, o);
+        Conv::store(rows, r * a.S + (o - r * a.H), v, lo_off);
+    }
+}
+
 // ------------------------------------------------------------------ FP32 frame-split kernel
 //
 // 4 waves, one per SIMD; each wave owns 32 frames of the 128-frame chunk and computes all
@@ -359,17 +484,20 @@ __device__ __forceinline__ void stage_span(const FwdArgs &a, const Chunk &ch, ty
 // flight into registers (PRE per thread); it is written to LDS after the loop.
 template <int RTB, int PRE>
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
-void k_melt_f32_fs(FwdArgs a, const f32x4 *__restrict__ bpack, GroupTableBig gt) {
+void k_melt_f32_fs(FwdArgs a, const f32x4 *__restrict__ bpack, int NG) {
     extern __shared__ float lds[];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int nch = *a.n_chunks;
-    const int NG = gt.n;
+    const int GH = a.Hp / 8;     // k-groups per full hop segment
     zero_pad_columns<ConvF32>(a, kChunkF32 + a.J - 1, lds, 256, 0);
+    // basis as a buffer: one VGPR offset per row tile, the k-group as a scalar offset
+    const __amdgpu_buffer_rsrc_t brs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)bpack, (short)0, a.row_tiles * NG * 64 * 16, 0x00020000);
     float pf[PRE];
     int c = blockIdx.x;
     Chunk nxt;
     if (c < nch) {
-        nxt = a.chunks[c];
+        nxt = read_chunk(a.chunks, c);
         span_load<PRE, 256>(a, nxt, pf);
     }
     for (; c < nch; c += gridDim.x) {
@@ -377,43 +505,114 @@ void k_melt_f32_fs(FwdArgs a, const f32x4 *__restrict__ bpack, GroupTableBig gt)
         __syncthreads();
         span_store<ConvF32, PRE, 256>(a, ch, pf, lds, 0);
         __syncthreads();
-        if (c + (int)gridDim.x < nch) {
-            nxt = a.chunks[c + gridDim.x];
-            span_load<PRE, 256>(a, nxt, pf);
-        }
+        const bool more = c + (int)gridDim.x < nch;
+        if (more) nxt = read_chunk(a.chunks, c + gridDim.x);
         const int fbase = wid * 32;
-        if (fbase >= ch.n_frames) continue;
+        if (fbase >= ch.n_frames) {
+            if (more) span_load<PRE, 256>(a, nxt, pf);
+            continue;
+        }
         const float *lp = lds + (fbase + (lane & 31)) * a.S + 4 * (lane >> 5);
         for (int rb = 0; rb < a.row_tiles; rb += RTB) {
             f32x16 acc[RTB];
 #pragma unroll
             for (int r = 0; r < RTB; ++r) acc[r] = f32x16{};
-            const f32x4 *bp = bpack + (size_t)rb * NG * 64 + lane;
-            f32x4 acur[RTB], anxt[RTB];
+            int voff[RTB];
 #pragma unroll
-            for (int r = 0; r < RTB; ++r) acur[r] = (rb + r < a.row_tiles) ? bp[(size_t)r * NG * 64] : f32x4{};
-            f32x4 bcur = *(const f32x4 *)(lp + gt.lds_off[0]), bnxt;
-            for (int g = 0; g < NG; ++g) {
-                if (g + 1 < NG) {
+            for (int r = 0; r < RTB; ++r) voff[r] = ((min(rb + r, a.row_tiles - 1) * NG) * 64 + lane) * 16;
+            // operands of k-group g: basis fragments of the RTB row tiles, and the frame
+            // fragment at LDS offset (g / GH) S + 8 (g % GH)
+            auto load = [&](f32x4 (&A)[RTB], f32x4 &B, int g) {
+                const int j = g / GH;
 #pragma unroll
-                    for (int r = 0; r < RTB; ++r)
-                        anxt[r] = (rb + r < a.row_tiles) ? bp[((size_t)r * NG + g + 1) * 64] : f32x4{};
-                    bnxt = *(const f32x4 *)(lp + gt.lds_off[g + 1]);
-                }
+                for (int r = 0; r < RTB; ++r)
+                    A[r] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(brs, voff[r], g * 1024, 0));
+                B = *(const f32x4 *)(lp + j * a.S + 8 * (g - j * GH));
+            };
+            auto mma = [&](const f32x4 (&A)[RTB], const f32x4 &B) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
                     for (int r = 0; r < RTB; ++r)
-                        acc[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(acur[r][i], bcur[i], acc[r], 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < RTB; ++r) acur[r] = anxt[r];
-                bcur = bnxt;
+                        acc[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[r][i], B[i], acc[r], 0, 0, 0);
+            };
+            f32x4 A0[RTB], A1[RTB], B0, B1;
+            load(A0, B0, 0);
+            for (int g = 0; g < NG; g += 2) {
+                // ping-pong: the next group's loads are in flight while this group multiplies;
+                // indices past the end are clamped so every load is unconditional.  The
+                // scheduling barriers keep each load block above the MFMAs it overlaps.
+                load(A1, B1, min(g + 1, NG - 1));
+                __builtin_amdgcn_sched_barrier(0);
+                mma(A0, B0);
+                __builtin_amdgcn_sched_barrier(0);
+                load(A0, B0, min(g + 2, NG - 1));
+                __builtin_amdgcn_sched_barrier(0);
+                // past the last group the B fragment is zeroed instead of branching, so the
+                // loads above cannot be sunk into a conditional block
+                const float keep = (g + 1 < NG) ? 1.0f : 0.0f;
+                B1 *= keep;
+                mma(A1, B1);
+                __builtin_amdgcn_sched_barrier(0);
             }
+            // the next chunk's span is requested only after the last basis wait of the
+            // last row block: vmcnt drains in order, so loads issued earlier would hold up
+            // every basis wait; here their latency overlaps the epilogue instead
+            if (more && rb + RTB >= a.row_tiles) span_load<PRE, 256>(a, nxt, pf);
 #pragma unroll
             for (int r = 0; r < RTB; ++r)
                 if (rb + r < a.row_tiles) store_tile(a, ch, rb + r, fbase + (lane & 31), lane, acc[r]);
         }
     }
+}
+
+// ------------------------------------------------------------------ 16-bit register-tile MFMA sweep
+//
+// Two 32-frame tiles (LDS rows at l0 and l1) against a wave's basis tile held in registers:
+// NS k-groups of 16, one v_mfma_f32_32x32x16 per tile and group.  The frame fragments are
+// read D groups ahead into a ring of registers, and scheduling barriers keep each group's
+// reads above the multiplies they overlap, so LDS latency hides behind D groups of MFMAs.
+// X3 adds hi*lo + lo*hi products from the low parts (basis in Al, frames at lo_off).
+template <int NS, bool X3, bool IS_F16>
+__device__ __forceinline__ void mfma_sweep(const uint4 (&A)[NS], const uint4 (&Al)[X3 ? NS : 1],
+                                           const unsigned short *l0, const unsigned short *l1,
+                                           const GroupTableBig &gt, int lo_off, f32x16 &acc0, f32x16 &acc1) {
+    constexpr int D = X3 ? 1 : 4;
+    uint4 b0[D], b1[D], c0[X3 ? D : 1], c1[X3 ? D : 1];
+    auto fetch = [&](int s, int slot) {
+        const int o = gt.lds_off[s];
+        b0[slot] = *(const uint4 *)(l0 + o);
+        b1[slot] = *(const uint4 *)(l1 + o);
+        if constexpr (X3) {
+            c0[slot] = *(const uint4 *)(l0 + lo_off + o);
+            c1[slot] = *(const uint4 *)(l1 + lo_off + o);
+        }
+    };
+#pragma unroll
+    for (int s = 0; s < D && s < NS; ++s) fetch(s, s);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int slot = s % D;
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (IS_F16) {
+            const f16x8 av = __builtin_bit_cast(f16x8, A[s]);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, __builtin_bit_cast(f16x8, b0[slot]), acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, __builtin_bit_cast(f16x8, b1[slot]), acc1, 0, 0, 0);
+        } else {
+            const bf16x8 av = __builtin_bit_cast(bf16x8, A[s]);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, b0[slot]), acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, b1[slot]), acc1, 0, 0, 0);
+            if constexpr (X3) {
+                const bf16x8 al = __builtin_bit_cast(bf16x8, Al[s]);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, __builtin_bit_cast(bf16x8, b0[slot]), acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, __builtin_bit_cast(bf16x8, b1[slot]), acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, c0[slot]), acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, c1[slot]), acc1, 0, 0, 0);
+            }
+        }
+        if (s + D < NS) fetch(s + D, slot);
+    }
+    __builtin_amdgcn_sched_barrier(0);
 }
 
 // ------------------------------------------------------------------ 16-bit row-split kernel
@@ -441,7 +640,7 @@ __global__ __launch_bounds__(512) void k_melt_h16_rs(FwdArgs a, const uint4 *__r
     zero_pad_columns<Conv>(a, bf + a.J - 1, lds16, nthreads, lo_off);
     const int nch = *a.n_chunks;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
-        const Chunk ch = a.chunks[c];
+        const Chunk ch = read_chunk(a.chunks, c);
         __syncthreads();
         stage_span<Conv, 8>(a, ch, lds16, nthreads, lo_off);
         __syncthreads();
@@ -450,31 +649,9 @@ __global__ __launch_bounds__(512) void k_melt_h16_rs(FwdArgs a, const uint4 *__r
             const bool two = ft + 1 < nft;
             f32x16 acc0 = f32x16{}, acc1 = f32x16{};
             const unsigned short *l0 = lds16 + (ft * 32 + (lane & 31)) * a.S + 8 * (lane >> 5);
-            const unsigned short *l1 = l0 + 32 * a.S;
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const int o = gt.lds_off[s];
-                const uint4 b0 = *(const uint4 *)(l0 + o);
-                const uint4 b1 = two ? *(const uint4 *)(l1 + o) : uint4{};
-                if constexpr (IS_F16) {
-                    const f16x8 av = __builtin_bit_cast(f16x8, A[s]);
-                    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, __builtin_bit_cast(f16x8, b0), acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, __builtin_bit_cast(f16x8, b1), acc1, 0, 0, 0);
-                } else {
-                    const bf16x8 av = __builtin_bit_cast(bf16x8, A[s]);
-                    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, b0), acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, b1), acc1, 0, 0, 0);
-                    if constexpr (X3) {
-                        const uint4 c0 = *(const uint4 *)(l0 + lo_off + o);
-                        const uint4 c1 = two ? *(const uint4 *)(l1 + lo_off + o) : uint4{};
-                        const bf16x8 al = __builtin_bit_cast(bf16x8, Al[s]);
-                        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, __builtin_bit_cast(bf16x8, b0), acc0, 0, 0, 0);
-                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, __builtin_bit_cast(bf16x8, b1), acc1, 0, 0, 0);
-                        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, c0), acc0, 0, 0, 0);
-                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, c1), acc1, 0, 0, 0);
-                    }
-                }
-            }
+            // a lone last tile multiplies its own rows twice rather than branching
+            const unsigned short *l1 = two ? l0 + 32 * a.S : l0;
+            mfma_sweep<NS, X3, IS_F16>(A, Al, l0, l1, gt, lo_off, acc0, acc1);
             store_tile(a, ch, rt, ft * 32 + (lane & 31), lane, acc0);
             if (two) store_tile(a, ch, rt, (ft + 1) * 32 + (lane & 31), lane, acc1);
         }
@@ -557,7 +734,7 @@ __global__ __launch_bounds__(512) void k_melt_f8_rs(FwdArgs a, const i32x8 *__re
     zero_pad_columns<ConvF32>(a, rows_max, xs, nthreads, 0);
     const int nch = *a.n_chunks;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
-        const Chunk ch = a.chunks[c];
+        const Chunk ch = read_chunk(a.chunks, c);
         __syncthreads();
         stage_span<ConvF32, 8>(a, ch, xs, nthreads, 0);
         __syncthreads();
@@ -637,6 +814,51 @@ __global__ __launch_bounds__(512) void k_melt_f8_rs(FwdArgs a, const i32x8 *__re
     }
 }
 
+// Row-split 16-bit kernel with direct-to-LDS staging (default for BF16/FP16/BF16X3): as
+// k_melt_h16_rs, but chunk c+1's span is copied into an FP32 scratch area while chunk c is
+// multiplied; after a barrier all threads convert it into the operand rows.
+template <class Conv, int NS, bool X3, bool IS_F16>
+__global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__restrict__ bhi,
+                                                     const uint4 *__restrict__ blo, GroupTableBig gt, int bf,
+                                                     int scr_off) {
+    extern __shared__ float lds_as[];
+    const int lane = threadIdx.x & 63, rt = threadIdx.x >> 6;
+    const int lo_off = a.S * (bf + a.J - 1);
+    unsigned short *rows = reinterpret_cast<unsigned short *>(lds_as);
+    float *scratch = lds_as + scr_off;             // FP32 span, after the operand rows
+    zero_pad_columns<Conv>(a, bf + a.J - 1, rows, blockDim.x, lo_off);
+    uint4 A[NS];
+    uint4 Al[X3 ? NS : 1];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) A[s] = bhi[((size_t)rt * NS + s) * 64 + lane];
+    if constexpr (X3) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) Al[s] = blo[((size_t)rt * NS + s) * 64 + lane];
+    }
+    const int nch = *a.n_chunks;
+    int c = blockIdx.x;
+    if (c < nch) async_span(a, read_chunk(a.chunks, c), scratch);
+    for (; c < nch; c += gridDim.x) {
+        const Chunk ch = read_chunk(a.chunks, c);
+        async_wait();
+        __syncthreads();                           // span of chunk c is in scratch; rows are free
+        convert_span<Conv>(a, ch, scratch, rows, lo_off);
+        __syncthreads();                           // rows ready; scratch is free
+        if (c + (int)gridDim.x < nch) async_span(a, read_chunk(a.chunks, c + gridDim.x), scratch);
+        const int nft = (ch.n_frames + 31) >> 5;
+        for (int ft = 0; ft < nft; ft += 2) {
+            const bool two = ft + 1 < nft;
+            f32x16 acc0 = f32x16{}, acc1 = f32x16{};
+            const unsigned short *l0 = rows + (ft * 32 + (lane & 31)) * a.S + 8 * (lane >> 5);
+            // a lone last tile multiplies its own rows twice rather than branching
+            const unsigned short *l1 = two ? l0 + 32 * a.S : l0;
+            mfma_sweep<NS, X3, IS_F16>(A, Al, l0, l1, gt, lo_off, acc0, acc1);
+            store_tile(a, ch, rt, ft * 32 + (lane & 31), lane, acc0);
+            if (two) store_tile(a, ch, rt, (ft + 1) * 32 + (lane & 31), lane, acc1);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ 16-bit frame-split kernel
 // Fallback for frame lengths whose basis tile does not fit in registers: as the FP32
 // frame-split kernel, one 32x32x16 MFMA per k-group.
@@ -649,7 +871,7 @@ __global__ __launch_bounds__(256, 1) void k_melt_h16_fs(FwdArgs a, const uint4 *
     const int NG = gt.n;
     zero_pad_columns<Conv>(a, kChunkF32 + a.J - 1, lds16, 256, 0);
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
-        const Chunk ch = a.chunks[c];
+        const Chunk ch = read_chunk(a.chunks, c);
         __syncthreads();
         stage_span<Conv, 8>(a, ch, lds16, 256, 0);
         __syncthreads();
@@ -804,7 +1026,10 @@ melt_status launch_schedule(Plan &p, int which, const int64_t *d_off, int n_clip
     k_schedule<<<1, 1024, 0, s>>>(d_off, n_clips, p.N, p.H, bf, p.d_chunks[which], p.chunk_cap[which],
                                   p.d_nchunks + which);
     st = hip_check(hipGetLastError(), "schedule launch");
-    if (st == MELT_OK) p.prepared_frames[which] = n_frames;
+    if (st == MELT_OK) {
+        p.prepared_frames[which] = n_frames;
+        if (which == 0) p.prepared_variant = p.tune_variant;
+    }
     return st;
 }
 
@@ -813,37 +1038,81 @@ melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H
     return hip_check(hipGetLastError(), "frame offsets launch");
 }
 
-// Kernel variants.  FP32: frame-split (basis streamed).  BF16/FP16/BF16X3: row-split
-// (basis in registers) when a register tile exists for the frame geometry, else the
-// 16-bit frame-split kernel (not for BF16X3).
-static bool use_row_split(const Plan &p) {
-    const int prec = p.cfg.precision;
-    if (prec == MELT_PREC_FP32 || prec == MELT_PREC_FP8_E4M3) return false;
-    if (!(rs_supported(p.geo16.n_groups) && p.row_tiles <= 8)) return false;
-    return prec == MELT_PREC_BF16X3 || p.tune_h16 == 0;
+// Kernel variants of a plan, in the order the autotuner times them (p.tune_variant selects;
+// the first one is the default):
+//   FP32       frame-split with register prefetch
+//   BF16/FP16  row-split with direct-to-LDS staging (128- then 64-frame chunks), row-split
+//              with register staging, frame-split (the only one when the frame is too long
+//              for a register tile)
+//   BF16X3     row-split with direct-to-LDS staging (96- then 64-frame chunks), row-split
+//              with register staging
+//   FP8        row-split
+enum VariantKind { V_F32_FS, V_H16_AS, V_H16_RS, V_H16_FS, V_F8_RS };
+struct Variant {
+    VariantKind kind;
+    int bf;          // frames per chunk
+};
+
+static bool rs_fits(const Plan &p) { return rs_supported(p.geo16.n_groups) && p.row_tiles <= 8; }
+
+// LDS of the direct-to-LDS 16-bit kernel: operand rows, then the FP32 span scratch (16-byte aligned)
+static size_t as_rows_bytes(const Plan &p, int bf) {
+    const bool x3 = p.cfg.precision == MELT_PREC_BF16X3;
+    return (size_t)(bf + p.geo16.J - 1) * lds_stride(p.geo16.Hp, 2) * 2 * (x3 ? 2 : 1);
+}
+static size_t as_lds_bytes(const Plan &p, int bf) {
+    return ((as_rows_bytes(p, bf) + 15) & ~size_t(15)) + (size_t)(bf + p.geo16.J - 1) * p.H * 4;
 }
 
-int forward_variants(const Plan &p) {
-    if (p.cfg.precision == MELT_PREC_FP32 || p.cfg.precision == MELT_PREC_BF16X3 ||
-        p.cfg.precision == MELT_PREC_FP8_E4M3)
-        return 1;
-    return rs_supported(p.geo16.n_groups) && p.row_tiles <= 8 ? 2 : 1;
+static std::vector<Variant> variant_list(const Plan &p) {
+    std::vector<Variant> v;
+    switch (p.cfg.precision) {
+    case MELT_PREC_FP32: v.push_back({V_F32_FS, kBF32}); break;
+    case MELT_PREC_FP8_E4M3: v.push_back({V_F8_RS, kBF32}); break;
+    default: {
+        const bool x3 = p.cfg.precision == MELT_PREC_BF16X3;
+        if (rs_fits(p)) {
+            for (int bf : {128, 96, 64}) {
+                if (bf == (x3 ? 128 : 96)) continue;
+                if (as_lds_bytes(p, bf) <= (size_t)kMaxLds) v.push_back({V_H16_AS, bf});
+            }
+            v.push_back({V_H16_RS, 128});
+        }
+        if (!x3) v.push_back({V_H16_FS, kBF32});
+    }
+    }
+    return v;
 }
 
-const char *forward_variant_name(const Plan &p, int v) {
-    if (p.cfg.precision == MELT_PREC_FP32) return "f32-frame-split";
-    if (p.cfg.precision == MELT_PREC_FP8_E4M3) return "f8-row-split";
-    if (rs_supported(p.geo16.n_groups) && p.row_tiles <= 8 && v == 0) return "h16-row-split";
-    return "h16-frame-split";
+static Variant variant_at(const Plan &p, int i) {
+    const std::vector<Variant> v = variant_list(p);
+    if (v.empty()) return {V_H16_FS, kBF32};      // unsupported geometry: the launch reports it
+    return v[i >= 0 && (size_t)i < v.size() ? i : 0];
 }
 
-int melt_chunk_frames(const Plan &p) { return use_row_split(p) ? 128 : kBF32; }
+int forward_variants(const Plan &p) { return (int)variant_list(p).size(); }
+
+const char *forward_variant_name(const Plan &p, int i) {
+    static thread_local char buf[64];
+    const std::vector<Variant> v = variant_list(p);
+    if (i < 0 || (size_t)i >= v.size()) return "none";
+    const char *k = v[i].kind == V_F32_FS   ? "f32-frame-split"
+                    : v[i].kind == V_H16_AS ? "h16-row-split-lds-dma"
+                    : v[i].kind == V_H16_RS ? "h16-row-split"
+                    : v[i].kind == V_H16_FS ? "h16-frame-split"
+                                            : "f8-row-split";
+    std::snprintf(buf, sizeof(buf), "%s-bf%d", k, v[i].bf);
+    return buf;
+}
+
+int melt_chunk_frames(const Plan &p, int variant) { return variant_at(p, variant).bf; }
+int melt_chunk_frames(const Plan &p) { return melt_chunk_frames(p, p.tune_variant); }
 
 template <int RTB, int PRE>
 static melt_status launch_f32_pre(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid,
                                   hipStream_t s) {
     allow_lds(k_melt_f32_fs<RTB, PRE>);
-    k_melt_f32_fs<RTB, PRE><<<grid, 256, lds, s>>>(a, (const f32x4 *)p.d_pack_f32, gt);
+    k_melt_f32_fs<RTB, PRE><<<grid, 256, lds, s>>>(a, (const f32x4 *)p.d_pack_f32, gt.n);
     return hip_check(hipGetLastError(), "melt f32 launch");
 }
 
@@ -882,6 +1151,28 @@ static melt_status launch_f8(Plan &p, const FwdArgs &a, size_t lds, int grid, in
     return hip_check(hipGetLastError(), "melt f8 launch");
 }
 
+template <class Conv, int NS, bool X3, bool F16>
+static melt_status launch_as_ns(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+                                int scr_off, hipStream_t s) {
+    allow_lds(k_melt_h16_as<Conv, NS, X3, F16>);
+    k_melt_h16_as<Conv, NS, X3, F16><<<grid, 64 * p.row_tiles, lds, s>>>(
+        a, (const uint4 *)p.d_pack_h16, (const uint4 *)p.d_pack_lo, gt, bf, scr_off);
+    return hip_check(hipGetLastError(), "melt h16 lds-dma launch");
+}
+
+template <class Conv, bool X3, bool F16>
+static melt_status launch_as(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+                             int scr_off, hipStream_t s) {
+    switch (p.geo16.n_groups) {
+    case 10: return launch_as_ns<Conv, 10, X3, F16>(p, a, gt, lds, grid, bf, scr_off, s);
+    case 16: return launch_as_ns<Conv, 16, X3, F16>(p, a, gt, lds, grid, bf, scr_off, s);
+    case 20: return launch_as_ns<Conv, 20, X3, F16>(p, a, gt, lds, grid, bf, scr_off, s);
+    case 25: return launch_as_ns<Conv, 25, X3, F16>(p, a, gt, lds, grid, bf, scr_off, s);
+    case 32: return launch_as_ns<Conv, 32, X3, F16>(p, a, gt, lds, grid, bf, scr_off, s);
+    default: return set_error(MELT_E_UNSUPPORTED, "no register tile for this frame length");
+    }
+}
+
 template <class Conv, bool X3, bool F16>
 static melt_status launch_rs(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
                              hipStream_t s) {
@@ -899,12 +1190,13 @@ melt_status launch_melt_main(Plan &p, const float *d_wave, float *d_out, float *
     const int64_t n_frames = p.prepared_frames[0];
     if (n_frames < 0) return set_error(MELT_E_INVALID_ARG, "no batch prepared");
     if (n_frames == 0) return MELT_OK;
-    return launch_melt_table(p, p.d_chunks[0], p.d_nchunks, n_frames / melt_chunk_frames(p) + 1, n_frames, d_wave,
-                             d_out, d_proj, s);
+    const int v = p.prepared_variant;
+    return launch_melt_table(p, v, p.d_chunks[0], p.d_nchunks, n_frames / melt_chunk_frames(p, v) + 1, n_frames,
+                             d_wave, d_out, d_proj, s);
 }
 
-melt_status launch_melt_table(Plan &p, const Chunk *tab, const int *n_tab, int64_t est_chunks, int64_t n_frames,
-                              const float *d_wave, float *d_out, float *d_proj, hipStream_t s) {
+melt_status launch_melt_table(Plan &p, int variant, const Chunk *tab, const int *n_tab, int64_t est_chunks,
+                              int64_t n_frames, const float *d_wave, float *d_out, float *d_proj, hipStream_t s) {
     const int prec = p.cfg.precision;
     if (prec == MELT_PREC_FP32) {
         const Geometry &g = p.geo32;
@@ -916,9 +1208,8 @@ melt_status launch_melt_table(Plan &p, const Chunk *tab, const int *n_tab, int64
         const GroupTableBig gt = make_table(g, S);
         const int64_t est = est_chunks;
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, (int64_t)p.cu_count * grid_mult(p, 1)));
-        // row tiles per block: at most 5 (2 for the deepest prefetch) so the accumulators,
-        // the basis prefetch and the sample prefetch fit one wave's 512 registers; blocks
-        // of equal size
+        // register-prefetch variant: row tiles per block at most 5 (2 for the deepest
+        // prefetch) so accumulators, basis prefetch and sample prefetch fit 512 registers
         const int need = ((kBF32 + g.J - 1) * p.H + 255) / 256;
         const int cap = need <= 88 ? 5 : 2;
         const int blocks = (p.row_tiles + cap - 1) / cap;
@@ -938,13 +1229,26 @@ melt_status launch_melt_table(Plan &p, const Chunk *tab, const int *n_tab, int64
         if (g.n_groups > 512) return set_error(MELT_E_UNSUPPORTED, "frame too long");
         const FwdArgs a = make_args(p, g, S, d_wave, d_out, d_proj, n_frames, tab, n_tab);
         const GroupTableBig gt = make_table(g, S);
-        if (use_row_split(p)) {
-            const int bf = 128;
+        const Variant var = variant_at(p, variant);
+        if (var.kind == V_H16_AS) {
+            const int bf = var.bf;
+            const size_t lds = as_lds_bytes(p, bf);
+            if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
+            const int scr_off = (int)(((as_rows_bytes(p, bf) + 15) & ~size_t(15)) / 4);
+            const int per_cu = std::max(1, (int)(kMaxLds / lds));
+            const int grid = (int)std::max<int64_t>(
+                1, std::min<int64_t>(est_chunks, (int64_t)p.cu_count * grid_mult(p, std::min(per_cu, 2))));
+            if (x3) return launch_as<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, scr_off, s);
+            if (f16) return launch_as<ConvF16, false, true>(p, a, gt, lds, grid, bf, scr_off, s);
+            return launch_as<ConvBF16, false, false>(p, a, gt, lds, grid, bf, scr_off, s);
+        }
+        if (var.kind == V_H16_RS) {
+            const int bf = var.bf;
             const size_t lds = (size_t)(bf + g.J - 1) * S * 2 * (x3 ? 2 : 1);
             if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
             const int per_cu = std::max(1, (int)(kMaxLds / lds));
-            const int64_t est = est_chunks;
-            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, (int64_t)p.cu_count * grid_mult(p, std::min(per_cu, 2))));
+            const int grid = (int)std::max<int64_t>(
+                1, std::min<int64_t>(est_chunks, (int64_t)p.cu_count * grid_mult(p, std::min(per_cu, 2))));
             if (x3) return launch_rs<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, s);
             if (f16) return launch_rs<ConvF16, false, true>(p, a, gt, lds, grid, bf, s);
             return launch_rs<ConvBF16, false, false>(p, a, gt, lds, grid, bf, s);

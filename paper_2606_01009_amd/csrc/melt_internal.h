@@ -73,6 +73,7 @@ struct Plan {
     int *d_nchunks = nullptr;          // [2]
     int64_t chunk_cap[2] = {0, 0};
     int64_t prepared_frames[2] = {-1, -1};   // n_frames of the batch each table describes
+    int prepared_variant = 0;                // kernel variant table 0 was built for
     // backward: dx basis layout and workspaces (grown on demand)
     void *d_pack_dx = nullptr;
     size_t pack_dx_cap = 0;
@@ -82,7 +83,7 @@ struct Plan {
     size_t bwd_rows_cap = 0;
     // tuning
     int cu_count = 256;
-    int tune_f32 = 0, tune_h16 = 0, tune_f8 = 0;   // index of the chosen kernel variant
+    int tune_variant = 0;                          // index of the chosen kernel variant
     int tune_grid = 0;                             // workgroups per CU (0 = kernel default)
     std::string last_tune;
 };
@@ -103,15 +104,17 @@ melt_status launch_schedule(Plan &p, int which, const int64_t *d_off, int n_clip
                             hipStream_t s);
 melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H, int64_t *d_fo,
                                  hipStream_t s);
-// chunk size (frames) of the MelT kernel for the plan's precision / of the comparator
+// chunk size (frames) of MelT kernel variant v / of the plan's chosen variant / of the comparator
+int melt_chunk_frames(const Plan &p, int variant);
 int melt_chunk_frames(const Plan &p);
 int stft_chunk_frames(const Plan &p);
 // main kernels over the batch prepared in table 0 / table 1
 melt_status launch_melt_main(Plan &p, const float *d_wave, float *d_out, float *d_proj, hipStream_t s);
 melt_status launch_stft_main(Plan &p, const float *d_wave, float *d_out, hipStream_t s);
-// main MelT kernel over an explicit chunk table (streaming); est_chunks sizes the grid
-melt_status launch_melt_table(Plan &p, const Chunk *tab, const int *n_tab, int64_t est_chunks, int64_t n_frames,
-                              const float *d_wave, float *d_out, float *d_proj, hipStream_t s);
+// main MelT kernel (variant v) over an explicit chunk table built with that variant's chunk
+// size (streaming); est_chunks sizes the grid
+melt_status launch_melt_table(Plan &p, int variant, const Chunk *tab, const int *n_tab, int64_t est_chunks,
+                              int64_t n_frames, const float *d_wave, float *d_out, float *d_proj, hipStream_t s);
 int forward_variants(const Plan &p);
 void apply_tune_cache(Plan &p);          // stream.hip: apply a MELT_AUTOTUNE_CACHE entry
 const char *forward_variant_name(const Plan &p, int variant);

@@ -20,7 +20,7 @@
 
 struct melt_stream_s {
     melt::Plan *plan;
-    int n_streams, max_chunk, max_frames, cps, bf;
+    int n_streams, max_chunk, max_frames, cps, bf, variant;
     int asm_stride;             // samples per stream in the assembly buffer
     float *d_carry;             // [n_streams][N]
     int *d_carry_len;           // [n_streams]
@@ -129,8 +129,7 @@ void apply_tune_cache(Plan &p) {
     int v = 0, g = 0;
     if (cache_lookup(path, tune_key(p), v, g)) {
         if (v >= 0 && v < forward_variants(p)) {
-            p.tune_h16 = v;
-            p.tune_f32 = v;
+            p.tune_variant = v;
         }
         if (g >= 0 && g <= 4) p.tune_grid = g;
     }
@@ -155,7 +154,8 @@ melt_status melt_stream_create(melt_plan plan, int32_t n_streams, int32_t max_ch
     S->n_streams = n_streams;
     S->max_chunk = max_chunk_len;
     S->max_frames = (max_chunk_len - 1) / p->H + 1;
-    S->bf = melt_chunk_frames(*p);
+    S->variant = p->tune_variant;     // kept for the life of the state
+    S->bf = melt_chunk_frames(*p, S->variant);
     S->cps = (S->max_frames + S->bf - 1) / S->bf;
     // assembly stride: carry (< N) + chunk + the J - 1 hop rows a chunk's span may reach past
     // its last frame; multiple of 4 samples
@@ -211,12 +211,32 @@ melt_status melt_stream_push(melt_stream_state S, const float *d_chunk, int32_t 
                                                    d_frames_emitted, S->n_streams);
     st = hip_check(hipGetLastError(), "stream assemble");
     if (st != MELT_OK) return st;
-    st = launch_melt_table(p, S->d_tab, S->d_ntab, (int64_t)S->n_streams * S->cps,
+    st = launch_melt_table(p, S->variant, S->d_tab, S->d_ntab, (int64_t)S->n_streams * S->cps,
                            (int64_t)S->n_streams * S->max_frames, S->d_asm, d_out, nullptr, s);
     if (st != MELT_OK) return st;
     k_stream_keep<<<S->n_streams, 256, 0, s>>>(chunk_len, S->d_carry, S->d_carry_len, p.N, p.H, S->d_asm,
                                                S->asm_stride);
     return hip_check(hipGetLastError(), "stream keep");
+}
+
+int32_t melt_variant_count(melt_plan plan) {
+    const Plan *p = reinterpret_cast<const Plan *>(plan);
+    return p ? forward_variants(*p) : 0;
+}
+
+const char *melt_variant_name(melt_plan plan, int32_t v) {
+    const Plan *p = reinterpret_cast<const Plan *>(plan);
+    return p ? forward_variant_name(*p, v) : "none";
+}
+
+melt_status melt_set_variant(melt_plan plan, int32_t v, int32_t grid_per_cu) {
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (!p) return set_error(MELT_E_INVALID_ARG, "plan is NULL");
+    if (v < 0 || v >= forward_variants(*p)) return set_error(MELT_E_INVALID_ARG, "variant out of range");
+    if (grid_per_cu < 0 || grid_per_cu > 4) return set_error(MELT_E_INVALID_ARG, "grid_per_cu must be in [0, 4]");
+    p->tune_variant = v;
+    p->tune_grid = grid_per_cu;
+    return MELT_OK;
 }
 
 melt_status melt_autotune(melt_plan plan, int64_t total_frames, char *desc, int32_t desc_len) {
@@ -240,14 +260,14 @@ melt_status melt_autotune(melt_plan plan, int64_t total_frames, char *desc, int3
     ok = ok && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
     if (ok) ok = hipMemset(d_wave, 0, sizeof(float) * off[n_clips]) == hipSuccess &&
                  hipMemcpy(d_off, off.data(), sizeof(int64_t) * (n_clips + 1), hipMemcpyHostToDevice) == hipSuccess;
-    const int save_v = p->tune_h16, save_g = p->tune_grid;
+    const int save_v = p->tune_variant, save_g = p->tune_grid;
     int best_v = save_v, best_g = save_g;
     double best_us = 1e300;
     std::string best_name;
     if (ok) {
         for (int v = 0; v < forward_variants(*p) && st == MELT_OK; ++v) {
             for (int g = 1; g <= 3 && st == MELT_OK; ++g) {
-                p->tune_h16 = p->tune_f32 = v;
+                p->tune_variant = v;
                 p->tune_grid = g;
                 st = launch_schedule(*p, 0, d_off, n_clips, melt_chunk_frames(*p), T, nullptr);
                 for (int w = 0; w < 2 && st == MELT_OK; ++w) st = launch_melt_main(*p, d_wave, d_out, nullptr, nullptr);
@@ -259,6 +279,8 @@ melt_status melt_autotune(melt_plan plan, int64_t total_frames, char *desc, int3
                 float ms = 0;
                 (void)hipEventElapsedTime(&ms, e0, e1);
                 const double us = ms * 1000.0 / 5;
+                if (std::getenv("MELT_AUTOTUNE_VERBOSE"))
+                    std::fprintf(stderr, "melt_autotune: %s grid=%d: %.1f us\n", forward_variant_name(*p, v), g, us);
                 if (us < best_us) {
                     best_us = us;
                     best_v = v;
@@ -268,7 +290,7 @@ melt_status melt_autotune(melt_plan plan, int64_t total_frames, char *desc, int3
             }
         }
     }
-    p->tune_h16 = p->tune_f32 = best_v;
+    p->tune_variant = best_v;
     p->tune_grid = best_g;
     p->prepared_frames[0] = -1;
     if (e0) (void)hipEventDestroy(e0);
@@ -278,7 +300,7 @@ melt_status melt_autotune(melt_plan plan, int64_t total_frames, char *desc, int3
     (void)hipFree(d_off);
     if (!ok) return set_error(MELT_E_NO_MEMORY, "autotune buffers");
     if (st != MELT_OK) {
-        p->tune_h16 = p->tune_f32 = save_v;
+        p->tune_variant = save_v;
         p->tune_grid = save_g;
         return st;
     }

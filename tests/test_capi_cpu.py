@@ -67,3 +67,6 @@ def test_null_arguments_rejected(lib):
     assert L.melt_plan_create(None, 0, None) == lib.MELT_E_INVALID_ARG
     assert L.melt_forward(None, None, None, 0, 0, None, None) == lib.MELT_E_INVALID_ARG
     assert L.melt_plan_destroy(None) == lib.MELT_OK
+    assert L.melt_variant_count(None) == 0
+    assert L.melt_variant_name(None, 0) == b"none"
+    assert L.melt_set_variant(None, 0, 0) == lib.MELT_E_INVALID_ARG

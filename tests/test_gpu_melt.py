@@ -117,6 +117,31 @@ def test_ragged_edge_cases(torch, melt, orc, prec):
     assert np.array_equal(L2, L[-L2.shape[0]:])
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp8"])
+def test_every_kernel_variant(torch, melt, orc, prec):
+    """Every kernel variant of the precision (staging scheme x frames per chunk), pinned with
+    melt_set_variant, on clips that end chunks of 64, 96 and 128 frames exactly, one frame
+    past them and mid-way.  Geometries: the 16 kHz front end (hop a multiple of 4: vector
+    span conversion), hop 50 (two-byte aligned rows: element-wise conversion) and N=480,
+    hop 161 (32 k-groups, odd hop)."""
+    geoms = [(16000, 400, 160, 80), (16000, 400, 50, 40), (16000, 480, 161, 64)]
+    if prec == "fp8":
+        geoms = geoms[:1]
+    for sr, N, H, M in geoms:
+        lengths = [0, N - 1, N, N + 1] + [(f - 1) * H + N + d for f in (64, 65, 96, 97, 128, 129, 200) for d in (0, 3)]
+        wave, off = workloads.random_clips(lengths, seed=N + H)
+        plan = melt.MeltPlan(sample_rate=sr, n_fft=N, hop=H, n_mels=M, precision=prec)
+        n = melt.melt_variant_count(plan.handle)
+        assert n >= 1
+        for v in range(n):
+            melt.melt_set_variant(plan.handle, v, 0)
+            name = melt.melt_variant_name(plan.handle, v)
+            L, _ = _gpu_forward(torch, melt, plan, wave, off)
+            _check(orc, melt, plan, L, wave, off, prec, label=f"N={N} H={H} {prec} {name}")
+        with pytest.raises(melt.MeltError):
+            melt.melt_set_variant(plan.handle, n, 0)
+
+
 @pytest.mark.parametrize("geom", [(16000, 512, 128, 128), (22050, 1024, 256, 128), (16000, 400, 100, 40),
                                   (8000, 256, 80, 24)])
 def test_other_geometries(torch, melt, orc, geom):
