@@ -106,7 +106,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="time only the FP32 MelT path and the comparator")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled error check")
-    ap.add_argument("--only", default=None, help="time one path only: fp32|bf16|fp16|bf16x3|fp8|stft (profiling)")
+    ap.add_argument("--only", default=None, help="time one path only: fp32|bf16|fp16|bf16x3|fp8|stft|copy (profiling)")
     ap.add_argument("--sweep", action="store_true", help="time every kernel variant of every precision and exit")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -170,6 +170,13 @@ def main():
     if args.only:
         if args.only == "stft":
             run_stft()
+        elif args.only == "copy":
+            # a plain elementwise copy of the waveform buffer (read + write of 122.9 MB per
+            # launch): the known-size kernel against which HBM traffic counters are scaled
+            dst = torch.empty_like(d_wave)
+            copy_ms = time_launches(torch, lambda: torch.mul(d_wave, 1.0, out=dst), args.steps, args.warmup)
+            log(f"bench: copy kernel {wave.nbytes / 1e6:.1f} MB read + written: {copy_ms * 1e3:.1f} us, "
+                f"{2 * wave.nbytes / (copy_ms * 1e-3) / 1e9:.0f} GB/s")
         else:
             run_melt(args.only)
         return 0

@@ -94,7 +94,7 @@ typedef struct {
     int32_t mel_formula;   /* melt_mel_formula */
     int32_t placement;     /* melt_freq_placement */
     int32_t output;        /* melt_output */
-    double  log_eps;       /* eps > 0 of the log kinds (default 1e-10) */
+    double  log_eps;       /* eps of the log kinds, >= 1.18e-38 (the smallest normal FP32; default 1e-10) */
     int32_t precision;     /* melt_precision of melt_forward */
     int32_t fb_norm;       /* melt_fb_norm of stft_mel_forward */
 } melt_config;

@@ -39,7 +39,9 @@ def build(verbose: bool = False, jobs: int | None = None) -> Path:
     """Compile every csrc source and link libmelt.so.  Always rebuilds."""
     OUT_DIR.mkdir(exist_ok=True)
     obj_dir = OUT_DIR / "obj"
-    obj_dir.mkdir(exist_ok=True)
+    if obj_dir.exists():
+        shutil.rmtree(obj_dir)          # objects of removed sources must not link
+    obj_dir.mkdir()
     srcs = sorted([p for p in CSRC.iterdir() if p.suffix in (".hip", ".cpp")])
     cc = hipcc()
 

@@ -32,7 +32,9 @@ static melt_status validate(const melt_config &c) {
     if (c.mel_formula < 0 || c.mel_formula > 1) return set_error(MELT_E_INVALID_ARG, "bad mel_formula");
     if (c.placement < 0 || c.placement > 1) return set_error(MELT_E_INVALID_ARG, "bad placement");
     if (c.output < 0 || c.output > 3) return set_error(MELT_E_INVALID_ARG, "bad output");
-    if (!(c.log_eps > 0.0) || !std::isfinite(c.log_eps)) return set_error(MELT_E_INVALID_ARG, "log_eps must be > 0");
+    // the log epilogues take the hardware logarithm of S + eps, which needs a normal FP32 argument
+    if (!(c.log_eps >= 1.1754943508222875e-38) || !std::isfinite(c.log_eps))
+        return set_error(MELT_E_INVALID_ARG, "log_eps must be >= 1.18e-38 (the smallest normal FP32)");
     if (c.precision < 0 || c.precision > 4) return set_error(MELT_E_INVALID_ARG, "bad precision");
     if (c.fb_norm < 0 || c.fb_norm > 1) return set_error(MELT_E_INVALID_ARG, "bad fb_norm");
     return MELT_OK;

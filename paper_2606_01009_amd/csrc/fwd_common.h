@@ -1,0 +1,564 @@
+// MelT forward on gfx950: implicit framing in LDS + basis GEMM on MFMA + fused energy/log.
+//
+// Eq. (dmp_projection): R = X W^(r)T, I = X W^(i)T; Eq. (dmp_matrix_energy): S = R.R + I.I;
+// Eq. (meltf): out = log(S + eps).  The GEMM is computed transposed, Y^T = W X^T, so that
+// MFMA A operand = basis rows and B operand = frames, and the accumulator of one lane holds
+// one frame's values for 16 basis rows.  The basis rows of a 32-row tile are permuted so
+// that those 16 rows are the cos/sin pairs of 8 consecutive Mel bins: R^2 + I^2 is formed
+// in-lane and each lane writes 8 consecutive outputs (two 16-byte stores).
+//
+// Frames are never materialised.  A chunk of up to BF consecutive frames of one clip needs
+// the contiguous sample span [start, start + (BF - 1) H + N); it is staged once into LDS
+// as "hop-block" rows (row r = samples [rH, rH + H), padded), and frame t is the
+// concatenation of the first L_j samples of rows t + j, j = 0..J-1.  Reading the B operand
+// of k-group (j, c) for the 32 frames of a tile is then 32 rows at one column: the padded
+// row stride makes those reads bank-conflict free even though frames overlap.
+//
+// This header holds what the forward kernels share: the chunk-table access, the argument
+// block, the fused energy/log epilogue, the operand formats, the span staging helpers and
+// the host-side geometry helpers.  The kernels live in melt_f32.hip, melt_h16.hip and
+// melt_f8.hip; melt_fwd.hip holds the schedule, the basis packing and the variant table.
+#pragma once
+#include <vector>
+#include "melt_internal.h"
+
+namespace melt {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+struct GroupTableBig {
+    int n;
+    int lds_off[512];
+};
+
+constexpr int kChunkF32 = 128;   // frames per chunk of the frame-split kernels (4 waves x 32)
+
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------------ basis row order and formats
+
+// Row permutation of a 32-row tile.  The 32x32 MFMA accumulator puts row
+// i = 8 g + 4 h + q (g = 0..3, h = lane / 32, q = 0..3) in register 4 g + q of lane half h.
+// Row i carries Mel bin 8 h + 2 g + q / 2 of the tile, cosine for even q, sine for odd q,
+// so register pairs (4g, 4g+1) and (4g+2, 4g+3) are (R, I) of consecutive Mel bins.
+__device__ inline void tile_row_to_mel(int i, int &mel_local, int &part) {
+    const int g = i >> 3, h = (i >> 2) & 1, q = i & 3;
+    mel_local = 8 * h + 2 * g + (q >> 1);
+    part = q & 1;
+}
+
+// Value of packed element (rt, group, lane, e): basis row (part, mel) at column
+// k = j H + c + (group_size / 2) * (lane / 32) + e, zero outside the segment / N / M.
+__device__ inline float packed_value(const float *__restrict__ b32, int M, int N, int H, int rt, int j, int c,
+                                     int half_group, int lane, int e) {
+    int mel_local, part;
+    tile_row_to_mel(lane & 31, mel_local, part);
+    const int mel = rt * 16 + mel_local;
+    const int col = c + half_group * (lane >> 5) + e;
+    const int Lj = min(H, N - j * H);
+    if (mel >= M || col >= Lj) return 0.0f;
+    return b32[(size_t)(part * M + mel) * N + j * H + col];
+}
+
+__device__ inline unsigned short f32_to_bf16_bits(float x) {
+    __bf16 b = (__bf16)x;
+    return __builtin_bit_cast(unsigned short, b);
+}
+__device__ inline unsigned short f32_to_f16_bits(float x) {
+    _Float16 h = (_Float16)x;
+    return __builtin_bit_cast(unsigned short, h);
+}
+__device__ inline float bf16_bits_to_f32(unsigned short u) {
+    return __builtin_bit_cast(float, (unsigned)u << 16);
+}
+
+// four FP32 values -> four E4M3 bytes (round to nearest even, saturating)
+__device__ __forceinline__ unsigned fp8x4(float a, float b, float c, float d) {
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+    return (unsigned)w;
+}
+
+// ------------------------------------------------------------------ shared device pieces
+
+// A chunk-table entry read into scalar registers (every lane of a workgroup uses the same
+// chunk, so buffer descriptors built from it need no waterfall loop).
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return (int64_t)(((uint64_t)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ Chunk read_chunk(const Chunk *tab, int c) {
+    Chunk e = tab[c];
+    e.sample_start = uniform64(e.sample_start);
+    e.sample_end = uniform64(e.sample_end);
+    e.out_row = uniform64(e.out_row);
+    e.n_frames = __builtin_amdgcn_readfirstlane(e.n_frames);
+    e.clip = __builtin_amdgcn_readfirstlane(e.clip);
+    return e;
+}
+
+struct FwdArgs {
+    const float *wave;
+    const Chunk *chunks;
+    const int *n_chunks;
+    float *out;
+    float *proj;
+    int64_t n_frames;
+    int M, J, H, Hp, S;    // S = LDS row stride in elements
+    int row_tiles;
+    int out_kind;
+    float eps;
+    float invH;            // 1 / H rounded to FP32 (row index of a span position)
+};
+
+// Natural log from the hardware base-2 logarithm (v_log_f32, about 1 ulp on normal
+// inputs) times ln 2.  Arguments are S + eps or sqrt(S) + eps with S >= 0 and eps >= the
+// smallest normal FP32 (the plan rejects smaller eps), so they are always normal.
+__device__ __forceinline__ float ln_normal(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
+
+__device__ inline float out_map(float S, int kind, float eps) {
+    switch (kind) {
+    case MELT_OUT_LOG_POWER: return ln_normal(S + eps);
+    case MELT_OUT_LOG_MAGNITUDE: return ln_normal(sqrtf(S) + eps);
+    case MELT_OUT_POWER: return S;
+    default: return sqrtf(S);
+    }
+}
+
+// Writes one 32-frame x 16-Mel tile from the accumulator of lane `lane` (frame
+// `f_local` of the chunk).  Register pairs (4g, 4g+1), (4g+2, 4g+3) are (R, I) of Mel bins
+// 8h + 2g and 8h + 2g + 1 of the tile.
+__device__ inline void store_tile(const FwdArgs &a, const Chunk &ch, int rt, int f_local, int lane,
+                                  const f32x16 &acc) {
+    if (f_local >= ch.n_frames) return;
+    const int64_t row = ch.out_row + f_local;
+    if (row >= a.n_frames) return;
+    const int h = lane >> 5;
+    const int mel0 = rt * 16 + 8 * h;
+    if (mel0 >= a.M) return;
+    float v[8];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        v[2 * g] = out_map(acc[4 * g] * acc[4 * g] + acc[4 * g + 1] * acc[4 * g + 1], a.out_kind, a.eps);
+        v[2 * g + 1] = out_map(acc[4 * g + 2] * acc[4 * g + 2] + acc[4 * g + 3] * acc[4 * g + 3], a.out_kind, a.eps);
+    }
+    float *o = a.out + row * a.M + mel0;
+    if (mel0 + 8 <= a.M && (a.M & 3) == 0) {
+        *(f32x4 *)o = f32x4{v[0], v[1], v[2], v[3]};
+        *(f32x4 *)(o + 4) = f32x4{v[4], v[5], v[6], v[7]};
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (mel0 + e < a.M) o[e] = v[e];
+    }
+    if (a.proj) {
+        float *p = a.proj + row * (2 * a.M) + 2 * mel0;
+        if (mel0 + 8 <= a.M && (a.M & 1) == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) *(f32x4 *)(p + 4 * q) = f32x4{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                if (mel0 + e / 2 < a.M) p[e] = acc[e];
+        }
+    }
+}
+
+// Operand formats of the staged frames.  store writes one element; store4 writes four
+// consecutive ones (i a multiple of 4).
+__device__ __forceinline__ unsigned pack2(unsigned short lo, unsigned short hi) { return lo | ((unsigned)hi << 16); }
+
+struct ConvF32 {
+    typedef float elem_t;
+    __device__ static void store(float *l, int i, float v, int) { l[i] = v; }
+    __device__ static void store4(float *l, int i, f32x4 v, int) { *(f32x4 *)(l + i) = v; }
+};
+struct ConvBF16 {
+    typedef unsigned short elem_t;
+    __device__ static void store(unsigned short *l, int i, float v, int) { l[i] = f32_to_bf16_bits(v); }
+    __device__ static void store4(unsigned short *l, int i, f32x4 v, int) {
+        *(uint2 *)(l + i) = uint2{pack2(f32_to_bf16_bits(v[0]), f32_to_bf16_bits(v[1])),
+                                  pack2(f32_to_bf16_bits(v[2]), f32_to_bf16_bits(v[3]))};
+    }
+};
+struct ConvF16 {
+    typedef unsigned short elem_t;
+    __device__ static void store(unsigned short *l, int i, float v, int) { l[i] = f32_to_f16_bits(v); }
+    __device__ static void store4(unsigned short *l, int i, f32x4 v, int) {
+        *(uint2 *)(l + i) = uint2{pack2(f32_to_f16_bits(v[0]), f32_to_f16_bits(v[1])),
+                                  pack2(f32_to_f16_bits(v[2]), f32_to_f16_bits(v[3]))};
+    }
+};
+// split-bf16: the high part at [i], the low part at [i + lo_off]
+struct ConvBF16X3 {
+    typedef unsigned short elem_t;
+    __device__ static void store(unsigned short *l, int i, float v, int lo_off) {
+        const unsigned short hb = f32_to_bf16_bits(v);
+        l[i] = hb;
+        l[i + lo_off] = f32_to_bf16_bits(v - bf16_bits_to_f32(hb));
+    }
+    __device__ static void store4(unsigned short *l, int i, f32x4 v, int lo_off) {
+        unsigned short h[4], r[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            h[e] = f32_to_bf16_bits(v[e]);
+            r[e] = f32_to_bf16_bits(v[e] - bf16_bits_to_f32(h[e]));
+        }
+        *(uint2 *)(l + i) = uint2{pack2(h[0], h[1]), pack2(h[2], h[3])};
+        *(uint2 *)(l + i + lo_off) = uint2{pack2(r[0], r[1]), pack2(r[2], r[3])};
+    }
+};
+
+// Register staging of a chunk's contiguous sample span [start, start + (n_frames + J - 1) H):
+// element u of a thread is span position o = tid + u * NT, so every load instruction of a
+// wave reads 64 consecutive samples.  span_load issues all PRE loads at once (one memory
+// round trip); span_store scatters them into the padded hop-block rows (row o / H, column
+// o % H).  Samples at or past the clip end read as 0.
+template <int PRE, int NT>
+__device__ __forceinline__ void span_load(const FwdArgs &a, const Chunk &ch, float (&pf)[PRE]) {
+    // buffer descriptor over [start, min(start + span, clip end)): loads past it return 0,
+    // so the clip end needs no branch; one VGPR offset serves all PRE loads
+    const int64_t start = ch.sample_start;
+    const int64_t span = (int64_t)(ch.n_frames + a.J - 1) * a.H;
+    const int64_t lim = ch.sample_end - start < span ? ch.sample_end - start : span;
+    const int records = (int)(lim > 0 ? lim * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(a.wave + start), (short)0, records, 0x00020000);
+    const int voff = (int)threadIdx.x * 4;
+#pragma unroll
+    for (int u = 0; u < PRE; ++u)
+        pf[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, u * NT * 4, 0));
+}
+
+__device__ __forceinline__ int span_row(const FwdArgs &a, int o) {
+    int r = (int)(((float)o + 0.5f) * a.invH);
+    const int c = o - r * a.H;
+    r += (c >= a.H) - (c < 0);
+    return r;
+}
+
+template <class Conv, int PRE, int NT>
+__device__ __forceinline__ void span_store(const FwdArgs &a, const Chunk &ch, const float (&pf)[PRE],
+                                           typename Conv::elem_t *lds, int lo_off) {
+    // element u of the thread is span position tid + u NT; its row and column advance by
+    // (dr, dc) per element, so no division per element
+    const int span = (ch.n_frames + a.J - 1) * a.H;
+    const int dr = NT / a.H, dc = NT - dr * a.H;
+    const int dad = dr * a.S + dc, wrap = a.S - a.H;
+    int c = (int)threadIdx.x;
+    const int r0 = span_row(a, c);
+    c -= r0 * a.H;
+    int ad = r0 * a.S + c;
+    const bool full = span >= PRE * NT;           // whole register tile valid: no per-element branch
+#pragma unroll
+    for (int u = 0; u < PRE; ++u) {
+        if (full || (int)threadIdx.x + u * NT < span) Conv::store(lds, ad, pf[u], lo_off);
+        c += dc;
+        ad += dad;
+        if (c >= a.H) {
+            c -= a.H;
+            ad += wrap;
+        }
+    }
+}
+
+// Zero the pad columns [H, Hp) of `rows` LDS rows (never written by span_store).
+template <class Conv>
+__device__ __forceinline__ void zero_pad_columns(const FwdArgs &a, int rows, typename Conv::elem_t *lds, int nthreads,
+                                                 int lo_off) {
+    const int w = a.Hp - a.H;
+    if (w <= 0) return;
+    for (int i = threadIdx.x; i < rows * w; i += nthreads) {
+        const int r = i / w, c = a.H + (i - r * w);
+        Conv::store(lds, r * a.S + c, 0.0f, lo_off);
+    }
+}
+
+// Staging without the register pipeline (the 16-bit kernels): batches of U loads per thread.
+template <class Conv, int U>
+__device__ __forceinline__ void stage_span(const FwdArgs &a, const Chunk &ch, typename Conv::elem_t *lds,
+                                           int nthreads, int lo_off) {
+    const int span = (ch.n_frames + a.J - 1) * a.H;
+    for (int base = threadIdx.x; base < span; base += U * nthreads) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int o = base + u * nthreads;
+            const int64_t s = ch.sample_start + o;
+            v[u] = (o < span && s < ch.sample_end) ? a.wave[s] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int o = base + u * nthreads;
+            if (o < span) {
+                const int r = span_row(a, o);
+                Conv::store(lds, r * a.S + (o - r * a.H), v[u], lo_off);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ direct-to-LDS staging
+// The chunk's contiguous sample span is copied HBM -> LDS by global_load_lds_dword: each
+// wave instruction moves 64 consecutive samples straight into LDS with no registers, so
+// the copy of chunk c+1 runs while the MFMAs of chunk c execute.  Positions at or past
+// `valid` (the span clipped to the clip end) are not loaded; consumers read them as 0.
+__device__ __forceinline__ int span_valid(const FwdArgs &a, const Chunk &ch) {
+    const int span = (ch.n_frames + a.J - 1) * a.H;
+    int64_t lim = ch.sample_end - ch.sample_start;
+    lim = lim < 0 ? 0 : lim;
+    return (int)(lim < span ? lim : span);
+}
+
+// The copies are issued with inline assembly: the compiler does not track them, so it adds no
+// wait for them before the LDS reads of the MFMA loop (which never touch the scratch area);
+// async_wait and a barrier order them before the scratch is read.  M0 holds the wave's LDS
+// destination; one wait state separates its write from the copy.
+__device__ __forceinline__ unsigned lds_addr(const void *p) {
+    return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+
+__device__ __forceinline__ void lds_dma_x4(const float *g, unsigned lds) {
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds) : "memory", "m0");
+}
+
+__device__ __forceinline__ void lds_dma_x1(const float *g, unsigned lds) {
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dword %0, off" ::"v"(g), "s"(lds) : "memory", "m0");
+}
+
+// 16-byte copies (256 samples per wave instruction) over the whole blocks of the valid span,
+// then 4-byte copies over its last partial block, so no lane reads past the clip end.
+__device__ __forceinline__ void async_span(const FwdArgs &a, const Chunk &ch, float *scratch) {
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
+    const int valid = span_valid(a, ch);
+    const float *src = a.wave + ch.sample_start;
+    const unsigned base = __builtin_amdgcn_readfirstlane(lds_addr(scratch));
+    const int nfull = valid >> 8;
+    for (int b = wid; b < nfull; b += nw) lds_dma_x4(src + b * 256 + 4 * lane, base + b * 1024);
+    for (int b = 4 * nfull + wid; b * 64 < valid; b += nw) {
+        const int o = b * 64 + lane;
+        if (o < valid) lds_dma_x1(src + o, base + b * 256);
+    }
+}
+
+__device__ __forceinline__ void async_wait() {
+    __builtin_amdgcn_s_waitcnt(0);     // this wave's direct-to-LDS copies have landed
+}
+
+// scratch (contiguous span) -> padded hop-block rows in the kernel's operand format.  With
+// H a multiple of 4, four consecutive samples never straddle a row: one 16-byte LDS read and
+// one vector write per thread and step.
+template <class Conv>
+__device__ __forceinline__ void convert_span(const FwdArgs &a, const Chunk &ch, const float *scratch,
+                                             typename Conv::elem_t *rows, int lo_off) {
+    const int span = (ch.n_frames + a.J - 1) * a.H;
+    const int valid = span_valid(a, ch);
+    if ((a.H & 3) == 0) {
+        // Vectors of 4 samples, thread-strided by step = 4 nt; four per thread and pass, so
+        // their LDS reads are in flight together.  The row and column advance by (dr, dc)
+        // per vector, so no division per element.
+        const int nt = blockDim.x, step = 4 * nt;
+        const int dr = step / a.H, dc = step - dr * a.H;
+        const int dad = dr * a.S + dc, wrap = a.S - a.H;
+        int c = 4 * (int)threadIdx.x;
+        const int r0 = span_row(a, c);
+        c -= r0 * a.H;
+        int ad = r0 * a.S + c;
+        for (int o0 = 4 * (int)threadIdx.x; o0 < span; o0 += 4 * step) {
+            f32x4 v[4];
+            int at[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int o = o0 + u * step;
+                v[u] = o < span ? *(const f32x4 *)(scratch + o) : f32x4{};
+                at[u] = ad;
+                c += dc;
+                ad += dad;
+                if (c >= a.H) {
+                    c -= a.H;
+                    ad += wrap;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int o = o0 + u * step;
+                if (o < span) {
+                    if (o + 4 > valid) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (o + e >= valid) v[u][e] = 0.0f;
+                    }
+                    Conv::store4(rows, at[u], v[u], lo_off);
+                }
+            }
+        }
+        return;
+    }
+    for (int o = threadIdx.x; o < span; o += blockDim.x) {
+        const float v = o < valid ? scratch[o] : 0.0f;
+        const int r = span_row(a, o);
+        Conv::store(rows, r * a.S + (o - r * a.H), v, lo_off);
+    }
+}
+
+// ------------------------------------------------------------------ staged epilogue
+//
+// Writes one 32-frame x 16-Mel tile through a wave-private LDS area (32 rows of 20 floats):
+// each lane first writes its frame's 8 mapped values, then reads back one 4-Mel quarter of
+// a frame, so one 16-byte store instruction covers 16 frames x 64 contiguous bytes instead
+// of 64 scattered 16-byte pieces.  The optional projection output keeps the direct path.
+constexpr int kStageStride = 20;                  // floats per staged frame row
+constexpr int kStageFloats = 32 * kStageStride;   // per wave
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline void store_tile_staged(const FwdArgs &a, const Chunk &ch, int rt, int f_base, int lane,
+                                         const f32x16 &acc, float *stage) {
+    const int h = lane >> 5, fl = lane & 31;
+    f32x4 v0, v1;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        v0[2 * g] = out_map(acc[4 * g] * acc[4 * g] + acc[4 * g + 1] * acc[4 * g + 1], a.out_kind, a.eps);
+        v0[2 * g + 1] = out_map(acc[4 * g + 2] * acc[4 * g + 2] + acc[4 * g + 3] * acc[4 * g + 3], a.out_kind, a.eps);
+        v1[2 * g] = out_map(acc[8 + 4 * g] * acc[8 + 4 * g] + acc[9 + 4 * g] * acc[9 + 4 * g], a.out_kind, a.eps);
+        v1[2 * g + 1] = out_map(acc[10 + 4 * g] * acc[10 + 4 * g] + acc[11 + 4 * g] * acc[11 + 4 * g], a.out_kind, a.eps);
+    }
+    *(f32x4 *)(stage + fl * kStageStride + 8 * h) = v0;
+    *(f32x4 *)(stage + fl * kStageStride + 8 * h + 4) = v1;
+    wave_sync();
+    const int mq = lane & 3;
+    const int mel = rt * 16 + 4 * mq;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int fr = (lane >> 2) + 16 * k;
+        const int f_local = f_base + fr;
+        const int64_t row = ch.out_row + f_local;
+        const f32x4 w = *(const f32x4 *)(stage + fr * kStageStride + 4 * mq);
+        if (f_local < ch.n_frames && row < a.n_frames && mel < a.M) {
+            float *o = a.out + row * a.M + mel;
+            if ((a.M & 3) == 0) {
+                *(f32x4 *)o = w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (mel + e < a.M) o[e] = w[e];
+            }
+        }
+    }
+    wave_sync();                                  // the area is reused by the next tile
+    if (a.proj) {
+        const int f_local = f_base + fl;
+        const int64_t row = ch.out_row + f_local;
+        const int mel0 = rt * 16 + 8 * h;
+        if (f_local < ch.n_frames && row < a.n_frames && mel0 < a.M) {
+            float *p = a.proj + row * (2 * a.M) + 2 * mel0;
+            if (mel0 + 8 <= a.M) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) *(f32x4 *)(p + 4 * q) = f32x4{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+            } else {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    if (mel0 + e / 2 < a.M) p[e] = acc[e];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host-side geometry
+
+constexpr int kBF32 = kChunkF32;
+constexpr int kMaxLds = 160 * 1024;
+
+inline int lds_stride(int Hp, int esize) {
+    // row stride (elements) whose dword count is an odd multiple of 4, so that the 16-byte
+    // reads of 8 consecutive rows at one column fall in 8 distinct 4-bank groups
+    const int per_dword = 4 / esize;
+    int dw = (Hp + per_dword - 1) / per_dword;
+    dw = ((dw + 3) / 4) * 4;
+    if ((dw / 4) % 2 == 0) dw += 4;
+    return dw * per_dword;
+}
+
+inline GroupTableBig make_table(const Geometry &g, int S) {
+    GroupTableBig t{};
+    t.n = g.n_groups;
+    for (int i = 0; i < g.n_groups && i < 512; ++i) t.lds_off[i] = g.seg_of_group[i] * S + g.col_of_group[i];
+    return t;
+}
+
+// One forward launch: the chunk table, the batch and the destination.
+struct FwdTask {
+    const Chunk *tab;
+    const int *n_tab;
+    int64_t est_chunks;    // upper bound on the table's entries (sizes the grid)
+    int64_t n_frames;
+    const float *wave;
+    float *out;
+    float *proj;
+    hipStream_t stream;
+};
+
+inline FwdArgs make_args(const Plan &p, const Geometry &g, int S, const FwdTask &t) {
+    FwdArgs a;
+    a.wave = t.wave;
+    a.chunks = t.tab;
+    a.n_chunks = t.n_tab;
+    a.out = t.out;
+    a.proj = t.proj;
+    a.n_frames = t.n_frames;
+    a.M = p.M;
+    a.J = g.J;
+    a.H = p.H;
+    a.Hp = g.Hp;
+    a.S = S;
+    a.row_tiles = p.row_tiles;
+    a.out_kind = p.cfg.output;
+    a.eps = (float)p.cfg.log_eps;
+    a.invH = (float)(1.0 / p.H);
+    return a;
+}
+
+template <class K>
+inline void allow_lds(K kern) {
+    (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+}
+
+// persistent grid: min(chunks, CUs x workgroups per CU (tuned value, else dflt))
+inline int persistent_grid(const Plan &p, int64_t est_chunks, int dflt) {
+    const int per_cu = p.tune_grid > 0 ? p.tune_grid : dflt;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(est_chunks, (int64_t)p.cu_count * per_cu));
+}
+
+// 16-bit row-split kernels: k-group counts with a compiled register tile
+inline bool rs_supported(int NS) { return NS == 25 || NS == 32 || NS == 20 || NS == 16 || NS == 10; }
+inline bool rs_fits(const Plan &p) { return rs_supported(p.geo16.n_groups) && p.row_tiles <= 8; }
+
+// LDS of the direct-to-LDS 16-bit kernel: operand rows, then the FP32 span scratch (16-byte aligned)
+inline size_t as_rows_bytes(const Plan &p, int bf) {
+    const bool x3 = p.cfg.precision == MELT_PREC_BF16X3;
+    return (size_t)(bf + p.geo16.J - 1) * lds_stride(p.geo16.Hp, 2) * 2 * (x3 ? 2 : 1);
+}
+// ... then the epilogue areas of the waves (byte offset, 16-byte aligned)
+inline size_t as_stage_offset(const Plan &p, int bf) {
+    return ((((as_rows_bytes(p, bf) + 15) & ~size_t(15)) + (size_t)(bf + p.geo16.J - 1) * p.H * 4) + 15) & ~size_t(15);
+}
+inline size_t as_lds_bytes(const Plan &p, int bf) {
+    return as_stage_offset(p, bf) + (size_t)p.row_tiles * kStageFloats * 4;
+}
+
+// per-family launchers (melt_f32.hip, melt_h16.hip, melt_f8.hip)
+melt_status launch_melt_f32(Plan &p, const FwdTask &t);
+enum H16Kind { H16_LDS_DMA = 0, H16_REGISTER_STAGED = 1, H16_FRAME_SPLIT = 2 };
+melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf);
+melt_status launch_melt_f8(Plan &p, const FwdTask &t);
+
+}  // namespace melt

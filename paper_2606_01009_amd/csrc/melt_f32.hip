@@ -1,0 +1,144 @@
+// MelT forward, FP32 operands: v_mfma_f32_32x32x2f32 over a frame-split chunk with the basis
+// streamed from L2 (Eq. dmp_projection, Eq. dmp_matrix_energy, Eq. meltf).
+#include "fwd_common.h"
+
+namespace melt {
+
+// ------------------------------------------------------------------ FP32 frame-split kernel
+//
+// 4 waves, one per SIMD; each wave owns 32 frames of the 128-frame chunk and computes all
+// Mel bins for them, in blocks of RTB row tiles (RTB accumulators of 16 registers).  The
+// basis is streamed from L2 in fragment order (one 16-byte load per row tile per 8-wide
+// k-group, shared by the 4 waves through L1) and prefetched one group ahead.  While the
+// MFMA loop of chunk c runs, the sample span of the workgroup's next chunk is already in
+// flight into registers (PRE per thread); it is written to LDS after the loop.
+template <int RTB, int PRE>
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(1, 1)))
+void k_melt_f32_fs(FwdArgs a, const f32x4 *__restrict__ bpack, int NG) {
+    extern __shared__ float lds[];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nch = *a.n_chunks;
+    const int GH = a.Hp / 8;     // k-groups per full hop segment
+    zero_pad_columns<ConvF32>(a, kChunkF32 + a.J - 1, lds, 256, 0);
+    // basis as a buffer: one VGPR offset per row tile, the k-group as a scalar offset
+    const __amdgpu_buffer_rsrc_t brs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)bpack, (short)0, a.row_tiles * NG * 64 * 16, 0x00020000);
+    float pf[PRE];
+    int c = blockIdx.x;
+    Chunk nxt;
+    if (c < nch) {
+        nxt = read_chunk(a.chunks, c);
+        span_load<PRE, 256>(a, nxt, pf);
+    }
+    for (; c < nch; c += gridDim.x) {
+        const Chunk ch = nxt;
+        __syncthreads();
+        span_store<ConvF32, PRE, 256>(a, ch, pf, lds, 0);
+        __syncthreads();
+        const bool more = c + (int)gridDim.x < nch;
+        if (more) nxt = read_chunk(a.chunks, c + gridDim.x);
+        const int fbase = wid * 32;
+        if (fbase >= ch.n_frames) {
+            if (more) span_load<PRE, 256>(a, nxt, pf);
+            continue;
+        }
+        const float *lp = lds + (fbase + (lane & 31)) * a.S + 4 * (lane >> 5);
+        for (int rb = 0; rb < a.row_tiles; rb += RTB) {
+            f32x16 acc[RTB];
+#pragma unroll
+            for (int r = 0; r < RTB; ++r) acc[r] = f32x16{};
+            int voff[RTB];
+#pragma unroll
+            for (int r = 0; r < RTB; ++r) voff[r] = ((min(rb + r, a.row_tiles - 1) * NG) * 64 + lane) * 16;
+            // operands of k-group g: basis fragments of the RTB row tiles, and the frame
+            // fragment at LDS offset (g / GH) S + 8 (g % GH)
+            auto load = [&](f32x4 (&A)[RTB], f32x4 &B, int g) {
+                const int j = g / GH;
+#pragma unroll
+                for (int r = 0; r < RTB; ++r)
+                    A[r] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(brs, voff[r], g * 1024, 0));
+                B = *(const f32x4 *)(lp + j * a.S + 8 * (g - j * GH));
+            };
+            auto mma = [&](const f32x4 (&A)[RTB], const f32x4 &B) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int r = 0; r < RTB; ++r)
+                        acc[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[r][i], B[i], acc[r], 0, 0, 0);
+            };
+            f32x4 A0[RTB], A1[RTB], B0, B1;
+            load(A0, B0, 0);
+            for (int g = 0; g < NG; g += 2) {
+                // ping-pong: the next group's loads are in flight while this group multiplies;
+                // indices past the end are clamped so every load is unconditional.  The
+                // scheduling barriers keep each load block above the MFMAs it overlaps.
+                load(A1, B1, min(g + 1, NG - 1));
+                __builtin_amdgcn_sched_barrier(0);
+                mma(A0, B0);
+                __builtin_amdgcn_sched_barrier(0);
+                load(A0, B0, min(g + 2, NG - 1));
+                __builtin_amdgcn_sched_barrier(0);
+                // past the last group the B fragment is zeroed instead of branching, so the
+                // loads above cannot be sunk into a conditional block
+                const float keep = (g + 1 < NG) ? 1.0f : 0.0f;
+                B1 *= keep;
+                mma(A1, B1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // the next chunk's span is requested only after the last basis wait of the
+            // last row block: vmcnt drains in order, so loads issued earlier would hold up
+            // every basis wait; here their latency overlaps the epilogue instead
+            if (more && rb + RTB >= a.row_tiles) span_load<PRE, 256>(a, nxt, pf);
+#pragma unroll
+            for (int r = 0; r < RTB; ++r)
+                if (rb + r < a.row_tiles) store_tile(a, ch, rb + r, fbase + (lane & 31), lane, acc[r]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launch
+
+template <int RTB, int PRE>
+static melt_status launch_f32_pre(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid,
+                                  hipStream_t s) {
+    allow_lds(k_melt_f32_fs<RTB, PRE>);
+    k_melt_f32_fs<RTB, PRE><<<grid, 256, lds, s>>>(a, (const f32x4 *)p.d_pack_f32, gt.n);
+    return hip_check(hipGetLastError(), "melt f32 launch");
+}
+
+// register prefetch depth: span of a full chunk, (128 + J - 1) H samples over 256 threads
+template <int RTB>
+static melt_status launch_f32_rtb(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid,
+                                  hipStream_t s) {
+    const int need = ((kBF32 + a.J - 1) * a.H + 255) / 256;
+    if (need <= 48) return launch_f32_pre<RTB, 48>(p, a, gt, lds, grid, s);
+    if (need <= 88) return launch_f32_pre<RTB, 88>(p, a, gt, lds, grid, s);
+    if (need <= 136) return launch_f32_pre<RTB, 136>(p, a, gt, lds, grid, s);
+    return set_error(MELT_E_UNSUPPORTED, "hop too large for the FP32 register pipeline");
+}
+
+melt_status launch_melt_f32(Plan &p, const FwdTask &t) {
+    const Geometry &g = p.geo32;
+    const int S = lds_stride(g.Hp, 4);
+    const size_t lds = (size_t)(kBF32 + g.J - 1) * S * 4;
+    if (lds > (size_t)kMaxLds || g.n_groups > 512)
+        return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS for FP32 kernel");
+    const FwdArgs a = make_args(p, g, S, t);
+    const GroupTableBig gt = make_table(g, S);
+    const int grid = persistent_grid(p, t.est_chunks, 1);
+    const hipStream_t s = t.stream;
+    // row tiles per block at most 5 (2 for the deepest prefetch) so accumulators, basis
+    // prefetch and sample prefetch fit 512 registers
+    const int need = ((kBF32 + g.J - 1) * p.H + 255) / 256;
+    const int cap = need <= 88 ? 5 : 2;
+    const int blocks = (p.row_tiles + cap - 1) / cap;
+    switch ((p.row_tiles + blocks - 1) / blocks) {
+    case 1: return launch_f32_rtb<1>(p, a, gt, lds, grid, s);
+    case 2: return launch_f32_rtb<2>(p, a, gt, lds, grid, s);
+    case 3: return launch_f32_rtb<3>(p, a, gt, lds, grid, s);
+    case 4: return launch_f32_rtb<4>(p, a, gt, lds, grid, s);
+    default: return launch_f32_rtb<5>(p, a, gt, lds, grid, s);
+    }
+}
+
+}  // namespace melt

@@ -1,0 +1,151 @@
+// MelT forward, FP8-E4M3 operands with per-frame and per-row scaling:
+// v_mfma_scale_f32_32x32x64_f8f6f4 with unit block scales, FP32 accumulation and an FP32
+// unscaling epilogue (Eq. dmp_projection, Eq. dmp_matrix_energy, Eq. meltf).
+#include "fwd_common.h"
+
+namespace melt {
+
+// ------------------------------------------------------------------ FP8 E4M3 row-split kernel
+//
+// Per-frame scaling needs one quantised copy of every frame (a sample belongs to ~N/H
+// frames with different scales), so the chunk's FP32 span is staged as hop-block rows, the
+// maximum |x| of every frame is formed from per-row maxima, and each frame is quantised
+// with s_t = 448 / max|x_t| into a frame-major E4M3 image in LDS (K = n padded to 64).
+// One wave per 32-row basis tile keeps its E4M3 rows (pre-scaled by r_j = 448 / max|W_j|)
+// in registers; v_mfma_scale_f32_32x32x64_f8f6f4 with unit block scales multiplies; the
+// epilogue divides by s_t r_j in FP32 before R^2 + I^2.
+
+template <int NG>
+__global__ __launch_bounds__(512) void k_melt_f8_rs(FwdArgs a, const i32x8 *__restrict__ bq, const float *__restrict__ rinv_g,
+                                                    int N, int bf) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & 63, rt = threadIdx.x >> 6, nthreads = blockDim.x, nw = nthreads >> 6;
+    constexpr int KP = NG * 64;             // padded frame length in the E4M3 image
+    constexpr int SQ = KP + 16;             // row stride (bytes): 4 x odd dwords -> conflict-free 16-byte reads
+    const int rows_max = bf + a.J - 1;
+    float *xs = lds;                                                 // FP32 hop-block rows
+    unsigned char *xq = reinterpret_cast<unsigned char *>(lds + rows_max * a.S);   // [bf][SQ] E4M3
+    float *sinv = reinterpret_cast<float *>(xq + bf * SQ);           // [bf] 1 / s_t
+    float *mfull = sinv + bf;                                        // [rows] max over the row
+    float *mpre = mfull + rows_max;                                  // [rows] max over the last segment's prefix
+    const int Llast = N - (a.J - 1) * a.H;                           // length of the last segment
+    i32x8 A[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) A[g] = bq[((size_t)rt * NG + g) * 64 + lane];
+    float rinv[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) rinv[r] = rinv_g[rt * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)];
+    zero_pad_columns<ConvF32>(a, rows_max, xs, nthreads, 0);
+    const int nch = *a.n_chunks;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const Chunk ch = read_chunk(a.chunks, c);
+        __syncthreads();
+        stage_span<ConvF32, 8>(a, ch, xs, nthreads, 0);
+        __syncthreads();
+        // per-row maxima (whole row, and the prefix the last segment uses)
+        const int rows = ch.n_frames + a.J - 1;
+        for (int r = rt; r < rows; r += nw) {
+            float mf = 0.0f, mp = 0.0f;
+            for (int col = lane; col < a.H; col += 64) {
+                const float v = fabsf(xs[r * a.S + col]);
+                mf = fmaxf(mf, v);
+                if (col < Llast) mp = fmaxf(mp, v);
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                mf = fmaxf(mf, __shfl_xor(mf, o));
+                mp = fmaxf(mp, __shfl_xor(mp, o));
+            }
+            if (lane == 0) {
+                mfull[r] = mf;
+                mpre[r] = mp;
+            }
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < ch.n_frames; t += nthreads) {
+            float mx = mpre[t + a.J - 1];
+            for (int j = 0; j + 1 < a.J; ++j) mx = fmaxf(mx, mfull[t + j]);
+            const float s = mx > 0.0f ? __fdiv_rn(448.0f, mx) : 1.0f;
+            sinv[t] = s;                       // scale itself; inverted in the epilogue
+        }
+        __syncthreads();
+        // quantise: frame t, samples n = 4u..4u+3 -> one 32-bit LDS word
+        for (int i = threadIdx.x; i < ch.n_frames * (KP / 4); i += nthreads) {
+            const int t = i / (KP / 4), u = i - t * (KP / 4);
+            const float s = sinv[t];
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int n = 4 * u + e;
+                float x = 0.0f;
+                if (n < N) {
+                    const int j = n / a.H, col = n - j * a.H;
+                    x = xs[(t + j) * a.S + col];
+                }
+                v[e] = __fmul_rn(x, s);
+            }
+            *reinterpret_cast<unsigned *>(xq + t * SQ + 4 * u) = fp8x4(v[0], v[1], v[2], v[3]);
+        }
+        __syncthreads();
+        const int nft = (ch.n_frames + 31) >> 5;
+        for (int ft = 0; ft < nft; ft += 2) {
+            const bool two = ft + 1 < nft;
+            f32x16 acc0 = f32x16{}, acc1 = f32x16{};
+            const unsigned char *q0 = xq + (ft * 32 + (lane & 31)) * SQ + 32 * (lane >> 5);
+            const unsigned char *q1 = q0 + 32 * SQ;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const uint4 b0l = *(const uint4 *)(q0 + 64 * g), b0h = *(const uint4 *)(q0 + 64 * g + 16);
+                i32x8 B0 = {(int)b0l.x, (int)b0l.y, (int)b0l.z, (int)b0l.w, (int)b0h.x, (int)b0h.y, (int)b0h.z, (int)b0h.w};
+                acc0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[g], B0, acc0, 0, 0, 0, 127, 0, 127);
+                if (two) {
+                    const uint4 b1l = *(const uint4 *)(q1 + 64 * g), b1h = *(const uint4 *)(q1 + 64 * g + 16);
+                    i32x8 B1 = {(int)b1l.x, (int)b1l.y, (int)b1l.z, (int)b1l.w, (int)b1h.x, (int)b1h.y, (int)b1h.z, (int)b1h.w};
+                    acc1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[g], B1, acc1, 0, 0, 0, 127, 0, 127);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (u == 1 && !two) break;
+                f32x16 &acc = u ? acc1 : acc0;
+                const int f = (ft + u) * 32 + (lane & 31);
+                const float is = f < ch.n_frames ? 1.0f / sinv[f] : 0.0f;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[r] = acc[r] * (is * rinv[r]);
+                store_tile(a, ch, rt, f, lane, acc);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launch
+
+template <int NG>
+static melt_status launch_f8(Plan &p, const FwdArgs &a, size_t lds, int grid, int bf, hipStream_t s) {
+    allow_lds(k_melt_f8_rs<NG>);
+    k_melt_f8_rs<NG><<<grid, 64 * p.row_tiles, lds, s>>>(a, (const i32x8 *)p.d_pack_f8, p.d_rowscale, p.N, bf);
+    return hip_check(hipGetLastError(), "melt f8 launch");
+}
+
+melt_status launch_melt_f8(Plan &p, const FwdTask &t) {
+    const Geometry &g = p.geo32;
+    const int S = lds_stride(g.Hp, 4);
+    const int ng8 = (p.N + 63) / 64;
+    const int bf = kBF32;
+    const int rows_max = bf + g.J - 1;
+    const size_t lds = (size_t)rows_max * S * 4 + (size_t)bf * (ng8 * 64 + 16) + (size_t)bf * 4 + 2 * (size_t)rows_max * 4;
+    if (lds > (size_t)kMaxLds || p.row_tiles > 8)
+        return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS for the FP8 kernel");
+    const FwdArgs a = make_args(p, g, S, t);
+    const int grid = persistent_grid(p, t.est_chunks, 1);
+    const hipStream_t s = t.stream;
+    switch (ng8) {
+    case 4: return launch_f8<4>(p, a, lds, grid, bf, s);
+    case 7: return launch_f8<7>(p, a, lds, grid, bf, s);
+    case 8: return launch_f8<8>(p, a, lds, grid, bf, s);
+    case 16: return launch_f8<16>(p, a, lds, grid, bf, s);
+    default: return set_error(MELT_E_UNSUPPORTED, "FP8 kernel supports n_fft in (192, 256], (384, 512], (960, 1024]");
+    }
+}
+
+}  // namespace melt

@@ -1,0 +1,297 @@
+// MelT forward, 16-bit operands (BF16, FP16, split-BF16x3): v_mfma_f32_32x32x16_{bf16,f16}
+// with FP32 accumulation (Eq. dmp_projection, Eq. dmp_matrix_energy, Eq. meltf).
+#include "fwd_common.h"
+
+namespace melt {
+
+// ------------------------------------------------------------------ 16-bit register-tile MFMA sweep
+//
+// Two 32-frame tiles (LDS rows at l0 and l1) against a wave's basis tile held in registers:
+// NS k-groups of 16, one v_mfma_f32_32x32x16 per tile and group.  The frame fragments are
+// read D groups ahead into a ring of registers, and scheduling barriers keep each group's
+// reads above the multiplies they overlap, so LDS latency hides behind D groups of MFMAs.
+// X3 adds hi*lo + lo*hi products from the low parts (basis in Al, frames at lo_off).
+template <int NS, bool X3, bool IS_F16>
+__device__ __forceinline__ void mfma_sweep(const uint4 (&A)[NS], const uint4 (&Al)[X3 ? NS : 1],
+                                           const unsigned short *l0, const unsigned short *l1,
+                                           const GroupTableBig &gt, int lo_off, f32x16 &acc0, f32x16 &acc1) {
+    constexpr int D = X3 ? 1 : 4;
+    uint4 b0[D], b1[D], c0[X3 ? D : 1], c1[X3 ? D : 1];
+    auto fetch = [&](int s, int slot) {
+        const int o = gt.lds_off[s];
+        b0[slot] = *(const uint4 *)(l0 + o);
+        b1[slot] = *(const uint4 *)(l1 + o);
+        if constexpr (X3) {
+            c0[slot] = *(const uint4 *)(l0 + lo_off + o);
+            c1[slot] = *(const uint4 *)(l1 + lo_off + o);
+        }
+    };
+#pragma unroll
+    for (int s = 0; s < D && s < NS; ++s) fetch(s, s);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int slot = s % D;
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (IS_F16) {
+            const f16x8 av = __builtin_bit_cast(f16x8, A[s]);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, __builtin_bit_cast(f16x8, b0[slot]), acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, __builtin_bit_cast(f16x8, b1[slot]), acc1, 0, 0, 0);
+        } else {
+            const bf16x8 av = __builtin_bit_cast(bf16x8, A[s]);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, b0[slot]), acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, b1[slot]), acc1, 0, 0, 0);
+            if constexpr (X3) {
+                const bf16x8 al = __builtin_bit_cast(bf16x8, Al[s]);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, __builtin_bit_cast(bf16x8, b0[slot]), acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, __builtin_bit_cast(bf16x8, b1[slot]), acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, c0[slot]), acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, c1[slot]), acc1, 0, 0, 0);
+            }
+        }
+        if (s + D < NS) fetch(s + D, slot);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// ------------------------------------------------------------------ 16-bit row-split kernel
+//
+// One wave per 32-row basis tile (16 Mel bins); the wave keeps its whole basis tile in
+// registers for the life of the persistent kernel (NS k-groups of 16 x 16-bit values per
+// lane = 4 VGPRs each) and sweeps every frame tile of every chunk, two tiles at a time.
+// Frames are staged in LDS already rounded to the 16-bit format.  X3 adds the low parts
+// (split-bf16: hi*hi + hi*lo + lo*hi).
+template <class Conv, int NS, bool X3, bool IS_F16>
+__global__ __launch_bounds__(512) void k_melt_h16_rs(FwdArgs a, const uint4 *__restrict__ bhi,
+                                                     const uint4 *__restrict__ blo, GroupTableBig gt, int bf) {
+    extern __shared__ unsigned short lds16[];
+    const int lane = threadIdx.x & 63, rt = threadIdx.x >> 6;
+    const int nthreads = blockDim.x;
+    uint4 A[NS];
+    uint4 Al[X3 ? NS : 1];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) A[s] = bhi[((size_t)rt * NS + s) * 64 + lane];
+    if constexpr (X3) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) Al[s] = blo[((size_t)rt * NS + s) * 64 + lane];
+    }
+    const int lo_off = a.S * (bf + a.J - 1);
+    zero_pad_columns<Conv>(a, bf + a.J - 1, lds16, nthreads, lo_off);
+    const int nch = *a.n_chunks;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const Chunk ch = read_chunk(a.chunks, c);
+        __syncthreads();
+        stage_span<Conv, 8>(a, ch, lds16, nthreads, lo_off);
+        __syncthreads();
+        const int nft = (ch.n_frames + 31) >> 5;
+        for (int ft = 0; ft < nft; ft += 2) {
+            const bool two = ft + 1 < nft;
+            f32x16 acc0 = f32x16{}, acc1 = f32x16{};
+            const unsigned short *l0 = lds16 + (ft * 32 + (lane & 31)) * a.S + 8 * (lane >> 5);
+            // a lone last tile multiplies its own rows twice rather than branching
+            const unsigned short *l1 = two ? l0 + 32 * a.S : l0;
+            mfma_sweep<NS, X3, IS_F16>(A, Al, l0, l1, gt, lo_off, acc0, acc1);
+            store_tile(a, ch, rt, ft * 32 + (lane & 31), lane, acc0);
+            if (two) store_tile(a, ch, rt, (ft + 1) * 32 + (lane & 31), lane, acc1);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ 16-bit row-split kernel, direct-to-LDS staging
+//
+// Row-split 16-bit kernel with direct-to-LDS staging (default for BF16/FP16/BF16X3): as
+// k_melt_h16_rs, but chunk c+1's span is copied into an FP32 scratch area while chunk c is
+// multiplied; after a barrier all threads convert it into the operand rows.
+template <class Conv, int NS, bool X3, bool IS_F16>
+__global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__restrict__ bhi,
+                                                     const uint4 *__restrict__ blo, GroupTableBig gt, int bf,
+                                                     int scr_off, int stage_off) {
+    extern __shared__ float lds_as[];
+    const int lane = threadIdx.x & 63, rt = threadIdx.x >> 6;
+    const int lo_off = a.S * (bf + a.J - 1);
+    unsigned short *rows = reinterpret_cast<unsigned short *>(lds_as);
+    float *scratch = lds_as + scr_off;             // FP32 span, after the operand rows
+    zero_pad_columns<Conv>(a, bf + a.J - 1, rows, blockDim.x, lo_off);
+    uint4 A[NS];
+    uint4 Al[X3 ? NS : 1];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) A[s] = bhi[((size_t)rt * NS + s) * 64 + lane];
+    if constexpr (X3) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) Al[s] = blo[((size_t)rt * NS + s) * 64 + lane];
+    }
+    float *stage = lds_as + stage_off + rt * kStageFloats;
+    const int nch = *a.n_chunks;
+    int c = blockIdx.x;
+    if (c < nch) async_span(a, read_chunk(a.chunks, c), scratch);
+    async_wait();
+    for (; c < nch; c += gridDim.x) {
+        const Chunk ch = read_chunk(a.chunks, c);
+        __syncthreads();                           // span of chunk c is in scratch; rows are free
+        convert_span<Conv>(a, ch, scratch, rows, lo_off);
+        __syncthreads();                           // rows ready; scratch is free
+        if (c + (int)gridDim.x < nch) async_span(a, read_chunk(a.chunks, c + gridDim.x), scratch);
+        const int nft = (ch.n_frames + 31) >> 5;
+        for (int ft = 0; ft < nft; ft += 2) {
+            const bool two = ft + 1 < nft;
+            f32x16 acc0 = f32x16{}, acc1 = f32x16{};
+            // opaque to the optimiser, so that it does not keep (lane offset + group offset)
+            // of every k-group live in registers across the loop
+            int off = (ft * 32 + (lane & 31)) * a.S + 8 * (lane >> 5);
+            asm volatile("" : "+v"(off));
+            const unsigned short *l0 = rows + off;
+            // a lone last tile multiplies its own rows twice rather than branching
+            const unsigned short *l1 = two ? l0 + 32 * a.S : l0;
+            mfma_sweep<NS, X3, IS_F16>(A, Al, l0, l1, gt, lo_off, acc0, acc1);
+            // the next chunk's copy must land before the barrier that starts the next
+            // iteration; waiting here, ahead of the last tiles' stores, leaves those stores
+            // in flight across the barrier instead of waiting for them too
+            if (ft + 2 >= nft) async_wait();
+            store_tile_staged(a, ch, rt, ft * 32, lane, acc0, stage);
+            if (two) store_tile_staged(a, ch, rt, (ft + 1) * 32, lane, acc1, stage);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ 16-bit frame-split kernel
+// Fallback for frame lengths whose basis tile does not fit in registers: as the FP32
+// frame-split kernel, one 32x32x16 MFMA per k-group.
+template <class Conv, int RTB, bool IS_F16>
+__global__ __launch_bounds__(256, 1) void k_melt_h16_fs(FwdArgs a, const uint4 *__restrict__ bpack,
+                                                        GroupTableBig gt) {
+    extern __shared__ unsigned short lds16[];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nch = *a.n_chunks;
+    const int NG = gt.n;
+    zero_pad_columns<Conv>(a, kChunkF32 + a.J - 1, lds16, 256, 0);
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const Chunk ch = read_chunk(a.chunks, c);
+        __syncthreads();
+        stage_span<Conv, 8>(a, ch, lds16, 256, 0);
+        __syncthreads();
+        const int fbase = wid * 32;
+        if (fbase >= ch.n_frames) continue;
+        const unsigned short *lp = lds16 + (fbase + (lane & 31)) * a.S + 8 * (lane >> 5);
+        for (int rb = 0; rb < a.row_tiles; rb += RTB) {
+            f32x16 acc[RTB];
+#pragma unroll
+            for (int r = 0; r < RTB; ++r) acc[r] = f32x16{};
+            const uint4 *bp = bpack + (size_t)rb * NG * 64 + lane;
+            for (int g = 0; g < NG; ++g) {
+                const uint4 b = *(const uint4 *)(lp + gt.lds_off[g]);
+#pragma unroll
+                for (int r = 0; r < RTB; ++r) {
+                    if (rb + r >= a.row_tiles) continue;
+                    const uint4 av = bp[((size_t)r * NG + g) * 64];
+                    if constexpr (IS_F16)
+                        acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, av),
+                                                                        __builtin_bit_cast(f16x8, b), acc[r], 0, 0, 0);
+                    else
+                        acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
+                                                                         __builtin_bit_cast(bf16x8, b), acc[r], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < RTB; ++r)
+                if (rb + r < a.row_tiles) store_tile(a, ch, rb + r, fbase + (lane & 31), lane, acc[r]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launch
+
+template <class Conv, bool F16, int RTB>
+static melt_status launch_h16fs_rtb(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid,
+                                    hipStream_t s) {
+    allow_lds(k_melt_h16_fs<Conv, RTB, F16>);
+    k_melt_h16_fs<Conv, RTB, F16><<<grid, 256, lds, s>>>(a, (const uint4 *)p.d_pack_h16, gt);
+    return hip_check(hipGetLastError(), "melt h16 fs launch");
+}
+
+template <class Conv, int NS, bool X3, bool F16>
+static melt_status launch_rs_ns(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+                                hipStream_t s) {
+    allow_lds(k_melt_h16_rs<Conv, NS, X3, F16>);
+    k_melt_h16_rs<Conv, NS, X3, F16><<<grid, 64 * p.row_tiles, lds, s>>>(
+        a, (const uint4 *)p.d_pack_h16, (const uint4 *)p.d_pack_lo, gt, bf);
+    return hip_check(hipGetLastError(), "melt h16 rs launch");
+}
+
+template <class Conv, int NS, bool X3, bool F16>
+static melt_status launch_as_ns(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+                                int scr_off, hipStream_t s) {
+    allow_lds(k_melt_h16_as<Conv, NS, X3, F16>);
+    const int stage_off = (int)(as_stage_offset(p, bf) / 4);
+    k_melt_h16_as<Conv, NS, X3, F16><<<grid, 64 * p.row_tiles, lds, s>>>(
+        a, (const uint4 *)p.d_pack_h16, (const uint4 *)p.d_pack_lo, gt, bf, scr_off, stage_off);
+    return hip_check(hipGetLastError(), "melt h16 lds-dma launch");
+}
+
+template <class Conv, bool X3, bool F16>
+static melt_status launch_as(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+                             int scr_off, hipStream_t s) {
+    switch (p.geo16.n_groups) {
+    case 10: return launch_as_ns<Conv, 10, X3, F16>(p, a, gt, lds, grid, bf, scr_off, s);
+    case 16: return launch_as_ns<Conv, 16, X3, F16>(p, a, gt, lds, grid, bf, scr_off, s);
+    case 20: return launch_as_ns<Conv, 20, X3, F16>(p, a, gt, lds, grid, bf, scr_off, s);
+    case 25: return launch_as_ns<Conv, 25, X3, F16>(p, a, gt, lds, grid, bf, scr_off, s);
+    case 32: return launch_as_ns<Conv, 32, X3, F16>(p, a, gt, lds, grid, bf, scr_off, s);
+    default: return set_error(MELT_E_UNSUPPORTED, "no register tile for this frame length");
+    }
+}
+
+template <class Conv, bool X3, bool F16>
+static melt_status launch_rs(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+                             hipStream_t s) {
+    switch (p.geo16.n_groups) {
+    case 10: return launch_rs_ns<Conv, 10, X3, F16>(p, a, gt, lds, grid, bf, s);
+    case 16: return launch_rs_ns<Conv, 16, X3, F16>(p, a, gt, lds, grid, bf, s);
+    case 20: return launch_rs_ns<Conv, 20, X3, F16>(p, a, gt, lds, grid, bf, s);
+    case 25: return launch_rs_ns<Conv, 25, X3, F16>(p, a, gt, lds, grid, bf, s);
+    case 32: return launch_rs_ns<Conv, 32, X3, F16>(p, a, gt, lds, grid, bf, s);
+    default: return set_error(MELT_E_UNSUPPORTED, "no register tile for this frame length");
+    }
+}
+
+melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf) {
+    const int prec = p.cfg.precision;
+    const Geometry &g = p.geo16;
+    const int S = lds_stride(g.Hp, 2);
+    const bool f16 = prec == MELT_PREC_FP16;
+    const bool x3 = prec == MELT_PREC_BF16X3;
+    if (g.n_groups > 512) return set_error(MELT_E_UNSUPPORTED, "frame too long");
+    const FwdArgs a = make_args(p, g, S, t);
+    const GroupTableBig gt = make_table(g, S);
+    const hipStream_t s = t.stream;
+    if (kind == H16_LDS_DMA) {
+        const size_t lds = as_lds_bytes(p, bf);
+        if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
+        const int scr_off = (int)(((as_rows_bytes(p, bf) + 15) & ~size_t(15)) / 4);
+        const int grid = persistent_grid(p, t.est_chunks, std::min(std::max(1, (int)(kMaxLds / lds)), 2));
+        if (x3) return launch_as<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, scr_off, s);
+        if (f16) return launch_as<ConvF16, false, true>(p, a, gt, lds, grid, bf, scr_off, s);
+        return launch_as<ConvBF16, false, false>(p, a, gt, lds, grid, bf, scr_off, s);
+    }
+    if (kind == H16_REGISTER_STAGED) {
+        const size_t lds = (size_t)(bf + g.J - 1) * S * 2 * (x3 ? 2 : 1);
+        if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
+        const int grid = persistent_grid(p, t.est_chunks, std::min(std::max(1, (int)(kMaxLds / lds)), 2));
+        if (x3) return launch_rs<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, s);
+        if (f16) return launch_rs<ConvF16, false, true>(p, a, gt, lds, grid, bf, s);
+        return launch_rs<ConvBF16, false, false>(p, a, gt, lds, grid, bf, s);
+    }
+    if (x3) return set_error(MELT_E_UNSUPPORTED, "BF16X3 needs the register-tile kernel (frame too long)");
+    const size_t lds = (size_t)(kBF32 + g.J - 1) * S * 2;
+    if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
+    const int grid = persistent_grid(p, t.est_chunks, 2);
+    switch (std::min(p.row_tiles, 8)) {
+    case 1: return f16 ? launch_h16fs_rtb<ConvF16, true, 1>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 1>(p, a, gt, lds, grid, s);
+    case 2: return f16 ? launch_h16fs_rtb<ConvF16, true, 2>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 2>(p, a, gt, lds, grid, s);
+    case 4: return f16 ? launch_h16fs_rtb<ConvF16, true, 4>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 4>(p, a, gt, lds, grid, s);
+    case 3:
+    case 5:
+    case 6: return f16 ? launch_h16fs_rtb<ConvF16, true, 6>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 6>(p, a, gt, lds, grid, s);
+    default: return f16 ? launch_h16fs_rtb<ConvF16, true, 8>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 8>(p, a, gt, lds, grid, s);
+    }
+}
+
+}  // namespace melt

@@ -218,8 +218,9 @@ struct StftArgs {
     float eps;
 };
 
+// ln from the hardware base-2 logarithm; v + eps >= eps >= the smallest normal FP32
 __device__ __forceinline__ float stft_out_map(float v, int kind, float eps) {
-    return (kind <= MELT_OUT_LOG_MAGNITUDE) ? logf(v + eps) : v;
+    return (kind <= MELT_OUT_LOG_MAGNITUDE) ? __builtin_amdgcn_logf(v + eps) * 0.693147180559945309f : v;
 }
 
 // Orders this wave's LDS traffic: everything before is complete and visible to every lane

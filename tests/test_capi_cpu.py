@@ -51,7 +51,7 @@ def test_host_only_entry_points(lib):
 
 
 @pytest.mark.parametrize("field,value", [("n_fft", 1), ("n_fft", 5000), ("hop", 0), ("n_mels", 0), ("n_mels", 600),
-                                         ("fmax", 9000.0), ("fmin", -1.0), ("log_eps", 0.0), ("precision", 9),
+                                         ("fmax", 9000.0), ("fmin", -1.0), ("log_eps", 0.0), ("log_eps", 1e-39), ("precision", 9),
                                          ("output", 7), ("sample_rate", 0.0)])
 def test_invalid_configs_rejected(lib, field, value):
     c = lib.melt_config_default()
