@@ -559,6 +559,7 @@ inline size_t as_lds_bytes(const Plan &p, int bf) {
 melt_status launch_melt_f32(Plan &p, const FwdTask &t);
 enum H16Kind { H16_LDS_DMA = 0, H16_REGISTER_STAGED = 1, H16_FRAME_SPLIT = 2 };
 melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf);
-melt_status launch_melt_f8(Plan &p, const FwdTask &t);
+melt_status launch_melt_f8(Plan &p, const FwdTask &t, bool lds_dma, int bf);
+size_t f8_as_lds_bytes(const Plan &p, int bf);   // LDS of the direct-to-LDS FP8 kernel
 
 }  // namespace melt

@@ -118,6 +118,163 @@ __global__ __launch_bounds__(512) void k_melt_f8_rs(FwdArgs a, const i32x8 *__re
     }
 }
 
+// ------------------------------------------------------------------ FP8 kernel, direct-to-LDS staging
+//
+// As k_melt_f8_rs, with the chunk's sample span copied HBM -> LDS by direct-to-LDS loads
+// (async_span) while the previous chunk multiplies.  Frame t of the chunk is span samples
+// [tH, tH + N), so the per-row maxima and the E4M3 image are read straight from the
+// contiguous span (no hop-block rows, no division per element).  Positions at or past the
+// valid span (clip end) count as 0.  Outputs leave through store_tile_staged.
+template <int NG>
+__global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__restrict__ bq,
+                                                    const float *__restrict__ rinv_g, int N, int bf, int scr_off,
+                                                    int stage_off) {
+    extern __shared__ float lds_f8[];
+    const int lane = threadIdx.x & 63, nthreads = blockDim.x;
+    const int rt = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = nthreads >> 6;
+    constexpr int KP = NG * 64;             // padded frame length in the E4M3 image
+    constexpr int SQ = KP + 16;             // row stride (bytes): 4 x odd dwords -> conflict-free 16-byte reads
+    const int rows_max = bf + a.J - 1;
+    unsigned char *xq = reinterpret_cast<unsigned char *>(lds_f8);              // [bf][SQ] E4M3
+    float *sinv = reinterpret_cast<float *>(xq + bf * SQ);                       // [bf] s_t
+    float *mfull = sinv + bf;                                                    // [rows] max over the row
+    float *mpre = mfull + rows_max;                                              // [rows] max over the last segment's prefix
+    float *scratch = lds_f8 + scr_off;                                           // FP32 span
+    float *stage = lds_f8 + stage_off + rt * kStageFloats;
+    const int Llast = N - (a.J - 1) * a.H;                                       // length of the last segment
+    i32x8 A[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) A[g] = bq[((size_t)rt * NG + g) * 64 + lane];
+    float rinv[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) rinv[r] = rinv_g[rt * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)];
+    const int nch = *a.n_chunks;
+    int c = blockIdx.x;
+    if (c < nch) async_span(a, read_chunk(a.chunks, c), scratch);
+    async_wait();
+    for (; c < nch; c += gridDim.x) {
+        const Chunk ch = read_chunk(a.chunks, c);
+        const int valid = span_valid(a, ch);
+        __syncthreads();                           // span of chunk c is in scratch; the image is free
+        // per-row maxima over the whole row and over its first Llast samples
+        const int rows = ch.n_frames + a.J - 1;
+        if ((a.H & 3) == 0 && (Llast & 3) == 0) {
+            // one thread per hop row, 16-byte reads; each thread starts its walk through a
+            // column range at a column rotated by its lane, so that the 16 rows read by 16
+            // consecutive lanes fall in distinct bank groups
+            const int qa = Llast >> 2, qb = (a.H - Llast) >> 2;     // vectors before / after Llast
+            for (int r = threadIdx.x; r < rows; r += nthreads) {
+                const int base = r * a.H;
+                const bool whole = base + a.H <= valid;
+                float ma = 0.0f, mb = 0.0f;
+                for (int k = 0, q = lane % (qa > 0 ? qa : 1); k < qa; ++k) {
+                    const int o = base + 4 * q;
+                    f32x4 x = *(const f32x4 *)(scratch + o);
+                    if (!whole)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (o + e >= valid) x[e] = 0.0f;
+                    ma = fmaxf(ma, fmaxf(fmaxf(fabsf(x[0]), fabsf(x[1])), fmaxf(fabsf(x[2]), fabsf(x[3]))));
+                    if (++q == qa) q = 0;
+                }
+                for (int k = 0, q = lane % (qb > 0 ? qb : 1); k < qb; ++k) {
+                    const int o = base + Llast + 4 * q;
+                    f32x4 x = *(const f32x4 *)(scratch + o);
+                    if (!whole)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (o + e >= valid) x[e] = 0.0f;
+                    mb = fmaxf(mb, fmaxf(fmaxf(fabsf(x[0]), fabsf(x[1])), fmaxf(fabsf(x[2]), fabsf(x[3]))));
+                    if (++q == qb) q = 0;
+                }
+                mfull[r] = fmaxf(ma, mb);
+                mpre[r] = ma;
+            }
+        } else {
+            // general hops: one wave per hop row with a cross-lane reduction
+            for (int r = rt; r < rows; r += nw) {
+                float mf = 0.0f, mp = 0.0f;
+                for (int col = lane; col < a.H; col += 64) {
+                    const int o = r * a.H + col;
+                    const float v = o < valid ? fabsf(scratch[o]) : 0.0f;
+                    mf = fmaxf(mf, v);
+                    if (col < Llast) mp = fmaxf(mp, v);
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    mf = fmaxf(mf, __shfl_xor(mf, o));
+                    mp = fmaxf(mp, __shfl_xor(mp, o));
+                }
+                if (lane == 0) {
+                    mfull[r] = mf;
+                    mpre[r] = mp;
+                }
+            }
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < ch.n_frames; t += nthreads) {
+            float mx = mpre[t + a.J - 1];
+            for (int j = 0; j + 1 < a.J; ++j) mx = fmaxf(mx, mfull[t + j]);
+            sinv[t] = mx > 0.0f ? __fdiv_rn(448.0f, mx) : 1.0f;     // the scale; inverted in the epilogue
+        }
+        __syncthreads();
+        // quantise: one wave per frame, lane = 4-sample word of the padded frame
+        const bool vec = (a.H & 3) == 0 && (N & 3) == 0;
+        for (int t = rt; t < ch.n_frames; t += nw) {
+            const float s = sinv[t];
+            const int base = t * a.H;
+            const bool whole = vec && base + N <= valid;    // every sample of the frame present
+            unsigned *dst = reinterpret_cast<unsigned *>(xq + t * SQ);
+#pragma unroll
+            for (int k = 0; k < (KP / 4 + 63) / 64; ++k) {
+                const int u = lane + 64 * k;
+                if (u >= KP / 4) break;
+                const int n0 = 4 * u, o = base + n0;
+                f32x4 x;
+                if (whole) {
+                    x = n0 < N ? *(const f32x4 *)(scratch + o) : f32x4{};
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) x[e] = (n0 + e < N && o + e < valid) ? scratch[o + e] : 0.0f;
+                }
+                dst[u] = fp8x4(__fmul_rn(x[0], s), __fmul_rn(x[1], s), __fmul_rn(x[2], s), __fmul_rn(x[3], s));
+            }
+        }
+        __syncthreads();                           // image ready; scratch is free
+        if (c + (int)gridDim.x < nch) async_span(a, read_chunk(a.chunks, c + gridDim.x), scratch);
+        const int nft = (ch.n_frames + 31) >> 5;
+        for (int ft = 0; ft < nft; ft += 2) {
+            const bool two = ft + 1 < nft;
+            f32x16 acc0 = f32x16{}, acc1 = f32x16{};
+            const unsigned char *q0 = xq + (ft * 32 + (lane & 31)) * SQ + 32 * (lane >> 5);
+            // a lone last tile multiplies its own frames twice rather than branching
+            const unsigned char *q1 = two ? q0 + 32 * SQ : q0;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const uint4 b0l = *(const uint4 *)(q0 + 64 * g), b0h = *(const uint4 *)(q0 + 64 * g + 16);
+                const uint4 b1l = *(const uint4 *)(q1 + 64 * g), b1h = *(const uint4 *)(q1 + 64 * g + 16);
+                const i32x8 B0 = {(int)b0l.x, (int)b0l.y, (int)b0l.z, (int)b0l.w, (int)b0h.x, (int)b0h.y, (int)b0h.z, (int)b0h.w};
+                const i32x8 B1 = {(int)b1l.x, (int)b1l.y, (int)b1l.z, (int)b1l.w, (int)b1h.x, (int)b1h.y, (int)b1h.z, (int)b1h.w};
+                acc0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[g], B0, acc0, 0, 0, 0, 127, 0, 127);
+                acc1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[g], B1, acc1, 0, 0, 0, 127, 0, 127);
+            }
+            // the next chunk's copy must land before the barrier that starts the next
+            // iteration; waiting ahead of the last tiles' stores leaves those in flight
+            if (ft + 2 >= nft) async_wait();
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (u == 1 && !two) break;
+                f32x16 &acc = u ? acc1 : acc0;
+                const int f = (ft + u) * 32 + (lane & 31);
+                const float is = f < ch.n_frames ? 1.0f / sinv[f] : 0.0f;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[r] = acc[r] * (is * rinv[r]);
+                store_tile_staged(a, ch, rt, (ft + u) * 32, lane, acc, stage);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launch
 
 template <int NG>
@@ -127,18 +284,49 @@ static melt_status launch_f8(Plan &p, const FwdArgs &a, size_t lds, int grid, in
     return hip_check(hipGetLastError(), "melt f8 launch");
 }
 
-melt_status launch_melt_f8(Plan &p, const FwdTask &t) {
+// LDS of the direct-to-LDS FP8 kernel at bf frames per chunk: the E4M3 image, the scales
+// and row maxima, the FP32 span (16-byte aligned), then the epilogue areas
+size_t f8_as_scratch_offset(const Plan &p, int bf) {
+    const int ng8 = (p.N + 63) / 64;
+    const size_t img = (size_t)bf * (ng8 * 64 + 16) + (size_t)bf * 4 + 2 * (size_t)(bf + p.geo32.J - 1) * 4;
+    return (img + 15) & ~size_t(15);
+}
+size_t f8_as_stage_offset(const Plan &p, int bf) {
+    return (f8_as_scratch_offset(p, bf) + (size_t)(bf + p.geo32.J - 1) * p.H * 4 + 15) & ~size_t(15);
+}
+size_t f8_as_lds_bytes(const Plan &p, int bf) { return f8_as_stage_offset(p, bf) + (size_t)p.row_tiles * kStageFloats * 4; }
+
+template <int NG>
+static melt_status launch_f8_as(Plan &p, const FwdArgs &a, size_t lds, int grid, int bf, hipStream_t s) {
+    allow_lds(k_melt_f8_as<NG>);
+    k_melt_f8_as<NG><<<grid, 64 * p.row_tiles, lds, s>>>(a, (const i32x8 *)p.d_pack_f8, p.d_rowscale, p.N, bf,
+                                                         (int)(f8_as_scratch_offset(p, bf) / 4),
+                                                         (int)(f8_as_stage_offset(p, bf) / 4));
+    return hip_check(hipGetLastError(), "melt f8 lds-dma launch");
+}
+
+melt_status launch_melt_f8(Plan &p, const FwdTask &t, bool lds_dma, int bf) {
     const Geometry &g = p.geo32;
     const int S = lds_stride(g.Hp, 4);
     const int ng8 = (p.N + 63) / 64;
-    const int bf = kBF32;
-    const int rows_max = bf + g.J - 1;
-    const size_t lds = (size_t)rows_max * S * 4 + (size_t)bf * (ng8 * 64 + 16) + (size_t)bf * 4 + 2 * (size_t)rows_max * 4;
-    if (lds > (size_t)kMaxLds || p.row_tiles > 8)
-        return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS for the FP8 kernel");
+    if (p.row_tiles > 8) return set_error(MELT_E_UNSUPPORTED, "too many Mel bins for the FP8 kernel");
     const FwdArgs a = make_args(p, g, S, t);
     const int grid = persistent_grid(p, t.est_chunks, 1);
     const hipStream_t s = t.stream;
+    if (lds_dma) {
+        const size_t lds = f8_as_lds_bytes(p, bf);
+        if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS for the FP8 kernel");
+        switch (ng8) {
+        case 4: return launch_f8_as<4>(p, a, lds, grid, bf, s);
+        case 7: return launch_f8_as<7>(p, a, lds, grid, bf, s);
+        case 8: return launch_f8_as<8>(p, a, lds, grid, bf, s);
+        case 16: return launch_f8_as<16>(p, a, lds, grid, bf, s);
+        default: return set_error(MELT_E_UNSUPPORTED, "FP8 kernel supports n_fft in (192, 256], (384, 512], (960, 1024]");
+        }
+    }
+    const int rows_max = bf + g.J - 1;
+    const size_t lds = (size_t)rows_max * S * 4 + (size_t)bf * (ng8 * 64 + 16) + (size_t)bf * 4 + 2 * (size_t)rows_max * 4;
+    if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS for the FP8 kernel");
     switch (ng8) {
     case 4: return launch_f8<4>(p, a, lds, grid, bf, s);
     case 7: return launch_f8<7>(p, a, lds, grid, bf, s);

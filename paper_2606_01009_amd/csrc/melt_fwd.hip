@@ -249,8 +249,9 @@ melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H
 //              for a register tile)
 //   BF16X3     row-split with direct-to-LDS staging (96- then 64-frame chunks), row-split
 //              with register staging
-//   FP8        row-split
-enum VariantKind { V_F32_FS, V_H16_AS, V_H16_RS, V_H16_FS, V_F8_RS };
+//   FP8        row-split with direct-to-LDS staging (the largest chunk that fits LDS),
+//              row-split with register staging
+enum VariantKind { V_F32_FS, V_H16_AS, V_H16_RS, V_H16_FS, V_F8_AS, V_F8_RS };
 struct Variant {
     VariantKind kind;
     int bf;          // frames per chunk
@@ -260,7 +261,14 @@ static std::vector<Variant> variant_list(const Plan &p) {
     std::vector<Variant> v;
     switch (p.cfg.precision) {
     case MELT_PREC_FP32: v.push_back({V_F32_FS, kBF32}); break;
-    case MELT_PREC_FP8_E4M3: v.push_back({V_F8_RS, kBF32}); break;
+    case MELT_PREC_FP8_E4M3:
+        for (int bf : {128, 96, 64, 32})
+            if (f8_as_lds_bytes(p, bf) <= (size_t)kMaxLds) {
+                v.push_back({V_F8_AS, bf});
+                break;
+            }
+        v.push_back({V_F8_RS, kBF32});
+        break;
     default: {
         const bool x3 = p.cfg.precision == MELT_PREC_BF16X3;
         if (rs_fits(p)) {
@@ -292,6 +300,7 @@ const char *forward_variant_name(const Plan &p, int i) {
                     : v[i].kind == V_H16_AS ? "h16-row-split-lds-dma"
                     : v[i].kind == V_H16_RS ? "h16-row-split"
                     : v[i].kind == V_H16_FS ? "h16-frame-split"
+                    : v[i].kind == V_F8_AS  ? "f8-row-split-lds-dma"
                                             : "f8-row-split";
     std::snprintf(buf, sizeof(buf), "%s-bf%d", k, v[i].bf);
     return buf;
@@ -318,7 +327,8 @@ melt_status launch_melt_table(Plan &p, int variant, const Chunk *tab, const int 
     case V_H16_AS: return launch_melt_h16(p, t, H16_LDS_DMA, v.bf);
     case V_H16_RS: return launch_melt_h16(p, t, H16_REGISTER_STAGED, v.bf);
     case V_H16_FS: return launch_melt_h16(p, t, H16_FRAME_SPLIT, v.bf);
-    case V_F8_RS: return launch_melt_f8(p, t);
+    case V_F8_AS: return launch_melt_f8(p, t, true, v.bf);
+    case V_F8_RS: return launch_melt_f8(p, t, false, v.bf);
     }
     return set_error(MELT_E_UNSUPPORTED, "precision not implemented");
 }
