@@ -213,13 +213,13 @@ struct ConvBF16X3 {
     }
 };
 
-// Register staging of a chunk's contiguous sample span [start, start + (n_frames + J - 1) H):
-// element u of a thread is span position o = tid + u * NT, so every load instruction of a
+// Register staging of a chunk's contiguous sample span [start, start + (n_frames + J - 1) H)
+// by NT threads: element u of thread t is span position o = t + u * NT, so every load instruction of a
 // wave reads 64 consecutive samples.  span_load issues all PRE loads at once (one memory
 // round trip); span_store scatters them into the padded hop-block rows (row o / H, column
 // o % H).  Samples at or past the clip end read as 0.
 template <int PRE, int NT>
-__device__ __forceinline__ void span_load(const FwdArgs &a, const Chunk &ch, float (&pf)[PRE]) {
+__device__ __forceinline__ void span_load(const FwdArgs &a, const Chunk &ch, float (&pf)[PRE], int t) {
     // buffer descriptor over [start, min(start + span, clip end)): loads past it return 0,
     // so the clip end needs no branch; one VGPR offset serves all PRE loads
     const int64_t start = ch.sample_start;
@@ -228,7 +228,7 @@ __device__ __forceinline__ void span_load(const FwdArgs &a, const Chunk &ch, flo
     const int records = (int)(lim > 0 ? lim * 4 : 0);
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc((void *)(a.wave + start), (short)0, records, 0x00020000);
-    const int voff = (int)threadIdx.x * 4;
+    const int voff = t * 4;
 #pragma unroll
     for (int u = 0; u < PRE; ++u)
         pf[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, u * NT * 4, 0));
@@ -243,26 +243,27 @@ __device__ __forceinline__ int span_row(const FwdArgs &a, int o) {
 
 template <class Conv, int PRE, int NT>
 __device__ __forceinline__ void span_store(const FwdArgs &a, const Chunk &ch, const float (&pf)[PRE],
-                                           typename Conv::elem_t *lds, int lo_off) {
+                                           typename Conv::elem_t *lds, int lo_off, int t) {
     // element u of the thread is span position tid + u NT; its row and column advance by
     // (dr, dc) per element, so no division per element
     const int span = (ch.n_frames + a.J - 1) * a.H;
     const int dr = NT / a.H, dc = NT - dr * a.H;
     const int dad = dr * a.S + dc, wrap = a.S - a.H;
-    int c = (int)threadIdx.x;
+    int c = t;
     const int r0 = span_row(a, c);
     c -= r0 * a.H;
     int ad = r0 * a.S + c;
     const bool full = span >= PRE * NT;           // whole register tile valid: no per-element branch
 #pragma unroll
     for (int u = 0; u < PRE; ++u) {
-        if (full || (int)threadIdx.x + u * NT < span) Conv::store(lds, ad, pf[u], lo_off);
+        if (full || t + u * NT < span) Conv::store(lds, ad, pf[u], lo_off);
         c += dc;
         ad += dad;
         if (c >= a.H) {
             c -= a.H;
             ad += wrap;
         }
+        asm volatile("" : "+v"(ad), "+v"(c));      // no address computed ahead (registers)
     }
 }
 
@@ -556,7 +557,7 @@ inline size_t as_lds_bytes(const Plan &p, int bf) {
 }
 
 // per-family launchers (melt_f32.hip, melt_h16.hip, melt_f8.hip)
-melt_status launch_melt_f32(Plan &p, const FwdTask &t);
+melt_status launch_melt_f32(Plan &p, const FwdTask &t, bool warp_specialised);
 enum H16Kind { H16_LDS_DMA = 0, H16_REGISTER_STAGED = 1, H16_FRAME_SPLIT = 2 };
 melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf);
 melt_status launch_melt_f8(Plan &p, const FwdTask &t, bool lds_dma, int bf);

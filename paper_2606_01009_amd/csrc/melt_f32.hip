@@ -28,18 +28,18 @@ void k_melt_f32_fs(FwdArgs a, const f32x4 *__restrict__ bpack, int NG) {
     Chunk nxt;
     if (c < nch) {
         nxt = read_chunk(a.chunks, c);
-        span_load<PRE, 256>(a, nxt, pf);
+        span_load<PRE, 256>(a, nxt, pf, tid);
     }
     for (; c < nch; c += gridDim.x) {
         const Chunk ch = nxt;
         __syncthreads();
-        span_store<ConvF32, PRE, 256>(a, ch, pf, lds, 0);
+        span_store<ConvF32, PRE, 256>(a, ch, pf, lds, 0, tid);
         __syncthreads();
         const bool more = c + (int)gridDim.x < nch;
         if (more) nxt = read_chunk(a.chunks, c + gridDim.x);
         const int fbase = wid * 32;
         if (fbase >= ch.n_frames) {
-            if (more) span_load<PRE, 256>(a, nxt, pf);
+            if (more) span_load<PRE, 256>(a, nxt, pf, tid);
             continue;
         }
         const float *lp = lds + (fbase + (lane & 31)) * a.S + 4 * (lane >> 5);
@@ -88,11 +88,107 @@ void k_melt_f32_fs(FwdArgs a, const f32x4 *__restrict__ bpack, int NG) {
             // the next chunk's span is requested only after the last basis wait of the
             // last row block: vmcnt drains in order, so loads issued earlier would hold up
             // every basis wait; here their latency overlaps the epilogue instead
-            if (more && rb + RTB >= a.row_tiles) span_load<PRE, 256>(a, nxt, pf);
+            if (more && rb + RTB >= a.row_tiles) span_load<PRE, 256>(a, nxt, pf, tid);
 #pragma unroll
             for (int r = 0; r < RTB; ++r)
                 if (rb + r < a.row_tiles) store_tile(a, ch, rb + r, fbase + (lane & 31), lane, acc[r]);
         }
+    }
+}
+
+// ------------------------------------------------------------------ FP32 warp-specialised kernel
+//
+// 8 waves, 2 per SIMD: waves 0-3 multiply exactly as k_melt_f32_fs (32 frames each, basis
+// streamed from L2), waves 4-7 only stage.  The stagers hold the next chunk's span in
+// their own registers, loaded a whole chunk ahead, so the multiply waves' waits for basis
+// fragments never include sample loads (the wait counter drains in order).  Per chunk:
+// barrier A after the MFMA loop (the rows are free), then the stagers write the next rows
+// while the multiply waves run the epilogue, then barrier B.  The two roles run separate
+// loops with the same barriers, so their registers are allocated independently.
+template <int RTB, int PRE>
+__global__ __attribute__((amdgpu_flat_work_group_size(512, 512), amdgpu_waves_per_eu(2, 2)))
+void k_melt_f32_ws(FwdArgs a, const f32x4 *__restrict__ bpack, int NG) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nch = *a.n_chunks;
+    zero_pad_columns<ConvF32>(a, kChunkF32 + a.J - 1, lds, 512, 0);
+    int c = blockIdx.x;
+    if (wid >= 4) {
+        const int lt = (int)threadIdx.x - 256;
+        float pf[PRE];
+        if (c < nch) {
+            const Chunk ch = read_chunk(a.chunks, c);
+            span_load<PRE, 256>(a, ch, pf, lt);
+            span_store<ConvF32, PRE, 256>(a, ch, pf, lds, 0, lt);
+        }
+        __syncthreads();                           // rows of the first chunk ready
+        if (c + (int)gridDim.x < nch) span_load<PRE, 256>(a, read_chunk(a.chunks, c + gridDim.x), pf, lt);
+        for (; c < nch; c += gridDim.x) {
+            __syncthreads();                       // A: the multiply waves are done with the rows
+            const int cn = c + gridDim.x;
+            if (cn < nch) span_store<ConvF32, PRE, 256>(a, read_chunk(a.chunks, cn), pf, lds, 0, lt);
+            __syncthreads();                       // B: rows of the next chunk ready
+            if (cn + (int)gridDim.x < nch) span_load<PRE, 256>(a, read_chunk(a.chunks, cn + gridDim.x), pf, lt);
+        }
+        return;
+    }
+    const int GH = a.Hp / 8;     // k-groups per full hop segment
+    const __amdgpu_buffer_rsrc_t brs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)bpack, (short)0, a.row_tiles * NG * 64 * 16, 0x00020000);
+    __syncthreads();
+    for (; c < nch; c += gridDim.x) {
+        const Chunk ch = read_chunk(a.chunks, c);
+        const int fbase = wid * 32;
+        const bool active = fbase < ch.n_frames;
+        const float *lp = lds + (fbase + (lane & 31)) * a.S + 4 * (lane >> 5);
+        for (int rb = 0; rb < a.row_tiles; rb += RTB) {
+            const bool last = rb + RTB >= a.row_tiles;
+            f32x16 acc[RTB];
+#pragma unroll
+            for (int r = 0; r < RTB; ++r) acc[r] = f32x16{};
+            if (active) {
+                int voff[RTB];
+#pragma unroll
+                for (int r = 0; r < RTB; ++r) voff[r] = ((min(rb + r, a.row_tiles - 1) * NG) * 64 + lane) * 16;
+                auto load = [&](f32x4 (&A)[RTB], f32x4 &B, int g) {
+                    const int j = g / GH;
+#pragma unroll
+                    for (int r = 0; r < RTB; ++r)
+                        A[r] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(brs, voff[r], g * 1024, 0));
+                    B = *(const f32x4 *)(lp + j * a.S + 8 * (g - j * GH));
+                };
+                auto mma = [&](const f32x4 (&A)[RTB], const f32x4 &B) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int r = 0; r < RTB; ++r)
+                            acc[r] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[r][i], B[i], acc[r], 0, 0, 0);
+                };
+                // ping-pong as in k_melt_f32_fs
+                f32x4 A0[RTB], A1[RTB], B0, B1;
+                load(A0, B0, 0);
+                for (int g = 0; g < NG; g += 2) {
+                    load(A1, B1, min(g + 1, NG - 1));
+                    __builtin_amdgcn_sched_barrier(0);
+                    mma(A0, B0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    load(A0, B0, min(g + 2, NG - 1));
+                    __builtin_amdgcn_sched_barrier(0);
+                    const float keep = (g + 1 < NG) ? 1.0f : 0.0f;
+                    B1 *= keep;
+                    mma(A1, B1);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            if (last) __syncthreads();             // A: every row read; the stagers may overwrite
+            if (active) {
+#pragma unroll
+                for (int r = 0; r < RTB; ++r)
+                    if (rb + r < a.row_tiles) store_tile(a, ch, rb + r, fbase + (lane & 31), lane, acc[r]);
+            }
+        }
+        __syncthreads();                           // B: rows of the next chunk ready
     }
 }
 
@@ -117,7 +213,24 @@ static melt_status launch_f32_rtb(Plan &p, const FwdArgs &a, const GroupTableBig
     return set_error(MELT_E_UNSUPPORTED, "hop too large for the FP32 register pipeline");
 }
 
-melt_status launch_melt_f32(Plan &p, const FwdTask &t) {
+template <int RTB, int PRE>
+static melt_status launch_f32_ws_pre(const FwdArgs &a, const f32x4 *bp, int NG, size_t lds, int grid, hipStream_t s) {
+    allow_lds(k_melt_f32_ws<RTB, PRE>);
+    k_melt_f32_ws<RTB, PRE><<<grid, 512, lds, s>>>(a, bp, NG);
+    return hip_check(hipGetLastError(), "melt f32 ws launch");
+}
+
+template <int RTB>
+static melt_status launch_f32_ws_rtb(Plan &p, const FwdArgs &a, int NG, size_t lds, int grid, hipStream_t s) {
+    const f32x4 *bp = (const f32x4 *)p.d_pack_f32;
+    const int need = ((kBF32 + a.J - 1) * a.H + 255) / 256;
+    if (need <= 48) return launch_f32_ws_pre<RTB, 48>(a, bp, NG, lds, grid, s);
+    if (need <= 88) return launch_f32_ws_pre<RTB, 88>(a, bp, NG, lds, grid, s);
+    if (need <= 136) return launch_f32_ws_pre<RTB, 136>(a, bp, NG, lds, grid, s);
+    return set_error(MELT_E_UNSUPPORTED, "hop too large for the FP32 staging waves");
+}
+
+melt_status launch_melt_f32(Plan &p, const FwdTask &t, bool warp_specialised) {
     const Geometry &g = p.geo32;
     const int S = lds_stride(g.Hp, 4);
     const size_t lds = (size_t)(kBF32 + g.J - 1) * S * 4;
@@ -127,6 +240,18 @@ melt_status launch_melt_f32(Plan &p, const FwdTask &t) {
     const GroupTableBig gt = make_table(g, S);
     const int grid = persistent_grid(p, t.est_chunks, 1);
     const hipStream_t s = t.stream;
+    if (warp_specialised) {
+        // row tiles per block at most 5: accumulators and the basis ping-pong within the
+        // 256 registers of two waves per SIMD
+        const int blocks = (p.row_tiles + 4) / 5;
+        switch ((p.row_tiles + blocks - 1) / blocks) {
+        case 1: return launch_f32_ws_rtb<1>(p, a, gt.n, lds, grid, s);
+        case 2: return launch_f32_ws_rtb<2>(p, a, gt.n, lds, grid, s);
+        case 3: return launch_f32_ws_rtb<3>(p, a, gt.n, lds, grid, s);
+        case 4: return launch_f32_ws_rtb<4>(p, a, gt.n, lds, grid, s);
+        default: return launch_f32_ws_rtb<5>(p, a, gt.n, lds, grid, s);
+        }
+    }
     // row tiles per block at most 5 (2 for the deepest prefetch) so accumulators, basis
     // prefetch and sample prefetch fit 512 registers
     const int need = ((kBF32 + g.J - 1) * p.H + 255) / 256;

@@ -243,7 +243,7 @@ melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H
 
 // Kernel variants of a plan, in the order the autotuner times them (p.tune_variant selects;
 // the first one is the default):
-//   FP32       frame-split with register prefetch
+//   FP32       frame-split with staging waves, frame-split with register prefetch
 //   BF16/FP16  row-split with direct-to-LDS staging (128- then 64-frame chunks), row-split
 //              with register staging, frame-split (the only one when the frame is too long
 //              for a register tile)
@@ -251,7 +251,7 @@ melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H
 //              with register staging
 //   FP8        row-split with direct-to-LDS staging (the largest chunk that fits LDS),
 //              row-split with register staging
-enum VariantKind { V_F32_FS, V_H16_AS, V_H16_RS, V_H16_FS, V_F8_AS, V_F8_RS };
+enum VariantKind { V_F32_WS, V_F32_FS, V_H16_AS, V_H16_RS, V_H16_FS, V_F8_AS, V_F8_RS };
 struct Variant {
     VariantKind kind;
     int bf;          // frames per chunk
@@ -260,7 +260,10 @@ struct Variant {
 static std::vector<Variant> variant_list(const Plan &p) {
     std::vector<Variant> v;
     switch (p.cfg.precision) {
-    case MELT_PREC_FP32: v.push_back({V_F32_FS, kBF32}); break;
+    case MELT_PREC_FP32:
+        v.push_back({V_F32_WS, kBF32});
+        v.push_back({V_F32_FS, kBF32});
+        break;
     case MELT_PREC_FP8_E4M3:
         for (int bf : {128, 96, 64, 32})
             if (f8_as_lds_bytes(p, bf) <= (size_t)kMaxLds) {
@@ -296,7 +299,8 @@ const char *forward_variant_name(const Plan &p, int i) {
     static thread_local char buf[64];
     const std::vector<Variant> v = variant_list(p);
     if (i < 0 || (size_t)i >= v.size()) return "none";
-    const char *k = v[i].kind == V_F32_FS   ? "f32-frame-split"
+    const char *k = v[i].kind == V_F32_WS   ? "f32-frame-split-warp-specialised"
+                    : v[i].kind == V_F32_FS ? "f32-frame-split"
                     : v[i].kind == V_H16_AS ? "h16-row-split-lds-dma"
                     : v[i].kind == V_H16_RS ? "h16-row-split"
                     : v[i].kind == V_H16_FS ? "h16-frame-split"
@@ -323,7 +327,8 @@ melt_status launch_melt_table(Plan &p, int variant, const Chunk *tab, const int 
     const FwdTask t{tab, n_tab, est_chunks, n_frames, d_wave, d_out, d_proj, s};
     const Variant v = variant_at(p, variant);
     switch (v.kind) {
-    case V_F32_FS: return launch_melt_f32(p, t);
+    case V_F32_WS: return launch_melt_f32(p, t, true);
+    case V_F32_FS: return launch_melt_f32(p, t, false);
     case V_H16_AS: return launch_melt_h16(p, t, H16_LDS_DMA, v.bf);
     case V_H16_RS: return launch_melt_h16(p, t, H16_REGISTER_STAGED, v.bf);
     case V_H16_FS: return launch_melt_h16(p, t, H16_FRAME_SPLIT, v.bf);
