@@ -245,11 +245,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_stft_mel(StftArgs a) {
     constexpr int BUF = (N1 * LDB > N ? N1 * LDB : N);
     extern __shared__ float smem[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    constexpr int PB = 2 * FPW * NB;              // floats of one wave's power spectra
     cf *tw = reinterpret_cast<cf *>(smem);                            // [N1][N2]: exp(-2 pi i n2 k1 / N)
     float *fbw = reinterpret_cast<float *>(tw + N);                   // [nnz]
     int *fbs = reinterpret_cast<int *>(fbw + a.fb_nnz);               // [M]
     int *fbo = fbs + a.M;                                             // [M+1]
     cf *buf = reinterpret_cast<cf *>(fbo + a.M + 2) + wid * FPW * BUF;   // this wave's FFT rows
+    // each wave's 2 FPW power spectra [2 FPW][NB]
+    float *pw = reinterpret_cast<float *>(reinterpret_cast<cf *>(fbo + a.M + 2) + WAVES * FPW * BUF) + wid * PB;
     for (int i = threadIdx.x; i < N; i += 64 * WAVES) {
         const int k1 = i / N2, n2 = i - k1 * N2;
         const float2 t = a.twiddle[(n2 * k1) % N];
@@ -331,19 +334,18 @@ __global__ __launch_bounds__(64 * WAVES) void k_stft_mel(StftArgs a) {
             }
         }
         wave_sync();
-        // steps 4-5: separate the two real spectra bin by bin inside each filter's support,
-        // |X_k|^2 (or |X_k|), triangular weights, output map, coalesced store
         const int f0 = 2 * FPW * cur_sub;
-        for (int t = lane; t < FPW * a.M; t += 64) {
-            const int p = t / a.M, m = t - p * a.M;
-            const int fa = f0 + 2 * p;
-            if (fa >= cur.n_frames) continue;
-            const cf *rowz = buf + p * BUF;
-            float acc_a = 0.0f, acc_b = 0.0f;
-            const int k0 = fbs[m];
-            for (int j = fbo[m]; j < fbo[m + 1]; ++j) {
-                const int k = k0 + (j - fbo[m]);
-                const cf zk = rowz[k], zn = rowz[(N - k) % N];
+        // step 4: separate the two real spectra of each FFT, |X_k|^2 (or |X_k|) on every bin
+        // k = 0..N/2, into pw[2 p + {0, 1}][k]
+        {
+            int p = 0, k = lane;                   // item lane + 64 i = p NB + k, advanced without division
+            for (int t = lane; t < FPW * NB; t += 64) {
+                while (k >= NB) {
+                    k -= NB;
+                    ++p;
+                }
+                const cf *rowz = buf + p * BUF;
+                const cf zk = rowz[k], zn = rowz[k == 0 ? 0 : N - k];
                 // A = (Z[k] + conj Z[N-k]) / 2,  B = (Z[k] - conj Z[N-k]) / (2i)
                 const float ar = 0.5f * (zk.x + zn.x), ai = 0.5f * (zk.y - zn.y);
                 const float br = 0.5f * (zk.y + zn.y), bi = -0.5f * (zk.x - zn.x);
@@ -352,13 +354,55 @@ __global__ __launch_bounds__(64 * WAVES) void k_stft_mel(StftArgs a) {
                     pa = sqrtf(pa);
                     pb = sqrtf(pb);
                 }
-                acc_a += fbw[j] * pa;
-                acc_b += fbw[j] * pb;
+                pw[(2 * p) * NB + k] = pa;
+                pw[(2 * p + 1) * NB + k] = pb;
+                k += 64;
             }
-            const int64_t row = cur.out_row + fa;
-            if (row < a.n_frames) a.out[row * a.M + m] = stft_out_map(acc_a, a.out_kind, a.eps);
-            if (fa + 1 < cur.n_frames && row + 1 < a.n_frames)
-                a.out[(row + 1) * a.M + m] = stft_out_map(acc_b, a.out_kind, a.eps);
+        }
+        wave_sync();
+        // step 5: one lane per (Mel filter, half of the 2 FPW spectra): each weight read serves
+        // FPW spectra, bins two at a time; sums in increasing k; output map; coalesced store
+        {
+            int h = 0, m = lane;                   // item lane + 64 i = h M + m
+            for (int t = lane; t < 2 * a.M; t += 64) {
+                while (m >= a.M) {
+                    m -= a.M;
+                    ++h;
+                }
+                const float *ps = pw + h * FPW * NB + fbs[m];
+                const int j0 = fbo[m], j1 = fbo[m + 1];
+                float acc[FPW];
+#pragma unroll
+                for (int f = 0; f < FPW; ++f) acc[f] = 0.0f;
+                int j = j0;
+                for (; j + 1 < j1; j += 2) {
+                    const float w0 = fbw[j], w1 = fbw[j + 1];
+                    float p0[FPW], p1[FPW];
+#pragma unroll
+                    for (int f = 0; f < FPW; ++f) {
+                        p0[f] = ps[f * NB + (j - j0)];
+                        p1[f] = ps[f * NB + (j - j0) + 1];
+                    }
+#pragma unroll
+                    for (int f = 0; f < FPW; ++f) {
+                        acc[f] += w0 * p0[f];
+                        acc[f] += w1 * p1[f];
+                    }
+                }
+                if (j < j1) {
+                    const float w0 = fbw[j];
+#pragma unroll
+                    for (int f = 0; f < FPW; ++f) acc[f] += w0 * ps[f * NB + (j - j0)];
+                }
+#pragma unroll
+                for (int f = 0; f < FPW; ++f) {
+                    const int fa = f0 + h * FPW + f;
+                    const int64_t row = cur.out_row + fa;
+                    if (fa < cur.n_frames && row < a.n_frames)
+                        a.out[row * a.M + m] = stft_out_map(acc[f], a.out_kind, a.eps);
+                }
+                m += 64;
+            }
         }
         wave_sync();
     }
@@ -390,7 +434,9 @@ size_t stft_lds_bytes(const StftShape &s, int M, int nnz) {
     const int LDB = s.N2 + 1;
     const int BUF = std::max(s.N1 * LDB, N);
     const size_t head = (size_t)N * 8 + (size_t)nnz * 4 + (size_t)(2 * M + 2) * 4;
-    return ((head + 7) / 8) * 8 + (size_t)kStftWaves * s.FPW * BUF * 8;
+    size_t bytes = ((head + 7) / 8) * 8 + (size_t)kStftWaves * s.FPW * BUF * 8;
+    bytes += (size_t)kStftWaves * 2 * s.FPW * (N / 2 + 1) * 4;      // power spectra
+    return bytes;
 }
 
 template <int N1, int N2, int SUB>
