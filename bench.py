@@ -203,6 +203,7 @@ def main():
         return 0
 
     fp32, plan32 = run_melt("fp32")
+    plan32_variant = 0          # the plan's default kernel variant, the one timed
     comparator = run_stft()
     variants = {}
     if not args.no_variants:
@@ -217,7 +218,7 @@ def main():
     achieved = T * flop_per_frame / (fp32["kernel_ms"] * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32"] / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / (PEAK["f32"] / 1e12), "traffic": traffic,
-                "kernel": "k_melt_f32_fs (MelT FP32 projection + energy + log)",
+                "kernel": f"{melt.melt_variant_name(plan32.handle, plan32_variant)} (MelT FP32 projection + energy + log)",
                 "flop_per_launch": T * flop_per_frame, "kernel_ms": fp32["kernel_ms"],
                 "kernel_source_id": source_id}
 
