@@ -65,9 +65,13 @@ typedef enum { MELT_FB_NORM_NONE = 0, MELT_FB_NORM_SLANEY = 1 } melt_fb_norm;
 
 /* Output map applied to S = R^2 + I^2 (MelT) or to the filterbank sum (comparator):
  * ln(S + eps) (Eq. meltf), ln(sqrt(S) + eps), S, sqrt(S).  For the comparator the
- * magnitude kinds aggregate |X_k| instead of |X_k|^2. */
+ * magnitude kinds aggregate |X_k| instead of |X_k|^2.  MELT_OUT_MFCC is the cepstrum of
+ * the log power, C = ln(S + eps) D^T with D the first n_mfcc rows of the orthonormal
+ * DCT-II over the M Mel bins (Eq. mfcct_matrix: MFCCT for MelT; conventional MFCC for the
+ * comparator); its rows are n_mfcc wide instead of n_mels. */
 typedef enum {
-    MELT_OUT_LOG_POWER = 0, MELT_OUT_LOG_MAGNITUDE = 1, MELT_OUT_POWER = 2, MELT_OUT_MAGNITUDE = 3
+    MELT_OUT_LOG_POWER = 0, MELT_OUT_LOG_MAGNITUDE = 1, MELT_OUT_POWER = 2, MELT_OUT_MAGNITUDE = 3,
+    MELT_OUT_MFCC = 4
 } melt_output;
 
 /* Arithmetic of the projection GEMM (all accumulate in FP32; the basis is computed in
@@ -97,6 +101,7 @@ typedef struct {
     double  log_eps;       /* eps of the log kinds, >= 1.18e-38 (the smallest normal FP32; default 1e-10) */
     int32_t precision;     /* melt_precision of melt_forward */
     int32_t fb_norm;       /* melt_fb_norm of stft_mel_forward */
+    int32_t n_mfcc;        /* K, cepstral coefficients of MELT_OUT_MFCC, 1 .. n_mels (default 40) */
 } melt_config;
 
 typedef struct melt_plan_s *melt_plan;
@@ -104,7 +109,7 @@ typedef struct melt_stream_s *melt_stream_state;
 
 /* Fills `cfg` with the paper's spectral configuration at 16 kHz: N = 400, H = 160,
  * M = 80, symmetric Hann, HTK, filter-centre placement, fmin 0, fmax 8000, log power,
- * eps 1e-10, FP32, peak-1 filters.  cfg: host, caller-owned. */
+ * eps 1e-10, FP32, peak-1 filters, 40 cepstral coefficients.  cfg: host, caller-owned. */
 melt_status melt_config_default(melt_config *cfg);
 
 /* Number of frames of a clip of n_samples samples (see the conventions above); 0 if
@@ -157,7 +162,9 @@ melt_status melt_frame_offsets(melt_plan plan, const int64_t *d_clip_offsets, in
  *   n_frames       T, the number of rows of d_out; the sum of the clips' frame counts must
  *                  equal it (rows past the computed total are left untouched and frames
  *                  beyond n_frames are not written)
- *   d_out          device float32 [n_frames, n_mels] (written)
+ *   d_out          device float32 [n_frames, n_mels] (written); [n_frames, n_mfcc] for
+ *                  MELT_OUT_MFCC, which runs the Mel kernel into a plan workspace and then
+ *                  the DCT-II product
  * Errors: MELT_E_INVALID_ARG (NULL pointers with n_frames > 0, negative counts). */
 melt_status melt_forward(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets,
                          int32_t n_clips, int64_t n_frames, float *d_out, void *stream);
@@ -194,7 +201,8 @@ melt_status stft_mel_forward_prepared(melt_plan plan, const float *d_wave, float
  *   G[t, 2m]   = g[t,m] map'(S) 2 R[t,m],  G[t, 2m+1] = g[t,m] map'(S) 2 I[t,m]
  *   d_grad_wave[s] = sum over frames t and n with start_t + n = s of (G W)[t, n]
  *   d_grad_basis   = G^T X in the stacked order of melt_plan_get_basis
- *   d_grad_out   device float32 [n_frames, n_mels] (read only)
+ *   d_grad_out   device float32 [n_frames, n_mels] (read only); [n_frames, n_mfcc] for
+ *                MELT_OUT_MFCC (the cepstrum is linear: dL = dC D, then as log power)
  *   d_proj       device float32 [n_frames, 2 n_mels] from melt_forward_proj, or NULL to
  *                recompute the projections
  *   d_grad_wave  device float32, same length as d_wave's samples up to
@@ -218,9 +226,12 @@ melt_status melt_backward(melt_plan plan, const float *d_wave, const int64_t *d_
  *   melt_stream_push     appends chunk_len (1..max_chunk_len) samples to every stream:
  *                        d_chunk device float32 [n_streams, chunk_len] (row-major);
  *                        writes stream s's new frames to d_out (device float32
- *                        [n_streams, max_frames, n_mels]) rows [s * max_frames, + k) and
- *                        k to d_frames_emitted[s] (device int32 [n_streams]).
- * A push is three kernel launches (assemble, project, keep the tail) with no host
+ *                        [n_streams, max_frames, n_mels], or n_mfcc wide for
+ *                        MELT_OUT_MFCC) rows [s * max_frames, + k) and k to
+ *                        d_frames_emitted[s] (device int32 [n_streams]); under
+ *                        MELT_OUT_MFCC the rows past k are written too, with no meaning.
+ * A push is three kernel launches (four under MELT_OUT_MFCC: assemble, project, cepstrum,
+ * keep the tail) with no host
  * synchronisation and no allocation: it can be captured in a hipGraph and replayed with
  * new chunk contents (one graph per chunk length).  Pushes on one state must be ordered
  * (one stream). */

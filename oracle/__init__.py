@@ -277,5 +277,13 @@ def dct2_ortho(K: int, M: int) -> np.ndarray:
     return D
 
 
+def cepstrum(L: np.ndarray, K: int) -> np.ndarray:
+    """Eq. mfcct_matrix: C = L D^T for log-Mel rows L [T, M] and D the first K rows of the
+    orthonormal DCT-II over M (MFCCT when L is the MelT log power, conventional MFCC when L
+    is the filterbank log power)."""
+    L = np.asarray(L, np.float64)
+    return L @ dct2_ortho(K, L.shape[1]).T
+
+
 def num_threads() -> int:
     return int(lib().oracle_num_threads())

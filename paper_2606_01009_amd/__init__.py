@@ -27,7 +27,7 @@ MELT_WIN_HANN_SYMMETRIC, MELT_WIN_HANN_PERIODIC, MELT_WIN_RECT = range(3)
 MELT_MEL_HTK, MELT_MEL_SLANEY = range(2)
 MELT_PLACE_FILTER_CENTRES, MELT_PLACE_LINSPACE = range(2)
 MELT_FB_NORM_NONE, MELT_FB_NORM_SLANEY = range(2)
-MELT_OUT_LOG_POWER, MELT_OUT_LOG_MAGNITUDE, MELT_OUT_POWER, MELT_OUT_MAGNITUDE = range(4)
+MELT_OUT_LOG_POWER, MELT_OUT_LOG_MAGNITUDE, MELT_OUT_POWER, MELT_OUT_MAGNITUDE, MELT_OUT_MFCC = range(5)
 MELT_PREC_FP32, MELT_PREC_BF16, MELT_PREC_FP16, MELT_PREC_FP8_E4M3, MELT_PREC_BF16X3 = range(5)
 PRECISIONS = {"fp32": MELT_PREC_FP32, "bf16": MELT_PREC_BF16, "fp16": MELT_PREC_FP16,
               "fp8": MELT_PREC_FP8_E4M3, "bf16x3": MELT_PREC_BF16X3}
@@ -48,7 +48,7 @@ class melt_config(ctypes.Structure):
                 ("window", ctypes.c_int32), ("n_mels", ctypes.c_int32), ("fmin", ctypes.c_double),
                 ("fmax", ctypes.c_double), ("mel_formula", ctypes.c_int32), ("placement", ctypes.c_int32),
                 ("output", ctypes.c_int32), ("log_eps", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("fb_norm", ctypes.c_int32)]
+                ("fb_norm", ctypes.c_int32), ("n_mfcc", ctypes.c_int32)]
 
 
 _lib = None
@@ -271,7 +271,8 @@ def melt_set_variant(plan, v: int, grid_per_cu: int = 0) -> None:
 
 def make_config(sample_rate=16000.0, n_fft=400, hop=160, n_mels=80, fmin=0.0, fmax=None, *,
                 precision="fp32", output=MELT_OUT_LOG_POWER, log_eps=1e-10, window=MELT_WIN_HANN_SYMMETRIC,
-                mel_formula=MELT_MEL_HTK, placement=MELT_PLACE_FILTER_CENTRES, fb_norm=MELT_FB_NORM_NONE):
+                mel_formula=MELT_MEL_HTK, placement=MELT_PLACE_FILTER_CENTRES, fb_norm=MELT_FB_NORM_NONE,
+                n_mfcc=40):
     c = melt_config_default()
     c.sample_rate = float(sample_rate)
     c.n_fft = int(n_fft)
@@ -286,6 +287,7 @@ def make_config(sample_rate=16000.0, n_fft=400, hop=160, n_mels=80, fmin=0.0, fm
     c.mel_formula = int(mel_formula)
     c.placement = int(placement)
     c.fb_norm = int(fb_norm)
+    c.n_mfcc = int(n_mfcc)
     return c
 
 
@@ -296,7 +298,7 @@ def total_frames(clip_offsets, n_fft: int, hop: int) -> int:
 
 class MeltStream:
     """Owns a streaming state over a MeltPlan; push() takes a [n_streams, chunk_len] tensor and
-    returns (frames [n_streams, max_frames, n_mels], counts [n_streams]) device tensors (reused
+    returns (frames [n_streams, max_frames, out_cols], counts [n_streams]) device tensors (reused
     between pushes)."""
 
     def __init__(self, plan: "MeltPlan", n_streams: int, max_chunk_len: int):
@@ -306,7 +308,7 @@ class MeltStream:
         self.handle = melt_stream_create(plan.handle, n_streams, max_chunk_len)
         self.max_frames = melt_stream_max_frames(self.handle)
         dev = f"cuda:{plan.device}"
-        self.out = torch.zeros((n_streams, self.max_frames, plan.n_mels), dtype=torch.float32, device=dev)
+        self.out = torch.zeros((n_streams, self.max_frames, plan.out_cols), dtype=torch.float32, device=dev)
         self.count = torch.zeros(n_streams, dtype=torch.int32, device=dev)
 
     def push(self, chunk):
@@ -336,6 +338,8 @@ class MeltPlan:
         self.device = device
         self.handle = melt_plan_create(self.cfg, device)
         self.n_mels, self.n_fft, self.hop = self.cfg.n_mels, self.cfg.n_fft, self.cfg.hop
+        # width of an output row: n_mfcc cepstral coefficients under MELT_OUT_MFCC, else n_mels
+        self.out_cols = self.cfg.n_mfcc if self.cfg.output == MELT_OUT_MFCC else self.n_mels
 
     def close(self):
         if getattr(self, "handle", None) is not None and _lib is not None:
@@ -359,7 +363,7 @@ class MeltPlan:
 
     def _out(self, n_frames, cols=None):
         import torch
-        return torch.empty((n_frames, cols or self.n_mels), dtype=torch.float32, device=f"cuda:{self.device}")
+        return torch.empty((n_frames, cols or self.out_cols), dtype=torch.float32, device=f"cuda:{self.device}")
 
     def forward(self, d_wave, d_offsets, n_frames, out=None, proj=None):
         out = self._out(n_frames) if out is None else out

@@ -31,7 +31,9 @@ static melt_status validate(const melt_config &c) {
     if (c.window < 0 || c.window > 2) return set_error(MELT_E_INVALID_ARG, "bad window");
     if (c.mel_formula < 0 || c.mel_formula > 1) return set_error(MELT_E_INVALID_ARG, "bad mel_formula");
     if (c.placement < 0 || c.placement > 1) return set_error(MELT_E_INVALID_ARG, "bad placement");
-    if (c.output < 0 || c.output > 3) return set_error(MELT_E_INVALID_ARG, "bad output");
+    if (c.output < 0 || c.output > 4) return set_error(MELT_E_INVALID_ARG, "bad output");
+    if (c.output == MELT_OUT_MFCC && (c.n_mfcc < 1 || c.n_mfcc > c.n_mels))
+        return set_error(MELT_E_INVALID_ARG, "n_mfcc must be in [1, n_mels]");
     // the log epilogues take the hardware logarithm of S + eps, which needs a normal FP32 argument
     if (!(c.log_eps >= 1.1754943508222875e-38) || !std::isfinite(c.log_eps))
         return set_error(MELT_E_INVALID_ARG, "log_eps must be >= 1.18e-38 (the smallest normal FP32)");
@@ -46,7 +48,8 @@ static void free_plan(Plan *p) {
     (void)hipDeviceSynchronize();
     void *bufs[] = {p->d_basis32, p->d_pack_f32, p->d_pack_h16, p->d_pack_lo, p->d_pack_f8, p->d_rowscale,
                     p->d_fb_w, p->d_fb_start, p->d_fb_off, p->d_twiddle, p->d_window, p->d_chunks[0],
-                    p->d_chunks[1], p->d_nchunks, p->d_pack_dx, p->d_bwd_ws, p->d_bwd_rows};
+                    p->d_chunks[1], p->d_nchunks, p->d_pack_dx, p->d_bwd_ws, p->d_bwd_rows, p->d_dct,
+                    p->d_lmel};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -89,6 +92,7 @@ melt_status melt_config_default(melt_config *cfg) {
     cfg->log_eps = 1e-10;
     cfg->precision = MELT_PREC_FP32;
     cfg->fb_norm = MELT_FB_NORM_NONE;
+    cfg->n_mfcc = 40;
     return MELT_OK;
 }
 
@@ -129,6 +133,15 @@ melt_status melt_plan_create(const melt_config *cfg, int device, melt_plan *out)
         std::vector<float> b32(nb);
         for (size_t i = 0; i < nb; ++i) b32[i] = float(p->basis64[i]);
         st = hip_check(hipMemcpy(p->d_basis32, b32.data(), nb * sizeof(float), hipMemcpyHostToDevice), "upload basis");
+    }
+    p->K = cfg->output == MELT_OUT_MFCC ? cfg->n_mfcc : 0;
+    p->kern_out = cfg->output == MELT_OUT_MFCC ? MELT_OUT_LOG_POWER : cfg->output;
+    if (st == MELT_OK && p->K > 0) {
+        std::vector<float> D;
+        dct_matrix(p->K, p->M, D);
+        st = alloc((void **)&p->d_dct, D.size() * sizeof(float));
+        if (st == MELT_OK)
+            st = hip_check(hipMemcpy(p->d_dct, D.data(), D.size() * sizeof(float), hipMemcpyHostToDevice), "upload DCT");
     }
     if (st == MELT_OK) st = pack_basis(*p, nullptr);
     if (st == MELT_OK) st = stft_plan_build(*p);

@@ -522,7 +522,7 @@ inline FwdArgs make_args(const Plan &p, const Geometry &g, int S, const FwdTask 
     a.Hp = g.Hp;
     a.S = S;
     a.row_tiles = p.row_tiles;
-    a.out_kind = p.cfg.output;
+    a.out_kind = p.kern_out;
     a.eps = (float)p.cfg.log_eps;
     a.invH = (float)(1.0 / p.H);
     return a;

@@ -331,14 +331,22 @@ melt_status launch_melt_backward(Plan &p, const float *d_wave, const int64_t *d_
     const size_t g_b = sizeof(float) * n_frames * Q;
     const size_t fs_b = sizeof(int64_t) * n_frames;
     const size_t part_b = d_gbasis ? sizeof(float) * splits * Q * N : 0;
+    const size_t gl_b = p.K > 0 ? sizeof(float) * n_frames * M : 0;   // dL = dC D under MFCC
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    melt_status st = grow(&p.d_bwd_ws, &p.bwd_ws_cap, al(proj_b) + al(g_b) + al(fs_b) + al(part_b) + 256);
+    melt_status st = grow(&p.d_bwd_ws, &p.bwd_ws_cap, al(proj_b) + al(g_b) + al(fs_b) + al(part_b) + al(gl_b) + 256);
     if (st != MELT_OK) return st;
     char *w = (char *)p.d_bwd_ws;
     float *proj_ws = (float *)w;
     float *G = (float *)(w + al(proj_b));
     int64_t *fstart = (int64_t *)(w + al(proj_b) + al(g_b));
     float *part = (float *)(w + al(proj_b) + al(g_b) + al(fs_b));
+    if (p.K > 0) {
+        // the cepstrum is linear: upstream over the log-Mel rows is dC D
+        float *gl = (float *)(w + al(proj_b) + al(g_b) + al(fs_b) + al(part_b));
+        st = launch_row_matmul(d_gout, n_frames, p.K, M, p.d_dct, 1, M, gl, s);
+        if (st != MELT_OK) return st;
+        d_gout = gl;
+    }
     // forward chunk table (table 0); projections recomputed when not supplied
     st = launch_schedule(p, 0, d_off, n_clips, melt_chunk_frames(p), n_frames, s);
     if (st != MELT_OK) return st;
@@ -354,7 +362,7 @@ melt_status launch_melt_backward(Plan &p, const float *d_wave, const int64_t *d_
     if (st != MELT_OK) return st;
     const int64_t nchunk_est = n_frames / melt_chunk_frames(p) + n_clips + 1;
     const int grid_prep = (int)std::min<int64_t>(nchunk_est, (int64_t)p.cu_count * 4);
-    k_bwd_prep<<<grid_prep, 256, 0, s>>>(p.d_chunks[0], p.d_nchunks, d_gout, proj, n_frames, M, H, p.cfg.output,
+    k_bwd_prep<<<grid_prep, 256, 0, s>>>(p.d_chunks[0], p.d_nchunks, d_gout, proj, n_frames, M, H, p.kern_out,
                                          (float)p.cfg.log_eps, G, fstart);
     st = hip_check(hipGetLastError(), "bwd prep");
     if (st != MELT_OK) return st;

@@ -272,6 +272,7 @@ __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__re
                 store_tile_staged(a, ch, rt, (ft + u) * 32, lane, acc, stage);
             }
         }
+        if (nft == 0) async_wait();                // a frameless chunk (streaming) still waits for the copy
     }
 }
 

@@ -318,8 +318,16 @@ melt_status launch_melt_main(Plan &p, const float *d_wave, float *d_out, float *
     if (n_frames < 0) return set_error(MELT_E_INVALID_ARG, "no batch prepared");
     if (n_frames == 0) return MELT_OK;
     const int v = p.prepared_variant;
-    return launch_melt_table(p, v, p.d_chunks[0], p.d_nchunks, n_frames / melt_chunk_frames(p, v) + 1, n_frames,
-                             d_wave, d_out, d_proj, s);
+    if (p.K == 0)
+        return launch_melt_table(p, v, p.d_chunks[0], p.d_nchunks, n_frames / melt_chunk_frames(p, v) + 1, n_frames,
+                                 d_wave, d_out, d_proj, s);
+    // MFCCT (Eq. mfcct_matrix): log-Mel rows into the plan workspace, then C = L D^T
+    melt_status st = ensure_lmel(p, n_frames);
+    if (st == MELT_OK)
+        st = launch_melt_table(p, v, p.d_chunks[0], p.d_nchunks, n_frames / melt_chunk_frames(p, v) + 1, n_frames,
+                               d_wave, p.d_lmel, d_proj, s);
+    if (st != MELT_OK) return st;
+    return launch_row_matmul(p.d_lmel, n_frames, p.M, p.K, p.d_dct, p.M, 1, d_out, s);
 }
 
 melt_status launch_melt_table(Plan &p, int variant, const Chunk *tab, const int *n_tab, int64_t est_chunks,

@@ -149,6 +149,7 @@ __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__r
             store_tile_staged(a, ch, rt, ft * 32, lane, acc0, stage);
             if (two) store_tile_staged(a, ch, rt, (ft + 1) * 32, lane, acc1, stage);
         }
+        if (nft == 0) async_wait();                // a frameless chunk (streaming) still waits for the copy
     }
 }
 

@@ -81,6 +81,12 @@ struct Plan {
     size_t bwd_ws_cap = 0;
     void *d_bwd_rows = nullptr;
     size_t bwd_rows_cap = 0;
+    // MFCCT: the K x M DCT-II (device) and the log-Mel workspace it reads (grown on demand)
+    int K = 0;                         // cepstral coefficients (MELT_OUT_MFCC), else 0
+    int kern_out = 0;                  // output map of the Mel kernels (log power under MFCC)
+    float *d_dct = nullptr;
+    float *d_lmel = nullptr;
+    size_t lmel_cap = 0;
     // tuning
     int cu_count = 256;
     int tune_variant = 0;                          // index of the chosen kernel variant
@@ -119,6 +125,11 @@ int forward_variants(const Plan &p);
 void apply_tune_cache(Plan &p);          // stream.hip: apply a MELT_AUTOTUNE_CACHE entry
 const char *forward_variant_name(const Plan &p, int variant);
 melt_status stft_plan_build(Plan &p);
+// MFCCT (mfcc.hip): out[r][j] = sum_i in[r][i] A[j sj + i si]; the DCT-II; the workspace
+melt_status launch_row_matmul(const float *in, int64_t rows, int I, int J, const float *A, int sj, int si, float *out,
+                              hipStream_t s);
+void dct_matrix(int K, int M, std::vector<float> &D);
+melt_status ensure_lmel(Plan &p, int64_t rows);
 melt_status launch_melt_backward(Plan &p, const float *d_wave, const int64_t *d_off, int n_clips,
                                  int64_t n_frames, const float *d_gout, const float *d_proj,
                                  float *d_gwave, float *d_gbasis, hipStream_t s);

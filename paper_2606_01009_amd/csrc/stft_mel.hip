@@ -496,11 +496,18 @@ melt_status launch_stft_main(Plan &p, const float *d_wave, float *d_out, hipStre
     const size_t lds = stft_lds_bytes(sh, p.M, p.fb_nnz);
     if (lds > 160 * 1024) return set_error(MELT_E_UNSUPPORTED, "comparator LDS too large");
     const int bf = stft_chunk_frames(p);
+    // MFCC: the log-Mel rows go to the plan workspace, then the DCT-II product to d_out
+    float *mel_out = d_out;
+    if (p.K > 0) {
+        const melt_status st = ensure_lmel(p, n_frames);
+        if (st != MELT_OK) return st;
+        mel_out = p.d_lmel;
+    }
     StftArgs a;
     a.wave = d_wave;
     a.chunks = p.d_chunks[1];
     a.n_chunks = p.d_nchunks + 1;
-    a.out = d_out;
+    a.out = mel_out;
     a.n_frames = n_frames;
     a.window = p.d_window;
     a.twiddle = p.d_twiddle;
@@ -510,19 +517,22 @@ melt_status launch_stft_main(Plan &p, const float *d_wave, float *d_out, hipStre
     a.fb_nnz = p.fb_nnz;
     a.M = p.M;
     a.H = p.H;
-    a.out_kind = p.cfg.output;
+    a.out_kind = p.kern_out;
     a.eps = (float)p.cfg.log_eps;
     const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / lds)));
     const int64_t est = (n_frames / bf + 1 + kStftWaves - 1) / kStftWaves;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, (int64_t)p.cu_count * per_cu));
+    melt_status st;
     switch (p.N) {
-    case 400: return launch_shape<20, 20, 8>(a, lds, grid, s);
-    case 512: return launch_shape<16, 32, 8>(a, lds, grid, s);
-    case 1024: return launch_shape<32, 32, 8>(a, lds, grid, s);
-    case 256: return launch_shape<16, 16, 8>(a, lds, grid, s);
-    case 1200: return launch_shape<30, 40, 16>(a, lds, grid, s);
+    case 400: st = launch_shape<20, 20, 8>(a, lds, grid, s); break;
+    case 512: st = launch_shape<16, 32, 8>(a, lds, grid, s); break;
+    case 1024: st = launch_shape<32, 32, 8>(a, lds, grid, s); break;
+    case 256: st = launch_shape<16, 16, 8>(a, lds, grid, s); break;
+    case 1200: st = launch_shape<30, 40, 16>(a, lds, grid, s); break;
     default: return set_error(MELT_E_UNSUPPORTED, "n_fft");
     }
+    if (st != MELT_OK || p.K == 0) return st;
+    return launch_row_matmul(p.d_lmel, n_frames, p.M, p.K, p.d_dct, p.M, 1, d_out, s);
 }
 
 }  // namespace melt

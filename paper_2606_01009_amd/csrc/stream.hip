@@ -27,6 +27,7 @@ struct melt_stream_s {
     float *d_asm;               // [n_streams][asm_stride]
     melt::Chunk *d_tab;         // [n_streams * cps]
     int *d_ntab;
+    float *d_lmel;              // [n_streams * max_frames][n_mels] log-Mel rows (MELT_OUT_MFCC only)
 };
 
 namespace melt {
@@ -165,6 +166,11 @@ melt_status melt_stream_create(melt_plan plan, int32_t n_streams, int32_t max_ch
     ok = ok && hipMalloc(&S->d_asm, sizeof(float) * (size_t)n_streams * S->asm_stride) == hipSuccess;
     ok = ok && hipMalloc(&S->d_tab, sizeof(Chunk) * (size_t)n_streams * S->cps) == hipSuccess;
     ok = ok && hipMalloc(&S->d_ntab, sizeof(int)) == hipSuccess;
+    S->d_lmel = nullptr;
+    if (ok && p->K > 0) {
+        const size_t bytes = sizeof(float) * (size_t)n_streams * S->max_frames * p->M;
+        ok = hipMalloc(&S->d_lmel, bytes) == hipSuccess && hipMemset(S->d_lmel, 0, bytes) == hipSuccess;
+    }
     if (!ok) {
         melt_stream_destroy(S);
         return set_error(MELT_E_NO_MEMORY, "stream buffers");
@@ -183,7 +189,7 @@ melt_status melt_stream_destroy(melt_stream_state S) {
     if (!S) return MELT_OK;
     (void)hipSetDevice(S->plan->device);
     (void)hipDeviceSynchronize();
-    void *b[] = {S->d_carry, S->d_carry_len, S->d_asm, S->d_tab, S->d_ntab};
+    void *b[] = {S->d_carry, S->d_carry_len, S->d_asm, S->d_tab, S->d_ntab, S->d_lmel};
     for (void *x : b)
         if (x) (void)hipFree(x);
     delete S;
@@ -211,9 +217,15 @@ melt_status melt_stream_push(melt_stream_state S, const float *d_chunk, int32_t 
                                                    d_frames_emitted, S->n_streams);
     st = hip_check(hipGetLastError(), "stream assemble");
     if (st != MELT_OK) return st;
-    st = launch_melt_table(p, S->variant, S->d_tab, S->d_ntab, (int64_t)S->n_streams * S->cps,
-                           (int64_t)S->n_streams * S->max_frames, S->d_asm, d_out, nullptr, s);
+    const int64_t rows = (int64_t)S->n_streams * S->max_frames;
+    st = launch_melt_table(p, S->variant, S->d_tab, S->d_ntab, (int64_t)S->n_streams * S->cps, rows, S->d_asm,
+                           p.K > 0 ? S->d_lmel : d_out, nullptr, s);
     if (st != MELT_OK) return st;
+    if (p.K > 0) {
+        // MFCCT over the whole slot block (rows past a stream's emitted count carry no meaning)
+        st = launch_row_matmul(S->d_lmel, rows, p.M, p.K, p.d_dct, p.M, 1, d_out, s);
+        if (st != MELT_OK) return st;
+    }
     k_stream_keep<<<S->n_streams, 256, 0, s>>>(chunk_len, S->d_carry, S->d_carry_len, p.N, p.H, S->d_asm,
                                                S->asm_stride);
     return hip_check(hipGetLastError(), "stream keep");

@@ -103,6 +103,51 @@ def fft_pair_norms(wave, offsets, n_fft, hop, window):
     return np.concatenate(out) if out else np.zeros(0)
 
 
+def log_error_radius(R, I, A_r, A_i, n_terms, eps, extra_rel=1.0):
+    """A finite per-bin bound on |L_gpu - L| for the cepstrum: the log_power_bound, and on
+    vacuous bins the width of the interval the GPU value is confined to."""
+    bound, vac, S, dS = log_power_bound(R, I, A_r, A_i, n_terms, eps, extra_rel)
+    L = np.log(S + eps)
+    width = np.maximum(np.log(S + dS + eps) - L, L - np.log(eps * (1 - 2 * U32))) + 1e-6
+    return np.where(vac, width, bound), L
+
+
+def check_cepstrum(C_gpu, L, bL, D, label=""):
+    """C = L D^T (Eq. mfcct_matrix) from log-Mel rows L with per-bin error radius bL: the
+    FP32 product adds gamma_M sum |D||L| plus the FP32 rounding of D (u sum |D||L|), so
+        |C_gpu - C| <= |D| bL + (gamma_M + u) |D| |L| + u |C|."""
+    C_gpu = np.asarray(C_gpu, np.float64)
+    M = D.shape[1]
+    C = L @ D.T
+    g = M * U32 / (1 - M * U32) + U32
+    bound = bL @ np.abs(D).T + g * (np.abs(L) @ np.abs(D).T) + U32 * np.abs(C) + 1e-30
+    err = np.abs(C_gpu - C)
+    bad = err > bound
+    if np.any(bad):
+        idx = np.argwhere(bad)[:8]
+        lines = [f"t={t} k={k} gpu={C_gpu[t, k]:.9g} oracle={C[t, k]:.9g} err={err[t, k]:.3g} bound={bound[t, k]:.3g}"
+                 for t, k in idx]
+        raise AssertionError(f"{label}: {int(bad.sum())} of {bad.size} coefficients beyond the bound\n" + "\n".join(lines))
+    return {"max_abs": float(err.max()) if err.size else 0.0, "max_bound": float(bound.max()) if bound.size else 0.0}
+
+
+def stft_log_bound(P, F, pair_norm2, n_fft, eps, c_fft=4.0):
+    """Per-bin bound of the FFT + filterbank log-Mel output (see check_stft_log); returns
+    (bound, vacuous, mel, dmel)."""
+    levels = np.log2(n_fft)
+    delta = c_fft * U32 * levels * np.sqrt(n_fft * pair_norm2)
+    absX = np.sqrt(P)
+    dP = 2 * absX * delta[:, None] + delta[:, None] ** 2
+    mel = P @ F.T
+    nnz = np.count_nonzero(F, axis=1)
+    dmel = dP @ F.T + (nnz[None, :] + 3) * U32 * mel
+    den = mel + eps - dmel
+    vac = den <= 0
+    L = np.log(mel + eps)
+    bound = np.where(vac, np.inf, dmel / np.where(vac, 1.0, den)) + 4 * np.spacing(np.abs(L).astype(np.float32)) + U32
+    return bound, vac, mel, dmel
+
+
 def check_stft_log(L_gpu, P, F, pair_norm2, n_fft, eps, c_fft=4.0, label=""):
     """Bound for the FFT + filterbank path.  A floating-point FFT of size N has a norm-wise
     error ||dZ||_2 <= levels * eta * ||Z||_2 with eta a few u per butterfly level; Z here

@@ -407,3 +407,22 @@ def test_paper_log_convention(orc):
     # the other candidate conventions do not reproduce the printed pair
     assert round(d["nat"] * 20.0 / math.log(10.0), 2) != d["dB"]
     assert round(d["nat"] * 10.0, 2) != d["dB"]
+
+
+def test_cepstrum_closed_forms(orc):
+    """Eq. mfcct_matrix: a constant log-Mel row c has only the DC coefficient c sqrt(M); with
+    K = M the orthonormal DCT-II inverts exactly (C D = L); a single cosine row
+    cos(pi k0 (m + 1/2) / M) has only coefficient k0, of size sqrt(M / 2)."""
+    M = 80
+    L = np.full((2, M), -3.25)
+    C = orc.cepstrum(L, 40)
+    assert np.allclose(C[:, 0], -3.25 * np.sqrt(M), rtol=1e-14) and np.allclose(C[:, 1:], 0.0, atol=1e-12)
+    rng = np.random.default_rng(4)
+    L = rng.standard_normal((5, M))
+    C = orc.cepstrum(L, M)
+    assert np.allclose(C @ orc.dct2_ortho(M, M), L, atol=1e-12)
+    k0 = 7
+    row = np.cos(np.pi * k0 * (np.arange(M) + 0.5) / M)[None, :]
+    C = orc.cepstrum(row, 40)
+    assert abs(C[0, k0] - np.sqrt(M / 2)) < 1e-12
+    assert np.allclose(np.delete(C[0], k0), 0.0, atol=1e-12)
