@@ -109,6 +109,70 @@ def load_traffic(path, source_id):
     return t.get("hbm_bytes_per_launch")
 
 
+def call_ms(torch, fn, calls=20, warmup=5, busy_ms=30.0):
+    """Median over 5 trials of the mean time of `calls` back-to-back calls (HIP events),
+    after about busy_ms of back-to-back calls so that the clocks have ramped up."""
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < busy_ms:
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+    trials = sorted(time_launches(torch, fn, calls, warmup if t == 0 else 1) for t in range(5))
+    return trials[2]
+
+
+def run_workloads(torch, melt, workloads, path):
+    """The paper's efficiency workloads (Experiments) on synthetic stand-ins: per call,
+    MelT FP32 / BF16 / BF16x3 against the FFT + filterbank path, each call a whole
+    forward (chunk schedule + kernel).  Spectral configuration 16 kHz, N=400, H=160, fmin 80,
+    fmax 7600; cepstral configuration N=1200, M=128, K=40, 0-8 kHz (Table "Audio frontend
+    configuration")."""
+    rows = []
+
+    def measure(tag, wave, offsets, sr, N, H, M, fmin, fmax, output=0, K=40, precs=("fp32", "bf16", "bf16x3")):
+        T = melt.total_frames(offsets, N, H)
+        d_wave = torch.from_numpy(wave).cuda()
+        d_off = torch.from_numpy(offsets).cuda()
+        cols = K if output == melt.MELT_OUT_MFCC else M
+        out = torch.empty((T, cols), dtype=torch.float32, device="cuda")
+        rec = {"workload": tag, "frames": T, "clips": len(offsets) - 1, "n_fft": N, "hop": H, "n_mels": M,
+               "output": "mfcc" if output == melt.MELT_OUT_MFCC else "log_power"}
+        for prec in precs:
+            try:
+                plan = melt.MeltPlan(sample_rate=sr, n_fft=N, hop=H, n_mels=M, fmin=fmin, fmax=fmax, precision=prec,
+                                     output=output, n_mfcc=K)
+                rec[f"melt_{prec}_ms"] = call_ms(torch, lambda: plan.forward(d_wave, d_off, T, out=out))
+            except melt.MeltError as e:
+                rec[f"melt_{prec}_error"] = str(e)
+        plan = melt.MeltPlan(sample_rate=sr, n_fft=N, hop=H, n_mels=M, fmin=fmin, fmax=fmax, output=output, n_mfcc=K)
+        rec["fft_ms"] = call_ms(torch, lambda: plan.stft_mel(d_wave, d_off, T, out=out))
+        for prec in precs:
+            if f"melt_{prec}_ms" in rec:
+                rec[f"speedup_{prec}_vs_fft"] = rec["fft_ms"] / rec[f"melt_{prec}_ms"]
+        log(f"workload {tag}: " + ", ".join(f"{k} {v:.4g}" for k, v in rec.items() if isinstance(v, float)))
+        rows.append(rec)
+
+    # cepstral configuration: MFCCT vs MFCC on the 64 x 30 s batch
+    cfg = workloads.config2(n_fft=1200, hop=160)
+    measure("cepstral 64x30s N=1200 M=128 K=40 (MFCCT vs MFCC)", cfg["wave"], cfg["offsets"], 16000.0, 1200, 160,
+            128, 0.0, 8000.0, output=melt.MELT_OUT_MFCC, precs=("fp32", "bf16"))
+    # duration sweep: one clip of 1..160 s
+    for sec in (1, 4, 10, 40, 160):
+        cfg = workloads.config2(n_clips=1, seconds=float(sec))
+        measure(f"duration {sec} s", cfg["wave"], cfg["offsets"], 16000.0, 400, 160, 80, 80.0, 7600.0)
+    # Mel-bin sweep on 16 clips of 4 s
+    for M in (40, 80, 128, 256, 512):
+        cfg = workloads.config2(n_mels=M, n_clips=16, seconds=4.0)
+        measure(f"n_mels {M} (16 x 4 s)", cfg["wave"], cfg["offsets"], 16000.0, 400, 160, M, 80.0, 7600.0)
+    # batch sweep of 4 s clips
+    for B in (1, 16, 64, 256):
+        cfg = workloads.config2(n_clips=B, seconds=4.0)
+        measure(f"batch {B} x 4 s", cfg["wave"], cfg["offsets"], 16000.0, 400, 160, 80, 80.0, 7600.0)
+    with open(path, "w") as fh:
+        for r in rows:
+            fh.write(json.dumps(r) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +184,9 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the sampled error check")
     ap.add_argument("--only", default=None, help="time one path only: fp32|bf16|fp16|bf16x3|fp8|stft|copy (profiling)")
     ap.add_argument("--sweep", action="store_true", help="time every kernel variant of every precision and exit")
+    ap.add_argument("--workloads", default=None,
+                    help="write the paper's efficiency workloads on synthetic stand-ins (cepstral configuration, "
+                         "duration, Mel-bin and batch sweeps) as JSON lines to this file and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported (the frames of a batch "
@@ -180,6 +247,10 @@ def main():
             res["error_vs_fp64_oracle"] = sampled_error_db(out.cpu().numpy(), wave, offsets, "stft", None, n_mels=M)
         log(f"bench: FFT+filterbank: {res['frames_per_s'] / 1e6:.1f} M frames/s, kernel {kern_ms * 1e3:.1f} us")
         return res
+
+    if args.workloads:
+        run_workloads(torch, melt, workloads, args.workloads)
+        return 0
 
     if args.sweep:
         for prec in ("fp32", "bf16", "fp16", "bf16x3", "fp8"):

@@ -12,7 +12,7 @@ namespace melt {
 __global__ __launch_bounds__(1024) void k_schedule(const int64_t *__restrict__ off, int n_clips, int N,
                                                    int H, int bf, Chunk *__restrict__ tab, int64_t cap,
                                                    int *__restrict__ n_out) {
-    __shared__ int64_t sf[1024], sc[1024];
+    __shared__ int64_t sf[1024], sc[1024], s_start[1024], s_len[1024];
     __shared__ int64_t carry_f, carry_c;
     const int tid = threadIdx.x;
     if (tid == 0) carry_f = carry_c = 0;
@@ -28,8 +28,10 @@ __global__ __launch_bounds__(1024) void k_schedule(const int64_t *__restrict__ o
         const int64_t K = (T + bf - 1) / bf;
         sf[tid] = T;
         sc[tid] = K;
+        s_start[tid] = st;
+        s_len[tid] = L;
         __syncthreads();
-        for (int d = 1; d < 1024; d <<= 1) {
+        for (int d = 1; d < 1024; d <<= 1) {           // inclusive prefix sums of T and K
             const int64_t vf = tid >= d ? sf[tid - d] : 0;
             const int64_t vc = tid >= d ? sc[tid - d] : 0;
             __syncthreads();
@@ -37,17 +39,29 @@ __global__ __launch_bounds__(1024) void k_schedule(const int64_t *__restrict__ o
             sc[tid] += vc;
             __syncthreads();
         }
-        const int64_t fb = carry_f + sf[tid] - T;
-        const int64_t cb = carry_c + sc[tid] - K;
-        for (int64_t k = 0; k < K; ++k) {
-            const int64_t idx = cb + k;
+        // entries of this block of clips, written by all threads: entry q belongs to the
+        // first clip t whose inclusive chunk prefix exceeds q (binary search)
+        const int64_t total = sc[1023];
+        for (int64_t q = tid; q < total; q += 1024) {
+            int lo = 0, hi = 1023;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (sc[mid] > q) hi = mid;
+                else lo = mid + 1;
+            }
+            const int t = lo;
+            const int64_t kc0 = t > 0 ? sc[t - 1] : 0;         // clip t's first entry in the block
+            const int64_t k = q - kc0;                          // chunk index within the clip
+            const int64_t Tt = sf[t] - (t > 0 ? sf[t - 1] : 0);
+            const int64_t fb = carry_f + (t > 0 ? sf[t - 1] : 0);
+            const int64_t idx = carry_c + q;
             if (idx >= cap) break;
             Chunk e;
-            e.sample_start = st + k * bf * (int64_t)H;
-            e.sample_end = st + L;
+            e.sample_start = s_start[t] + k * bf * (int64_t)H;
+            e.sample_end = s_start[t] + s_len[t];
             e.out_row = fb + k * bf;
-            e.n_frames = (int)((T - k * bf) < bf ? (T - k * bf) : bf);
-            e.clip = c;
+            e.n_frames = (int)((Tt - k * bf) < bf ? (Tt - k * bf) : bf);
+            e.clip = base + t;
             tab[idx] = e;
         }
         __syncthreads();
@@ -221,8 +235,14 @@ melt_status ensure_chunks(Plan &p, int which, int64_t needed) {
     return MELT_OK;
 }
 
-melt_status launch_schedule(Plan &p, int which, const int64_t *d_off, int n_clips, int bf, int64_t n_frames,
+melt_status launch_schedule(Plan &p, int which, const int64_t *d_off, int n_clips, int bf_max, int64_t n_frames,
                             hipStream_t s) {
+    // Chunks of at most bf_max frames (the kernel's LDS image).  The comparator sizes its
+    // chunks to the batch (whole sub-tasks, a few chunks per resident wave); measured, the
+    // same for the MelT kernels costs more in per-chunk overhead than it gains, so their
+    // chunks keep the full size.
+    int bf = bf_max;
+    if (which == 1 && n_frames > 0) bf = std::min(bf_max, stft_batch_chunk_frames(p, n_frames));
     const int64_t need = n_frames / bf + n_clips + 1;
     melt_status st = ensure_chunks(p, which, need);
     if (st != MELT_OK) return st;
@@ -231,6 +251,7 @@ melt_status launch_schedule(Plan &p, int which, const int64_t *d_off, int n_clip
     st = hip_check(hipGetLastError(), "schedule launch");
     if (st == MELT_OK) {
         p.prepared_frames[which] = n_frames;
+        p.prepared_bf[which] = bf;
         if (which == 0) p.prepared_variant = p.tune_variant;
     }
     return st;
@@ -318,14 +339,13 @@ melt_status launch_melt_main(Plan &p, const float *d_wave, float *d_out, float *
     if (n_frames < 0) return set_error(MELT_E_INVALID_ARG, "no batch prepared");
     if (n_frames == 0) return MELT_OK;
     const int v = p.prepared_variant;
+    const int64_t est = n_frames / p.prepared_bf[0] + 1;   // chunk count (a lower bound sizes the grid)
     if (p.K == 0)
-        return launch_melt_table(p, v, p.d_chunks[0], p.d_nchunks, n_frames / melt_chunk_frames(p, v) + 1, n_frames,
-                                 d_wave, d_out, d_proj, s);
+        return launch_melt_table(p, v, p.d_chunks[0], p.d_nchunks, est, n_frames, d_wave, d_out, d_proj, s);
     // MFCCT (Eq. mfcct_matrix): log-Mel rows into the plan workspace, then C = L D^T
     melt_status st = ensure_lmel(p, n_frames);
     if (st == MELT_OK)
-        st = launch_melt_table(p, v, p.d_chunks[0], p.d_nchunks, n_frames / melt_chunk_frames(p, v) + 1, n_frames,
-                               d_wave, p.d_lmel, d_proj, s);
+        st = launch_melt_table(p, v, p.d_chunks[0], p.d_nchunks, est, n_frames, d_wave, p.d_lmel, d_proj, s);
     if (st != MELT_OK) return st;
     return launch_row_matmul(p.d_lmel, n_frames, p.M, p.K, p.d_dct, p.M, 1, d_out, s);
 }

@@ -74,6 +74,7 @@ struct Plan {
     int64_t chunk_cap[2] = {0, 0};
     int64_t prepared_frames[2] = {-1, -1};   // n_frames of the batch each table describes
     int prepared_variant = 0;                // kernel variant table 0 was built for
+    int prepared_bf[2] = {128, 32};          // frames per chunk of each table
     // backward: dx basis layout and workspaces (grown on demand)
     void *d_pack_dx = nullptr;
     size_t pack_dx_cap = 0;
@@ -114,6 +115,7 @@ melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H
 int melt_chunk_frames(const Plan &p, int variant);
 int melt_chunk_frames(const Plan &p);
 int stft_chunk_frames(const Plan &p);
+int stft_batch_chunk_frames(const Plan &p, int64_t n_frames);   // comparator chunk size for a batch
 // main kernels over the batch prepared in table 0 / table 1
 melt_status launch_melt_main(Plan &p, const float *d_wave, float *d_out, float *d_proj, hipStream_t s);
 melt_status launch_stft_main(Plan &p, const float *d_wave, float *d_out, hipStream_t s);

@@ -486,6 +486,35 @@ int stft_chunk_frames(const Plan &p) {
     return stft_shape(p.N, sh) ? 2 * sh.FPW * sh.SUB : 32;
 }
 
+// Chunk size for a batch of n_frames, in whole sub-tasks (1 to SUB).  Waves take chunks from
+// a queue, so a batch runs in ceil(chunks / resident waves) rounds, each as long as one chunk.
+// A short batch (at most four one-sub-task rounds) takes one sub-task per chunk, which
+// spreads it widest.  Otherwise the size minimises rounds x (per-chunk cost), with a chunk
+// of s sub-tasks costing about 3 + 10 s (measured at N = 400 on 64 x 30 s: one sub-task
+// ~10 us per wave at full occupancy, ~3 us of per-chunk fetch and set-up); a partly filled
+// last round is what that avoids.
+int stft_batch_chunk_frames(const Plan &p, int64_t n_frames) {
+    StftShape sh;
+    if (!stft_shape(p.N, sh)) return 32;
+    const int sub = 2 * sh.FPW;
+    const size_t lds = stft_lds_bytes(sh, p.M, p.fb_nnz);
+    const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(lds, 1))));
+    const int64_t waves = (int64_t)p.cu_count * per_cu * kStftWaves;
+    const int64_t tasks = (n_frames + sub - 1) / sub;
+    if (tasks <= 4 * waves) return sub;
+    int best_s = 1;
+    int64_t best_cost = -1;
+    for (int s = 1; s <= sh.SUB; ++s) {
+        const int64_t chunks = (tasks + s - 1) / s;
+        const int64_t cost = (chunks + waves - 1) / waves * (3 + 10 * (int64_t)s);
+        if (best_cost < 0 || cost <= best_cost) {
+            best_cost = cost;
+            best_s = s;
+        }
+    }
+    return best_s * sub;
+}
+
 melt_status launch_stft_main(Plan &p, const float *d_wave, float *d_out, hipStream_t s) {
     StftShape sh;
     if (!stft_shape(p.N, sh) || !p.d_twiddle)
@@ -495,7 +524,7 @@ melt_status launch_stft_main(Plan &p, const float *d_wave, float *d_out, hipStre
     if (n_frames == 0) return MELT_OK;
     const size_t lds = stft_lds_bytes(sh, p.M, p.fb_nnz);
     if (lds > 160 * 1024) return set_error(MELT_E_UNSUPPORTED, "comparator LDS too large");
-    const int bf = stft_chunk_frames(p);
+    const int bf = p.prepared_bf[1];
     // MFCC: the log-Mel rows go to the plan workspace, then the DCT-II product to d_out
     float *mel_out = d_out;
     if (p.K > 0) {

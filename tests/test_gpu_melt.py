@@ -117,6 +117,18 @@ def test_ragged_edge_cases(torch, melt, orc, prec):
     assert np.array_equal(L2, L[-L2.shape[0]:])
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_many_clips_schedule(torch, melt, orc, prec):
+    """2600 clips of 0 to N + 12 H samples (empty, sub-frame and short clips): the chunk
+    schedule's prefix sums carry across blocks of 1024 clips."""
+    lengths = np.random.default_rng(31).integers(0, 400 + 12 * 160, 2600)
+    wave, off = workloads.random_clips(lengths, seed=32)
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80, precision=prec)
+    L, _ = _gpu_forward(torch, melt, plan, wave, off)
+    assert L.shape[0] == sum(melt.melt_num_frames(int(n), 400, 160) for n in lengths)
+    _check(orc, melt, plan, L, wave, off, prec, label=f"2600 clips {prec}")
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp8"])
 def test_every_kernel_variant(torch, melt, orc, prec):
     """Every kernel variant of the precision (staging scheme x frames per chunk), pinned with

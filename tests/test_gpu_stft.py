@@ -120,3 +120,30 @@ def test_full_size_sampled(torch, melt, orc):
     pos = {f: i for i, f in enumerate(ids)}
     pn = np.array([e[i] + (e[pos[f ^ 1]] if (f ^ 1) in pos else e.max()) for i, f in enumerate(ids)])
     parity.check_stft_log(L[ids], P, F, pn, 400, 1e-10, label="stft full sampled")
+
+
+def _many_lengths(n, N, H, seed):
+    """n clip lengths from 0 to N + 12 H samples (empty, sub-frame and short clips), so the
+    chunk schedule runs over several blocks of 1024 clips."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, N + 12 * H, n)
+
+
+def test_many_clips_schedule(torch, melt, orc):
+    """2600 clips: the schedule's prefix sums carry across blocks of 1024 clips, and the
+    chunk table of a short batch uses one-sub-task chunks."""
+    lengths = _many_lengths(2600, 400, 160, seed=21)
+    wave, off = workloads.random_clips(lengths, seed=22)
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80)
+    L = _run(torch, melt, plan, wave, off)
+    assert L.shape[0] == sum(melt.melt_num_frames(int(n), 400, 160) for n in lengths)
+    _check(orc, plan, L, wave, off, 16000.0, 0.0, 8000.0, label="stft 2600 clips")
+
+
+def test_long_single_clip(torch, melt, orc):
+    """One 160 s clip (15 998 frames): many chunks of one clip, written in parallel."""
+    wave, off = workloads.random_clips([160 * 16000], seed=23)
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80)
+    L = _run(torch, melt, plan, wave, off)
+    assert L.shape == (15998, 80)
+    _check(orc, plan, L, wave, off, 16000.0, 0.0, 8000.0, label="stft one 160 s clip")
