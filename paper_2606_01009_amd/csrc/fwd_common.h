@@ -120,12 +120,31 @@ struct FwdArgs {
 // smallest normal FP32 (the plan rejects smaller eps), so they are always normal.
 __device__ __forceinline__ float ln_normal(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
 
-__device__ inline float out_map(float S, int kind, float eps) {
+template <int KIND>
+__device__ __forceinline__ float out_map_k(float S, float eps) {
+    if constexpr (KIND == MELT_OUT_LOG_POWER) return ln_normal(S + eps);
+    else if constexpr (KIND == MELT_OUT_LOG_MAGNITUDE) return ln_normal(sqrtf(S) + eps);
+    else if constexpr (KIND == MELT_OUT_POWER) return S;
+    else return sqrtf(S);
+}
+
+// Energies S = R^2 + I^2 of the 8 Mel bins a lane holds in one 32x32 accumulator (register
+// pairs (4g, 4g+1) and (4g+2, 4g+3) are (R, I) of bins 2g and 2g+1), mapped to the output
+// kind.  The kind is uniform, so it is switched on once per tile rather than per element.
+template <int KIND>
+__device__ __forceinline__ void map8_k(const f32x16 &acc, float eps, float (&v)[8]) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        v[2 * g] = out_map_k<KIND>(acc[4 * g] * acc[4 * g] + acc[4 * g + 1] * acc[4 * g + 1], eps);
+        v[2 * g + 1] = out_map_k<KIND>(acc[4 * g + 2] * acc[4 * g + 2] + acc[4 * g + 3] * acc[4 * g + 3], eps);
+    }
+}
+__device__ __forceinline__ void map8(const f32x16 &acc, int kind, float eps, float (&v)[8]) {
     switch (kind) {
-    case MELT_OUT_LOG_POWER: return ln_normal(S + eps);
-    case MELT_OUT_LOG_MAGNITUDE: return ln_normal(sqrtf(S) + eps);
-    case MELT_OUT_POWER: return S;
-    default: return sqrtf(S);
+    case MELT_OUT_LOG_POWER: map8_k<MELT_OUT_LOG_POWER>(acc, eps, v); break;
+    case MELT_OUT_LOG_MAGNITUDE: map8_k<MELT_OUT_LOG_MAGNITUDE>(acc, eps, v); break;
+    case MELT_OUT_POWER: map8_k<MELT_OUT_POWER>(acc, eps, v); break;
+    default: map8_k<MELT_OUT_MAGNITUDE>(acc, eps, v); break;
     }
 }
 
@@ -141,11 +160,7 @@ __device__ inline void store_tile(const FwdArgs &a, const Chunk &ch, int rt, int
     const int mel0 = rt * 16 + 8 * h;
     if (mel0 >= a.M) return;
     float v[8];
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        v[2 * g] = out_map(acc[4 * g] * acc[4 * g] + acc[4 * g + 1] * acc[4 * g + 1], a.out_kind, a.eps);
-        v[2 * g + 1] = out_map(acc[4 * g + 2] * acc[4 * g + 2] + acc[4 * g + 3] * acc[4 * g + 3], a.out_kind, a.eps);
-    }
+    map8(acc, a.out_kind, a.eps, v);
     float *o = a.out + row * a.M + mel0;
     if (mel0 + 8 <= a.M && (a.M & 3) == 0) {
         *(f32x4 *)o = f32x4{v[0], v[1], v[2], v[3]};
@@ -425,14 +440,9 @@ __device__ __forceinline__ void wave_sync() {
 __device__ inline void store_tile_staged(const FwdArgs &a, const Chunk &ch, int rt, int f_base, int lane,
                                          const f32x16 &acc, float *stage) {
     const int h = lane >> 5, fl = lane & 31;
-    f32x4 v0, v1;
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-        v0[2 * g] = out_map(acc[4 * g] * acc[4 * g] + acc[4 * g + 1] * acc[4 * g + 1], a.out_kind, a.eps);
-        v0[2 * g + 1] = out_map(acc[4 * g + 2] * acc[4 * g + 2] + acc[4 * g + 3] * acc[4 * g + 3], a.out_kind, a.eps);
-        v1[2 * g] = out_map(acc[8 + 4 * g] * acc[8 + 4 * g] + acc[9 + 4 * g] * acc[9 + 4 * g], a.out_kind, a.eps);
-        v1[2 * g + 1] = out_map(acc[10 + 4 * g] * acc[10 + 4 * g] + acc[11 + 4 * g] * acc[11 + 4 * g], a.out_kind, a.eps);
-    }
+    float v[8];
+    map8(acc, a.out_kind, a.eps, v);
+    const f32x4 v0{v[0], v[1], v[2], v[3]}, v1{v[4], v[5], v[6], v[7]};
     *(f32x4 *)(stage + fl * kStageStride + 8 * h) = v0;
     *(f32x4 *)(stage + fl * kStageStride + 8 * h + 4) = v1;
     wave_sync();
@@ -552,8 +562,19 @@ inline size_t as_rows_bytes(const Plan &p, int bf) {
 inline size_t as_stage_offset(const Plan &p, int bf) {
     return ((((as_rows_bytes(p, bf) + 15) & ~size_t(15)) + (size_t)(bf + p.geo16.J - 1) * p.H * 4) + 15) & ~size_t(15);
 }
+// Waves of the direct-to-LDS 16-bit kernel: `full` waves own one row tile each; when one or
+// two row tiles remain beyond a multiple of four, four more waves share them (psplit waves
+// per tile), so the work spreads evenly over the CU's four SIMDs.
+struct WaveLayout {
+    int full, psplit, waves;
+};
+inline WaveLayout h16_layout(const Plan &p) {
+    const int RT = p.row_tiles, rem = RT % 4;
+    if ((rem == 1 || rem == 2) && RT - rem + 4 <= 8) return {RT - rem, 4 / rem, RT - rem + 4};
+    return {RT, 1, RT};
+}
 inline size_t as_lds_bytes(const Plan &p, int bf) {
-    return as_stage_offset(p, bf) + (size_t)p.row_tiles * kStageFloats * 4;
+    return as_stage_offset(p, bf) + (size_t)h16_layout(p).waves * kStageFloats * 4;
 }
 
 // per-family launchers (melt_f32.hip, melt_h16.hip, melt_f8.hip)

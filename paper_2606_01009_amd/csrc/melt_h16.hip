@@ -53,6 +53,43 @@ __device__ __forceinline__ void mfma_sweep(const uint4 (&A)[NS], const uint4 (&A
     __builtin_amdgcn_sched_barrier(0);
 }
 
+// Sweep over one 32-frame tile into one accumulator (back-to-back MFMAs on the same
+// accumulator forward their result).  X3: hi*hi, lo*hi and hi*lo per k-group, which keeps
+// the hi and lo basis tiles (8 NS VGPRs) beside a single tile's 16 accumulators.
+template <int NS, bool X3, bool IS_F16>
+__device__ __forceinline__ void mfma_sweep1(const uint4 (&A)[NS], const uint4 (&Al)[X3 ? NS : 1],
+                                            const unsigned short *l0, const GroupTableBig &gt, int lo_off,
+                                            f32x16 &acc) {
+    constexpr int D = X3 ? 1 : 4;
+    uint4 b[D], c[X3 ? D : 1];
+    auto fetch = [&](int s, int slot) {
+        const int o = gt.lds_off[s];
+        b[slot] = *(const uint4 *)(l0 + o);
+        if constexpr (X3) c[slot] = *(const uint4 *)(l0 + lo_off + o);
+    };
+#pragma unroll
+    for (int s = 0; s < D && s < NS; ++s) fetch(s, s);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int slot = s % D;
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (IS_F16) {
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, A[s]),
+                                                         __builtin_bit_cast(f16x8, b[slot]), acc, 0, 0, 0);
+        } else {
+            const bf16x8 ah = __builtin_bit_cast(bf16x8, A[s]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, __builtin_bit_cast(bf16x8, b[slot]), acc, 0, 0, 0);
+            if constexpr (X3) {
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, Al[s]),
+                                                              __builtin_bit_cast(bf16x8, b[slot]), acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, __builtin_bit_cast(bf16x8, c[slot]), acc, 0, 0, 0);
+            }
+        }
+        if (s + D < NS) fetch(s + D, slot);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // ------------------------------------------------------------------ 16-bit row-split kernel
 //
 // One wave per 32-row basis tile (16 Mel bins); the wave keeps its whole basis tile in
@@ -101,12 +138,24 @@ __global__ __launch_bounds__(512) void k_melt_h16_rs(FwdArgs a, const uint4 *__r
 // Row-split 16-bit kernel with direct-to-LDS staging (default for BF16/FP16/BF16X3): as
 // k_melt_h16_rs, but chunk c+1's span is copied into an FP32 scratch area while chunk c is
 // multiplied; after a barrier all threads convert it into the operand rows.
+//
+// Wave layout (balanced over the CU's four SIMDs): waves 0..full-1 each own one row tile and
+// sweep every frame tile of the chunk, two at a time; the remaining row tiles (one or two)
+// are shared by four waves, psplit per tile, each taking every psplit-th frame tile.  With
+// 80 Mel bins (5 row tiles) that is 8 waves, 4 for tile 4, so every SIMD carries 1.25 row
+// tiles of work instead of one SIMD carrying two.
 template <class Conv, int NS, bool X3, bool IS_F16>
 __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__restrict__ bhi,
                                                      const uint4 *__restrict__ blo, GroupTableBig gt, int bf,
-                                                     int scr_off, int stage_off) {
+                                                     int scr_off, int stage_off, int full, int psplit) {
     extern __shared__ float lds_as[];
-    const int lane = threadIdx.x & 63, rt = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int rt = wid, part = 0, P = 1;
+    if (wid >= full) {
+        rt = full + (wid - full) / psplit;
+        part = (wid - full) % psplit;
+        P = psplit;
+    }
     const int lo_off = a.S * (bf + a.J - 1);
     unsigned short *rows = reinterpret_cast<unsigned short *>(lds_as);
     float *scratch = lds_as + scr_off;             // FP32 span, after the operand rows
@@ -119,7 +168,7 @@ __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__r
 #pragma unroll
         for (int s = 0; s < NS; ++s) Al[s] = blo[((size_t)rt * NS + s) * 64 + lane];
     }
-    float *stage = lds_as + stage_off + rt * kStageFloats;
+    float *stage = lds_as + stage_off + wid * kStageFloats;
     const int nch = *a.n_chunks;
     int c = blockIdx.x;
     if (c < nch) async_span(a, read_chunk(a.chunks, c), scratch);
@@ -131,25 +180,41 @@ __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__r
         __syncthreads();                           // rows ready; scratch is free
         if (c + (int)gridDim.x < nch) async_span(a, read_chunk(a.chunks, c + gridDim.x), scratch);
         const int nft = (ch.n_frames + 31) >> 5;
-        for (int ft = 0; ft < nft; ft += 2) {
-            const bool two = ft + 1 < nft;
+        // The next chunk's copy must land before the barrier that starts the next iteration.
+        // Each wave waits ahead of its last tile's stores (so those stores stay in flight
+        // across the barrier), or after the loop if it had no tile.
+        bool waited = false;
+        const int step = (P == 1 && !X3) ? 2 : P;
+        for (int ft = part; ft < nft; ft += step) {
             f32x16 acc0 = f32x16{}, acc1 = f32x16{};
             // opaque to the optimiser, so that it does not keep (lane offset + group offset)
             // of every k-group live in registers across the loop
             int off = (ft * 32 + (lane & 31)) * a.S + 8 * (lane >> 5);
             asm volatile("" : "+v"(off));
             const unsigned short *l0 = rows + off;
-            // a lone last tile multiplies its own rows twice rather than branching
-            const unsigned short *l1 = two ? l0 + 32 * a.S : l0;
-            mfma_sweep<NS, X3, IS_F16>(A, Al, l0, l1, gt, lo_off, acc0, acc1);
-            // the next chunk's copy must land before the barrier that starts the next
-            // iteration; waiting here, ahead of the last tiles' stores, leaves those stores
-            // in flight across the barrier instead of waiting for them too
-            if (ft + 2 >= nft) async_wait();
+            if constexpr (!X3) {
+                if (step == 2) {
+                    const bool two = ft + 1 < nft;
+                    // a lone last tile multiplies its own rows twice rather than branching
+                    const unsigned short *l1 = two ? l0 + 32 * a.S : l0;
+                    mfma_sweep<NS, false, IS_F16>(A, Al, l0, l1, gt, lo_off, acc0, acc1);
+                    if (ft + 2 >= nft) {
+                        async_wait();
+                        waited = true;
+                    }
+                    store_tile_staged(a, ch, rt, ft * 32, lane, acc0, stage);
+                    if (two) store_tile_staged(a, ch, rt, (ft + 1) * 32, lane, acc1, stage);
+                    continue;
+                }
+            }
+            mfma_sweep1<NS, X3, IS_F16>(A, Al, l0, gt, lo_off, acc0);
+            if (ft + step >= nft) {
+                async_wait();
+                waited = true;
+            }
             store_tile_staged(a, ch, rt, ft * 32, lane, acc0, stage);
-            if (two) store_tile_staged(a, ch, rt, (ft + 1) * 32, lane, acc1, stage);
         }
-        if (nft == 0) async_wait();                // a frameless chunk (streaming) still waits for the copy
+        if (!waited) async_wait();                 // no tile for this wave (or a frameless chunk)
     }
 }
 
@@ -222,8 +287,9 @@ static melt_status launch_as_ns(Plan &p, const FwdArgs &a, const GroupTableBig &
                                 int scr_off, hipStream_t s) {
     allow_lds(k_melt_h16_as<Conv, NS, X3, F16>);
     const int stage_off = (int)(as_stage_offset(p, bf) / 4);
-    k_melt_h16_as<Conv, NS, X3, F16><<<grid, 64 * p.row_tiles, lds, s>>>(
-        a, (const uint4 *)p.d_pack_h16, (const uint4 *)p.d_pack_lo, gt, bf, scr_off, stage_off);
+    const WaveLayout w = h16_layout(p);
+    k_melt_h16_as<Conv, NS, X3, F16><<<grid, 64 * w.waves, lds, s>>>(
+        a, (const uint4 *)p.d_pack_h16, (const uint4 *)p.d_pack_lo, gt, bf, scr_off, stage_off, w.full, w.psplit);
     return hip_check(hipGetLastError(), "melt h16 lds-dma launch");
 }
 

@@ -135,10 +135,14 @@ def test_every_kernel_variant(torch, melt, orc, prec):
     melt_set_variant, on clips that end chunks of 64, 96 and 128 frames exactly, one frame
     past them and mid-way.  Geometries: the 16 kHz front end (hop a multiple of 4: vector
     span conversion), hop 50 (two-byte aligned rows: element-wise conversion) and N=480,
-    hop 161 (32 k-groups, odd hop)."""
-    geoms = [(16000, 400, 160, 80), (16000, 400, 50, 40), (16000, 480, 161, 64)]
+    hop 161 (32 k-groups, odd hop); 16, 24 and 96 Mel bins (1, 2 and 6 row tiles: the
+    16-bit kernel's waves that share a row tile by frame tiles)."""
+    geoms = [(16000, 400, 160, 80), (16000, 400, 50, 40), (16000, 480, 161, 64),
+             (16000, 400, 160, 16), (16000, 400, 160, 24), (16000, 512, 128, 96)]
     if prec == "fp8":
         geoms = geoms[:1]
+    elif prec == "fp32":
+        geoms = geoms[:3]
     for sr, N, H, M in geoms:
         lengths = [0, N - 1, N, N + 1] + [(f - 1) * H + N + d for f in (64, 65, 96, 97, 128, 129, 200) for d in (0, 3)]
         wave, off = workloads.random_clips(lengths, seed=N + H)
