@@ -562,19 +562,19 @@ inline size_t as_rows_bytes(const Plan &p, int bf) {
 inline size_t as_stage_offset(const Plan &p, int bf) {
     return ((((as_rows_bytes(p, bf) + 15) & ~size_t(15)) + (size_t)(bf + p.geo16.J - 1) * p.H * 4) + 15) & ~size_t(15);
 }
-// Waves of the direct-to-LDS 16-bit kernel: `full` waves own one row tile each; when one or
+// Waves of the direct-to-LDS row-split kernels: `full` waves own one row tile each; when one or
 // two row tiles remain beyond a multiple of four, four more waves share them (psplit waves
 // per tile), so the work spreads evenly over the CU's four SIMDs.
 struct WaveLayout {
     int full, psplit, waves;
 };
-inline WaveLayout h16_layout(const Plan &p) {
+inline WaveLayout wave_layout(const Plan &p) {
     const int RT = p.row_tiles, rem = RT % 4;
     if ((rem == 1 || rem == 2) && RT - rem + 4 <= 8) return {RT - rem, 4 / rem, RT - rem + 4};
     return {RT, 1, RT};
 }
 inline size_t as_lds_bytes(const Plan &p, int bf) {
-    return as_stage_offset(p, bf) + (size_t)h16_layout(p).waves * kStageFloats * 4;
+    return as_stage_offset(p, bf) + (size_t)wave_layout(p).waves * kStageFloats * 4;
 }
 
 // per-family launchers (melt_f32.hip, melt_h16.hip, melt_f8.hip)

@@ -124,14 +124,22 @@ __global__ __launch_bounds__(512) void k_melt_f8_rs(FwdArgs a, const i32x8 *__re
 // (async_span) while the previous chunk multiplies.  Frame t of the chunk is span samples
 // [tH, tH + N), so the per-row maxima and the E4M3 image are read straight from the
 // contiguous span (no hop-block rows, no division per element).  Positions at or past the
-// valid span (clip end) count as 0.  Outputs leave through store_tile_staged.
+// valid span (clip end) count as 0.  Outputs leave through store_tile_staged.  Waves map
+// to row tiles and frame tiles as in the 16-bit kernel (wave_layout: one or two leftover
+// row tiles are shared by four waves, by frame tiles).
 template <int NG>
 __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__restrict__ bq,
                                                     const float *__restrict__ rinv_g, int N, int bf, int scr_off,
-                                                    int stage_off) {
+                                                    int stage_off, int full, int psplit) {
     extern __shared__ float lds_f8[];
     const int lane = threadIdx.x & 63, nthreads = blockDim.x;
-    const int rt = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = nthreads >> 6;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = nthreads >> 6;
+    int rt = wid, part = 0, P = 1;
+    if (wid >= full) {
+        rt = full + (wid - full) / psplit;
+        part = (wid - full) % psplit;
+        P = psplit;
+    }
     constexpr int KP = NG * 64;             // padded frame length in the E4M3 image
     constexpr int SQ = KP + 16;             // row stride (bytes): 4 x odd dwords -> conflict-free 16-byte reads
     const int rows_max = bf + a.J - 1;
@@ -140,7 +148,7 @@ __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__re
     float *mfull = sinv + bf;                                                    // [rows] max over the row
     float *mpre = mfull + rows_max;                                              // [rows] max over the last segment's prefix
     float *scratch = lds_f8 + scr_off;                                           // FP32 span
-    float *stage = lds_f8 + stage_off + rt * kStageFloats;
+    float *stage = lds_f8 + stage_off + wid * kStageFloats;
     const int Llast = N - (a.J - 1) * a.H;                                       // length of the last segment
     i32x8 A[NG];
 #pragma unroll
@@ -192,7 +200,7 @@ __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__re
             }
         } else {
             // general hops: one wave per hop row with a cross-lane reduction
-            for (int r = rt; r < rows; r += nw) {
+            for (int r = wid; r < rows; r += nw) {
                 float mf = 0.0f, mp = 0.0f;
                 for (int col = lane; col < a.H; col += 64) {
                     const int o = r * a.H + col;
@@ -220,7 +228,7 @@ __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__re
         __syncthreads();
         // quantise: one wave per frame, lane = 4-sample word of the padded frame
         const bool vec = (a.H & 3) == 0 && (N & 3) == 0;
-        for (int t = rt; t < ch.n_frames; t += nw) {
+        for (int t = wid; t < ch.n_frames; t += nw) {
             const float s = sinv[t];
             const int base = t * a.H;
             const bool whole = vec && base + N <= valid;    // every sample of the frame present
@@ -243,24 +251,39 @@ __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__re
         __syncthreads();                           // image ready; scratch is free
         if (c + (int)gridDim.x < nch) async_span(a, read_chunk(a.chunks, c + gridDim.x), scratch);
         const int nft = (ch.n_frames + 31) >> 5;
-        for (int ft = 0; ft < nft; ft += 2) {
-            const bool two = ft + 1 < nft;
+        // The next chunk's copy must land before the barrier that starts the next iteration:
+        // each wave waits ahead of its last tiles' stores (leaving those in flight), or after
+        // the loop if it had no tile.
+        bool waited = false;
+        const int step = P == 1 ? 2 : P;
+        for (int ft = part; ft < nft; ft += step) {
+            const bool two = step == 2 && ft + 1 < nft;
             f32x16 acc0 = f32x16{}, acc1 = f32x16{};
             const unsigned char *q0 = xq + (ft * 32 + (lane & 31)) * SQ + 32 * (lane >> 5);
-            // a lone last tile multiplies its own frames twice rather than branching
-            const unsigned char *q1 = two ? q0 + 32 * SQ : q0;
+            if (step == 2) {
+                // a lone last tile multiplies its own frames twice rather than branching
+                const unsigned char *q1 = two ? q0 + 32 * SQ : q0;
 #pragma unroll
-            for (int g = 0; g < NG; ++g) {
-                const uint4 b0l = *(const uint4 *)(q0 + 64 * g), b0h = *(const uint4 *)(q0 + 64 * g + 16);
-                const uint4 b1l = *(const uint4 *)(q1 + 64 * g), b1h = *(const uint4 *)(q1 + 64 * g + 16);
-                const i32x8 B0 = {(int)b0l.x, (int)b0l.y, (int)b0l.z, (int)b0l.w, (int)b0h.x, (int)b0h.y, (int)b0h.z, (int)b0h.w};
-                const i32x8 B1 = {(int)b1l.x, (int)b1l.y, (int)b1l.z, (int)b1l.w, (int)b1h.x, (int)b1h.y, (int)b1h.z, (int)b1h.w};
-                acc0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[g], B0, acc0, 0, 0, 0, 127, 0, 127);
-                acc1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[g], B1, acc1, 0, 0, 0, 127, 0, 127);
+                for (int g = 0; g < NG; ++g) {
+                    const uint4 b0l = *(const uint4 *)(q0 + 64 * g), b0h = *(const uint4 *)(q0 + 64 * g + 16);
+                    const uint4 b1l = *(const uint4 *)(q1 + 64 * g), b1h = *(const uint4 *)(q1 + 64 * g + 16);
+                    const i32x8 B0 = {(int)b0l.x, (int)b0l.y, (int)b0l.z, (int)b0l.w, (int)b0h.x, (int)b0h.y, (int)b0h.z, (int)b0h.w};
+                    const i32x8 B1 = {(int)b1l.x, (int)b1l.y, (int)b1l.z, (int)b1l.w, (int)b1h.x, (int)b1h.y, (int)b1h.z, (int)b1h.w};
+                    acc0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[g], B0, acc0, 0, 0, 0, 127, 0, 127);
+                    acc1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[g], B1, acc1, 0, 0, 0, 127, 0, 127);
+                }
+            } else {
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    const uint4 b0l = *(const uint4 *)(q0 + 64 * g), b0h = *(const uint4 *)(q0 + 64 * g + 16);
+                    const i32x8 B0 = {(int)b0l.x, (int)b0l.y, (int)b0l.z, (int)b0l.w, (int)b0h.x, (int)b0h.y, (int)b0h.z, (int)b0h.w};
+                    acc0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[g], B0, acc0, 0, 0, 0, 127, 0, 127);
+                }
             }
-            // the next chunk's copy must land before the barrier that starts the next
-            // iteration; waiting ahead of the last tiles' stores leaves those in flight
-            if (ft + 2 >= nft) async_wait();
+            if (ft + step >= nft) {
+                async_wait();
+                waited = true;
+            }
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 if (u == 1 && !two) break;
@@ -272,7 +295,7 @@ __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__re
                 store_tile_staged(a, ch, rt, (ft + u) * 32, lane, acc, stage);
             }
         }
-        if (nft == 0) async_wait();                // a frameless chunk (streaming) still waits for the copy
+        if (!waited) async_wait();                 // no tile for this wave (or a frameless chunk)
     }
 }
 
@@ -295,14 +318,17 @@ size_t f8_as_scratch_offset(const Plan &p, int bf) {
 size_t f8_as_stage_offset(const Plan &p, int bf) {
     return (f8_as_scratch_offset(p, bf) + (size_t)(bf + p.geo32.J - 1) * p.H * 4 + 15) & ~size_t(15);
 }
-size_t f8_as_lds_bytes(const Plan &p, int bf) { return f8_as_stage_offset(p, bf) + (size_t)p.row_tiles * kStageFloats * 4; }
+size_t f8_as_lds_bytes(const Plan &p, int bf) {
+    return f8_as_stage_offset(p, bf) + (size_t)wave_layout(p).waves * kStageFloats * 4;
+}
 
 template <int NG>
 static melt_status launch_f8_as(Plan &p, const FwdArgs &a, size_t lds, int grid, int bf, hipStream_t s) {
     allow_lds(k_melt_f8_as<NG>);
-    k_melt_f8_as<NG><<<grid, 64 * p.row_tiles, lds, s>>>(a, (const i32x8 *)p.d_pack_f8, p.d_rowscale, p.N, bf,
-                                                         (int)(f8_as_scratch_offset(p, bf) / 4),
-                                                         (int)(f8_as_stage_offset(p, bf) / 4));
+    const WaveLayout w = wave_layout(p);
+    k_melt_f8_as<NG><<<grid, 64 * w.waves, lds, s>>>(a, (const i32x8 *)p.d_pack_f8, p.d_rowscale, p.N, bf,
+                                                     (int)(f8_as_scratch_offset(p, bf) / 4),
+                                                     (int)(f8_as_stage_offset(p, bf) / 4), w.full, w.psplit);
     return hip_check(hipGetLastError(), "melt f8 lds-dma launch");
 }
 

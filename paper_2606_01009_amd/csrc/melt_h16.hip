@@ -287,7 +287,7 @@ static melt_status launch_as_ns(Plan &p, const FwdArgs &a, const GroupTableBig &
                                 int scr_off, hipStream_t s) {
     allow_lds(k_melt_h16_as<Conv, NS, X3, F16>);
     const int stage_off = (int)(as_stage_offset(p, bf) / 4);
-    const WaveLayout w = h16_layout(p);
+    const WaveLayout w = wave_layout(p);
     k_melt_h16_as<Conv, NS, X3, F16><<<grid, 64 * w.waves, lds, s>>>(
         a, (const uint4 *)p.d_pack_h16, (const uint4 *)p.d_pack_lo, gt, bf, scr_off, stage_off, w.full, w.psplit);
     return hip_check(hipGetLastError(), "melt h16 lds-dma launch");
