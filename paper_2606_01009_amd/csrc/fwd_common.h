@@ -282,6 +282,46 @@ __device__ __forceinline__ void span_store(const FwdArgs &a, const Chunk &ch, co
     }
 }
 
+// Vector form for H a multiple of 4 (four consecutive samples never straddle a row): vector
+// v of thread t holds span samples [4(t + v NT), +4).  Each vector's row and column are
+// computed on their own (no chain through the previous element), and it is written with
+// one 16-byte LDS store.  A vector that crosses the clip end is loaded element by element
+// (the buffer descriptor returns 0 past it).
+template <int PV, int NT>
+__device__ __forceinline__ void span_load4(const FwdArgs &a, const Chunk &ch, f32x4 (&pv)[PV], int t) {
+    const int64_t start = ch.sample_start;
+    const int64_t span = (int64_t)(ch.n_frames + a.J - 1) * a.H;
+    const int64_t lim = ch.sample_end - start < span ? ch.sample_end - start : span;
+    const int records = (int)(lim > 0 ? lim * 4 : 0);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(a.wave + start), (short)0, records, 0x00020000);
+#pragma unroll
+    for (int v = 0; v < PV; ++v) {
+        const int o = 4 * (t + v * NT);
+        if (o + 4 <= records / 4) {
+            pv[v] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, o * 4, 0, 0));
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                pv[v][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (o + e) * 4, 0, 0));
+        }
+    }
+}
+
+template <int PV, int NT>
+__device__ __forceinline__ void span_store4(const FwdArgs &a, const Chunk &ch, const f32x4 (&pv)[PV], float *lds,
+                                            int t) {
+    const int span = (ch.n_frames + a.J - 1) * a.H;
+#pragma unroll
+    for (int v = 0; v < PV; ++v) {
+        const int o = 4 * (t + v * NT);
+        if (o < span) {
+            const int r = span_row(a, o);
+            *(f32x4 *)(lds + r * a.S + (o - r * a.H)) = pv[v];
+        }
+    }
+}
+
 // Zero the pad columns [H, Hp) of `rows` LDS rows (never written by span_store).
 template <class Conv>
 __device__ __forceinline__ void zero_pad_columns(const FwdArgs &a, int rows, typename Conv::elem_t *lds, int nthreads,

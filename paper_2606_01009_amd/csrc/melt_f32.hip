@@ -103,19 +103,134 @@ void k_melt_f32_fs(FwdArgs a, const f32x4 *__restrict__ bpack, int NG) {
 // their own registers, loaded a whole chunk ahead, so the multiply waves' waits for basis
 // fragments never include sample loads (the wait counter drains in order).  Per chunk:
 // barrier A after the MFMA loop (the rows are free), then the stagers write the next rows
-// while the multiply waves run the epilogue, then barrier B.  The two roles run separate
-// loops with the same barriers, so their registers are allocated independently.
-template <int RTB, int PRE>
+// while the multiply waves empty their accumulators, then barrier B.  The two roles run
+// separate loops with the same barriers, so their registers are allocated independently.
+//
+// HANDOFF: the multiply waves only write the energies R^2 + I^2 of the last row-tile block
+// into an LDS buffer (frame-major, row stride hs floats) between A and B; after B the
+// stagers map them to the output kind and store whole output rows, coalesced, while the
+// multiply waves already run the next chunk's MFMAs.  The stagers finish reading before
+// the next barrier A, after which the buffer is written again.  Without it (LDS too small)
+// the multiply waves store their tiles themselves.
+// Mel bins [m0, M) of the chunk's frames (m0: first bin of the last row-tile block, a
+// multiple of 16; the earlier blocks were stored by the multiply waves themselves).
+template <int KIND>
+__device__ __forceinline__ void handoff_rows(const FwdArgs &a, const Chunk &ch, const float *hb, int hs, int m0,
+                                             int lt) {
+    // thread lt takes 4-Mel groups lt, lt + 256, ...: frame f = idx / Q, group q = idx % Q,
+    // advanced incrementally
+    const int Q = (a.M - m0 + 3) >> 2, total = ch.n_frames * Q;
+    const int df = 256 / Q, dq = 256 - df * Q;
+    int f = lt / Q, q = lt - f * Q;
+    for (int idx = lt; idx < total; idx += 256) {
+        const int m = m0 + 4 * q;
+        const f32x4 e = *(const f32x4 *)(hb + f * hs + m);
+        const int64_t row = ch.out_row + f;
+        if (row < a.n_frames) {
+            float *o = a.out + row * a.M + m;
+            const f32x4 v{out_map_k<KIND>(e[0], a.eps), out_map_k<KIND>(e[1], a.eps), out_map_k<KIND>(e[2], a.eps),
+                          out_map_k<KIND>(e[3], a.eps)};
+            if ((a.M & 3) == 0) {
+                *(f32x4 *)o = v;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (m + k < a.M) o[k] = v[k];
+            }
+        }
+        f += df;
+        q += dq;
+        if (q >= Q) {
+            q -= Q;
+            ++f;
+        }
+    }
+}
+
+// energies of one 32x32 accumulator tile into the handoff buffer (8 Mel bins per lane)
+__device__ __forceinline__ void handoff_tile(float *hb, int hs, int f_local, int rt, int lane, const f32x16 &acc) {
+    const int mel0 = rt * 16 + 8 * (lane >> 5);
+    f32x4 e0, e1;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        e0[2 * g] = acc[4 * g] * acc[4 * g] + acc[4 * g + 1] * acc[4 * g + 1];
+        e0[2 * g + 1] = acc[4 * g + 2] * acc[4 * g + 2] + acc[4 * g + 3] * acc[4 * g + 3];
+        e1[2 * g] = acc[8 + 4 * g] * acc[8 + 4 * g] + acc[9 + 4 * g] * acc[9 + 4 * g];
+        e1[2 * g + 1] = acc[10 + 4 * g] * acc[10 + 4 * g] + acc[11 + 4 * g] * acc[11 + 4 * g];
+    }
+    *(f32x4 *)(hb + f_local * hs + mel0) = e0;
+    *(f32x4 *)(hb + f_local * hs + mel0 + 4) = e1;
+}
+
+// the raw (R, I) projection of one tile, when requested
+__device__ __forceinline__ void store_proj(const FwdArgs &a, const Chunk &ch, int rt, int f_local, int lane,
+                                           const f32x16 &acc) {
+    if (!a.proj || f_local >= ch.n_frames) return;
+    const int64_t row = ch.out_row + f_local;
+    const int mel0 = rt * 16 + 8 * (lane >> 5);
+    if (row >= a.n_frames || mel0 >= a.M) return;
+    float *p = a.proj + row * (2 * a.M) + 2 * mel0;
+    if (mel0 + 8 <= a.M && (a.M & 1) == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *(f32x4 *)(p + 4 * q) = f32x4{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            if (mel0 + e / 2 < a.M) p[e] = acc[e];
+    }
+}
+
+// stager waves' epilogue for chunk ch (HANDOFF): Mel bins of the last row-tile block
+template <int RTB>
+__device__ __forceinline__ void stager_epilogue(const FwdArgs &a, const Chunk &ch, const float *hb, int hs, int lt) {
+    const int m0 = ((a.row_tiles - 1) / RTB) * RTB * 16;
+    switch (a.out_kind) {
+    case MELT_OUT_LOG_POWER: handoff_rows<MELT_OUT_LOG_POWER>(a, ch, hb, hs, m0, lt); break;
+    case MELT_OUT_LOG_MAGNITUDE: handoff_rows<MELT_OUT_LOG_MAGNITUDE>(a, ch, hb, hs, m0, lt); break;
+    case MELT_OUT_POWER: handoff_rows<MELT_OUT_POWER>(a, ch, hb, hs, m0, lt); break;
+    default: handoff_rows<MELT_OUT_MAGNITUDE>(a, ch, hb, hs, m0, lt); break;
+    }
+}
+
+// The stager role with 16-byte vectors (H a multiple of 4); same barriers as the scalar
+// loop in k_melt_f32_ws.
+template <int RTB, int PV, bool HANDOFF>
+__device__ __forceinline__ void stage_rows_vec(const FwdArgs &a, const float *hb, int hs, float *lds, int lt, int c,
+                                               int nch) {
+    f32x4 pv[PV];
+    if (c < nch) {
+        const Chunk ch = read_chunk(a.chunks, c);
+        span_load4<PV, 256>(a, ch, pv, lt);
+        span_store4<PV, 256>(a, ch, pv, lds, lt);
+    }
+    __syncthreads();                               // rows of the first chunk ready
+    if (c + (int)gridDim.x < nch) span_load4<PV, 256>(a, read_chunk(a.chunks, c + gridDim.x), pv, lt);
+    for (; c < nch; c += gridDim.x) {
+        __syncthreads();                           // A: the multiply waves are done with the rows
+        const int cn = c + gridDim.x;
+        if (cn < nch) span_store4<PV, 256>(a, read_chunk(a.chunks, cn), pv, lds, lt);
+        __syncthreads();                           // B: rows of the next chunk ready; energies of chunk c in hb
+        if constexpr (HANDOFF) stager_epilogue<RTB>(a, read_chunk(a.chunks, c), hb, hs, lt);
+        if (cn + (int)gridDim.x < nch) span_load4<PV, 256>(a, read_chunk(a.chunks, cn + gridDim.x), pv, lt);
+    }
+}
+
+template <int RTB, int PRE, bool HANDOFF>
 __global__ __attribute__((amdgpu_flat_work_group_size(512, 512), amdgpu_waves_per_eu(2, 2)))
-void k_melt_f32_ws(FwdArgs a, const f32x4 *__restrict__ bpack, int NG) {
+void k_melt_f32_ws(FwdArgs a, const f32x4 *__restrict__ bpack, int NG, int hb_off, int hs) {
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nch = *a.n_chunks;
+    float *hb = lds + hb_off;                      // handoff buffer (HANDOFF only)
     zero_pad_columns<ConvF32>(a, kChunkF32 + a.J - 1, lds, 512, 0);
     int c = blockIdx.x;
     if (wid >= 4) {
         const int lt = (int)threadIdx.x - 256;
+        if ((a.H & 3) == 0) {
+            stage_rows_vec<RTB, PRE / 4, HANDOFF>(a, hb, hs, lds, lt, c, nch);
+            return;
+        }
         float pf[PRE];
         if (c < nch) {
             const Chunk ch = read_chunk(a.chunks, c);
@@ -128,7 +243,8 @@ void k_melt_f32_ws(FwdArgs a, const f32x4 *__restrict__ bpack, int NG) {
             __syncthreads();                       // A: the multiply waves are done with the rows
             const int cn = c + gridDim.x;
             if (cn < nch) span_store<ConvF32, PRE, 256>(a, read_chunk(a.chunks, cn), pf, lds, 0, lt);
-            __syncthreads();                       // B: rows of the next chunk ready
+            __syncthreads();                       // B: rows of the next chunk ready; energies of chunk c in hb
+            if constexpr (HANDOFF) stager_epilogue<RTB>(a, read_chunk(a.chunks, c), hb, hs, lt);
             if (cn + (int)gridDim.x < nch) span_load<PRE, 256>(a, read_chunk(a.chunks, cn + gridDim.x), pf, lt);
         }
         return;
@@ -184,8 +300,15 @@ void k_melt_f32_ws(FwdArgs a, const f32x4 *__restrict__ bpack, int NG) {
             if (last) __syncthreads();             // A: every row read; the stagers may overwrite
             if (active) {
 #pragma unroll
-                for (int r = 0; r < RTB; ++r)
-                    if (rb + r < a.row_tiles) store_tile(a, ch, rb + r, fbase + (lane & 31), lane, acc[r]);
+                for (int r = 0; r < RTB; ++r) {
+                    if (rb + r >= a.row_tiles) continue;
+                    if (HANDOFF && last) {
+                        handoff_tile(hb, hs, fbase + (lane & 31), rb + r, lane, acc[r]);
+                        store_proj(a, ch, rb + r, fbase + (lane & 31), lane, acc[r]);
+                    } else {
+                        store_tile(a, ch, rb + r, fbase + (lane & 31), lane, acc[r]);
+                    }
+                }
             }
         }
         __syncthreads();                           // B: rows of the next chunk ready
@@ -215,8 +338,18 @@ static melt_status launch_f32_rtb(Plan &p, const FwdArgs &a, const GroupTableBig
 
 template <int RTB, int PRE>
 static melt_status launch_f32_ws_pre(const FwdArgs &a, const f32x4 *bp, int NG, size_t lds, int grid, hipStream_t s) {
-    allow_lds(k_melt_f32_ws<RTB, PRE>);
-    k_melt_f32_ws<RTB, PRE><<<grid, 512, lds, s>>>(a, bp, NG);
+    // handoff buffer after the rows: 128 frames x hs floats, hs = 16 row tiles + 4 (an odd
+    // number of 16-byte groups, so the 32 frames a wave writes spread over the banks)
+    const int hs = a.row_tiles * 16 + 4;
+    const size_t hb_off = (lds + 15) & ~size_t(15);
+    const size_t with = hb_off + (size_t)kBF32 * hs * 4;
+    if (with <= (size_t)kMaxLds) {
+        allow_lds(k_melt_f32_ws<RTB, PRE, true>);
+        k_melt_f32_ws<RTB, PRE, true><<<grid, 512, with, s>>>(a, bp, NG, (int)(hb_off / 4), hs);
+    } else {
+        allow_lds(k_melt_f32_ws<RTB, PRE, false>);
+        k_melt_f32_ws<RTB, PRE, false><<<grid, 512, lds, s>>>(a, bp, NG, 0, 0);
+    }
     return hip_check(hipGetLastError(), "melt f32 ws launch");
 }
 
