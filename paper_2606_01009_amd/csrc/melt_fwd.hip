@@ -7,16 +7,26 @@ namespace melt {
 
 // ------------------------------------------------------------------ schedule
 
+// inclusive prefix sum over the 64 lanes of a wave (shuffles, no barrier)
+__device__ __forceinline__ int64_t wave_scan(int64_t v, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
 // One workgroup: prefix sums over the clips of frame counts and chunk counts, then the
 // chunk table.  n_chunks receives min(total, cap).
 __global__ __launch_bounds__(1024) void k_schedule(const int64_t *__restrict__ off, int n_clips, int N,
                                                    int H, int bf, Chunk *__restrict__ tab, int64_t cap,
                                                    int *__restrict__ n_out) {
     __shared__ int64_t sf[1024], sc[1024], s_start[1024], s_len[1024];
+    __shared__ int64_t wf[16], wc[16];
     __shared__ int64_t carry_f, carry_c;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (tid == 0) carry_f = carry_c = 0;
-    __syncthreads();
     for (int base = 0; base < n_clips; base += 1024) {
         const int c = base + tid;
         int64_t st = 0, L = 0;
@@ -26,19 +36,24 @@ __global__ __launch_bounds__(1024) void k_schedule(const int64_t *__restrict__ o
         }
         const int64_t T = (L >= N) ? 1 + (L - N) / H : 0;
         const int64_t K = (T + bf - 1) / bf;
-        sf[tid] = T;
-        sc[tid] = K;
+        // inclusive prefix sums of T and K over the block: within each wave, then across the
+        // 16 wave totals
+        const int64_t pf = wave_scan(T, lane), pc = wave_scan(K, lane);
+        if (lane == 63) {
+            wf[w] = pf;
+            wc[w] = pc;
+        }
+        __syncthreads();
+        int64_t of = 0, oc = 0;
+        for (int k = 0; k < w; ++k) {
+            of += wf[k];
+            oc += wc[k];
+        }
+        sf[tid] = pf + of;
+        sc[tid] = pc + oc;
         s_start[tid] = st;
         s_len[tid] = L;
         __syncthreads();
-        for (int d = 1; d < 1024; d <<= 1) {           // inclusive prefix sums of T and K
-            const int64_t vf = tid >= d ? sf[tid - d] : 0;
-            const int64_t vc = tid >= d ? sc[tid - d] : 0;
-            __syncthreads();
-            sf[tid] += vf;
-            sc[tid] += vc;
-            __syncthreads();
-        }
         // entries of this block of clips, written by all threads: entry q belongs to the
         // first clip t whose inclusive chunk prefix exceeds q (binary search)
         const int64_t total = sc[1023];
