@@ -30,7 +30,7 @@ PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "f16": 2.5e15, "fp8": 5.0e15, "hbm": 8.
 # the sources of the dominant kernel (the FP32 MelT projection): a change to either makes the
 # committed traffic counters stale
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2606_01009_amd", "csrc", f) for f in ("melt_f32.hip", "fwd_common.h")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "melt_f32_fs_config2_m80_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "melt_f32_ws_config2_m80_traffic.json")
 
 
 def log(msg):
@@ -129,6 +129,47 @@ def load_traffic(path, source_id):
     return t.get("hbm_bytes_per_launch")
 
 
+def _pmc_average(csv_path, name_part, counter):
+    """Mean per dispatch of `counter` over the dispatches of kernels whose name contains
+    name_part, from a rocprofv3 --pmc counter_collection.csv."""
+    import csv
+    tot, ids = 0.0, set()
+    with open(csv_path) as fh:
+        for r in csv.DictReader(fh):
+            if name_part in r["Kernel_Name"] and r["Counter_Name"] == counter:
+                tot += float(r["Counter_Value"])
+                ids.add(r["Dispatch_Id"])
+    if not ids:
+        raise SystemExit(f"no {counter} for {name_part} in {csv_path}")
+    return tot / len(ids), len(ids)
+
+
+def write_traffic(pmc_dir, T, bytes_algo, wave_bytes):
+    """Writes TRAFFIC_FILE from four rocprofv3 --pmc runs under pmc_dir (fp32_f, fp32_w:
+    FETCH_SIZE / WRITE_SIZE of `--only fp32`; copy_f, copy_w: the same of `--only copy`).
+    Each counter is scaled by what it reads for the copy kernel, which reads and writes
+    wave_bytes once per launch."""
+    find = lambda sub: os.path.join(pmc_dir, sub, "run_counter_collection.csv")
+    fetch, nf = _pmc_average(find("fp32_f"), "k_melt_f32_ws", "FETCH_SIZE")
+    write, nw = _pmc_average(find("fp32_w"), "k_melt_f32_ws", "WRITE_SIZE")
+    cf, _ = _pmc_average(find("copy_f"), "vectorized_elementwise_kernel", "FETCH_SIZE")
+    cw, _ = _pmc_average(find("copy_w"), "vectorized_elementwise_kernel", "WRITE_SIZE")
+    kib = wave_bytes / 1024.0
+    fs, ws = kib / cf, kib / cw
+    hbm = fetch * 1024 * fs + write * 1024 * ws
+    t = {"kernel": "k_melt_f32_ws (MelT FP32, 64 clips x 30 s, n_fft 400, hop 160, 80 Mel bins)",
+         "kernel_source_id": kernel_source_id(),
+         "fetch_kib_per_dispatch": round(fetch, 1), "write_kib_per_dispatch": round(write, 1),
+         "dispatches_averaged": [nf, nw], "fetch_scale": round(fs, 5), "write_scale": round(ws, 5),
+         "hbm_bytes_per_launch": int(hbm), "algorithmic_bytes_per_launch": int(bytes_algo), "frames": T,
+         "commands": [f"rocprofv3 --pmc {c} -d <dir>/{w}_{x} -o run --output-format csv -- python3 bench.py "
+                      f"--only {w} --steps 3 --warmup 1 --no-check"
+                      for w in ("fp32", "copy") for c, x in (("FETCH_SIZE", "f"), ("WRITE_SIZE", "w"))]}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(t, fh, indent=1)
+    log(f"bench: wrote {TRAFFIC_FILE}: {hbm / 1e6:.1f} MB per launch against {bytes_algo / 1e6:.1f} MB algorithmic")
+
+
 def call_ms(torch, fn, calls=20, warmup=5, busy_ms=30.0):
     """Median over 5 trials of the mean time of `calls` back-to-back calls (HIP events),
     after about busy_ms of back-to-back calls so that the clocks have ramped up."""
@@ -204,6 +245,9 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the sampled error check")
     ap.add_argument("--only", default=None, help="time one path only: fp32|bf16|fp16|bf16x3|fp8|stft|copy (profiling)")
     ap.add_argument("--sweep", action="store_true", help="time every kernel variant of every precision and exit")
+    ap.add_argument("--write-traffic", default=None, metavar="PMC_DIR",
+                    help="write the committed traffic summary of the FP32 kernel from rocprofv3 --pmc runs "
+                         "(subfolders fp32_f, fp32_w, copy_f, copy_w) and exit; runs on the CPU")
     ap.add_argument("--workloads", default=None,
                     help="write the paper's efficiency workloads on synthetic stand-ins (cepstral configuration, "
                          "duration, Mel-bin and batch sweeps) as JSON lines to this file and exit")
@@ -213,6 +257,15 @@ def main():
               f"are independent, so N GPUs would each take 1/N of the clips with no communication)",
               file=sys.stderr)
         return 2
+
+    if args.write_traffic:
+        # the same workload's sizes, from its generator (no GPU needed)
+        import workloads
+        cfg = workloads.config2(n_mels=args.n_mels)
+        T = int(sum(1 + (int(b - a) - 400) // 160 for a, b in zip(cfg["offsets"][:-1], cfg["offsets"][1:])))
+        wave_bytes = cfg["wave"].nbytes
+        write_traffic(args.write_traffic, T, wave_bytes + T * args.n_mels * 4 + 2 * args.n_mels * 400 * 4, wave_bytes)
+        return 0
 
     import torch
     import paper_2606_01009_amd as melt

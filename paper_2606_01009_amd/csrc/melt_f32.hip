@@ -112,14 +112,14 @@ void k_melt_f32_fs(FwdArgs a, const f32x4 *__restrict__ bpack, int NG) {
 // multiply waves already run the next chunk's MFMAs.  The stagers finish reading before
 // the next barrier A, after which the buffer is written again.  Without it (LDS too small)
 // the multiply waves store their tiles themselves.
-// Mel bins [m0, M) of the chunk's frames (m0: first bin of the last row-tile block, a
+// Mel bins [m0, m1) of the chunk's frames (m0: first bin of the last row-tile block, a
 // multiple of 16; the earlier blocks were stored by the multiply waves themselves).
 template <int KIND>
 __device__ __forceinline__ void handoff_rows(const FwdArgs &a, const Chunk &ch, const float *hb, int hs, int m0,
-                                             int lt) {
+                                             int m1, int lt) {
     // thread lt takes 4-Mel groups lt, lt + 256, ...: frame f = idx / Q, group q = idx % Q,
     // advanced incrementally
-    const int Q = (a.M - m0 + 3) >> 2, total = ch.n_frames * Q;
+    const int Q = (m1 - m0 + 3) >> 2, total = ch.n_frames * Q;
     const int df = 256 / Q, dq = 256 - df * Q;
     int f = lt / Q, q = lt - f * Q;
     for (int idx = lt; idx < total; idx += 256) {
@@ -130,12 +130,12 @@ __device__ __forceinline__ void handoff_rows(const FwdArgs &a, const Chunk &ch, 
             float *o = a.out + row * a.M + m;
             const f32x4 v{out_map_k<KIND>(e[0], a.eps), out_map_k<KIND>(e[1], a.eps), out_map_k<KIND>(e[2], a.eps),
                           out_map_k<KIND>(e[3], a.eps)};
-            if ((a.M & 3) == 0) {
+            if ((a.M & 3) == 0 && m + 4 <= m1) {
                 *(f32x4 *)o = v;
             } else {
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    if (m + k < a.M) o[k] = v[k];
+                    if (m + k < m1) o[k] = v[k];
             }
         }
         f += df;
@@ -180,72 +180,90 @@ __device__ __forceinline__ void store_proj(const FwdArgs &a, const Chunk &ch, in
     }
 }
 
-// stager waves' epilogue for chunk ch (HANDOFF): Mel bins of the last row-tile block
+// Work items: the persistent grid walks items w = chunk * rsplit + part; part p of a chunk
+// covers row tiles [p rps, min((p + 1) rps, row_tiles)).  rsplit > 1 spreads a batch with
+// fewer chunks than compute units over more workgroups (each stages its chunk itself).
+struct WorkItem {
+    int c, r_lo, r_hi;
+};
+__device__ __forceinline__ WorkItem work_item(const FwdArgs &a, int w, int rsplit, int rps) {
+    const int c = w / rsplit, part = w - c * rsplit;
+    const int r_lo = part * rps;
+    return {c, r_lo, min(r_lo + rps, a.row_tiles)};
+}
+
+// stager waves' epilogue for one work item (HANDOFF): Mel bins of its last row-tile block
 template <int RTB>
-__device__ __forceinline__ void stager_epilogue(const FwdArgs &a, const Chunk &ch, const float *hb, int hs, int lt) {
-    const int m0 = ((a.row_tiles - 1) / RTB) * RTB * 16;
+__device__ __forceinline__ void stager_epilogue(const FwdArgs &a, const WorkItem &it, const float *hb, int hs,
+                                                int lt) {
+    const Chunk ch = read_chunk(a.chunks, it.c);
+    const int m0 = (it.r_lo + ((it.r_hi - it.r_lo - 1) / RTB) * RTB) * 16;
+    const int m1 = min(it.r_hi * 16, a.M);
     switch (a.out_kind) {
-    case MELT_OUT_LOG_POWER: handoff_rows<MELT_OUT_LOG_POWER>(a, ch, hb, hs, m0, lt); break;
-    case MELT_OUT_LOG_MAGNITUDE: handoff_rows<MELT_OUT_LOG_MAGNITUDE>(a, ch, hb, hs, m0, lt); break;
-    case MELT_OUT_POWER: handoff_rows<MELT_OUT_POWER>(a, ch, hb, hs, m0, lt); break;
-    default: handoff_rows<MELT_OUT_MAGNITUDE>(a, ch, hb, hs, m0, lt); break;
+    case MELT_OUT_LOG_POWER: handoff_rows<MELT_OUT_LOG_POWER>(a, ch, hb, hs, m0, m1, lt); break;
+    case MELT_OUT_LOG_MAGNITUDE: handoff_rows<MELT_OUT_LOG_MAGNITUDE>(a, ch, hb, hs, m0, m1, lt); break;
+    case MELT_OUT_POWER: handoff_rows<MELT_OUT_POWER>(a, ch, hb, hs, m0, m1, lt); break;
+    default: handoff_rows<MELT_OUT_MAGNITUDE>(a, ch, hb, hs, m0, m1, lt); break;
     }
 }
 
 // The stager role with 16-byte vectors (H a multiple of 4); same barriers as the scalar
 // loop in k_melt_f32_ws.
 template <int RTB, int PV, bool HANDOFF>
-__device__ __forceinline__ void stage_rows_vec(const FwdArgs &a, const float *hb, int hs, float *lds, int lt, int c,
-                                               int nch) {
+__device__ __forceinline__ void stage_rows_vec(const FwdArgs &a, const float *hb, int hs, float *lds, int lt, int w,
+                                               int nwork, int rsplit, int rps) {
     f32x4 pv[PV];
-    if (c < nch) {
-        const Chunk ch = read_chunk(a.chunks, c);
+    const int G = gridDim.x;
+    if (w < nwork) {
+        const Chunk ch = read_chunk(a.chunks, w / rsplit);
         span_load4<PV, 256>(a, ch, pv, lt);
         span_store4<PV, 256>(a, ch, pv, lds, lt);
     }
-    __syncthreads();                               // rows of the first chunk ready
-    if (c + (int)gridDim.x < nch) span_load4<PV, 256>(a, read_chunk(a.chunks, c + gridDim.x), pv, lt);
-    for (; c < nch; c += gridDim.x) {
+    __syncthreads();                               // rows of the first item ready
+    if (w + G < nwork) span_load4<PV, 256>(a, read_chunk(a.chunks, (w + G) / rsplit), pv, lt);
+    for (; w < nwork; w += G) {
         __syncthreads();                           // A: the multiply waves are done with the rows
-        const int cn = c + gridDim.x;
-        if (cn < nch) span_store4<PV, 256>(a, read_chunk(a.chunks, cn), pv, lds, lt);
-        __syncthreads();                           // B: rows of the next chunk ready; energies of chunk c in hb
-        if constexpr (HANDOFF) stager_epilogue<RTB>(a, read_chunk(a.chunks, c), hb, hs, lt);
-        if (cn + (int)gridDim.x < nch) span_load4<PV, 256>(a, read_chunk(a.chunks, cn + gridDim.x), pv, lt);
+        const int wn = w + G;
+        if (wn < nwork) span_store4<PV, 256>(a, read_chunk(a.chunks, wn / rsplit), pv, lds, lt);
+        __syncthreads();                           // B: rows of the next item ready; energies of item w in hb
+        if constexpr (HANDOFF) stager_epilogue<RTB>(a, work_item(a, w, rsplit, rps), hb, hs, lt);
+        if (wn + G < nwork) span_load4<PV, 256>(a, read_chunk(a.chunks, (wn + G) / rsplit), pv, lt);
     }
 }
 
 template <int RTB, int PRE, bool HANDOFF>
 __global__ __attribute__((amdgpu_flat_work_group_size(512, 512), amdgpu_waves_per_eu(2, 2)))
-void k_melt_f32_ws(FwdArgs a, const f32x4 *__restrict__ bpack, int NG, int hb_off, int hs) {
+void k_melt_f32_ws(FwdArgs a, const f32x4 *__restrict__ bpack, int NG, int hb_off, int hs, int rsplit) {
     extern __shared__ float lds[];
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nch = *a.n_chunks;
+    const int nwork = *a.n_chunks * rsplit;
+    const int rps = (a.row_tiles + rsplit - 1) / rsplit;     // row tiles per work item
     float *hb = lds + hb_off;                      // handoff buffer (HANDOFF only)
     zero_pad_columns<ConvF32>(a, kChunkF32 + a.J - 1, lds, 512, 0);
-    int c = blockIdx.x;
+    int w = blockIdx.x;
+    const int G = gridDim.x;
     if (wid >= 4) {
         const int lt = (int)threadIdx.x - 256;
         if ((a.H & 3) == 0) {
-            stage_rows_vec<RTB, PRE / 4, HANDOFF>(a, hb, hs, lds, lt, c, nch);
+            stage_rows_vec<RTB, PRE / 4, HANDOFF>(a, hb, hs, lds, lt, w, nwork, rsplit, rps);
             return;
         }
         float pf[PRE];
-        if (c < nch) {
-            const Chunk ch = read_chunk(a.chunks, c);
+        if (w < nwork) {
+            const Chunk ch = read_chunk(a.chunks, w / rsplit);
             span_load<PRE, 256>(a, ch, pf, lt);
             span_store<ConvF32, PRE, 256>(a, ch, pf, lds, 0, lt);
         }
-        __syncthreads();                           // rows of the first chunk ready
-        if (c + (int)gridDim.x < nch) span_load<PRE, 256>(a, read_chunk(a.chunks, c + gridDim.x), pf, lt);
-        for (; c < nch; c += gridDim.x) {
+        __syncthreads();                           // rows of the first item ready
+        if (w + G < nwork) span_load<PRE, 256>(a, read_chunk(a.chunks, (w + G) / rsplit), pf, lt);
+        for (; w < nwork; w += G) {
             __syncthreads();                       // A: the multiply waves are done with the rows
-            const int cn = c + gridDim.x;
-            if (cn < nch) span_store<ConvF32, PRE, 256>(a, read_chunk(a.chunks, cn), pf, lds, 0, lt);
-            __syncthreads();                       // B: rows of the next chunk ready; energies of chunk c in hb
-            if constexpr (HANDOFF) stager_epilogue<RTB>(a, read_chunk(a.chunks, c), hb, hs, lt);
-            if (cn + (int)gridDim.x < nch) span_load<PRE, 256>(a, read_chunk(a.chunks, cn + gridDim.x), pf, lt);
+            const int wn = w + G;
+            if (wn < nwork) span_store<ConvF32, PRE, 256>(a, read_chunk(a.chunks, wn / rsplit), pf, lds, 0, lt);
+            __syncthreads();                       // B: rows of the next item ready; energies of item w in hb
+            if constexpr (HANDOFF) stager_epilogue<RTB>(a, work_item(a, w, rsplit, rps), hb, hs, lt);
+            if (wn + G < nwork) span_load<PRE, 256>(a, read_chunk(a.chunks, (wn + G) / rsplit), pf, lt);
         }
         return;
     }
@@ -253,20 +271,21 @@ void k_melt_f32_ws(FwdArgs a, const f32x4 *__restrict__ bpack, int NG, int hb_of
     const __amdgpu_buffer_rsrc_t brs = __builtin_amdgcn_make_buffer_rsrc(
         (void *)bpack, (short)0, a.row_tiles * NG * 64 * 16, 0x00020000);
     __syncthreads();
-    for (; c < nch; c += gridDim.x) {
-        const Chunk ch = read_chunk(a.chunks, c);
+    for (; w < nwork; w += G) {
+        const WorkItem it = work_item(a, w, rsplit, rps);
+        const Chunk ch = read_chunk(a.chunks, it.c);
         const int fbase = wid * 32;
         const bool active = fbase < ch.n_frames;
         const float *lp = lds + (fbase + (lane & 31)) * a.S + 4 * (lane >> 5);
-        for (int rb = 0; rb < a.row_tiles; rb += RTB) {
-            const bool last = rb + RTB >= a.row_tiles;
+        for (int rb = it.r_lo; rb < it.r_hi; rb += RTB) {
+            const bool last = rb + RTB >= it.r_hi;
             f32x16 acc[RTB];
 #pragma unroll
             for (int r = 0; r < RTB; ++r) acc[r] = f32x16{};
             if (active) {
                 int voff[RTB];
 #pragma unroll
-                for (int r = 0; r < RTB; ++r) voff[r] = ((min(rb + r, a.row_tiles - 1) * NG) * 64 + lane) * 16;
+                for (int r = 0; r < RTB; ++r) voff[r] = ((min(rb + r, it.r_hi - 1) * NG) * 64 + lane) * 16;
                 auto load = [&](f32x4 (&A)[RTB], f32x4 &B, int g) {
                     const int j = g / GH;
 #pragma unroll
@@ -301,7 +320,7 @@ void k_melt_f32_ws(FwdArgs a, const f32x4 *__restrict__ bpack, int NG, int hb_of
             if (active) {
 #pragma unroll
                 for (int r = 0; r < RTB; ++r) {
-                    if (rb + r >= a.row_tiles) continue;
+                    if (rb + r >= it.r_hi) continue;
                     if (HANDOFF && last) {
                         handoff_tile(hb, hs, fbase + (lane & 31), rb + r, lane, acc[r]);
                         store_proj(a, ch, rb + r, fbase + (lane & 31), lane, acc[r]);
@@ -311,7 +330,7 @@ void k_melt_f32_ws(FwdArgs a, const f32x4 *__restrict__ bpack, int NG, int hb_of
                 }
             }
         }
-        __syncthreads();                           // B: rows of the next chunk ready
+        __syncthreads();                           // B: rows of the next item ready
     }
 }
 
@@ -337,7 +356,8 @@ static melt_status launch_f32_rtb(Plan &p, const FwdArgs &a, const GroupTableBig
 }
 
 template <int RTB, int PRE>
-static melt_status launch_f32_ws_pre(const FwdArgs &a, const f32x4 *bp, int NG, size_t lds, int grid, hipStream_t s) {
+static melt_status launch_f32_ws_pre(const FwdArgs &a, const f32x4 *bp, int NG, size_t lds, int grid, int rsplit,
+                                     hipStream_t s) {
     // handoff buffer after the rows: 128 frames x hs floats, hs = 16 row tiles + 4 (an odd
     // number of 16-byte groups, so the 32 frames a wave writes spread over the banks)
     const int hs = a.row_tiles * 16 + 4;
@@ -345,21 +365,22 @@ static melt_status launch_f32_ws_pre(const FwdArgs &a, const f32x4 *bp, int NG, 
     const size_t with = hb_off + (size_t)kBF32 * hs * 4;
     if (with <= (size_t)kMaxLds) {
         allow_lds(k_melt_f32_ws<RTB, PRE, true>);
-        k_melt_f32_ws<RTB, PRE, true><<<grid, 512, with, s>>>(a, bp, NG, (int)(hb_off / 4), hs);
+        k_melt_f32_ws<RTB, PRE, true><<<grid, 512, with, s>>>(a, bp, NG, (int)(hb_off / 4), hs, rsplit);
     } else {
         allow_lds(k_melt_f32_ws<RTB, PRE, false>);
-        k_melt_f32_ws<RTB, PRE, false><<<grid, 512, lds, s>>>(a, bp, NG, 0, 0);
+        k_melt_f32_ws<RTB, PRE, false><<<grid, 512, lds, s>>>(a, bp, NG, 0, 0, rsplit);
     }
     return hip_check(hipGetLastError(), "melt f32 ws launch");
 }
 
 template <int RTB>
-static melt_status launch_f32_ws_rtb(Plan &p, const FwdArgs &a, int NG, size_t lds, int grid, hipStream_t s) {
+static melt_status launch_f32_ws_rtb(Plan &p, const FwdArgs &a, int NG, size_t lds, int grid, int rsplit,
+                                     hipStream_t s) {
     const f32x4 *bp = (const f32x4 *)p.d_pack_f32;
     const int need = ((kBF32 + a.J - 1) * a.H + 255) / 256;
-    if (need <= 48) return launch_f32_ws_pre<RTB, 48>(a, bp, NG, lds, grid, s);
-    if (need <= 88) return launch_f32_ws_pre<RTB, 88>(a, bp, NG, lds, grid, s);
-    if (need <= 136) return launch_f32_ws_pre<RTB, 136>(a, bp, NG, lds, grid, s);
+    if (need <= 48) return launch_f32_ws_pre<RTB, 48>(a, bp, NG, lds, grid, rsplit, s);
+    if (need <= 88) return launch_f32_ws_pre<RTB, 88>(a, bp, NG, lds, grid, rsplit, s);
+    if (need <= 136) return launch_f32_ws_pre<RTB, 136>(a, bp, NG, lds, grid, rsplit, s);
     return set_error(MELT_E_UNSUPPORTED, "hop too large for the FP32 staging waves");
 }
 
@@ -374,15 +395,25 @@ melt_status launch_melt_f32(Plan &p, const FwdTask &t, bool warp_specialised) {
     const int grid = persistent_grid(p, t.est_chunks, 1);
     const hipStream_t s = t.stream;
     if (warp_specialised) {
+        // A batch with fewer chunks than compute units splits each chunk's row tiles over
+        // rsplit workgroups (work items), so a short call still spreads over the machine;
+        // otherwise one workgroup takes a whole chunk.
+        int rsplit = 1;
+        if (t.est_chunks < p.cu_count && p.row_tiles > 1) {
+            rsplit = (int)std::min<int64_t>(p.row_tiles, (p.cu_count + t.est_chunks - 1) / std::max<int64_t>(t.est_chunks, 1));
+            rsplit = (p.row_tiles + (p.row_tiles + rsplit - 1) / rsplit - 1) / ((p.row_tiles + rsplit - 1) / rsplit);
+        }
+        const int rps = (p.row_tiles + rsplit - 1) / rsplit;
+        const int g2 = persistent_grid(p, t.est_chunks * rsplit, 1);
         // row tiles per block at most 5: accumulators and the basis ping-pong within the
         // 256 registers of two waves per SIMD
-        const int blocks = (p.row_tiles + 4) / 5;
-        switch ((p.row_tiles + blocks - 1) / blocks) {
-        case 1: return launch_f32_ws_rtb<1>(p, a, gt.n, lds, grid, s);
-        case 2: return launch_f32_ws_rtb<2>(p, a, gt.n, lds, grid, s);
-        case 3: return launch_f32_ws_rtb<3>(p, a, gt.n, lds, grid, s);
-        case 4: return launch_f32_ws_rtb<4>(p, a, gt.n, lds, grid, s);
-        default: return launch_f32_ws_rtb<5>(p, a, gt.n, lds, grid, s);
+        const int blocks = (rps + 4) / 5;
+        switch ((rps + blocks - 1) / blocks) {
+        case 1: return launch_f32_ws_rtb<1>(p, a, gt.n, lds, g2, rsplit, s);
+        case 2: return launch_f32_ws_rtb<2>(p, a, gt.n, lds, g2, rsplit, s);
+        case 3: return launch_f32_ws_rtb<3>(p, a, gt.n, lds, g2, rsplit, s);
+        case 4: return launch_f32_ws_rtb<4>(p, a, gt.n, lds, g2, rsplit, s);
+        default: return launch_f32_ws_rtb<5>(p, a, gt.n, lds, g2, rsplit, s);
         }
     }
     // row tiles per block at most 5 (2 for the deepest prefetch) so accumulators, basis

@@ -267,6 +267,7 @@ melt_status launch_schedule(Plan &p, int which, const int64_t *d_off, int n_clip
     if (st == MELT_OK) {
         p.prepared_frames[which] = n_frames;
         p.prepared_bf[which] = bf;
+        p.prepared_clips[which] = n_clips;
         if (which == 0) p.prepared_variant = p.tune_variant;
     }
     return st;
@@ -354,7 +355,8 @@ melt_status launch_melt_main(Plan &p, const float *d_wave, float *d_out, float *
     if (n_frames < 0) return set_error(MELT_E_INVALID_ARG, "no batch prepared");
     if (n_frames == 0) return MELT_OK;
     const int v = p.prepared_variant;
-    const int64_t est = n_frames / p.prepared_bf[0] + 1;   // chunk count (a lower bound sizes the grid)
+    // chunk count bound: every clip ends in at most one partial chunk
+    const int64_t est = n_frames / p.prepared_bf[0] + p.prepared_clips[0];
     if (p.K == 0)
         return launch_melt_table(p, v, p.d_chunks[0], p.d_nchunks, est, n_frames, d_wave, d_out, d_proj, s);
     // MFCCT (Eq. mfcct_matrix): log-Mel rows into the plan workspace, then C = L D^T

@@ -75,6 +75,7 @@ struct Plan {
     int64_t prepared_frames[2] = {-1, -1};   // n_frames of the batch each table describes
     int prepared_variant = 0;                // kernel variant table 0 was built for
     int prepared_bf[2] = {128, 32};          // frames per chunk of each table
+    int prepared_clips[2] = {0, 0};          // clips of the batch each table describes
     // backward: dx basis layout and workspaces (grown on demand)
     void *d_pack_dx = nullptr;
     size_t pack_dx_cap = 0;

@@ -549,7 +549,7 @@ melt_status launch_stft_main(Plan &p, const float *d_wave, float *d_out, hipStre
     a.out_kind = p.kern_out;
     a.eps = (float)p.cfg.log_eps;
     const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / lds)));
-    const int64_t est = (n_frames / bf + 1 + kStftWaves - 1) / kStftWaves;
+    const int64_t est = (n_frames / bf + p.prepared_clips[1] + kStftWaves - 1) / kStftWaves;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, (int64_t)p.cu_count * per_cu));
     melt_status st;
     switch (p.N) {
