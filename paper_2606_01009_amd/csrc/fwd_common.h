@@ -592,6 +592,8 @@ inline int persistent_grid(const Plan &p, int64_t est_chunks, int dflt) {
 // 16-bit row-split kernels: k-group counts with a compiled register tile
 inline bool rs_supported(int NS) { return NS == 25 || NS == 32 || NS == 20 || NS == 16 || NS == 10; }
 inline bool rs_fits(const Plan &p) { return rs_supported(p.geo16.n_groups) && p.row_tiles <= 8; }
+// the direct-to-LDS kernel: any Mel count (row groups of at most 8 tiles)
+inline bool as_fits(const Plan &p) { return rs_supported(p.geo16.n_groups); }
 
 // LDS of the direct-to-LDS 16-bit kernel: operand rows, then the FP32 span scratch (16-byte aligned)
 inline size_t as_rows_bytes(const Plan &p, int bf) {
@@ -602,16 +604,26 @@ inline size_t as_rows_bytes(const Plan &p, int bf) {
 inline size_t as_stage_offset(const Plan &p, int bf) {
     return ((((as_rows_bytes(p, bf) + 15) & ~size_t(15)) + (size_t)(bf + p.geo16.J - 1) * p.H * 4) + 15) & ~size_t(15);
 }
-// Waves of the direct-to-LDS row-split kernels: `full` waves own one row tile each; when one or
-// two row tiles remain beyond a multiple of four, four more waves share them (psplit waves
-// per tile), so the work spreads evenly over the CU's four SIMDs.
+// Waves of the direct-to-LDS row-split kernels for a group of `rt` row tiles: `full` waves own
+// one row tile each; when one or two row tiles remain beyond a multiple of four, four more
+// waves share them (psplit waves per tile), so the work spreads evenly over the CU's four
+// SIMDs.  More than 8 row tiles are cut into row groups of at most 8, one group per
+// workgroup, so that a wave's basis tile stays register-resident.
 struct WaveLayout {
     int full, psplit, waves;
 };
+__host__ __device__ inline WaveLayout layout_for(int rt) {
+    const int rem = rt % 4;
+    if ((rem == 1 || rem == 2) && rt - rem + 4 <= 8) return {rt - rem, 4 / rem, rt - rem + 4};
+    return {rt, 1, rt};
+}
+inline int row_groups(const Plan &p) { return (p.row_tiles + 7) / 8; }
+// the workgroup's waves: enough for the layout of every row group (the last may be smaller)
 inline WaveLayout wave_layout(const Plan &p) {
-    const int RT = p.row_tiles, rem = RT % 4;
-    if ((rem == 1 || rem == 2) && RT - rem + 4 <= 8) return {RT - rem, 4 / rem, RT - rem + 4};
-    return {RT, 1, RT};
+    const int rg = row_groups(p), gt_n = (p.row_tiles + rg - 1) / rg;
+    WaveLayout w = layout_for(gt_n);
+    w.waves = std::max(w.waves, layout_for(p.row_tiles - (rg - 1) * gt_n).waves);
+    return w;
 }
 inline size_t as_lds_bytes(const Plan &p, int bf) {
     return as_stage_offset(p, bf) + (size_t)wave_layout(p).waves * kStageFloats * 4;

@@ -311,13 +311,13 @@ static std::vector<Variant> variant_list(const Plan &p) {
         break;
     default: {
         const bool x3 = p.cfg.precision == MELT_PREC_BF16X3;
-        if (rs_fits(p)) {
+        if (as_fits(p)) {
             for (int bf : {128, 96, 64}) {
                 if (bf == (x3 ? 128 : 96)) continue;
                 if (as_lds_bytes(p, bf) <= (size_t)kMaxLds) v.push_back({V_H16_AS, bf});
             }
-            v.push_back({V_H16_RS, 128});
         }
+        if (rs_fits(p)) v.push_back({V_H16_RS, 128});
         if (!x3) v.push_back({V_H16_FS, kBF32});
     }
     }

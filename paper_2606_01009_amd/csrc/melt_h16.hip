@@ -147,15 +147,22 @@ __global__ __launch_bounds__(512) void k_melt_h16_rs(FwdArgs a, const uint4 *__r
 template <class Conv, int NS, bool X3, bool IS_F16>
 __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__restrict__ bhi,
                                                      const uint4 *__restrict__ blo, GroupTableBig gt, int bf,
-                                                     int scr_off, int stage_off, int full, int psplit) {
+                                                     int scr_off, int stage_off, int rgroups) {
     extern __shared__ float lds_as[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // row group of this workgroup (fixed for its life, so the basis stays in registers):
+    // tiles [grp * gt_n, min(RT, (grp + 1) * gt_n)); waves beyond the group's layout idle
+    const int grp = blockIdx.x % rgroups, gt_n = (a.row_tiles + rgroups - 1) / rgroups;
+    const int r0 = grp * gt_n, cnt = min(a.row_tiles - r0, gt_n);
+    const WaveLayout L = layout_for(cnt);
+    const bool idle = wid >= L.waves;
     int rt = wid, part = 0, P = 1;
-    if (wid >= full) {
-        rt = full + (wid - full) / psplit;
-        part = (wid - full) % psplit;
-        P = psplit;
+    if (wid >= L.full) {
+        rt = L.full + (wid - L.full) / L.psplit;
+        part = (wid - L.full) % L.psplit;
+        P = L.psplit;
     }
+    rt = idle ? r0 : r0 + rt;
     const int lo_off = a.S * (bf + a.J - 1);
     unsigned short *rows = reinterpret_cast<unsigned short *>(lds_as);
     float *scratch = lds_as + scr_off;             // FP32 span, after the operand rows
@@ -170,16 +177,17 @@ __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__r
     }
     float *stage = lds_as + stage_off + wid * kStageFloats;
     const int nch = *a.n_chunks;
-    int c = blockIdx.x;
+    const int cstep = gridDim.x / rgroups;         // the grid is a multiple of rgroups
+    int c = blockIdx.x / rgroups;
     if (c < nch) async_span(a, read_chunk(a.chunks, c), scratch);
     async_wait();
-    for (; c < nch; c += gridDim.x) {
+    for (; c < nch; c += cstep) {
         const Chunk ch = read_chunk(a.chunks, c);
         __syncthreads();                           // span of chunk c is in scratch; rows are free
         convert_span<Conv>(a, ch, scratch, rows, lo_off);
         __syncthreads();                           // rows ready; scratch is free
-        if (c + (int)gridDim.x < nch) async_span(a, read_chunk(a.chunks, c + gridDim.x), scratch);
-        const int nft = (ch.n_frames + 31) >> 5;
+        if (c + cstep < nch) async_span(a, read_chunk(a.chunks, c + cstep), scratch);
+        const int nft = idle ? 0 : (ch.n_frames + 31) >> 5;
         // The next chunk's copy must land before the barrier that starts the next iteration.
         // Each wave waits ahead of its last tile's stores (so those stores stay in flight
         // across the barrier), or after the loop if it had no tile.
@@ -288,8 +296,9 @@ static melt_status launch_as_ns(Plan &p, const FwdArgs &a, const GroupTableBig &
     allow_lds(k_melt_h16_as<Conv, NS, X3, F16>);
     const int stage_off = (int)(as_stage_offset(p, bf) / 4);
     const WaveLayout w = wave_layout(p);
+    const int rg = row_groups(p);
     k_melt_h16_as<Conv, NS, X3, F16><<<grid, 64 * w.waves, lds, s>>>(
-        a, (const uint4 *)p.d_pack_h16, (const uint4 *)p.d_pack_lo, gt, bf, scr_off, stage_off, w.full, w.psplit);
+        a, (const uint4 *)p.d_pack_h16, (const uint4 *)p.d_pack_lo, gt, bf, scr_off, stage_off, rg);
     return hip_check(hipGetLastError(), "melt h16 lds-dma launch");
 }
 
@@ -333,7 +342,11 @@ melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf) {
         const size_t lds = as_lds_bytes(p, bf);
         if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
         const int scr_off = (int)(((as_rows_bytes(p, bf) + 15) & ~size_t(15)) / 4);
-        const int grid = persistent_grid(p, t.est_chunks, std::min(std::max(1, (int)(kMaxLds / lds)), 2));
+        // one persistent set of workgroups per row group, each walking all chunks
+        const int rg = row_groups(p);
+        const int per_cu = std::min(std::max(1, (int)(kMaxLds / lds)), 2);
+        const int per_group = (int)std::max<int64_t>(1, std::min<int64_t>(t.est_chunks, ((int64_t)p.cu_count * per_cu + rg - 1) / rg));
+        const int grid = per_group * rg;
         if (x3) return launch_as<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, scr_off, s);
         if (f16) return launch_as<ConvF16, false, true>(p, a, gt, lds, grid, bf, scr_off, s);
         return launch_as<ConvBF16, false, false>(p, a, gt, lds, grid, bf, scr_off, s);

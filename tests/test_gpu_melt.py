@@ -136,9 +136,11 @@ def test_every_kernel_variant(torch, melt, orc, prec):
     past them and mid-way.  Geometries: the 16 kHz front end (hop a multiple of 4: vector
     span conversion), hop 50 (two-byte aligned rows: element-wise conversion) and N=480,
     hop 161 (32 k-groups, odd hop); 16, 24 and 96 Mel bins (1, 2 and 6 row tiles: the
-    16-bit kernel's waves that share a row tile by frame tiles)."""
+    16-bit kernel's waves that share a row tile by frame tiles); 144 and 256 Mel bins (row
+    groups of 5 + 4 and 8 + 8 tiles in the 16-bit kernel)."""
     geoms = [(16000, 400, 160, 80), (16000, 400, 50, 40), (16000, 480, 161, 64),
-             (16000, 400, 160, 16), (16000, 400, 160, 24), (16000, 512, 128, 96)]
+             (16000, 400, 160, 16), (16000, 400, 160, 24), (16000, 512, 128, 96),
+             (16000, 400, 160, 144), (16000, 400, 160, 256)]
     if prec == "fp8":
         geoms = geoms[:1]
     elif prec == "fp32":
