@@ -601,6 +601,7 @@ inline size_t as_rows_bytes(const Plan &p, int bf) {
     return (size_t)(bf + p.geo16.J - 1) * lds_stride(p.geo16.Hp, 2) * 2 * (x3 ? 2 : 1);
 }
 // ... then the epilogue areas of the waves (byte offset, 16-byte aligned)
+// (the 16-bit kernel stores its outputs straight from the accumulators: no epilogue area)
 inline size_t as_stage_offset(const Plan &p, int bf) {
     return ((((as_rows_bytes(p, bf) + 15) & ~size_t(15)) + (size_t)(bf + p.geo16.J - 1) * p.H * 4) + 15) & ~size_t(15);
 }
@@ -625,9 +626,7 @@ inline WaveLayout wave_layout(const Plan &p) {
     w.waves = std::max(w.waves, layout_for(p.row_tiles - (rg - 1) * gt_n).waves);
     return w;
 }
-inline size_t as_lds_bytes(const Plan &p, int bf) {
-    return as_stage_offset(p, bf) + (size_t)wave_layout(p).waves * kStageFloats * 4;
-}
+inline size_t as_lds_bytes(const Plan &p, int bf) { return as_stage_offset(p, bf); }
 
 // per-family launchers (melt_f32.hip, melt_h16.hip, melt_f8.hip)
 melt_status launch_melt_f32(Plan &p, const FwdTask &t, bool warp_specialised);

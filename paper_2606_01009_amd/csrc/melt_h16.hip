@@ -137,7 +137,8 @@ __global__ __launch_bounds__(512) void k_melt_h16_rs(FwdArgs a, const uint4 *__r
 //
 // Row-split 16-bit kernel with direct-to-LDS staging (default for BF16/FP16/BF16X3): as
 // k_melt_h16_rs, but chunk c+1's span is copied into an FP32 scratch area while chunk c is
-// multiplied; after a barrier all threads convert it into the operand rows.
+// multiplied; after a barrier all threads convert it into the operand rows.  Outputs are
+// stored straight from the accumulators (8 consecutive Mel bins per lane).
 //
 // Wave layout (balanced over the CU's four SIMDs): waves 0..full-1 each own one row tile and
 // sweep every frame tile of the chunk, two at a time; the remaining row tiles (one or two)
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(512) void k_melt_h16_rs(FwdArgs a, const uint4 *__r
 template <class Conv, int NS, bool X3, bool IS_F16>
 __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__restrict__ bhi,
                                                      const uint4 *__restrict__ blo, GroupTableBig gt, int bf,
-                                                     int scr_off, int stage_off, int rgroups) {
+                                                     int scr_off, int rgroups) {
     extern __shared__ float lds_as[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     // row group of this workgroup (fixed for its life, so the basis stays in registers):
@@ -175,7 +176,6 @@ __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__r
 #pragma unroll
         for (int s = 0; s < NS; ++s) Al[s] = blo[((size_t)rt * NS + s) * 64 + lane];
     }
-    float *stage = lds_as + stage_off + wid * kStageFloats;
     const int nch = *a.n_chunks;
     const int cstep = gridDim.x / rgroups;         // the grid is a multiple of rgroups
     int c = blockIdx.x / rgroups;
@@ -210,8 +210,8 @@ __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__r
                         async_wait();
                         waited = true;
                     }
-                    store_tile_staged(a, ch, rt, ft * 32, lane, acc0, stage);
-                    if (two) store_tile_staged(a, ch, rt, (ft + 1) * 32, lane, acc1, stage);
+                    store_tile(a, ch, rt, ft * 32 + (lane & 31), lane, acc0);
+                    if (two) store_tile(a, ch, rt, (ft + 1) * 32 + (lane & 31), lane, acc1);
                     continue;
                 }
             }
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__r
                 async_wait();
                 waited = true;
             }
-            store_tile_staged(a, ch, rt, ft * 32, lane, acc0, stage);
+            store_tile(a, ch, rt, ft * 32 + (lane & 31), lane, acc0);
         }
         if (!waited) async_wait();                 // no tile for this wave (or a frameless chunk)
     }
@@ -294,11 +294,10 @@ template <class Conv, int NS, bool X3, bool F16>
 static melt_status launch_as_ns(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
                                 int scr_off, hipStream_t s) {
     allow_lds(k_melt_h16_as<Conv, NS, X3, F16>);
-    const int stage_off = (int)(as_stage_offset(p, bf) / 4);
     const WaveLayout w = wave_layout(p);
     const int rg = row_groups(p);
     k_melt_h16_as<Conv, NS, X3, F16><<<grid, 64 * w.waves, lds, s>>>(
-        a, (const uint4 *)p.d_pack_h16, (const uint4 *)p.d_pack_lo, gt, bf, scr_off, stage_off, rg);
+        a, (const uint4 *)p.d_pack_h16, (const uint4 *)p.d_pack_lo, gt, bf, scr_off, rg);
     return hip_check(hipGetLastError(), "melt h16 lds-dma launch");
 }
 
