@@ -122,15 +122,15 @@ __global__ __launch_bounds__(512) void k_melt_f8_rs(FwdArgs a, const i32x8 *__re
 //
 // As k_melt_f8_rs, with the chunk's sample span copied HBM -> LDS by direct-to-LDS loads
 // (async_span) while the previous chunk multiplies.  Frame t of the chunk is span samples
-// [tH, tH + N), so the per-row maxima and the E4M3 image are read straight from the
-// contiguous span (no hop-block rows, no division per element).  Positions at or past the
-// valid span (clip end) count as 0.  Outputs leave through store_tile_staged.  Waves map
-// to row tiles and frame tiles as in the 16-bit kernel (wave_layout: one or two leftover
-// row tiles are shared by four waves, by frame tiles).
+// [tH, tH + N), so each frame's maximum and E4M3 image come straight from the contiguous
+// span (no hop-block rows, no division per element), in one pass per frame.  Positions at
+// or past the valid span (clip end) count as 0.  Outputs are stored straight from the
+// accumulators.  Waves map to row tiles and frame tiles as in the 16-bit kernel
+// (wave_layout: one or two leftover row tiles are shared by four waves, by frame tiles).
 template <int NG>
 __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__restrict__ bq,
                                                     const float *__restrict__ rinv_g, int N, int bf, int scr_off,
-                                                    int stage_off, int full, int psplit) {
+                                                    int full, int psplit) {
     extern __shared__ float lds_f8[];
     const int lane = threadIdx.x & 63, nthreads = blockDim.x;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = nthreads >> 6;
@@ -142,14 +142,9 @@ __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__re
     }
     constexpr int KP = NG * 64;             // padded frame length in the E4M3 image
     constexpr int SQ = KP + 16;             // row stride (bytes): 4 x odd dwords -> conflict-free 16-byte reads
-    const int rows_max = bf + a.J - 1;
     unsigned char *xq = reinterpret_cast<unsigned char *>(lds_f8);              // [bf][SQ] E4M3
     float *sinv = reinterpret_cast<float *>(xq + bf * SQ);                       // [bf] s_t
-    float *mfull = sinv + bf;                                                    // [rows] max over the row
-    float *mpre = mfull + rows_max;                                              // [rows] max over the last segment's prefix
     float *scratch = lds_f8 + scr_off;                                           // FP32 span
-    float *stage = lds_f8 + stage_off + wid * kStageFloats;
-    const int Llast = N - (a.J - 1) * a.H;                                       // length of the last segment
     i32x8 A[NG];
 #pragma unroll
     for (int g = 0; g < NG; ++g) A[g] = bq[((size_t)rt * NG + g) * 64 + lane];
@@ -164,88 +159,38 @@ __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__re
         const Chunk ch = read_chunk(a.chunks, c);
         const int valid = span_valid(a, ch);
         __syncthreads();                           // span of chunk c is in scratch; the image is free
-        // per-row maxima over the whole row and over its first Llast samples
-        const int rows = ch.n_frames + a.J - 1;
-        if ((a.H & 3) == 0 && (Llast & 3) == 0) {
-            // one thread per hop row, 16-byte reads; each thread starts its walk through a
-            // column range at a column rotated by its lane, so that the 16 rows read by 16
-            // consecutive lanes fall in distinct bank groups
-            const int qa = Llast >> 2, qb = (a.H - Llast) >> 2;     // vectors before / after Llast
-            for (int r = threadIdx.x; r < rows; r += nthreads) {
-                const int base = r * a.H;
-                const bool whole = base + a.H <= valid;
-                float ma = 0.0f, mb = 0.0f;
-                for (int k = 0, q = lane % (qa > 0 ? qa : 1); k < qa; ++k) {
-                    const int o = base + 4 * q;
-                    f32x4 x = *(const f32x4 *)(scratch + o);
-                    if (!whole)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (o + e >= valid) x[e] = 0.0f;
-                    ma = fmaxf(ma, fmaxf(fmaxf(fabsf(x[0]), fabsf(x[1])), fmaxf(fabsf(x[2]), fabsf(x[3]))));
-                    if (++q == qa) q = 0;
-                }
-                for (int k = 0, q = lane % (qb > 0 ? qb : 1); k < qb; ++k) {
-                    const int o = base + Llast + 4 * q;
-                    f32x4 x = *(const f32x4 *)(scratch + o);
-                    if (!whole)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (o + e >= valid) x[e] = 0.0f;
-                    mb = fmaxf(mb, fmaxf(fmaxf(fabsf(x[0]), fabsf(x[1])), fmaxf(fabsf(x[2]), fabsf(x[3]))));
-                    if (++q == qb) q = 0;
-                }
-                mfull[r] = fmaxf(ma, mb);
-                mpre[r] = ma;
-            }
-        } else {
-            // general hops: one wave per hop row with a cross-lane reduction
-            for (int r = wid; r < rows; r += nw) {
-                float mf = 0.0f, mp = 0.0f;
-                for (int col = lane; col < a.H; col += 64) {
-                    const int o = r * a.H + col;
-                    const float v = o < valid ? fabsf(scratch[o]) : 0.0f;
-                    mf = fmaxf(mf, v);
-                    if (col < Llast) mp = fmaxf(mp, v);
-                }
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    mf = fmaxf(mf, __shfl_xor(mf, o));
-                    mp = fmaxf(mp, __shfl_xor(mp, o));
-                }
-                if (lane == 0) {
-                    mfull[r] = mf;
-                    mpre[r] = mp;
-                }
-            }
-        }
-        __syncthreads();
-        for (int t = threadIdx.x; t < ch.n_frames; t += nthreads) {
-            float mx = mpre[t + a.J - 1];
-            for (int j = 0; j + 1 < a.J; ++j) mx = fmaxf(mx, mfull[t + j]);
-            sinv[t] = mx > 0.0f ? __fdiv_rn(448.0f, mx) : 1.0f;     // the scale; inverted in the epilogue
-        }
-        __syncthreads();
-        // quantise: one wave per frame, lane = 4-sample word of the padded frame
+        // one wave per frame: its samples (span [tH, tH + N), 0 at or past the clip end) are
+        // read once into registers, max |x| is reduced across the wave, then the frame is
+        // scaled by s_t = 448 / max and rounded to E4M3 straight from the registers
+        constexpr int KW = (KP / 4 + 63) / 64;     // 4-sample words per lane
         const bool vec = (a.H & 3) == 0 && (N & 3) == 0;
         for (int t = wid; t < ch.n_frames; t += nw) {
-            const float s = sinv[t];
             const int base = t * a.H;
             const bool whole = vec && base + N <= valid;    // every sample of the frame present
-            unsigned *dst = reinterpret_cast<unsigned *>(xq + t * SQ);
+            f32x4 x[KW];
+            float mx = 0.0f;
 #pragma unroll
-            for (int k = 0; k < (KP / 4 + 63) / 64; ++k) {
-                const int u = lane + 64 * k;
-                if (u >= KP / 4) break;
-                const int n0 = 4 * u, o = base + n0;
-                f32x4 x;
+            for (int k = 0; k < KW; ++k) {
+                const int n0 = 4 * (lane + 64 * k), o = base + n0;
                 if (whole) {
-                    x = n0 < N ? *(const f32x4 *)(scratch + o) : f32x4{};
+                    x[k] = n0 < N ? *(const f32x4 *)(scratch + o) : f32x4{};
                 } else {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) x[e] = (n0 + e < N && o + e < valid) ? scratch[o + e] : 0.0f;
+                    for (int e = 0; e < 4; ++e) x[k][e] = (n0 + e < N && o + e < valid) ? scratch[o + e] : 0.0f;
                 }
-                dst[u] = fp8x4(__fmul_rn(x[0], s), __fmul_rn(x[1], s), __fmul_rn(x[2], s), __fmul_rn(x[3], s));
+                mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x[k][0]), fabsf(x[k][1])), fmaxf(fabsf(x[k][2]), fabsf(x[k][3]))));
+            }
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d));
+            const float s = mx > 0.0f ? __fdiv_rn(448.0f, mx) : 1.0f;     // the scale; inverted in the epilogue
+            if (lane == 0) sinv[t] = s;
+            unsigned *dst = reinterpret_cast<unsigned *>(xq + t * SQ);
+#pragma unroll
+            for (int k = 0; k < KW; ++k) {
+                const int u = lane + 64 * k;
+                if (u < KP / 4)
+                    dst[u] = fp8x4(__fmul_rn(x[k][0], s), __fmul_rn(x[k][1], s), __fmul_rn(x[k][2], s),
+                                   __fmul_rn(x[k][3], s));
             }
         }
         __syncthreads();                           // image ready; scratch is free
@@ -292,7 +237,7 @@ __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__re
                 const float is = f < ch.n_frames ? 1.0f / sinv[f] : 0.0f;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[r] = acc[r] * (is * rinv[r]);
-                store_tile_staged(a, ch, rt, (ft + u) * 32, lane, acc, stage);
+                store_tile(a, ch, rt, (ft + u) * 32 + (lane & 31), lane, acc);
             }
         }
         if (!waited) async_wait();                 // no tile for this wave (or a frameless chunk)
@@ -312,14 +257,11 @@ static melt_status launch_f8(Plan &p, const FwdArgs &a, size_t lds, int grid, in
 // and row maxima, the FP32 span (16-byte aligned), then the epilogue areas
 size_t f8_as_scratch_offset(const Plan &p, int bf) {
     const int ng8 = (p.N + 63) / 64;
-    const size_t img = (size_t)bf * (ng8 * 64 + 16) + (size_t)bf * 4 + 2 * (size_t)(bf + p.geo32.J - 1) * 4;
+    const size_t img = (size_t)bf * (ng8 * 64 + 16) + (size_t)bf * 4;
     return (img + 15) & ~size_t(15);
 }
-size_t f8_as_stage_offset(const Plan &p, int bf) {
-    return (f8_as_scratch_offset(p, bf) + (size_t)(bf + p.geo32.J - 1) * p.H * 4 + 15) & ~size_t(15);
-}
 size_t f8_as_lds_bytes(const Plan &p, int bf) {
-    return f8_as_stage_offset(p, bf) + (size_t)wave_layout(p).waves * kStageFloats * 4;
+    return (f8_as_scratch_offset(p, bf) + (size_t)(bf + p.geo32.J - 1) * p.H * 4 + 15) & ~size_t(15);
 }
 
 template <int NG>
@@ -327,8 +269,7 @@ static melt_status launch_f8_as(Plan &p, const FwdArgs &a, size_t lds, int grid,
     allow_lds(k_melt_f8_as<NG>);
     const WaveLayout w = wave_layout(p);
     k_melt_f8_as<NG><<<grid, 64 * w.waves, lds, s>>>(a, (const i32x8 *)p.d_pack_f8, p.d_rowscale, p.N, bf,
-                                                     (int)(f8_as_scratch_offset(p, bf) / 4),
-                                                     (int)(f8_as_stage_offset(p, bf) / 4), w.full, w.psplit);
+                                                     (int)(f8_as_scratch_offset(p, bf) / 4), w.full, w.psplit);
     return hip_check(hipGetLastError(), "melt f8 lds-dma launch");
 }
 
