@@ -129,6 +129,91 @@ def load_traffic(path, source_id):
     return t.get("hbm_bytes_per_launch")
 
 
+def run_systems(torch, melt, workloads, path):
+    """The systems rows on synthetic stand-ins: the ragged batch (512 clips of U[0.5, 30] s;
+    16 kHz / N 512 / H 128 and 22.05 kHz / N 1024 / H 256, 128 Mel bins), streaming of 10 ms
+    chunks over 512 streams (per push, eager and replayed from a captured graph), and the
+    backward of the differentiation workload (32 x 10 s at 22.05 kHz, N 1024, H 256, 128 Mel
+    bins): forward with saved projections, then d/dwaveform and d/dbasis."""
+    rows = []
+
+    def emit(r):
+        rows.append(r)
+        log("system " + ", ".join(f"{k} {v:.4g}" if isinstance(v, float) else f"{k} {v}" for k, v in r.items()))
+
+    for variant in ("16k", "22k"):
+        cfg = workloads.config4(variant)
+        N, H, M, sr = cfg["n_fft"], cfg["hop"], cfg["n_mels"], cfg["sr"]
+        T = melt.total_frames(cfg["offsets"], N, H)
+        d_wave = torch.from_numpy(cfg["wave"]).cuda()
+        d_off = torch.from_numpy(cfg["offsets"]).cuda()
+        out = torch.empty((T, M), device="cuda")
+        r = {"workload": f"ragged 512 clips U[0.5,30] s, {variant}: sr {sr:g}, N {N}, H {H}, M {M}", "frames": T}
+        for prec in ("fp32", "bf16", "bf16x3"):
+            plan = melt.MeltPlan(sample_rate=sr, n_fft=N, hop=H, n_mels=M, fmin=0.0, fmax=sr / 2, precision=prec)
+            try:
+                ms = time_launches(torch, lambda: plan.forward(d_wave, d_off, T, out=out), 20, 5)
+            except melt.MeltError as e:
+                r[f"melt_{prec}_error"] = str(e)
+                continue
+            r[f"melt_{prec}_ms"] = ms
+            r[f"melt_{prec}_mframes_s"] = T / (ms * 1e-3) / 1e6
+            if prec == "fp32":
+                r["melt_fp32_tflops"] = T * 4 * N * M / (ms * 1e-3) / 1e12
+        plan = melt.MeltPlan(sample_rate=sr, n_fft=N, hop=H, n_mels=M, fmin=0.0, fmax=sr / 2)
+        ms = time_launches(torch, lambda: plan.stft_mel(d_wave, d_off, T, out=out), 20, 5)
+        r["fft_ms"] = ms
+        r["fft_mframes_s"] = T / (ms * 1e-3) / 1e6
+        emit(r)
+        del d_wave, out
+
+    # streaming: 512 streams, 10 ms chunks (160 samples at 16 kHz), N 512, H 128, 128 Mel bins
+    plan = melt.MeltPlan(sample_rate=16000.0, n_fft=512, hop=128, n_mels=128, fmin=0.0, fmax=8000.0)
+    n_streams, cl, pushes = 512, 160, 200
+    st = melt.MeltStream(plan, n_streams, cl)
+    x = torch.randn((n_streams, cl), device="cuda") * 0.1
+    st.push(x)
+    torch.cuda.synchronize()
+    eager = time_launches(torch, lambda: st.push(x), pushes, 20)
+    g = torch.cuda.CUDAGraph()
+    s2 = torch.cuda.Stream()
+    s2.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s2):
+        with torch.cuda.graph(g, stream=s2):
+            st.push(x)
+    torch.cuda.synchronize()
+    replay = time_launches(torch, g.replay, pushes, 20)
+    emitted = int(st.count.sum().item())
+    emit({"workload": "streaming 512 streams x 10 ms chunks (16 kHz, N 512, H 128, M 128)",
+          "push_eager_us": eager * 1e3, "push_graph_us": replay * 1e3, "frames_per_push": emitted,
+          "frames_per_s_graph": emitted / (replay * 1e-3)})
+    st.close()
+
+    # backward of the differentiation workload
+    cfg = workloads.config5()
+    N, H, M, sr = cfg["n_fft"], cfg["hop"], cfg["n_mels"], cfg["sr"]
+    T = melt.total_frames(cfg["offsets"], N, H)
+    d_wave = torch.from_numpy(cfg["wave"]).cuda()
+    d_off = torch.from_numpy(cfg["offsets"]).cuda()
+    gout = torch.from_numpy(workloads.upstream_grad(T, M)).cuda()
+    for prec in ("fp32", "bf16"):
+        plan = melt.MeltPlan(sample_rate=sr, n_fft=N, hop=H, n_mels=M, fmin=0.0, fmax=sr / 2, precision=prec)
+        out = torch.empty((T, M), device="cuda")
+        proj = torch.empty((T, 2 * M), device="cuda")
+        fwd = time_launches(torch, lambda: plan.forward(d_wave, d_off, T, out=out, proj=proj), 20, 5)
+        gw = torch.empty_like(d_wave)
+        gb = torch.empty((2 * M, N), device="cuda")
+        bwd = time_launches(torch, lambda: melt.melt_backward(plan.handle, d_wave, d_off, T, gout, proj, gw, gb),
+                            20, 5)
+        flop = 8.0 * N * M * T          # dX = G W and dW = G^T X, 4 N M each per frame
+        emit({"workload": f"backward 32 x 10 s, sr {sr:g}, N {N}, H {H}, M {M}, {prec} forward", "frames": T,
+              "forward_ms": fwd, "backward_ms": bwd, "backward_tflops": flop / (bwd * 1e-3) / 1e12,
+              "backward_frac_fp32_mfma": flop / (bwd * 1e-3) / PEAK["f32"]})
+    with open(path, "w") as fh:
+        for r in rows:
+            fh.write(json.dumps(r) + "\n")
+
+
 def _pmc_average(csv_path, name_part, counter):
     """Mean per dispatch of `counter` over the dispatches of kernels whose name contains
     name_part, from a rocprofv3 --pmc counter_collection.csv."""
@@ -248,6 +333,9 @@ def main():
     ap.add_argument("--write-traffic", default=None, metavar="PMC_DIR",
                     help="write the committed traffic summary of the FP32 kernel from rocprofv3 --pmc runs "
                          "(subfolders fp32_f, fp32_w, copy_f, copy_w) and exit; runs on the CPU")
+    ap.add_argument("--systems", default=None, metavar="PATH",
+                    help="time the ragged batch, streaming (eager and graph) and backward workloads; write JSON "
+                         "lines to PATH and exit")
     ap.add_argument("--workloads", default=None,
                     help="write the paper's efficiency workloads on synthetic stand-ins (cepstral configuration, "
                          "duration, Mel-bin and batch sweeps) as JSON lines to this file and exit")
@@ -323,6 +411,9 @@ def main():
 
     if args.workloads:
         run_workloads(torch, melt, workloads, args.workloads)
+        return 0
+    if args.systems:
+        run_systems(torch, melt, workloads, args.systems)
         return 0
 
     if args.sweep:
