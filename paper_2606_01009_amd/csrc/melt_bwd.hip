@@ -8,8 +8,10 @@
 //   k_bwd_prep   G and the start sample of every frame
 //   k_bwd_dx     owner-computes overlap-add: hop-block row b of dx is sum_j G[b - j] W_j,
 //                W_j = basis columns [jH, jH + H); each sample is written once
-//   k_bwd_dw     split-K GEMM G^T X over frames into per-split partials
+//   k_bwd_dw_tiled  split-K GEMM G^T X over frames into per-split partials (LDS-tiled)
 //   k_bwd_reduce fixed-order sum of the partials into the stacked [2M, N] gradient
+#include <algorithm>
+
 #include "melt_internal.h"
 
 namespace melt {
@@ -217,54 +219,77 @@ __global__ __launch_bounds__(256) void k_bwd_dx(const RowChunk *__restrict__ rc,
 
 // ------------------------------------------------------------------ dW: split-K G^T X
 
-// One wave per 32 x 32 tile of dW[q][n] (q interleaved), frames [t0, t1) of its split.
-// A[i = q][k = t] = G[t][q], B[k = t][col = n] = x[start_t + n].
-__global__ __launch_bounds__(256) void k_bwd_dw(const float *__restrict__ G, const int64_t *__restrict__ fstart,
-                                                const float *__restrict__ wave, int64_t T, int M, int N, int splits,
-                                                float *__restrict__ part) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+// dW = G^T X, split over frames into per-split partials (q interleaved: q = 2m + {0: cos, 1:
+// sin}).  A[i = q][k = t] = G[t][q], B[k = t][col = n] = x[start_t + n].  A workgroup owns a
+// 128 (q) x 128 (n) block of dW over frames [t0, t1) of its split; each wave a 64 x 64 quarter (2 x 2 MFMA tiles).
+// Per step, 16 frames of G (rows of q) and of the implicitly framed waveform (x[start_t + n])
+// are staged in LDS (the next step's loads in flight during the MFMAs), then each wave runs
+// 8 k-steps of 2 frames over its 4 tiles.  Rows are padded to 160 floats, so the two half-
+// waves (frames 2s and 2s + 1) read different banks.
+constexpr int kDwKB = 16, kDwRow = 160;
+__global__ __launch_bounds__(256) void k_bwd_dw_tiled(const float *__restrict__ G, const int64_t *__restrict__ fstart,
+                                                      const float *__restrict__ wave, int64_t T, int M, int N,
+                                                      int splits, float *__restrict__ part) {
+    __shared__ float Gs[kDwKB * kDwRow], Xs[kDwKB * kDwRow];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int Q = 2 * M;
-    const int QT = (Q + 31) / 32, NT = (N + 31) / 32;
-    const int64_t tile = (int64_t)blockIdx.x * 4 + wid;
-    const int64_t tiles = (int64_t)QT * NT;
-    if (tile >= tiles * splits) return;
-    const int split = (int)(tile / tiles);
-    const int tt = (int)(tile - (int64_t)split * tiles);
-    const int qt = tt / NT, nt = tt - qt * NT;
+    const int QB = (Q + 127) / 128, NB = (N + 127) / 128, blocks = QB * NB;
+    const int split = blockIdx.x / blocks, bb = blockIdx.x - split * blocks;
+    const int qb = bb / NB, nb = bb - qb * NB;
+    const int q0 = qb * 128, n0 = nb * 128;
     const int64_t per = (T + splits - 1) / splits;
-    const int64_t t0 = split * per, t1 = (t0 + per < T) ? t0 + per : T;
-    const int q = qt * 32 + (lane & 31), n = nt * 32 + (lane & 31);
-    const int h = lane >> 5;
-    const bool qv = q < Q, nv = n < N;
-    f32x16 acc = f32x16{};
-    int64_t t = t0;
-    // 8 frames (4 MFMA steps) per iteration, loads issued together
-    for (; t + 8 <= t1; t += 8) {
-        float a[4], b[4];
+    const int64_t t0 = (int64_t)split * per, t1 = t0 + per < T ? t0 + per : T;
+    const int wq = (wid & 1) * 64, wn = (wid >> 1) * 64;
+    const int h = lane >> 5, l32 = lane & 31;
+    // staging role: frame row sr of the step, 8 consecutive q and 8 consecutive n at sc
+    const int sr = tid >> 4, sc = (tid & 15) * 8;
+    f32x16 acc00 = f32x16{}, acc01 = f32x16{}, acc10 = f32x16{}, acc11 = f32x16{};
+    float gr[8], xr[8];
+    auto load = [&](int64_t tb) {
+        const int64_t tf = tb + sr;
+        const int64_t st = tf < t1 ? fstart[tf] : -1;      // -1: no frame (zero row)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t tf = t + 2 * i + h;
-            const int64_t st = fstart[tf];          // -1: frame not produced by the clips
-            a[i] = (qv && st >= 0) ? G[tf * Q + q] : 0.0f;
-            b[i] = (nv && st >= 0) ? wave[st + n] : 0.0f;
+        for (int e = 0; e < 8; ++e) {
+            const int q = q0 + sc + e, n = n0 + sc + e;
+            gr[e] = (st >= 0 && q < Q) ? G[tf * Q + q] : 0.0f;
+            xr[e] = (st >= 0 && n < N) ? wave[st + n] : 0.0f;
         }
+    };
+    if (t0 < t1) load(t0);
+    for (int64_t tb = t0; tb < t1; tb += kDwKB) {
+        __syncthreads();                               // the previous step's LDS reads are done
+        *(f32x4 *)(Gs + sr * kDwRow + sc) = f32x4{gr[0], gr[1], gr[2], gr[3]};
+        *(f32x4 *)(Gs + sr * kDwRow + sc + 4) = f32x4{gr[4], gr[5], gr[6], gr[7]};
+        *(f32x4 *)(Xs + sr * kDwRow + sc) = f32x4{xr[0], xr[1], xr[2], xr[3]};
+        *(f32x4 *)(Xs + sr * kDwRow + sc + 4) = f32x4{xr[4], xr[5], xr[6], xr[7]};
+        __syncthreads();
+        if (tb + kDwKB < t1) load(tb + kDwKB);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[i], acc, 0, 0, 0);
+        for (int k = 0; k < kDwKB / 2; ++k) {
+            const int row = (2 * k + h) * kDwRow;
+            const float a0 = Gs[row + wq + l32], a1 = Gs[row + wq + 32 + l32];
+            const float b0 = Xs[row + wn + l32], b1 = Xs[row + wn + 32 + l32];
+            acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc00, 0, 0, 0);
+            acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc01, 0, 0, 0);
+            acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc10, 0, 0, 0);
+            acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc11, 0, 0, 0);
+        }
     }
-    for (; t < t1; t += 2) {
-        const int64_t tf = t + h;
-        const int64_t st = tf < t1 ? fstart[tf] : -1;
-        const float a = (qv && st >= 0) ? G[tf * Q + q] : 0.0f;
-        const float b = (nv && st >= 0) ? wave[st + n] : 0.0f;
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
-    }
-    // lane holds column n, rows q = 32 qt + 8(r/4) + 4h + r%4
+    // lane holds column n, rows q = tile base + 8(r/4) + 4h + r%4 (interleaved q)
     float *p = part + (size_t)split * Q * N;
+    auto put = [&](const f32x16 &acc, int qbase, int nbase) {
+        const int n = nbase + l32;
+        if (n >= N) return;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int qq = qt * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        if (qq < Q && nv) p[(size_t)qq * N + n] = acc[r];
-    }
+        for (int r = 0; r < 16; ++r) {
+            const int qq = qbase + 8 * (r >> 2) + 4 * h + (r & 3);
+            if (qq < Q) p[(size_t)qq * N + n] = acc[r];
+        }
+    };
+    put(acc00, q0 + wq, n0 + wn);
+    put(acc01, q0 + wq, n0 + wn + 32);
+    put(acc10, q0 + wq + 32, n0 + wn);
+    put(acc11, q0 + wq + 32, n0 + wn + 32);
 }
 
 __global__ void k_bwd_reduce(const float *__restrict__ part, int splits, int M, int N, float *__restrict__ dW) {
@@ -326,7 +351,10 @@ melt_status launch_melt_backward(Plan &p, const float *d_wave, const int64_t *d_
     const int CT = (H + 31) / 32;
     if (d_gwave && CT > kMaxCT) return set_error(MELT_E_UNSUPPORTED, "backward d/dwave supports hop <= 256");
     // workspace: proj (if recomputed) | G | frame starts | dW partials
-    const int splits = (int)std::max<int64_t>(1, std::min<int64_t>(64, n_frames / 256));
+    // dW: 128 x 128 blocks, split over frames so that about two workgroups per CU run
+    const int dw_blocks = ((Q + 127) / 128) * ((N + 127) / 128);
+    const int splits = (int)std::max<int64_t>(
+        1, std::min<int64_t>({64, (2 * (int64_t)p.cu_count + dw_blocks - 1) / dw_blocks, n_frames / 64}));
     const size_t proj_b = d_proj ? 0 : sizeof(float) * n_frames * Q;
     const size_t g_b = sizeof(float) * n_frames * Q;
     const size_t fs_b = sizeof(int64_t) * n_frames;
@@ -394,8 +422,7 @@ melt_status launch_melt_backward(Plan &p, const float *d_wave, const int64_t *d_
         if (st != MELT_OK) return st;
     }
     if (d_gbasis) {
-        const int64_t tiles = (int64_t)((Q + 31) / 32) * ((N + 31) / 32) * splits;
-        k_bwd_dw<<<(int)((tiles + 3) / 4), 256, 0, s>>>(G, fstart, d_wave, n_frames, M, N, splits, part);
+        k_bwd_dw_tiled<<<dw_blocks * splits, 256, 0, s>>>(G, fstart, d_wave, n_frames, M, N, splits, part);
         st = hip_check(hipGetLastError(), "bwd dW");
         if (st != MELT_OK) return st;
         k_bwd_reduce<<<256, 256, 0, s>>>(part, splits, M, N, d_gbasis);
