@@ -1,19 +1,20 @@
 // Streaming MelT (many live audio streams, fixed-size pushes) and the autotuner.
 //
 // A stream holds the samples that no complete frame has used yet (fewer than n_fft).  A
-// push of chunk_len samples per stream:
-//   1. k_stream_assemble: per stream, [carry | chunk] into an assembly buffer and the number
-//      of complete frames k = floor((len - N) / H) + 1
-//   2. k_stream_pack + k_stream_copy: the k + J - 1 hop rows each stream's frames read are
-//      packed back to back into one buffer (J = ceil(N / H)), samples past a stream's end
-//      zeroed; viewed as one clip, its frame poff_s + t is stream s's frame t (the J - 1
-//      frames that straddle two streams are computed and discarded).  So the streams'
-//      frames share MFMA tiles instead of each stream's one or two new frames taking a
-//      32-frame tile of its own
-//   3. the MelT main kernel over that one clip (same kernels as melt_forward), into a
+// push of chunk_len samples per stream (len = carry + chunk_len samples, k = floor((len -
+// N) / H) + 1 complete frames):
+//   1. k_stream_pack (one workgroup): k per stream, the packed row offset of each stream
+//      (prefix sums of k + J - 1 over streams with k > 0, J = ceil(N / H)) and the chunk
+//      table of the packed clip
+//   2. k_stream_copy: per stream, the k + J - 1 hop rows its frames read, taken from
+//      [carry | chunk] (samples past the stream's end zeroed), into the packed buffer; and
+//      the unconsumed tail [k H, len) into a staging slot.  Viewed as one clip, the packed
+//      buffer's frame poff_s + t is stream s's frame t (the J - 1 frames that straddle two
+//      streams are computed and discarded), so the streams' frames share MFMA tiles
+//   3. the MelT main kernel over that clip (same kernels as melt_forward), into a
 //      frame-major scratch
-//   4. k_stream_scatter: each stream's k frames to its fixed output slot
-//   5. k_stream_keep: the unconsumed tail [k H, len) becomes the new carry
+//   4. k_stream_finish: per stream, its k frames to its output slot, and the tail becomes
+//      the new carry
 // Frames are therefore identical to melt_forward over the concatenated stream.  No host
 // synchronisation or allocation happens in a push, so it can be captured in a hipGraph.
 #include <cstdio>
@@ -28,12 +29,11 @@
 struct melt_stream_s {
     melt::Plan *plan;
     int n_streams, max_chunk, max_frames, bf, variant;
-    int asm_stride;             // samples per stream in the assembly buffer
     int64_t max_pack;           // frames of the packed clip at most: n_streams (max_frames + J - 1)
     int max_tab;                // chunks of the packed clip at most
     float *d_carry;             // [n_streams][N]
     int *d_carry_len;           // [n_streams]
-    float *d_asm;               // [n_streams][asm_stride]
+    float *d_tail;              // [n_streams][N] unconsumed tail of the push (next carry)
     float *d_pack;              // [(max_pack + J - 1) H + pad] packed hop rows
     float *d_tmp;               // [max_pack][n_mels] outputs of the packed clip
     int64_t *d_poff;            // [n_streams] first packed frame of each stream
@@ -44,31 +44,24 @@ struct melt_stream_s {
 
 namespace melt {
 
-__global__ __launch_bounds__(256) void k_stream_assemble(const float *__restrict__ chunk, int chunk_len,
-                                                         const float *__restrict__ carry, const int *__restrict__ carry_len,
-                                                         int N, int H, float *__restrict__ asmb, int asm_stride,
-                                                         int *__restrict__ emitted) {
-    const int s = blockIdx.x;
-    const int len0 = carry_len[s];
-    const int total = len0 + chunk_len;
-    float *dst = asmb + (size_t)s * asm_stride;
-    for (int i = threadIdx.x; i < len0; i += blockDim.x) dst[i] = carry[(size_t)s * N + i];
-    for (int i = threadIdx.x; i < chunk_len; i += blockDim.x) dst[len0 + i] = chunk[(size_t)s * chunk_len + i];
-    if (threadIdx.x == 0) emitted[s] = total >= N ? 1 + (total - N) / H : 0;
-}
-
-// one workgroup: packed row offsets of the streams (prefix sums of k + J - 1 over streams
-// with k > 0) and the chunk table of the packed clip
-__global__ __launch_bounds__(1024) void k_stream_pack(const int *__restrict__ emitted, int n_streams, int J, int H,
-                                                      int bf, int64_t *__restrict__ poff, Chunk *__restrict__ tab,
-                                                      int max_tab, int *__restrict__ ntab) {
+// one workgroup: frames per stream, packed row offsets (prefix sums of k + J - 1 over the
+// streams with k > 0) and the chunk table of the packed clip
+__global__ __launch_bounds__(1024) void k_stream_pack(const int *__restrict__ carry_len, int chunk_len, int n_streams,
+                                                      int N, int J, int H, int bf, int *__restrict__ emitted,
+                                                      int64_t *__restrict__ poff, Chunk *__restrict__ tab, int max_tab,
+                                                      int *__restrict__ ntab) {
     __shared__ int64_t wsum[16];
     __shared__ int64_t carry;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (tid == 0) carry = 0;
     for (int base = 0; base < n_streams; base += 1024) {
         const int st = base + tid;
-        const int k = st < n_streams ? emitted[st] : 0;
+        int k = 0;
+        if (st < n_streams) {
+            const int total = carry_len[st] + chunk_len;
+            k = total >= N ? 1 + (total - N) / H : 0;
+            emitted[st] = k;
+        }
         int64_t v = k > 0 ? k + J - 1 : 0, incl = v;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -99,44 +92,44 @@ __global__ __launch_bounds__(1024) void k_stream_pack(const int *__restrict__ em
     if (tid == 0) *ntab = nt;
 }
 
-// the hop rows of stream s's frames into the packed buffer; samples past the stream's end
-// are zero (they meet only zero basis weights or discarded frames, and must be finite)
-__global__ __launch_bounds__(256) void k_stream_copy(const float *__restrict__ asmb, int asm_stride,
-                                                     const int *__restrict__ carry_len, int chunk_len,
+// per stream: the hop rows of its frames from [carry | chunk] into the packed buffer (past
+// the stream's end: zero, since those samples meet only zero basis weights or discarded
+// frames and must be finite), and the tail [k H, len) into its staging slot
+__global__ __launch_bounds__(256) void k_stream_copy(const float *__restrict__ chunk, int chunk_len,
+                                                     const float *__restrict__ carry, const int *__restrict__ carry_len,
                                                      const int *__restrict__ emitted, const int64_t *__restrict__ poff,
-                                                     int J, int H, float *__restrict__ pack) {
+                                                     int N, int J, int H, float *__restrict__ pack,
+                                                     float *__restrict__ tail) {
     const int s = blockIdx.x;
     const int k = emitted[s];
-    if (k <= 0) return;
-    const int total = carry_len[s] + chunk_len;
-    const int n = (k + J - 1) * H;
-    const float *src = asmb + (size_t)s * asm_stride;
-    float *dst = pack + poff[s] * H;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = i < total ? src[i] : 0.0f;
+    const int len0 = carry_len[s], total = len0 + chunk_len;
+    const float *cs = carry + (size_t)s * N;
+    const float *xs = chunk + (size_t)s * chunk_len;
+    auto sample = [&](int i) { return i < len0 ? cs[i] : xs[i - len0]; };
+    if (k > 0) {
+        const int n = (k + J - 1) * H;
+        float *dst = pack + poff[s] * H;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = i < total ? sample(i) : 0.0f;
+    }
+    const int from = k * H;
+    for (int i = threadIdx.x; i < total - from; i += blockDim.x) tail[(size_t)s * N + i] = sample(from + i);
 }
 
-// stream s's k frames of the packed clip's outputs (width W) to its output slot
-__global__ __launch_bounds__(256) void k_stream_scatter(const float *__restrict__ tmp, const int *__restrict__ emitted,
-                                                        const int64_t *__restrict__ poff, int W, int max_frames,
-                                                        float *__restrict__ out) {
+// per stream: its k frames of the packed clip's outputs (width W) to its output slot, and
+// the staged tail becomes the carry
+__global__ __launch_bounds__(256) void k_stream_finish(const float *__restrict__ tmp, const int *__restrict__ emitted,
+                                                       const int64_t *__restrict__ poff, int W, int max_frames,
+                                                       float *__restrict__ out, int chunk_len, int N, int H,
+                                                       const float *__restrict__ tail, float *__restrict__ carry,
+                                                       int *__restrict__ carry_len) {
     const int s = blockIdx.x;
     const int k = emitted[s];
     const float *src = tmp + poff[s] * W;
     float *dst = out + (size_t)s * max_frames * W;
     for (int i = threadIdx.x; i < k * W; i += blockDim.x) dst[i] = src[i];
-}
-
-__global__ __launch_bounds__(256) void k_stream_keep(int chunk_len, float *__restrict__ carry, int *__restrict__ carry_len,
-                                                     int N, int H, const float *__restrict__ asmb, int asm_stride) {
-    const int s = blockIdx.x;
-    const int len0 = carry_len[s];
-    const int total = len0 + chunk_len;
-    const int k = total >= N ? 1 + (total - N) / H : 0;
-    const int from = k * H;
-    const int rem = total - from;
-    const float *src = asmb + (size_t)s * asm_stride + from;
-    for (int i = threadIdx.x; i < rem; i += blockDim.x) carry[(size_t)s * N + i] = src[i];
-    __syncthreads();   // every thread has read len0 before it is replaced
+    const int rem = carry_len[s] + chunk_len - k * H;
+    for (int i = threadIdx.x; i < rem; i += blockDim.x) carry[(size_t)s * N + i] = tail[(size_t)s * N + i];
+    __syncthreads();   // every thread has read carry_len before it is replaced
     if (threadIdx.x == 0) carry_len[s] = rem;
 }
 
@@ -225,9 +218,6 @@ melt_status melt_stream_create(melt_plan plan, int32_t n_streams, int32_t max_ch
     S->variant = p->tune_variant;     // kept for the life of the state
     S->bf = melt_chunk_frames(*p, S->variant);
     const int J = (p->N + p->H - 1) / p->H;
-    // assembly stride: carry (< N) + chunk, and room for the k + J - 1 hop rows the frames
-    // read; multiple of 4 samples
-    S->asm_stride = ((p->N + max_chunk_len + 4 * p->H + 3) / 4) * 4;
     S->max_pack = (int64_t)n_streams * (S->max_frames + J - 1);
     S->max_tab = (int)((S->max_pack + S->bf - 1) / S->bf);
     // packed buffer: the rows of every stream, plus the span a chunk's staging may read past
@@ -235,7 +225,7 @@ melt_status melt_stream_create(melt_plan plan, int32_t n_streams, int32_t max_ch
     const size_t pack_len = (size_t)(S->max_pack + J) * p->H + 64;
     bool ok = hipMalloc(&S->d_carry, sizeof(float) * (size_t)n_streams * p->N) == hipSuccess;
     ok = ok && hipMalloc(&S->d_carry_len, sizeof(int) * n_streams) == hipSuccess;
-    ok = ok && hipMalloc(&S->d_asm, sizeof(float) * (size_t)n_streams * S->asm_stride) == hipSuccess;
+    ok = ok && hipMalloc(&S->d_tail, sizeof(float) * (size_t)n_streams * p->N) == hipSuccess;
     ok = ok && hipMalloc(&S->d_pack, sizeof(float) * pack_len) == hipSuccess;
     ok = ok && hipMalloc(&S->d_tmp, sizeof(float) * (size_t)S->max_pack * p->M) == hipSuccess;
     ok = ok && hipMalloc(&S->d_poff, sizeof(int64_t) * n_streams) == hipSuccess;
@@ -265,7 +255,7 @@ melt_status melt_stream_destroy(melt_stream_state S) {
     if (!S) return MELT_OK;
     (void)hipSetDevice(S->plan->device);
     (void)hipDeviceSynchronize();
-    void *b[] = {S->d_carry, S->d_carry_len, S->d_asm, S->d_pack, S->d_tmp, S->d_poff, S->d_tab, S->d_ntab, S->d_lmel};
+    void *b[] = {S->d_carry, S->d_carry_len, S->d_tail, S->d_pack, S->d_tmp, S->d_poff, S->d_tab, S->d_ntab, S->d_lmel};
     for (void *x : b)
         if (x) (void)hipFree(x);
     delete S;
@@ -289,29 +279,25 @@ melt_status melt_stream_push(melt_stream_state S, const float *d_chunk, int32_t 
     melt_status st = hip_check(hipSetDevice(p.device), "hipSetDevice");
     if (st != MELT_OK) return st;
     const int J = (p.N + p.H - 1) / p.H;
-    k_stream_assemble<<<S->n_streams, 256, 0, s>>>(d_chunk, chunk_len, S->d_carry, S->d_carry_len, p.N, p.H, S->d_asm,
-                                                   S->asm_stride, d_frames_emitted);
-    k_stream_pack<<<1, 1024, 0, s>>>(d_frames_emitted, S->n_streams, J, p.H, S->bf, S->d_poff, S->d_tab, S->max_tab,
-                                     S->d_ntab);
-    k_stream_copy<<<S->n_streams, 256, 0, s>>>(S->d_asm, S->asm_stride, S->d_carry_len, chunk_len, d_frames_emitted,
-                                               S->d_poff, J, p.H, S->d_pack);
-    st = hip_check(hipGetLastError(), "stream assemble");
+    k_stream_pack<<<1, 1024, 0, s>>>(S->d_carry_len, chunk_len, S->n_streams, p.N, J, p.H, S->bf, d_frames_emitted,
+                                     S->d_poff, S->d_tab, S->max_tab, S->d_ntab);
+    k_stream_copy<<<S->n_streams, 256, 0, s>>>(d_chunk, chunk_len, S->d_carry, S->d_carry_len, d_frames_emitted,
+                                               S->d_poff, p.N, J, p.H, S->d_pack, S->d_tail);
+    st = hip_check(hipGetLastError(), "stream pack");
     if (st != MELT_OK) return st;
     st = launch_melt_table(p, S->variant, S->d_tab, S->d_ntab, S->max_tab, S->max_pack, S->d_pack, S->d_tmp, nullptr, s);
     if (st != MELT_OK) return st;
-    k_stream_scatter<<<S->n_streams, 256, 0, s>>>(S->d_tmp, d_frames_emitted, S->d_poff, p.M, S->max_frames,
-                                                  p.K > 0 ? S->d_lmel : d_out);
-    st = hip_check(hipGetLastError(), "stream scatter");
+    k_stream_finish<<<S->n_streams, 256, 0, s>>>(S->d_tmp, d_frames_emitted, S->d_poff, p.M, S->max_frames,
+                                                 p.K > 0 ? S->d_lmel : d_out, chunk_len, p.N, p.H, S->d_tail,
+                                                 S->d_carry, S->d_carry_len);
+    st = hip_check(hipGetLastError(), "stream finish");
     if (st != MELT_OK) return st;
     if (p.K > 0) {
         // MFCCT over the whole slot block (rows past a stream's emitted count carry no meaning)
         const int64_t rows = (int64_t)S->n_streams * S->max_frames;
         st = launch_row_matmul(S->d_lmel, rows, p.M, p.K, p.d_dct, p.M, 1, d_out, s);
-        if (st != MELT_OK) return st;
     }
-    k_stream_keep<<<S->n_streams, 256, 0, s>>>(chunk_len, S->d_carry, S->d_carry_len, p.N, p.H, S->d_asm,
-                                               S->asm_stride);
-    return hip_check(hipGetLastError(), "stream keep");
+    return st;
 }
 
 int32_t melt_variant_count(melt_plan plan) {
