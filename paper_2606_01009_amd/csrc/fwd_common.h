@@ -628,9 +628,38 @@ inline WaveLayout wave_layout(const Plan &p) {
 }
 inline size_t as_lds_bytes(const Plan &p, int bf) { return as_stage_offset(p, bf); }
 
+// K-split 16-bit kernel (frames too long for one wave's basis tile): two waves per row tile,
+// each with the k-groups of half the hop segments.  Needs an even segment count whose halves
+// hold the same k-groups at a constant row shift, and a register tile for the half.
+inline int ks_delta(const Plan &p, int S) {
+    const Geometry &g = p.geo16;
+    if (g.J % 2 != 0 || g.n_groups % 2 != 0) return -1;
+    const int h = g.n_groups / 2;
+    const int d = (g.J / 2) * S;
+    for (int i = 0; i < h; ++i)
+        if (g.seg_of_group[h + i] != g.seg_of_group[i] + g.J / 2 || g.col_of_group[h + i] != g.col_of_group[i])
+            return -1;
+    return d;
+}
+inline bool ks_fits(const Plan &p) {
+    const int h = p.geo16.n_groups / 2;
+    return (h == 16 || h == 20 || h == 25 || h == 32) && ks_delta(p, lds_stride(p.geo16.Hp, 2)) > 0;
+}
+inline int ks_row_groups(const Plan &p) { return (p.row_tiles + 3) / 4; }
+inline size_t ks_scratch_offset(const Plan &p, int bf) {
+    return ((size_t)(bf + p.geo16.J - 1) * lds_stride(p.geo16.Hp, 2) * 2 + 15) & ~size_t(15);
+}
+inline size_t ks_red_offset(const Plan &p, int bf) {
+    return (ks_scratch_offset(p, bf) + (size_t)(bf + p.geo16.J - 1) * p.H * 4 + 15) & ~size_t(15);
+}
+inline size_t ks_lds_bytes(const Plan &p, int bf) {
+    const int rg = ks_row_groups(p);
+    return ks_red_offset(p, bf) + (size_t)((p.row_tiles + rg - 1) / rg) * 2048 * 4;
+}
+
 // per-family launchers (melt_f32.hip, melt_h16.hip, melt_f8.hip)
 melt_status launch_melt_f32(Plan &p, const FwdTask &t, bool warp_specialised);
-enum H16Kind { H16_LDS_DMA = 0, H16_REGISTER_STAGED = 1, H16_FRAME_SPLIT = 2 };
+enum H16Kind { H16_LDS_DMA = 0, H16_REGISTER_STAGED = 1, H16_FRAME_SPLIT = 2, H16_K_SPLIT = 3 };
 melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf);
 melt_status launch_melt_f8(Plan &p, const FwdTask &t, bool lds_dma, int bf);
 size_t f8_as_lds_bytes(const Plan &p, int bf);   // LDS of the direct-to-LDS FP8 kernel

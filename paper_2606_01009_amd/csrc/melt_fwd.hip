@@ -288,7 +288,7 @@ melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H
 //              with register staging
 //   FP8        row-split with direct-to-LDS staging (the largest chunk that fits LDS),
 //              row-split with register staging
-enum VariantKind { V_F32_WS, V_F32_FS, V_H16_AS, V_H16_RS, V_H16_FS, V_F8_AS, V_F8_RS };
+enum VariantKind { V_F32_WS, V_F32_FS, V_H16_AS, V_H16_RS, V_H16_KS, V_H16_FS, V_F8_AS, V_F8_RS };
 struct Variant {
     VariantKind kind;
     int bf;          // frames per chunk
@@ -318,6 +318,12 @@ static std::vector<Variant> variant_list(const Plan &p) {
             }
         }
         if (rs_fits(p)) v.push_back({V_H16_RS, 128});
+        if (!x3 && !as_fits(p) && ks_fits(p))
+            for (int bf : {64, 32})
+                if (ks_lds_bytes(p, bf) <= (size_t)kMaxLds) {
+                    v.push_back({V_H16_KS, bf});
+                    break;
+                }
         if (!x3) v.push_back({V_H16_FS, kBF32});
     }
     }
@@ -340,6 +346,7 @@ const char *forward_variant_name(const Plan &p, int i) {
                     : v[i].kind == V_F32_FS ? "f32-frame-split"
                     : v[i].kind == V_H16_AS ? "h16-row-split-lds-dma"
                     : v[i].kind == V_H16_RS ? "h16-row-split"
+                    : v[i].kind == V_H16_KS ? "h16-k-split-lds-dma"
                     : v[i].kind == V_H16_FS ? "h16-frame-split"
                     : v[i].kind == V_F8_AS  ? "f8-row-split-lds-dma"
                                             : "f8-row-split";
@@ -376,6 +383,7 @@ melt_status launch_melt_table(Plan &p, int variant, const Chunk *tab, const int 
     case V_F32_FS: return launch_melt_f32(p, t, false);
     case V_H16_AS: return launch_melt_h16(p, t, H16_LDS_DMA, v.bf);
     case V_H16_RS: return launch_melt_h16(p, t, H16_REGISTER_STAGED, v.bf);
+    case V_H16_KS: return launch_melt_h16(p, t, H16_K_SPLIT, v.bf);
     case V_H16_FS: return launch_melt_h16(p, t, H16_FRAME_SPLIT, v.bf);
     case V_F8_AS: return launch_melt_f8(p, t, true, v.bf);
     case V_F8_RS: return launch_melt_f8(p, t, false, v.bf);

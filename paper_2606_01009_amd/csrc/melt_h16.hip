@@ -226,6 +226,77 @@ __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__r
     }
 }
 
+// ------------------------------------------------------------------ 16-bit K-split kernel
+//
+// For frames whose basis tile is too long for one wave's registers (N = 1024: 64 k-groups):
+// two waves share each row tile, each holding the k-groups of half the frame's hop segments
+// (the second half reads rows shifted by `delta` elements, J/2 hop rows).  Per pair of frame
+// tiles the second wave hands its partial sums to the first through LDS, which adds them
+// and stores.  A workgroup owns a row group of at most 4 tiles (8 waves); spans are staged
+// as in k_melt_h16_as.
+template <class Conv, int NS, bool IS_F16>
+__global__ __launch_bounds__(512) void k_melt_h16_ks(FwdArgs a, const uint4 *__restrict__ bhi, GroupTableBig gt,
+                                                     int bf, int scr_off, int red_off, int rgroups, int delta) {
+    extern __shared__ float lds_ks[];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int grp = blockIdx.x % rgroups, gt_n = (a.row_tiles + rgroups - 1) / rgroups;
+    const int r0 = grp * gt_n, cnt = min(a.row_tiles - r0, gt_n);
+    const int kh = wid / gt_n, rl = wid - kh * gt_n;
+    const bool idle = rl >= cnt;                   // a smaller last group leaves waves idle
+    const int rt = r0 + (idle ? 0 : rl);
+    unsigned short *rows = reinterpret_cast<unsigned short *>(lds_ks);
+    float *scratch = lds_ks + scr_off;
+    float *red = lds_ks + red_off + rl * 2048;     // [2 tiles][16 registers][64 lanes]
+    zero_pad_columns<Conv>(a, bf + a.J - 1, rows, blockDim.x, 0);
+    uint4 A[NS];
+    const uint4 Al[1] = {};
+#pragma unroll
+    for (int s = 0; s < NS; ++s) A[s] = bhi[((size_t)rt * (2 * NS) + kh * NS + s) * 64 + lane];
+    const int nch = *a.n_chunks;
+    const int cstep = gridDim.x / rgroups;
+    int c = blockIdx.x / rgroups;
+    if (c < nch) async_span(a, read_chunk(a.chunks, c), scratch);
+    async_wait();
+    for (; c < nch; c += cstep) {
+        const Chunk ch = read_chunk(a.chunks, c);
+        __syncthreads();                           // span of chunk c is in scratch; rows are free
+        convert_span<Conv>(a, ch, scratch, rows, 0);
+        __syncthreads();                           // rows ready; scratch is free
+        if (c + cstep < nch) async_span(a, read_chunk(a.chunks, c + cstep), scratch);
+        const int nft = (ch.n_frames + 31) >> 5;
+        for (int ft = 0; ft < nft; ft += 2) {      // the same trip count in every wave
+            const bool two = ft + 1 < nft;
+            f32x16 acc0 = f32x16{}, acc1 = f32x16{};
+            if (!idle) {
+                int off = (ft * 32 + (lane & 31)) * a.S + 8 * (lane >> 5) + kh * delta;
+                asm volatile("" : "+v"(off));
+                const unsigned short *l0 = rows + off;
+                const unsigned short *l1 = two ? l0 + 32 * a.S : l0;
+                mfma_sweep<NS, false, IS_F16>(A, Al, l0, l1, gt, 0, acc0, acc1);
+                if (kh == 1) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        red[r * 64 + lane] = acc0[r];
+                        red[1024 + r * 64 + lane] = acc1[r];
+                    }
+                }
+            }
+            __syncthreads();                       // partial sums of the second halves in LDS
+            if (!idle && kh == 0) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    acc0[r] += red[r * 64 + lane];
+                    acc1[r] += red[1024 + r * 64 + lane];
+                }
+                store_tile(a, ch, rt, ft * 32 + (lane & 31), lane, acc0);
+                if (two) store_tile(a, ch, rt, (ft + 1) * 32 + (lane & 31), lane, acc1);
+            }
+            __syncthreads();                       // the partial-sum area is free again
+        }
+        async_wait();                              // the next chunk's copy has landed
+    }
+}
+
 // ------------------------------------------------------------------ 16-bit frame-split kernel
 // Fallback for frame lengths whose basis tile does not fit in registers: as the FP32
 // frame-split kernel, one 32x32x16 MFMA per k-group.
@@ -327,6 +398,29 @@ static melt_status launch_rs(Plan &p, const FwdArgs &a, const GroupTableBig &gt,
     }
 }
 
+template <class Conv, int NS, bool F16>
+static melt_status launch_ks_ns(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+                                int rg, int delta, hipStream_t s) {
+    allow_lds(k_melt_h16_ks<Conv, NS, F16>);
+    const int gt_n = (p.row_tiles + rg - 1) / rg;
+    k_melt_h16_ks<Conv, NS, F16><<<grid, 128 * gt_n, lds, s>>>(a, (const uint4 *)p.d_pack_h16, gt, bf,
+                                                               (int)(ks_scratch_offset(p, bf) / 4),
+                                                               (int)(ks_red_offset(p, bf) / 4), rg, delta);
+    return hip_check(hipGetLastError(), "melt h16 k-split launch");
+}
+
+template <class Conv, bool F16>
+static melt_status launch_ks(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf, int rg,
+                             int delta, hipStream_t s) {
+    switch (p.geo16.n_groups / 2) {
+    case 16: return launch_ks_ns<Conv, 16, F16>(p, a, gt, lds, grid, bf, rg, delta, s);
+    case 20: return launch_ks_ns<Conv, 20, F16>(p, a, gt, lds, grid, bf, rg, delta, s);
+    case 25: return launch_ks_ns<Conv, 25, F16>(p, a, gt, lds, grid, bf, rg, delta, s);
+    case 32: return launch_ks_ns<Conv, 32, F16>(p, a, gt, lds, grid, bf, rg, delta, s);
+    default: return set_error(MELT_E_UNSUPPORTED, "no K-split register tile for this frame length");
+    }
+}
+
 melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf) {
     const int prec = p.cfg.precision;
     const Geometry &g = p.geo16;
@@ -349,6 +443,17 @@ melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf) {
         if (x3) return launch_as<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, scr_off, s);
         if (f16) return launch_as<ConvF16, false, true>(p, a, gt, lds, grid, bf, scr_off, s);
         return launch_as<ConvBF16, false, false>(p, a, gt, lds, grid, bf, scr_off, s);
+    }
+    if (kind == H16_K_SPLIT) {
+        if (x3 || !ks_fits(p)) return set_error(MELT_E_UNSUPPORTED, "K-split kernel: unsupported geometry");
+        const size_t lds = ks_lds_bytes(p, bf);
+        if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
+        const int rg = ks_row_groups(p);
+        const int per_group = (int)std::max<int64_t>(1, std::min<int64_t>(t.est_chunks, ((int64_t)p.cu_count + rg - 1) / rg));
+        const int grid = per_group * rg;
+        const int delta = ks_delta(p, S);
+        if (f16) return launch_ks<ConvF16, true>(p, a, gt, lds, grid, bf, rg, delta, s);
+        return launch_ks<ConvBF16, false>(p, a, gt, lds, grid, bf, rg, delta, s);
     }
     if (kind == H16_REGISTER_STAGED) {
         const size_t lds = (size_t)(bf + g.J - 1) * S * 2 * (x3 ? 2 : 1);
