@@ -292,8 +292,30 @@ __global__ __launch_bounds__(256) void k_bwd_dw_tiled(const float *__restrict__ 
     put(acc11, q0 + wq + 32, n0 + wn + 32);
 }
 
+// Sums the splits' partials in split order (so the result does not depend on the launch),
+// four consecutive n per thread with 16-byte loads when N is a multiple of 4, eight splits'
+// loads in flight at a time.
 __global__ void k_bwd_reduce(const float *__restrict__ part, int splits, int M, int N, float *__restrict__ dW) {
     const int64_t total = (int64_t)2 * M * N;
+    if ((N & 3) == 0) {
+        const int64_t total4 = total / 4;
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total4;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            f32x4 s = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            int k = 0;
+            for (; k + 8 <= splits; k += 8) {
+                f32x4 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = *(const f32x4 *)(part + (size_t)(k + u) * total + 4 * i);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s += v[u];
+            }
+            for (; k < splits; ++k) s += *(const f32x4 *)(part + (size_t)k * total + 4 * i);
+            const int q = (int)((4 * i) / N), n = (int)(4 * i - (int64_t)q * N);
+            *(f32x4 *)(dW + (size_t)((q & 1) * M + (q >> 1)) * N + n) = s;   // interleaved q -> stacked rows
+        }
+        return;
+    }
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
         float s = 0.0f;
         for (int k = 0; k < splits; ++k) s += part[(size_t)k * total + i];
@@ -425,7 +447,7 @@ melt_status launch_melt_backward(Plan &p, const float *d_wave, const int64_t *d_
         k_bwd_dw_tiled<<<dw_blocks * splits, 256, 0, s>>>(G, fstart, d_wave, n_frames, M, N, splits, part);
         st = hip_check(hipGetLastError(), "bwd dW");
         if (st != MELT_OK) return st;
-        k_bwd_reduce<<<256, 256, 0, s>>>(part, splits, M, N, d_gbasis);
+        k_bwd_reduce<<<512, 256, 0, s>>>(part, splits, M, N, d_gbasis);
         st = hip_check(hipGetLastError(), "bwd reduce");
     }
     return st;
