@@ -235,8 +235,8 @@ __device__ __forceinline__ void wave_sync() {
 // One wave owns FPW = 64 / TPF complex FFTs (2 FPW frames) per sub-task and runs the whole
 // pipeline for them with wave-local LDS only; a chunk is SUB sub-tasks; the workgroup's
 // waves take chunks independently (persistent loop over the chunk table).
-template <int N1, int N2, int WAVES, int SUB>
-__global__ __launch_bounds__(64 * WAVES) void k_stft_mel(StftArgs a) {
+template <int N1, int N2, int WAVES, int SUB, int WPE>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WPE))) void k_stft_mel(StftArgs a) {
     constexpr int N = N1 * N2;
     constexpr int NB = N / 2 + 1;
     constexpr int TPF = N1 > N2 ? N1 : N2;        // lanes per FFT
@@ -247,17 +247,20 @@ __global__ __launch_bounds__(64 * WAVES) void k_stft_mel(StftArgs a) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     constexpr int PB = 2 * FPW * NB;              // floats of one wave's power spectra
     cf *tw = reinterpret_cast<cf *>(smem);                            // [N1][N2]: exp(-2 pi i n2 k1 / N)
-    float *fbw = reinterpret_cast<float *>(tw + N);                   // [nnz]
+    float *wl = reinterpret_cast<float *>(tw + N);                    // [N] window
+    float *fbw = wl + N;                                              // [nnz]
     int *fbs = reinterpret_cast<int *>(fbw + a.fb_nnz);               // [M]
     int *fbo = fbs + a.M;                                             // [M+1]
     cf *buf = reinterpret_cast<cf *>(fbo + a.M + 2) + wid * FPW * BUF;   // this wave's FFT rows
-    // each wave's 2 FPW power spectra [2 FPW][NB]
-    float *pw = reinterpret_cast<float *>(reinterpret_cast<cf *>(fbo + a.M + 2) + WAVES * FPW * BUF) + wid * PB;
+    // each wave's 2 FPW power spectra [2 FPW][NB], written over its FFT rows once they are read
+    float *pw = reinterpret_cast<float *>(buf);
+    static_assert(PB * 4 <= FPW * BUF * 8, "power spectra must fit in the FFT rows");
     for (int i = threadIdx.x; i < N; i += 64 * WAVES) {
         const int k1 = i / N2, n2 = i - k1 * N2;
         const float2 t = a.twiddle[(n2 * k1) % N];
         tw[i] = cf{t.x, t.y};
     }
+    for (int i = threadIdx.x; i < N; i += 64 * WAVES) wl[i] = a.window[i];
     for (int i = threadIdx.x; i < a.fb_nnz; i += 64 * WAVES) fbw[i] = a.fb_w[i];
     for (int i = threadIdx.x; i < a.M; i += 64 * WAVES) fbs[i] = a.fb_start[i];
     for (int i = threadIdx.x; i <= a.M; i += 64 * WAVES) fbo[i] = a.fb_off[i];
@@ -266,9 +269,6 @@ __global__ __launch_bounds__(64 * WAVES) void k_stft_mel(StftArgs a) {
     const bool mag = (a.out_kind == MELT_OUT_LOG_MAGNITUDE || a.out_kind == MELT_OUT_MAGNITUDE);
     const int p1 = lane / TPF, n2 = lane - p1 * TPF;                  // step-1 role
     const bool act1 = p1 < FPW && n2 < N2;
-    float win[N1];
-#pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) win[n1] = act1 ? a.window[N2 * n1 + n2] : 0.0f;
 
     const int nch = *a.n_chunks;
     const int gw = blockIdx.x * WAVES + wid, nw = gridDim.x * WAVES;
@@ -289,15 +289,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_stft_mel(StftArgs a) {
     };
     int c = gw;
     Chunk ch;
-    if (c < nch) {
-        ch = a.chunks[c];
-        load(ch, 0);
-    }
+    if (c < nch) ch = a.chunks[c];
     int sub = 0;
     while (c < nch) {
         const Chunk cur = ch;
         const int cur_sub = sub;
-        // advance to the next sub-task (this chunk or the wave's next chunk) and prefetch it
+        load(cur, cur_sub);
+        // advance to the next sub-task (this chunk or the wave's next chunk)
         ++sub;
         if (2 * FPW * sub >= cur.n_frames || sub >= SUB) {
             sub = 0;
@@ -307,8 +305,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_stft_mel(StftArgs a) {
         // step 1: N1-point DFTs over n1, four-step twiddle, store as [k1][n2]
         cf z[N1];
 #pragma unroll
-        for (int n1 = 0; n1 < N1; ++n1) z[n1] = cf{xa[n1] * win[n1], xb[n1] * win[n1]};
-        if (c < nch) load(ch, sub);
+        for (int n1 = 0; n1 < N1; ++n1) {
+            const float wv = act1 ? wl[N2 * n1 + n2] : 0.0f;
+            z[n1] = cf{xa[n1] * wv, xb[n1] * wv};
+        }
         DFT<N1>::run(z);
         cf *row1 = buf + p1 * BUF;
         if (act1) {
@@ -336,26 +336,47 @@ __global__ __launch_bounds__(64 * WAVES) void k_stft_mel(StftArgs a) {
         wave_sync();
         const int f0 = 2 * FPW * cur_sub;
         // step 4: separate the two real spectra of each FFT, |X_k|^2 (or |X_k|) on every bin
-        // k = 0..N/2, into pw[2 p + {0, 1}][k]
+        // k = 0..N/2, into pw[2 p + {0, 1}][k].  Every lane first reads all its (Z[k], Z[N-k])
+        // pairs, then the wave synchronises and the spectra are written over the FFT rows.
         {
+            constexpr int IT = (FPW * NB + 63) / 64;
+            float pa[IT], pb[IT];
             int p = 0, k = lane;                   // item lane + 64 i = p NB + k, advanced without division
-            for (int t = lane; t < FPW * NB; t += 64) {
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
                 while (k >= NB) {
                     k -= NB;
                     ++p;
                 }
-                const cf *rowz = buf + p * BUF;
-                const cf zk = rowz[k], zn = rowz[k == 0 ? 0 : N - k];
-                // A = (Z[k] + conj Z[N-k]) / 2,  B = (Z[k] - conj Z[N-k]) / (2i)
-                const float ar = 0.5f * (zk.x + zn.x), ai = 0.5f * (zk.y - zn.y);
-                const float br = 0.5f * (zk.y + zn.y), bi = -0.5f * (zk.x - zn.x);
-                float pa = ar * ar + ai * ai, pb = br * br + bi * bi;
-                if (mag) {
-                    pa = sqrtf(pa);
-                    pb = sqrtf(pb);
+                pa[i] = pb[i] = 0.0f;
+                if (lane + 64 * i < FPW * NB) {
+                    const cf *rowz = buf + p * BUF;
+                    const cf zk = rowz[k], zn = rowz[k == 0 ? 0 : N - k];
+                    // A = (Z[k] + conj Z[N-k]) / 2,  B = (Z[k] - conj Z[N-k]) / (2i)
+                    const float ar = 0.5f * (zk.x + zn.x), ai = 0.5f * (zk.y - zn.y);
+                    const float br = 0.5f * (zk.y + zn.y), bi = -0.5f * (zk.x - zn.x);
+                    pa[i] = ar * ar + ai * ai;
+                    pb[i] = br * br + bi * bi;
+                    if (mag) {
+                        pa[i] = sqrtf(pa[i]);
+                        pb[i] = sqrtf(pb[i]);
+                    }
                 }
-                pw[(2 * p) * NB + k] = pa;
-                pw[(2 * p + 1) * NB + k] = pb;
+                k += 64;
+            }
+            wave_sync();                           // every FFT row read; pw may overwrite them
+            p = 0;
+            k = lane;
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                while (k >= NB) {
+                    k -= NB;
+                    ++p;
+                }
+                if (lane + 64 * i < FPW * NB) {
+                    pw[(2 * p) * NB + k] = pa[i];
+                    pw[(2 * p + 1) * NB + k] = pb[i];
+                }
                 k += 64;
             }
         }
@@ -433,17 +454,18 @@ size_t stft_lds_bytes(const StftShape &s, int M, int nnz) {
     const int N = s.N1 * s.N2;
     const int LDB = s.N2 + 1;
     const int BUF = std::max(s.N1 * LDB, N);
-    const size_t head = (size_t)N * 8 + (size_t)nnz * 4 + (size_t)(2 * M + 2) * 4;
-    size_t bytes = ((head + 7) / 8) * 8 + (size_t)kStftWaves * s.FPW * BUF * 8;
-    bytes += (size_t)kStftWaves * 2 * s.FPW * (N / 2 + 1) * 4;      // power spectra
-    return bytes;
+    const size_t head = (size_t)N * 8 + (size_t)N * 4 + (size_t)nnz * 4 + (size_t)(2 * M + 2) * 4;
+    return ((head + 7) / 8) * 8 + (size_t)kStftWaves * s.FPW * BUF * 8;   // the power spectra reuse the FFT rows
 }
 
+// waves per SIMD the kernel's registers are sized for: 3 (LDS allows three workgroups per CU),
+// 1 for the 1200-point shape (its 40-point register DFTs need the whole register file)
 template <int N1, int N2, int SUB>
 melt_status launch_shape(const StftArgs &a, size_t lds, int grid, hipStream_t s) {
-    (void)hipFuncSetAttribute((const void *)k_stft_mel<N1, N2, kStftWaves, SUB>,
+    constexpr int WPE = (N1 * N2 >= 1200) ? 1 : 3;
+    (void)hipFuncSetAttribute((const void *)k_stft_mel<N1, N2, kStftWaves, SUB, WPE>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    k_stft_mel<N1, N2, kStftWaves, SUB><<<grid, 64 * kStftWaves, lds, s>>>(a);
+    k_stft_mel<N1, N2, kStftWaves, SUB, WPE><<<grid, 64 * kStftWaves, lds, s>>>(a);
     return hip_check(hipGetLastError(), "stft_mel launch");
 }
 
