@@ -462,68 +462,6 @@ __device__ __forceinline__ void convert_span(const FwdArgs &a, const Chunk &ch, 
     }
 }
 
-// ------------------------------------------------------------------ staged epilogue
-//
-// Writes one 32-frame x 16-Mel tile through a wave-private LDS area (32 rows of 20 floats):
-// each lane first writes its frame's 8 mapped values, then reads back one 4-Mel quarter of
-// a frame, so one 16-byte store instruction covers 16 frames x 64 contiguous bytes instead
-// of 64 scattered 16-byte pieces.  The optional projection output keeps the direct path.
-constexpr int kStageStride = 20;                  // floats per staged frame row
-constexpr int kStageFloats = 32 * kStageStride;   // per wave
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ inline void store_tile_staged(const FwdArgs &a, const Chunk &ch, int rt, int f_base, int lane,
-                                         const f32x16 &acc, float *stage) {
-    const int h = lane >> 5, fl = lane & 31;
-    float v[8];
-    map8(acc, a.out_kind, a.eps, v);
-    const f32x4 v0{v[0], v[1], v[2], v[3]}, v1{v[4], v[5], v[6], v[7]};
-    *(f32x4 *)(stage + fl * kStageStride + 8 * h) = v0;
-    *(f32x4 *)(stage + fl * kStageStride + 8 * h + 4) = v1;
-    wave_sync();
-    const int mq = lane & 3;
-    const int mel = rt * 16 + 4 * mq;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const int fr = (lane >> 2) + 16 * k;
-        const int f_local = f_base + fr;
-        const int64_t row = ch.out_row + f_local;
-        const f32x4 w = *(const f32x4 *)(stage + fr * kStageStride + 4 * mq);
-        if (f_local < ch.n_frames && row < a.n_frames && mel < a.M) {
-            float *o = a.out + row * a.M + mel;
-            if ((a.M & 3) == 0) {
-                *(f32x4 *)o = w;
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (mel + e < a.M) o[e] = w[e];
-            }
-        }
-    }
-    wave_sync();                                  // the area is reused by the next tile
-    if (a.proj) {
-        const int f_local = f_base + fl;
-        const int64_t row = ch.out_row + f_local;
-        const int mel0 = rt * 16 + 8 * h;
-        if (f_local < ch.n_frames && row < a.n_frames && mel0 < a.M) {
-            float *p = a.proj + row * (2 * a.M) + 2 * mel0;
-            if (mel0 + 8 <= a.M) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) *(f32x4 *)(p + 4 * q) = f32x4{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
-            } else {
-#pragma unroll
-                for (int e = 0; e < 16; ++e)
-                    if (mel0 + e / 2 < a.M) p[e] = acc[e];
-            }
-        }
-    }
-}
-
 // ------------------------------------------------------------------ host-side geometry
 
 constexpr int kBF32 = kChunkF32;
@@ -600,10 +538,10 @@ inline size_t as_rows_bytes(const Plan &p, int bf) {
     const bool x3 = p.cfg.precision == MELT_PREC_BF16X3;
     return (size_t)(bf + p.geo16.J - 1) * lds_stride(p.geo16.Hp, 2) * 2 * (x3 ? 2 : 1);
 }
-// ... then the epilogue areas of the waves (byte offset, 16-byte aligned)
-// (the 16-bit kernel stores its outputs straight from the accumulators: no epilogue area)
-inline size_t as_stage_offset(const Plan &p, int bf) {
-    return ((((as_rows_bytes(p, bf) + 15) & ~size_t(15)) + (size_t)(bf + p.geo16.J - 1) * p.H * 4) + 15) & ~size_t(15);
+// ... then the FP32 span the chunk's copy lands in (16-byte aligned)
+inline size_t as_scratch_offset(const Plan &p, int bf) { return (as_rows_bytes(p, bf) + 15) & ~size_t(15); }
+inline size_t as_lds_bytes(const Plan &p, int bf) {
+    return (as_scratch_offset(p, bf) + (size_t)(bf + p.geo16.J - 1) * p.H * 4 + 15) & ~size_t(15);
 }
 // Waves of the direct-to-LDS row-split kernels for a group of `rt` row tiles: `full` waves own
 // one row tile each; when one or two row tiles remain beyond a multiple of four, four more
@@ -626,7 +564,6 @@ inline WaveLayout wave_layout(const Plan &p) {
     w.waves = std::max(w.waves, layout_for(p.row_tiles - (rg - 1) * gt_n).waves);
     return w;
 }
-inline size_t as_lds_bytes(const Plan &p, int bf) { return as_stage_offset(p, bf); }
 
 // K-split 16-bit kernel (frames too long for one wave's basis tile): two waves per row tile,
 // each with the k-groups of half the hop segments.  Needs an even segment count whose halves

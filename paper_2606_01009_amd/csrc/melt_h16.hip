@@ -434,7 +434,7 @@ melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf) {
     if (kind == H16_LDS_DMA) {
         const size_t lds = as_lds_bytes(p, bf);
         if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
-        const int scr_off = (int)(((as_rows_bytes(p, bf) + 15) & ~size_t(15)) / 4);
+        const int scr_off = (int)(as_scratch_offset(p, bf) / 4);
         // one persistent set of workgroups per row group, each walking all chunks
         const int rg = row_groups(p);
         const int per_cu = std::min(std::max(1, (int)(kMaxLds / lds)), 2);
