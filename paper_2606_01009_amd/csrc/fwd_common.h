@@ -115,6 +115,36 @@ struct FwdArgs {
     float invH;            // 1 / H rounded to FP32 (row index of a span position)
 };
 
+// Chunk descriptors of a persistent workgroup's iterations, staged in LDS.  Reading each
+// descriptor from the table when it is needed puts a memory load, and a wait for it, at the
+// top of every iteration; since a wave's vector memory operations complete in issue order,
+// that wait also drains the wave's earlier output stores.  Instead the entries of iterations
+// [w0, w0 + kRing + 2) are read once per kRing iterations (w0 a multiple of kRing), so an
+// iteration can also see the chunks one and two iterations ahead.  The fill must follow a
+// barrier that ends every read of the previous window and precede one before the reads.
+constexpr int kRing = 32;
+struct ChunkRing {
+    Chunk e[kRing + 2];
+};
+constexpr int kRingBytes = (int)sizeof(ChunkRing);
+__device__ __forceinline__ void ring_fill(ChunkRing &r, const Chunk *tab, int c_w0, int cstep, int nch) {
+    const int t = threadIdx.x;
+    if (t < kRing + 2) {
+        const int c = c_w0 + t * cstep;
+        if (c < nch) r.e[t] = tab[c];
+    }
+}
+// entry i of the window (iteration w0 + i); only meaningful for a chunk index below n_chunks
+__device__ __forceinline__ Chunk ring_get(const ChunkRing &r, int i) {
+    Chunk e = r.e[i];
+    e.sample_start = uniform64(e.sample_start);
+    e.sample_end = uniform64(e.sample_end);
+    e.out_row = uniform64(e.out_row);
+    e.n_frames = __builtin_amdgcn_readfirstlane(e.n_frames);
+    e.clip = __builtin_amdgcn_readfirstlane(e.clip);
+    return e;
+}
+
 // Natural log from the hardware base-2 logarithm (v_log_f32, about 1 ulp on normal
 // inputs) times ln 2.  Arguments are S + eps or sqrt(S) + eps with S >= 0 and eps >= the
 // smallest normal FP32 (the plan rejects smaller eps), so they are always normal.
@@ -387,23 +417,55 @@ __device__ __forceinline__ void lds_dma_x1(const float *g, unsigned lds) {
 }
 
 // 16-byte copies (256 samples per wave instruction) over the whole blocks of the valid span,
-// then 4-byte copies over its last partial block, so no lane reads past the clip end.
-__device__ __forceinline__ void async_span(const FwdArgs &a, const Chunk &ch, float *scratch) {
+// then 4-byte copies over its last partial block, so no lane reads past the clip end.  Waves
+// w of nw (wave-uniform) share the blocks; returns the number of copy instructions this wave
+// issued (each has at least one active lane).
+__device__ __forceinline__ int async_span_waves(const FwdArgs &a, const Chunk &ch, float *scratch, int w, int nw) {
     const int lane = threadIdx.x & 63;
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
     const int valid = span_valid(a, ch);
     const float *src = a.wave + ch.sample_start;
     const unsigned base = __builtin_amdgcn_readfirstlane(lds_addr(scratch));
     const int nfull = valid >> 8;
-    for (int b = wid; b < nfull; b += nw) lds_dma_x4(src + b * 256 + 4 * lane, base + b * 1024);
-    for (int b = 4 * nfull + wid; b * 64 < valid; b += nw) {
+    int n = 0;
+    for (int b = w; b < nfull; b += nw, ++n) lds_dma_x4(src + b * 256 + 4 * lane, base + b * 1024);
+    for (int b = 4 * nfull + w; b * 64 < valid; b += nw, ++n) {
         const int o = b * 64 + lane;
         if (o < valid) lds_dma_x1(src + o, base + b * 256);
     }
+    return n;
+}
+
+__device__ __forceinline__ int async_span(const FwdArgs &a, const Chunk &ch, float *scratch) {
+    return async_span_waves(a, ch, scratch, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), blockDim.x >> 6);
 }
 
 __device__ __forceinline__ void async_wait() {
     __builtin_amdgcn_s_waitcnt(0);     // this wave's direct-to-LDS copies have landed
+}
+
+// s_waitcnt vmcnt(N) alone (expcnt and lgkmcnt fields at their no-wait maxima).
+template <int N>
+__device__ __forceinline__ void waitcnt_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Waits until this wave's memory loads issued before its last n vector-memory instructions
+// have completed.  Loads (direct-to-LDS copies included) complete in issue order, so while
+// one of those older loads is outstanding, so are the n younger ones and the count exceeds
+// n; younger stores only make the wait stricter.  n is rounded down to an immediate, which
+// waits a little more than needed and never less.  n must be wave-uniform.
+__device__ __forceinline__ void wait_vm_younger(int n) {
+    n = __builtin_amdgcn_readfirstlane(n);
+    if (n >= 63) waitcnt_vm<63>();
+    else if (n >= 48) waitcnt_vm<48>();
+    else if (n >= 32) waitcnt_vm<32>();
+    else if (n >= 24) waitcnt_vm<24>();
+    else if (n >= 16) waitcnt_vm<16>();
+    else if (n >= 12) waitcnt_vm<12>();
+    else if (n >= 8) waitcnt_vm<8>();
+    else if (n >= 4) waitcnt_vm<4>();
+    else waitcnt_vm<0>();
 }
 
 // scratch (contiguous span) -> padded hop-block rows in the kernel's operand format.  With
@@ -517,8 +579,9 @@ inline FwdArgs make_args(const Plan &p, const Geometry &g, int S, const FwdTask 
 }
 
 template <class K>
-inline void allow_lds(K kern) {
-    (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+inline void allow_lds(K kern, int static_bytes = 0) {
+    // the limit covers dynamic LDS only: the kernel's static LDS comes off the 160 KB
+    (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds - static_bytes);
 }
 
 // persistent grid: min(chunks, CUs x workgroups per CU (tuned value, else dflt))
@@ -538,10 +601,11 @@ inline size_t as_rows_bytes(const Plan &p, int bf) {
     const bool x3 = p.cfg.precision == MELT_PREC_BF16X3;
     return (size_t)(bf + p.geo16.J - 1) * lds_stride(p.geo16.Hp, 2) * 2 * (x3 ? 2 : 1);
 }
-// ... then the FP32 span the chunk's copy lands in (16-byte aligned)
+// ... then nbuf FP32 spans the chunks' copies land in (each 16-byte aligned)
 inline size_t as_scratch_offset(const Plan &p, int bf) { return (as_rows_bytes(p, bf) + 15) & ~size_t(15); }
-inline size_t as_lds_bytes(const Plan &p, int bf) {
-    return (as_scratch_offset(p, bf) + (size_t)(bf + p.geo16.J - 1) * p.H * 4 + 15) & ~size_t(15);
+inline size_t as_span_bytes(const Plan &p, int bf) { return ((size_t)(bf + p.geo16.J - 1) * p.H * 4 + 15) & ~size_t(15); }
+inline size_t as_lds_bytes(const Plan &p, int bf, int nbuf = 1) {
+    return as_scratch_offset(p, bf) + (size_t)nbuf * as_span_bytes(p, bf);
 }
 // Waves of the direct-to-LDS row-split kernels for a group of `rt` row tiles: `full` waves own
 // one row tile each; when one or two row tiles remain beyond a multiple of four, four more
@@ -563,6 +627,20 @@ inline WaveLayout wave_layout(const Plan &p) {
     WaveLayout w = layout_for(gt_n);
     w.waves = std::max(w.waves, layout_for(p.row_tiles - (rg - 1) * gt_n).waves);
     return w;
+}
+
+// Producer/consumer 16-bit kernel: two operand-row buffers and nscr FP32 spans; needs
+// producer waves (beyond the full-tile ones) in every row group.
+inline size_t pp_rows_bytes(const Plan &p, int bf) { return (as_rows_bytes(p, bf) + 15) & ~size_t(15); }
+inline size_t pp_lds_bytes(const Plan &p, int bf, int nscr) {
+    return 2 * pp_rows_bytes(p, bf) + (size_t)nscr * as_span_bytes(p, bf);
+}
+inline bool pp_fits(const Plan &p) {
+    if (!as_fits(p)) return false;
+    const int rg = row_groups(p), gt_n = (p.row_tiles + rg - 1) / rg, nw = wave_layout(p).waves;
+    for (int g = 0; g < rg; ++g)
+        if (layout_for(std::min(p.row_tiles - g * gt_n, gt_n)).full >= nw) return false;
+    return true;
 }
 
 // K-split 16-bit kernel (frames too long for one wave's basis tile): two waves per row tile,
@@ -596,8 +674,8 @@ inline size_t ks_lds_bytes(const Plan &p, int bf) {
 
 // per-family launchers (melt_f32.hip, melt_h16.hip, melt_f8.hip)
 melt_status launch_melt_f32(Plan &p, const FwdTask &t, bool warp_specialised);
-enum H16Kind { H16_LDS_DMA = 0, H16_REGISTER_STAGED = 1, H16_FRAME_SPLIT = 2, H16_K_SPLIT = 3 };
-melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf);
+enum H16Kind { H16_LDS_DMA = 0, H16_REGISTER_STAGED = 1, H16_FRAME_SPLIT = 2, H16_K_SPLIT = 3, H16_PIPELINED = 4 };
+melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf, int nbuf = 1);
 melt_status launch_melt_f8(Plan &p, const FwdTask &t, bool lds_dma, int bf);
 size_t f8_as_lds_bytes(const Plan &p, int bf);   // LDS of the direct-to-LDS FP8 kernel
 

@@ -152,13 +152,22 @@ __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__re
 #pragma unroll
     for (int r = 0; r < 16; ++r) rinv[r] = rinv_g[rt * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)];
     const int nch = *a.n_chunks;
+    // the next chunk's span is copied by the waves with the least multiply work (those
+    // sharing a row tile; all waves when every wave owns one): only they wait for it, so
+    // the other waves never wait on their own output stores
+    const int dma0 = full < nw ? full : 0;
+    const bool dma_wave = wid >= dma0;
     int c = blockIdx.x;
     if (c < nch) async_span(a, read_chunk(a.chunks, c), scratch);
     async_wait();
-    for (; c < nch; c += gridDim.x) {
-        const Chunk ch = read_chunk(a.chunks, c);
-        const int valid = span_valid(a, ch);
+    __shared__ ChunkRing ring;
+    for (int it = 0; c < nch; c += gridDim.x, ++it) {
+        const int ri = it % kRing;
+        if (ri == 0) ring_fill(ring, a.chunks, c, gridDim.x, nch);
         __syncthreads();                           // span of chunk c is in scratch; the image is free
+        const Chunk ch = ring_get(ring, ri);
+        const Chunk chn = ring_get(ring, ri + 1);
+        const int valid = span_valid(a, ch);
         // one wave per frame: its samples (span [tH, tH + N), 0 at or past the clip end) are
         // read once into registers, max |x| is reduced across the wave, then the frame is
         // scaled by s_t = 448 / max and rounded to E4M3 straight from the registers
@@ -194,12 +203,12 @@ __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__re
             }
         }
         __syncthreads();                           // image ready; scratch is free
-        if (c + (int)gridDim.x < nch) async_span(a, read_chunk(a.chunks, c + gridDim.x), scratch);
+        if (dma_wave && c + (int)gridDim.x < nch) async_span_waves(a, chn, scratch, wid - dma0, nw - dma0);
         const int nft = (ch.n_frames + 31) >> 5;
         // The next chunk's copy must land before the barrier that starts the next iteration:
         // each wave waits ahead of its last tiles' stores (leaving those in flight), or after
         // the loop if it had no tile.
-        bool waited = false;
+        bool waited = !dma_wave;
         const int step = P == 1 ? 2 : P;
         for (int ft = part; ft < nft; ft += step) {
             const bool two = step == 2 && ft + 1 < nft;
@@ -225,7 +234,7 @@ __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__re
                     acc0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[g], B0, acc0, 0, 0, 0, 127, 0, 127);
                 }
             }
-            if (ft + step >= nft) {
+            if (!waited && ft + step >= nft) {
                 async_wait();
                 waited = true;
             }
@@ -266,7 +275,7 @@ size_t f8_as_lds_bytes(const Plan &p, int bf) {
 
 template <int NG>
 static melt_status launch_f8_as(Plan &p, const FwdArgs &a, size_t lds, int grid, int bf, hipStream_t s) {
-    allow_lds(k_melt_f8_as<NG>);
+    allow_lds(k_melt_f8_as<NG>, kRingBytes);
     const WaveLayout w = wave_layout(p);
     k_melt_f8_as<NG><<<grid, 64 * w.waves, lds, s>>>(a, (const i32x8 *)p.d_pack_f8, p.d_rowscale, p.N, bf,
                                                      (int)(f8_as_scratch_offset(p, bf) / 4), w.full, w.psplit);
@@ -283,7 +292,7 @@ melt_status launch_melt_f8(Plan &p, const FwdTask &t, bool lds_dma, int bf) {
     const hipStream_t s = t.stream;
     if (lds_dma) {
         const size_t lds = f8_as_lds_bytes(p, bf);
-        if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS for the FP8 kernel");
+        if (lds + kRingBytes > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS for the FP8 kernel");
         switch (ng8) {
         case 4: return launch_f8_as<4>(p, a, lds, grid, bf, s);
         case 7: return launch_f8_as<7>(p, a, lds, grid, bf, s);

@@ -281,17 +281,18 @@ melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H
 // Kernel variants of a plan, in the order the autotuner times them (p.tune_variant selects;
 // the first one is the default):
 //   FP32       frame-split with staging waves, frame-split with register prefetch
-//   BF16/FP16  row-split with direct-to-LDS staging (128- then 64-frame chunks), row-split
-//              with register staging, frame-split (the only one when the frame is too long
-//              for a register tile)
-//   BF16X3     row-split with direct-to-LDS staging (96- then 64-frame chunks), row-split
-//              with register staging
+//   BF16/FP16  row-split with direct-to-LDS staging (one span buffer: 128- then 64-frame
+//              chunks; then two span buffers), producer/consumer row-split (one span, then
+//              two; only with producer waves), row-split with register staging, frame-split
+//              (the only one when the frame is too long for a register tile)
+//   BF16X3     the same, with one-span chunks of 96 then 64 frames
 //   FP8        row-split with direct-to-LDS staging (the largest chunk that fits LDS),
 //              row-split with register staging
-enum VariantKind { V_F32_WS, V_F32_FS, V_H16_AS, V_H16_RS, V_H16_KS, V_H16_FS, V_F8_AS, V_F8_RS };
+enum VariantKind { V_F32_WS, V_F32_FS, V_H16_PP, V_H16_AS, V_H16_RS, V_H16_KS, V_H16_FS, V_F8_AS, V_F8_RS };
 struct Variant {
     VariantKind kind;
     int bf;          // frames per chunk
+    int nbuf = 1;    // FP32 span buffers of the direct-to-LDS 16-bit kernel
 };
 
 static std::vector<Variant> variant_list(const Plan &p) {
@@ -303,7 +304,7 @@ static std::vector<Variant> variant_list(const Plan &p) {
         break;
     case MELT_PREC_FP8_E4M3:
         for (int bf : {128, 96, 64, 32})
-            if (f8_as_lds_bytes(p, bf) <= (size_t)kMaxLds) {
+            if (f8_as_lds_bytes(p, bf) + kRingBytes <= (size_t)kMaxLds) {
                 v.push_back({V_F8_AS, bf});
                 break;
             }
@@ -312,10 +313,29 @@ static std::vector<Variant> variant_list(const Plan &p) {
     default: {
         const bool x3 = p.cfg.precision == MELT_PREC_BF16X3;
         if (as_fits(p)) {
+            // one span buffer (128 then 64 frames per chunk; 96 then 64 for BF16X3), then two
             for (int bf : {128, 96, 64}) {
                 if (bf == (x3 ? 128 : 96)) continue;
-                if (as_lds_bytes(p, bf) <= (size_t)kMaxLds) v.push_back({V_H16_AS, bf});
+                if (as_lds_bytes(p, bf) + kRingBytes <= (size_t)kMaxLds) v.push_back({V_H16_AS, bf, 1});
             }
+            for (int bf : {96, 64})
+                if (as_lds_bytes(p, bf, 2) + kRingBytes <= (size_t)kMaxLds) {
+                    v.push_back({V_H16_AS, bf, 2});
+                    break;
+                }
+        }
+        if (pp_fits(p)) {
+            // producer/consumer: one span (96 or 64 frames per chunk), then two spans
+            for (int bf : {96, 64})
+                if (pp_lds_bytes(p, bf, 1) + kRingBytes <= (size_t)kMaxLds) {
+                    v.push_back({V_H16_PP, bf, 1});
+                    break;
+                }
+            for (int bf : {96, 64})
+                if (pp_lds_bytes(p, bf, 2) + kRingBytes <= (size_t)kMaxLds) {
+                    v.push_back({V_H16_PP, bf, 2});
+                    break;
+                }
         }
         if (rs_fits(p)) v.push_back({V_H16_RS, 128});
         if (!x3 && !as_fits(p) && ks_fits(p))
@@ -342,9 +362,10 @@ const char *forward_variant_name(const Plan &p, int i) {
     static thread_local char buf[64];
     const std::vector<Variant> v = variant_list(p);
     if (i < 0 || (size_t)i >= v.size()) return "none";
-    const char *k = v[i].kind == V_F32_WS   ? "f32-frame-split-warp-specialised"
+    const char *k = v[i].kind == V_H16_PP   ? (v[i].nbuf == 2 ? "h16-producer-consumer-2span" : "h16-producer-consumer")
+                    : v[i].kind == V_F32_WS ? "f32-frame-split-warp-specialised"
                     : v[i].kind == V_F32_FS ? "f32-frame-split"
-                    : v[i].kind == V_H16_AS ? "h16-row-split-lds-dma"
+                    : v[i].kind == V_H16_AS ? (v[i].nbuf == 2 ? "h16-row-split-lds-dma2" : "h16-row-split-lds-dma")
                     : v[i].kind == V_H16_RS ? "h16-row-split"
                     : v[i].kind == V_H16_KS ? "h16-k-split-lds-dma"
                     : v[i].kind == V_H16_FS ? "h16-frame-split"
@@ -381,7 +402,8 @@ melt_status launch_melt_table(Plan &p, int variant, const Chunk *tab, const int 
     switch (v.kind) {
     case V_F32_WS: return launch_melt_f32(p, t, true);
     case V_F32_FS: return launch_melt_f32(p, t, false);
-    case V_H16_AS: return launch_melt_h16(p, t, H16_LDS_DMA, v.bf);
+    case V_H16_PP: return launch_melt_h16(p, t, H16_PIPELINED, v.bf, v.nbuf);
+    case V_H16_AS: return launch_melt_h16(p, t, H16_LDS_DMA, v.bf, v.nbuf);
     case V_H16_RS: return launch_melt_h16(p, t, H16_REGISTER_STAGED, v.bf);
     case V_H16_KS: return launch_melt_h16(p, t, H16_K_SPLIT, v.bf);
     case V_H16_FS: return launch_melt_h16(p, t, H16_FRAME_SPLIT, v.bf);

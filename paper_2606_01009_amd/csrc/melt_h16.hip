@@ -136,9 +136,19 @@ __global__ __launch_bounds__(512) void k_melt_h16_rs(FwdArgs a, const uint4 *__r
 // ------------------------------------------------------------------ 16-bit row-split kernel, direct-to-LDS staging
 //
 // Row-split 16-bit kernel with direct-to-LDS staging (default for BF16/FP16/BF16X3): as
-// k_melt_h16_rs, but chunk c+1's span is copied into an FP32 scratch area while chunk c is
-// multiplied; after a barrier all threads convert it into the operand rows.  Outputs are
-// stored straight from the accumulators (8 consecutive Mel bins per lane).
+// k_melt_h16_rs, but the chunks' spans are copied into FP32 scratch spans while earlier
+// chunks are multiplied; after a barrier all threads convert the current span into the
+// operand rows.  Outputs are stored straight from the accumulators (8 consecutive Mel bins
+// per lane).
+//
+// Span buffers: with nbuf = 1 the copy of chunk c+1 is issued after chunk c's conversion and
+// lands during its multiplies.  With nbuf = 2 the copy of chunk c+2 goes into the span just
+// converted, so a copy is in flight across a whole iteration, conversion included, and the
+// wait at the end of the iteration is for the copy issued one iteration earlier.
+//
+// The copies are issued by the waves with the least multiply work (those sharing a row tile,
+// or idle ones; all waves when every wave owns a tile).  Only those waves wait for them, so
+// the other waves never wait on their own output stores.
 //
 // Wave layout (balanced over the CU's four SIMDs): waves 0..full-1 each own one row tile and
 // sweep every frame tile of the chunk, two at a time; the remaining row tiles (one or two)
@@ -148,7 +158,7 @@ __global__ __launch_bounds__(512) void k_melt_h16_rs(FwdArgs a, const uint4 *__r
 template <class Conv, int NS, bool X3, bool IS_F16>
 __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__restrict__ bhi,
                                                      const uint4 *__restrict__ blo, GroupTableBig gt, int bf,
-                                                     int scr_off, int rgroups) {
+                                                     int scr_off, int scr_len, int nbuf, int rgroups) {
     extern __shared__ float lds_as[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     // row group of this workgroup (fixed for its life, so the basis stays in registers):
@@ -166,7 +176,8 @@ __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__r
     rt = idle ? r0 : r0 + rt;
     const int lo_off = a.S * (bf + a.J - 1);
     unsigned short *rows = reinterpret_cast<unsigned short *>(lds_as);
-    float *scratch = lds_as + scr_off;             // FP32 span, after the operand rows
+    float *span0 = lds_as + scr_off;               // FP32 spans, after the operand rows
+    float *span1 = span0 + (nbuf == 2 ? scr_len : 0);
     zero_pad_columns<Conv>(a, bf + a.J - 1, rows, blockDim.x, lo_off);
     uint4 A[NS];
     uint4 Al[X3 ? NS : 1];
@@ -176,22 +187,41 @@ __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__r
 #pragma unroll
         for (int s = 0; s < NS; ++s) Al[s] = blo[((size_t)rt * NS + s) * 64 + lane];
     }
+    const int nw = blockDim.x >> 6;
+    const int wu = __builtin_amdgcn_readfirstlane(wid);
+    const int dma0 = L.full < nw ? L.full : 0;     // first copying wave
+    const bool dma_wave = wu >= dma0;
     const int nch = *a.n_chunks;
     const int cstep = gridDim.x / rgroups;         // the grid is a multiple of rgroups
     int c = blockIdx.x / rgroups;
-    if (c < nch) async_span(a, read_chunk(a.chunks, c), scratch);
-    async_wait();
-    for (; c < nch; c += cstep) {
-        const Chunk ch = read_chunk(a.chunks, c);
-        __syncthreads();                           // span of chunk c is in scratch; rows are free
-        convert_span<Conv>(a, ch, scratch, rows, lo_off);
-        __syncthreads();                           // rows ready; scratch is free
-        if (c + cstep < nch) async_span(a, read_chunk(a.chunks, c + cstep), scratch);
+    // prologue: every wave copies the first span; the copying waves also start the second
+    if (c < nch) async_span(a, read_chunk(a.chunks, c), span0);
+    int ahead = 0;
+    if (nbuf == 2 && dma_wave && c + cstep < nch)
+        ahead = async_span_waves(a, read_chunk(a.chunks, c + cstep), span1, wu - dma0, nw - dma0);
+    wait_vm_younger(ahead);
+    __shared__ ChunkRing ring;
+    for (int it = 0; c < nch; c += cstep, ++it) {
+        const int ri = it % kRing;
+        if (ri == 0) ring_fill(ring, a.chunks, c, cstep, nch);
+        float *cur = (it & 1) ? span1 : span0;
+        __syncthreads();                           // span of chunk c has landed; rows are free
+        const Chunk ch = ring_get(ring, ri);
+        // the copy into `cur`: chunk c + nbuf * cstep.  The iteration ends with the copy of
+        // chunk c + cstep landed: with nbuf = 2 the `younger` copies just issued may still fly.
+        const int cn = c + nbuf * cstep;
+        const Chunk chn = ring_get(ring, ri + nbuf);
+        convert_span<Conv>(a, ch, cur, rows, lo_off);
+        __syncthreads();                           // rows ready; span `cur` is free
+        int younger = 0;
+        if (dma_wave && cn < nch) {
+            const int n = async_span_waves(a, chn, cur, wu - dma0, nw - dma0);
+            younger = nbuf == 2 ? n : 0;
+        }
         const int nft = idle ? 0 : (ch.n_frames + 31) >> 5;
-        // The next chunk's copy must land before the barrier that starts the next iteration.
-        // Each wave waits ahead of its last tile's stores (so those stores stay in flight
+        // A copying wave waits ahead of its last tile's stores (so those stores stay in flight
         // across the barrier), or after the loop if it had no tile.
-        bool waited = false;
+        bool waited = !dma_wave;
         const int step = (P == 1 && !X3) ? 2 : P;
         for (int ft = part; ft < nft; ft += step) {
             f32x16 acc0 = f32x16{}, acc1 = f32x16{};
@@ -206,8 +236,8 @@ __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__r
                     // a lone last tile multiplies its own rows twice rather than branching
                     const unsigned short *l1 = two ? l0 + 32 * a.S : l0;
                     mfma_sweep<NS, false, IS_F16>(A, Al, l0, l1, gt, lo_off, acc0, acc1);
-                    if (ft + 2 >= nft) {
-                        async_wait();
+                    if (!waited && ft + 2 >= nft) {
+                        wait_vm_younger(younger);
                         waited = true;
                     }
                     store_tile(a, ch, rt, ft * 32 + (lane & 31), lane, acc0);
@@ -216,13 +246,190 @@ __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__r
                 }
             }
             mfma_sweep1<NS, X3, IS_F16>(A, Al, l0, gt, lo_off, acc0);
-            if (ft + step >= nft) {
-                async_wait();
+            if (!waited && ft + step >= nft) {
+                wait_vm_younger(younger);
                 waited = true;
             }
             store_tile(a, ch, rt, ft * 32 + (lane & 31), lane, acc0);
         }
-        if (!waited) async_wait();                 // no tile for this wave (or a frameless chunk)
+        if (!waited) wait_vm_younger(younger);     // no tile for this wave (or a frameless chunk)
+    }
+}
+
+// ------------------------------------------------------------------ 16-bit row-split kernel, producer/consumer
+//
+// The same wave layout and multiplies as k_melt_h16_as, with the staging taken off the
+// multiply waves' path.  The waves from L.full on (those sharing a row tile, or idle ones)
+// are producers: each owns the 256-sample blocks b = pw, pw + np, ... of every chunk's span,
+// copies them HBM -> LDS (direct-to-LDS, FP32) and converts exactly those blocks into the
+// operand rows, so no producer ever waits for another's copy.  Two operand-row buffers
+// alternate: while all waves multiply chunk c from one, the producers fill the other with
+// chunk c + 1.  One barrier per chunk.
+//
+// nscr = 2 span buffers: the copy of chunk c + 2 is issued first thing in the iteration of
+// chunk c (into the span converted an iteration earlier) and waited for an iteration later;
+// nscr = 1: it is issued after chunk c + 1's conversion.  Needs L.full < waves in every row
+// group (checked by the host).
+template <class Conv>
+__device__ __forceinline__ void convert_owned(const FwdArgs &a, const Chunk &ch, const float *span,
+                                              typename Conv::elem_t *rows, int lo_off, int pw, int np) {
+    const int lane = threadIdx.x & 63;
+    const int sp = (ch.n_frames + a.J - 1) * a.H;
+    const int valid = span_valid(a, ch);
+    if ((a.H & 3) == 0) {
+        // four owned blocks per pass, their LDS reads in flight together; a vector never
+        // straddles a row and the span length is a multiple of 4
+        for (int b0 = pw; b0 * 256 < sp; b0 += 4 * np) {
+            f32x4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int o = (b0 + u * np) * 256 + 4 * lane;
+                v[u] = o < valid ? *(const f32x4 *)(span + o) : f32x4{};
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int o = (b0 + u * np) * 256 + 4 * lane;
+                if (o < sp) {
+                    if (o + 4 > valid) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (o + e >= valid) v[u][e] = 0.0f;
+                    }
+                    const int r = span_row(a, o);
+                    Conv::store4(rows, r * a.S + (o - r * a.H), v[u], lo_off);
+                }
+            }
+        }
+        return;
+    }
+    for (int b = pw; b * 256 < sp; b += np) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int o = b * 256 + 4 * lane + e;
+            if (o < sp) {
+                const float v = o < valid ? span[o] : 0.0f;
+                const int r = span_row(a, o);
+                Conv::store(rows, r * a.S + (o - r * a.H), v, lo_off);
+            }
+        }
+    }
+}
+
+// Direct-to-LDS copies of the valid span's blocks owned by producer pw of np: 16-byte copies
+// over whole blocks, 4-byte copies over the owned last partial block (no lane reads past the
+// clip end).  Returns the copy instructions issued (each has an active lane).
+__device__ __forceinline__ int copy_owned(const FwdArgs &a, const Chunk &ch, float *span, int pw, int np) {
+    const int lane = threadIdx.x & 63;
+    const int valid = span_valid(a, ch);
+    const float *src = a.wave + ch.sample_start;
+    const unsigned base = __builtin_amdgcn_readfirstlane(lds_addr(span));
+    const int nfull = valid >> 8;
+    int n = 0;
+    for (int b = pw; b < nfull; b += np, ++n) lds_dma_x4(src + b * 256 + 4 * lane, base + b * 1024);
+    if ((valid & 255) != 0 && nfull % np == pw) {
+        for (int q = 4 * nfull; q * 64 < valid; ++q, ++n) {
+            const int o = q * 64 + lane;
+            if (o < valid) lds_dma_x1(src + o, base + q * 256);
+        }
+    }
+    return n;
+}
+
+template <class Conv, int NS, bool X3, bool IS_F16>
+__global__ __launch_bounds__(512) void k_melt_h16_pp(FwdArgs a, const uint4 *__restrict__ bhi,
+                                                     const uint4 *__restrict__ blo, GroupTableBig gt, int bf,
+                                                     int rows_len, int scr_off, int scr_len, int nscr,
+                                                     int rgroups) {
+    extern __shared__ float lds_pp[];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int grp = blockIdx.x % rgroups, gt_n = (a.row_tiles + rgroups - 1) / rgroups;
+    const int r0 = grp * gt_n, cnt = min(a.row_tiles - r0, gt_n);
+    const WaveLayout L = layout_for(cnt);
+    const bool idle = wid >= L.waves;
+    int rt = wid, part = 0, P = 1;
+    if (wid >= L.full) {
+        rt = L.full + (wid - L.full) / L.psplit;
+        part = (wid - L.full) % L.psplit;
+        P = L.psplit;
+    }
+    rt = idle ? r0 : r0 + rt;
+    const int lo_off = a.S * (bf + a.J - 1);
+    unsigned short *rows0 = reinterpret_cast<unsigned short *>(lds_pp);
+    unsigned short *rows1 = rows0 + rows_len;
+    float *span0 = lds_pp + scr_off;
+    float *span1 = span0 + (nscr == 2 ? scr_len : 0);
+    zero_pad_columns<Conv>(a, bf + a.J - 1, rows0, blockDim.x, lo_off);
+    zero_pad_columns<Conv>(a, bf + a.J - 1, rows1, blockDim.x, lo_off);
+    uint4 A[NS];
+    uint4 Al[X3 ? NS : 1];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) A[s] = bhi[((size_t)rt * NS + s) * 64 + lane];
+    if constexpr (X3) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) Al[s] = blo[((size_t)rt * NS + s) * 64 + lane];
+    }
+    const int nw = blockDim.x >> 6;
+    const int wu = __builtin_amdgcn_readfirstlane(wid);
+    const bool producer = wu >= L.full;
+    const int np = nw - L.full, pw = wu - L.full;
+    const int nch = *a.n_chunks;
+    const int cstep = gridDim.x / rgroups;
+    int c = blockIdx.x / rgroups;
+    if (producer && c < nch) {
+        const Chunk c0 = read_chunk(a.chunks, c);
+        copy_owned(a, c0, span0, pw, np);
+        wait_vm_younger(0);
+        convert_owned<Conv>(a, c0, span0, rows0, lo_off, pw, np);
+        if (c + cstep < nch) copy_owned(a, read_chunk(a.chunks, c + cstep), span1, pw, np);
+    }
+    __syncthreads();
+    __shared__ ChunkRing ring;
+    for (int it = 0; c < nch; c += cstep, ++it) {
+        const int ri = it % kRing;
+        if (ri == 0) {
+            ring_fill(ring, a.chunks, c, cstep, nch);
+            __syncthreads();
+        }
+        const Chunk ch = ring_get(ring, ri);
+        const unsigned short *cur = (it & 1) ? rows1 : rows0;
+        unsigned short *nxt = (it & 1) ? rows0 : rows1;
+        if (producer && c + cstep < nch) {
+            // chunk c + cstep's span: span1 after even iterations; with one span buffer span0
+            const float *sn = ((it & 1) == 0) ? span1 : span0;
+            const Chunk cn = ring_get(ring, ri + 1);
+            const bool more = c + 2 * cstep < nch;
+            if (nscr == 2) {
+                float *sf = ((it & 1) == 0) ? span0 : span1;       // chunk c's span, converted
+                const int n = more ? copy_owned(a, ring_get(ring, ri + 2), sf, pw, np) : 0;
+                wait_vm_younger(n);
+                convert_owned<Conv>(a, cn, sn, nxt, lo_off, pw, np);
+            } else {
+                wait_vm_younger(0);
+                convert_owned<Conv>(a, cn, sn, nxt, lo_off, pw, np);
+                if (more) copy_owned(a, ring_get(ring, ri + 2), span0, pw, np);
+            }
+        }
+        const int nft = idle ? 0 : (ch.n_frames + 31) >> 5;
+        const int step = (P == 1 && !X3) ? 2 : P;
+        for (int ft = part; ft < nft; ft += step) {
+            f32x16 acc0 = f32x16{}, acc1 = f32x16{};
+            int off = (ft * 32 + (lane & 31)) * a.S + 8 * (lane >> 5);
+            asm volatile("" : "+v"(off));
+            const unsigned short *l0 = cur + off;
+            if constexpr (!X3) {
+                if (step == 2) {
+                    const bool two = ft + 1 < nft;
+                    const unsigned short *l1 = two ? l0 + 32 * a.S : l0;
+                    mfma_sweep<NS, false, IS_F16>(A, Al, l0, l1, gt, lo_off, acc0, acc1);
+                    store_tile(a, ch, rt, ft * 32 + (lane & 31), lane, acc0);
+                    if (two) store_tile(a, ch, rt, (ft + 1) * 32 + (lane & 31), lane, acc1);
+                    continue;
+                }
+            }
+            mfma_sweep1<NS, X3, IS_F16>(A, Al, l0, gt, lo_off, acc0);
+            store_tile(a, ch, rt, ft * 32 + (lane & 31), lane, acc0);
+        }
+        __syncthreads();       // rows `nxt` hold chunk c + cstep; rows `cur` are free
     }
 }
 
@@ -361,26 +568,56 @@ static melt_status launch_rs_ns(Plan &p, const FwdArgs &a, const GroupTableBig &
     return hip_check(hipGetLastError(), "melt h16 rs launch");
 }
 
+struct SpanBufs {
+    int off, len, n;    // first span (floats into LDS), floats per span, span count (1 or 2)
+};
+
 template <class Conv, int NS, bool X3, bool F16>
 static melt_status launch_as_ns(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
-                                int scr_off, hipStream_t s) {
-    allow_lds(k_melt_h16_as<Conv, NS, X3, F16>);
+                                SpanBufs sb, hipStream_t s) {
+    allow_lds(k_melt_h16_as<Conv, NS, X3, F16>, kRingBytes);
     const WaveLayout w = wave_layout(p);
     const int rg = row_groups(p);
     k_melt_h16_as<Conv, NS, X3, F16><<<grid, 64 * w.waves, lds, s>>>(
-        a, (const uint4 *)p.d_pack_h16, (const uint4 *)p.d_pack_lo, gt, bf, scr_off, rg);
+        a, (const uint4 *)p.d_pack_h16, (const uint4 *)p.d_pack_lo, gt, bf, sb.off, sb.len, sb.n, rg);
     return hip_check(hipGetLastError(), "melt h16 lds-dma launch");
 }
 
 template <class Conv, bool X3, bool F16>
 static melt_status launch_as(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
-                             int scr_off, hipStream_t s) {
+                             SpanBufs sb, hipStream_t s) {
     switch (p.geo16.n_groups) {
-    case 10: return launch_as_ns<Conv, 10, X3, F16>(p, a, gt, lds, grid, bf, scr_off, s);
-    case 16: return launch_as_ns<Conv, 16, X3, F16>(p, a, gt, lds, grid, bf, scr_off, s);
-    case 20: return launch_as_ns<Conv, 20, X3, F16>(p, a, gt, lds, grid, bf, scr_off, s);
-    case 25: return launch_as_ns<Conv, 25, X3, F16>(p, a, gt, lds, grid, bf, scr_off, s);
-    case 32: return launch_as_ns<Conv, 32, X3, F16>(p, a, gt, lds, grid, bf, scr_off, s);
+    case 10: return launch_as_ns<Conv, 10, X3, F16>(p, a, gt, lds, grid, bf, sb, s);
+    case 16: return launch_as_ns<Conv, 16, X3, F16>(p, a, gt, lds, grid, bf, sb, s);
+    case 20: return launch_as_ns<Conv, 20, X3, F16>(p, a, gt, lds, grid, bf, sb, s);
+    case 25: return launch_as_ns<Conv, 25, X3, F16>(p, a, gt, lds, grid, bf, sb, s);
+    case 32: return launch_as_ns<Conv, 32, X3, F16>(p, a, gt, lds, grid, bf, sb, s);
+    default: return set_error(MELT_E_UNSUPPORTED, "no register tile for this frame length");
+    }
+}
+
+template <class Conv, int NS, bool X3, bool F16>
+static melt_status launch_pp_ns(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+                                int nscr, hipStream_t s) {
+    allow_lds(k_melt_h16_pp<Conv, NS, X3, F16>, kRingBytes);
+    const WaveLayout w = wave_layout(p);
+    const int rg = row_groups(p);
+    const size_t rb = pp_rows_bytes(p, bf);
+    k_melt_h16_pp<Conv, NS, X3, F16><<<grid, 64 * w.waves, lds, s>>>(
+        a, (const uint4 *)p.d_pack_h16, (const uint4 *)p.d_pack_lo, gt, bf, (int)(rb / 2), (int)(2 * rb / 4),
+        (int)(as_span_bytes(p, bf) / 4), nscr, rg);
+    return hip_check(hipGetLastError(), "melt h16 producer/consumer launch");
+}
+
+template <class Conv, bool X3, bool F16>
+static melt_status launch_pp(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+                             int nscr, hipStream_t s) {
+    switch (p.geo16.n_groups) {
+    case 10: return launch_pp_ns<Conv, 10, X3, F16>(p, a, gt, lds, grid, bf, nscr, s);
+    case 16: return launch_pp_ns<Conv, 16, X3, F16>(p, a, gt, lds, grid, bf, nscr, s);
+    case 20: return launch_pp_ns<Conv, 20, X3, F16>(p, a, gt, lds, grid, bf, nscr, s);
+    case 25: return launch_pp_ns<Conv, 25, X3, F16>(p, a, gt, lds, grid, bf, nscr, s);
+    case 32: return launch_pp_ns<Conv, 32, X3, F16>(p, a, gt, lds, grid, bf, nscr, s);
     default: return set_error(MELT_E_UNSUPPORTED, "no register tile for this frame length");
     }
 }
@@ -421,7 +658,7 @@ static melt_status launch_ks(Plan &p, const FwdArgs &a, const GroupTableBig &gt,
     }
 }
 
-melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf) {
+melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf, int nbuf) {
     const int prec = p.cfg.precision;
     const Geometry &g = p.geo16;
     const int S = lds_stride(g.Hp, 2);
@@ -432,17 +669,30 @@ melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf) {
     const GroupTableBig gt = make_table(g, S);
     const hipStream_t s = t.stream;
     if (kind == H16_LDS_DMA) {
-        const size_t lds = as_lds_bytes(p, bf);
-        if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
-        const int scr_off = (int)(as_scratch_offset(p, bf) / 4);
+        if (nbuf != 1 && nbuf != 2) return set_error(MELT_E_INVALID_ARG, "span buffer count must be 1 or 2");
+        const size_t lds = as_lds_bytes(p, bf, nbuf);
+        if (lds + kRingBytes > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
+        const SpanBufs sb{(int)(as_scratch_offset(p, bf) / 4), (int)(as_span_bytes(p, bf) / 4), nbuf};
         // one persistent set of workgroups per row group, each walking all chunks
         const int rg = row_groups(p);
-        const int per_cu = std::min(std::max(1, (int)(kMaxLds / lds)), 2);
+        const int per_cu = std::min(std::max(1, (int)(kMaxLds / (lds + kRingBytes))), 2);
         const int per_group = (int)std::max<int64_t>(1, std::min<int64_t>(t.est_chunks, ((int64_t)p.cu_count * per_cu + rg - 1) / rg));
         const int grid = per_group * rg;
-        if (x3) return launch_as<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, scr_off, s);
-        if (f16) return launch_as<ConvF16, false, true>(p, a, gt, lds, grid, bf, scr_off, s);
-        return launch_as<ConvBF16, false, false>(p, a, gt, lds, grid, bf, scr_off, s);
+        if (x3) return launch_as<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, sb, s);
+        if (f16) return launch_as<ConvF16, false, true>(p, a, gt, lds, grid, bf, sb, s);
+        return launch_as<ConvBF16, false, false>(p, a, gt, lds, grid, bf, sb, s);
+    }
+    if (kind == H16_PIPELINED) {
+        if (!pp_fits(p)) return set_error(MELT_E_UNSUPPORTED, "producer/consumer kernel: no producer waves");
+        if (nbuf != 1 && nbuf != 2) return set_error(MELT_E_INVALID_ARG, "span buffer count must be 1 or 2");
+        const size_t lds = pp_lds_bytes(p, bf, nbuf);
+        if (lds + kRingBytes > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
+        const int rg = row_groups(p);
+        const int per_group = (int)std::max<int64_t>(1, std::min<int64_t>(t.est_chunks, ((int64_t)p.cu_count + rg - 1) / rg));
+        const int grid = per_group * rg;
+        if (x3) return launch_pp<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, nbuf, s);
+        if (f16) return launch_pp<ConvF16, false, true>(p, a, gt, lds, grid, bf, nbuf, s);
+        return launch_pp<ConvBF16, false, false>(p, a, gt, lds, grid, bf, nbuf, s);
     }
     if (kind == H16_K_SPLIT) {
         if (x3 || !ks_fits(p)) return set_error(MELT_E_UNSUPPORTED, "K-split kernel: unsupported geometry");
