@@ -215,27 +215,35 @@ __device__ inline void store_tile(const FwdArgs &a, const Chunk &ch, int rt, int
 
 // Operand formats of the staged frames.  store writes one element; store4 writes four
 // consecutive ones (i a multiple of 4).
-__device__ __forceinline__ unsigned pack2(unsigned short lo, unsigned short hi) { return lo | ((unsigned)hi << 16); }
-
 struct ConvF32 {
     typedef float elem_t;
     __device__ static void store(float *l, int i, float v, int) { l[i] = v; }
     __device__ static void store4(float *l, int i, f32x4 v, int) { *(f32x4 *)(l + i) = v; }
 };
+// two FP32 values -> two 16-bit values in one dword (the two-source v_cvt_pk_{bf16,f16}_f32,
+// round to nearest even, as the scalar conversions)
+typedef float cv_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 cv_bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 cv_f16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned pk_bf16(float a, float b) {
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(cv_f32x2{a, b}, cv_bf16x2));
+}
+__device__ __forceinline__ unsigned pk_f16(float a, float b) {
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(cv_f32x2{a, b}, cv_f16x2));
+}
+
 struct ConvBF16 {
     typedef unsigned short elem_t;
     __device__ static void store(unsigned short *l, int i, float v, int) { l[i] = f32_to_bf16_bits(v); }
     __device__ static void store4(unsigned short *l, int i, f32x4 v, int) {
-        *(uint2 *)(l + i) = uint2{pack2(f32_to_bf16_bits(v[0]), f32_to_bf16_bits(v[1])),
-                                  pack2(f32_to_bf16_bits(v[2]), f32_to_bf16_bits(v[3]))};
+        *(uint2 *)(l + i) = uint2{pk_bf16(v[0], v[1]), pk_bf16(v[2], v[3])};
     }
 };
 struct ConvF16 {
     typedef unsigned short elem_t;
     __device__ static void store(unsigned short *l, int i, float v, int) { l[i] = f32_to_f16_bits(v); }
     __device__ static void store4(unsigned short *l, int i, f32x4 v, int) {
-        *(uint2 *)(l + i) = uint2{pack2(f32_to_f16_bits(v[0]), f32_to_f16_bits(v[1])),
-                                  pack2(f32_to_f16_bits(v[2]), f32_to_f16_bits(v[3]))};
+        *(uint2 *)(l + i) = uint2{pk_f16(v[0], v[1]), pk_f16(v[2], v[3])};
     }
 };
 // split-bf16: the high part at [i], the low part at [i + lo_off]
@@ -247,14 +255,12 @@ struct ConvBF16X3 {
         l[i + lo_off] = f32_to_bf16_bits(v - bf16_bits_to_f32(hb));
     }
     __device__ static void store4(unsigned short *l, int i, f32x4 v, int lo_off) {
-        unsigned short h[4], r[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            h[e] = f32_to_bf16_bits(v[e]);
-            r[e] = f32_to_bf16_bits(v[e] - bf16_bits_to_f32(h[e]));
-        }
-        *(uint2 *)(l + i) = uint2{pack2(h[0], h[1]), pack2(h[2], h[3])};
-        *(uint2 *)(l + i + lo_off) = uint2{pack2(r[0], r[1]), pack2(r[2], r[3])};
+        const unsigned h01 = pk_bf16(v[0], v[1]), h23 = pk_bf16(v[2], v[3]);
+        // the high parts back in FP32: the low half of a dword shifted up, the high half masked
+        const float r0 = v[0] - __builtin_bit_cast(float, h01 << 16), r1 = v[1] - __builtin_bit_cast(float, h01 & 0xffff0000u);
+        const float r2 = v[2] - __builtin_bit_cast(float, h23 << 16), r3 = v[3] - __builtin_bit_cast(float, h23 & 0xffff0000u);
+        *(uint2 *)(l + i) = uint2{h01, h23};
+        *(uint2 *)(l + i + lo_off) = uint2{pk_bf16(r0, r1), pk_bf16(r2, r3)};
     }
 };
 
