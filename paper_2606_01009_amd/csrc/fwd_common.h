@@ -650,22 +650,32 @@ inline bool pp_fits(const Plan &p) {
 }
 
 // K-split 16-bit kernel (frames too long for one wave's basis tile): two waves per row tile,
-// each with the k-groups of half the hop segments.  Needs an even segment count whose halves
-// hold the same k-groups at a constant row shift, and a register tile for the half.
-inline int ks_delta(const Plan &p, int S) {
+// the first holding the k-groups of the first J0 hop segments (ns0 groups), the second the
+// rest (ns1 <= ns0 groups).  The split must leave the second half's groups at the first
+// half's columns, J0 rows further down, so the second wave reads the same offsets shifted by
+// delta = J0 S elements.  The halves need a compiled register tile (ks_supported).
+struct KSplit {
+    int ns0, ns1, delta;    // delta < 0: no valid split
+};
+inline bool ks_supported(int ns0, int ns1) {
+    return (ns0 == ns1 && (ns0 == 16 || ns0 == 20 || ns0 == 25 || ns0 == 32)) || (ns0 == 40 && ns1 == 35);
+}
+inline KSplit ks_split(const Plan &p, int S) {
     const Geometry &g = p.geo16;
-    if (g.J % 2 != 0 || g.n_groups % 2 != 0) return -1;
-    const int h = g.n_groups / 2;
-    const int d = (g.J / 2) * S;
-    for (int i = 0; i < h; ++i)
-        if (g.seg_of_group[h + i] != g.seg_of_group[i] + g.J / 2 || g.col_of_group[h + i] != g.col_of_group[i])
-            return -1;
-    return d;
+    const int G = g.n_groups;
+    for (int j0 = 1; j0 < g.J; ++j0) {
+        int h0 = 0;
+        while (h0 < G && g.seg_of_group[h0] < j0) ++h0;
+        const int h1 = G - h0;
+        if (h1 <= 0 || h1 > h0 || !ks_supported(h0, h1)) continue;
+        bool ok = true;
+        for (int i = 0; i < h1 && ok; ++i)
+            ok = g.seg_of_group[h0 + i] == g.seg_of_group[i] + j0 && g.col_of_group[h0 + i] == g.col_of_group[i];
+        if (ok) return {h0, h1, j0 * S};
+    }
+    return {0, 0, -1};
 }
-inline bool ks_fits(const Plan &p) {
-    const int h = p.geo16.n_groups / 2;
-    return (h == 16 || h == 20 || h == 25 || h == 32) && ks_delta(p, lds_stride(p.geo16.Hp, 2)) > 0;
-}
+inline bool ks_fits(const Plan &p) { return ks_split(p, lds_stride(p.geo16.Hp, 2)).delta > 0; }
 inline int ks_row_groups(const Plan &p) { return (p.row_tiles + 3) / 4; }
 inline size_t ks_scratch_offset(const Plan &p, int bf) {
     return ((size_t)(bf + p.geo16.J - 1) * lds_stride(p.geo16.Hp, 2) * 2 + 15) & ~size_t(15);

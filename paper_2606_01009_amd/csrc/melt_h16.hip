@@ -10,12 +10,12 @@ namespace melt {
 // NS k-groups of 16, one v_mfma_f32_32x32x16 per tile and group.  The frame fragments are
 // read D groups ahead into a ring of registers, and scheduling barriers keep each group's
 // reads above the multiplies they overlap, so LDS latency hides behind D groups of MFMAs.
-// X3 adds hi*lo + lo*hi products from the low parts (basis in Al, frames at lo_off).
-template <int NS, bool X3, bool IS_F16>
+// X3 adds hi*lo + lo*hi products from the low parts (basis in Al, frames at lo_off).  D is
+// the depth of the fragment ring (a shallower ring frees registers for a longer basis tile).
+template <int NS, bool X3, bool IS_F16, int D = (X3 ? 1 : 4)>
 __device__ __forceinline__ void mfma_sweep(const uint4 (&A)[NS], const uint4 (&Al)[X3 ? NS : 1],
                                            const unsigned short *l0, const unsigned short *l1,
                                            const GroupTableBig &gt, int lo_off, f32x16 &acc0, f32x16 &acc1) {
-    constexpr int D = X3 ? 1 : 4;
     uint4 b0[D], b1[D], c0[X3 ? D : 1], c1[X3 ? D : 1];
     auto fetch = [&](int s, int slot) {
         const int o = gt.lds_off[s];
@@ -435,15 +435,19 @@ __global__ __launch_bounds__(512) void k_melt_h16_pp(FwdArgs a, const uint4 *__r
 
 // ------------------------------------------------------------------ 16-bit K-split kernel
 //
-// For frames whose basis tile is too long for one wave's registers (N = 1024: 64 k-groups):
-// two waves share each row tile, each holding the k-groups of half the frame's hop segments
-// (the second half reads rows shifted by `delta` elements, J/2 hop rows).  Per pair of frame
-// tiles the second wave hands its partial sums to the first through LDS, which adds them
-// and stores.  A workgroup owns a row group of at most 4 tiles (8 waves); spans are staged
-// as in k_melt_h16_as.
-template <class Conv, int NS, bool IS_F16>
+// For frames whose basis tile is too long for one wave's registers (N = 1024: 64 k-groups;
+// N = 1200 at hop 160: 75): two waves share each row tile.  The first holds the k-groups of
+// the first hop segments (NS0 groups), the second the rest (NS1 <= NS0), whose columns are
+// the first half's, `delta` elements (whole hop rows) further down.  Per pair of frame tiles
+// the second wave hands its partial sums to the first through LDS, which adds them and
+// stores.  A workgroup owns a row group of at most 4 tiles (8 waves); spans are staged as in
+// k_melt_h16_as.
+template <class Conv, int NS0, int NS1, bool IS_F16>
 __global__ __launch_bounds__(512) void k_melt_h16_ks(FwdArgs a, const uint4 *__restrict__ bhi, GroupTableBig gt,
                                                      int bf, int scr_off, int red_off, int rgroups, int delta) {
+    static_assert(NS1 <= NS0, "the first half is the longer one");
+    constexpr int G = NS0 + NS1;
+    constexpr int D = NS0 > 32 ? 2 : 4;           // fragment ring depth: registers for NS0 = 40
     extern __shared__ float lds_ks[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int grp = blockIdx.x % rgroups, gt_n = (a.row_tiles + rgroups - 1) / rgroups;
@@ -455,10 +459,11 @@ __global__ __launch_bounds__(512) void k_melt_h16_ks(FwdArgs a, const uint4 *__r
     float *scratch = lds_ks + scr_off;
     float *red = lds_ks + red_off + rl * 2048;     // [2 tiles][16 registers][64 lanes]
     zero_pad_columns<Conv>(a, bf + a.J - 1, rows, blockDim.x, 0);
-    uint4 A[NS];
+    uint4 A[NS0];
     const uint4 Al[1] = {};
 #pragma unroll
-    for (int s = 0; s < NS; ++s) A[s] = bhi[((size_t)rt * (2 * NS) + kh * NS + s) * 64 + lane];
+    for (int s = 0; s < NS0; ++s)
+        A[s] = (kh == 0 || s < NS1) ? bhi[((size_t)rt * G + kh * NS0 + s) * 64 + lane] : uint4{};
     const int nch = *a.n_chunks;
     const int cstep = gridDim.x / rgroups;
     int c = blockIdx.x / rgroups;
@@ -479,7 +484,14 @@ __global__ __launch_bounds__(512) void k_melt_h16_ks(FwdArgs a, const uint4 *__r
                 asm volatile("" : "+v"(off));
                 const unsigned short *l0 = rows + off;
                 const unsigned short *l1 = two ? l0 + 32 * a.S : l0;
-                mfma_sweep<NS, false, IS_F16>(A, Al, l0, l1, gt, 0, acc0, acc1);
+                if constexpr (NS0 == NS1) {
+                    mfma_sweep<NS0, false, IS_F16, D>(A, Al, l0, l1, gt, 0, acc0, acc1);
+                } else if (kh == 0) {
+                    mfma_sweep<NS0, false, IS_F16, D>(A, Al, l0, l1, gt, 0, acc0, acc1);
+                } else {
+                    mfma_sweep<NS1, false, IS_F16, D>(reinterpret_cast<const uint4(&)[NS1]>(A), Al, l0, l1, gt, 0,
+                                                      acc0, acc1);
+                }
                 if (kh == 1) {
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
@@ -635,27 +647,26 @@ static melt_status launch_rs(Plan &p, const FwdArgs &a, const GroupTableBig &gt,
     }
 }
 
-template <class Conv, int NS, bool F16>
+template <class Conv, int NS0, int NS1, bool F16>
 static melt_status launch_ks_ns(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
                                 int rg, int delta, hipStream_t s) {
-    allow_lds(k_melt_h16_ks<Conv, NS, F16>);
+    allow_lds(k_melt_h16_ks<Conv, NS0, NS1, F16>);
     const int gt_n = (p.row_tiles + rg - 1) / rg;
-    k_melt_h16_ks<Conv, NS, F16><<<grid, 128 * gt_n, lds, s>>>(a, (const uint4 *)p.d_pack_h16, gt, bf,
-                                                               (int)(ks_scratch_offset(p, bf) / 4),
-                                                               (int)(ks_red_offset(p, bf) / 4), rg, delta);
+    k_melt_h16_ks<Conv, NS0, NS1, F16><<<grid, 128 * gt_n, lds, s>>>(a, (const uint4 *)p.d_pack_h16, gt, bf,
+                                                                     (int)(ks_scratch_offset(p, bf) / 4),
+                                                                     (int)(ks_red_offset(p, bf) / 4), rg, delta);
     return hip_check(hipGetLastError(), "melt h16 k-split launch");
 }
 
 template <class Conv, bool F16>
 static melt_status launch_ks(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf, int rg,
-                             int delta, hipStream_t s) {
-    switch (p.geo16.n_groups / 2) {
-    case 16: return launch_ks_ns<Conv, 16, F16>(p, a, gt, lds, grid, bf, rg, delta, s);
-    case 20: return launch_ks_ns<Conv, 20, F16>(p, a, gt, lds, grid, bf, rg, delta, s);
-    case 25: return launch_ks_ns<Conv, 25, F16>(p, a, gt, lds, grid, bf, rg, delta, s);
-    case 32: return launch_ks_ns<Conv, 32, F16>(p, a, gt, lds, grid, bf, rg, delta, s);
-    default: return set_error(MELT_E_UNSUPPORTED, "no K-split register tile for this frame length");
-    }
+                             const KSplit &k, hipStream_t s) {
+    if (k.ns0 == 16 && k.ns1 == 16) return launch_ks_ns<Conv, 16, 16, F16>(p, a, gt, lds, grid, bf, rg, k.delta, s);
+    if (k.ns0 == 20 && k.ns1 == 20) return launch_ks_ns<Conv, 20, 20, F16>(p, a, gt, lds, grid, bf, rg, k.delta, s);
+    if (k.ns0 == 25 && k.ns1 == 25) return launch_ks_ns<Conv, 25, 25, F16>(p, a, gt, lds, grid, bf, rg, k.delta, s);
+    if (k.ns0 == 32 && k.ns1 == 32) return launch_ks_ns<Conv, 32, 32, F16>(p, a, gt, lds, grid, bf, rg, k.delta, s);
+    if (k.ns0 == 40 && k.ns1 == 35) return launch_ks_ns<Conv, 40, 35, F16>(p, a, gt, lds, grid, bf, rg, k.delta, s);
+    return set_error(MELT_E_UNSUPPORTED, "no K-split register tile for this frame length");
 }
 
 melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf, int nbuf) {
@@ -701,9 +712,9 @@ melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf, int
         const int rg = ks_row_groups(p);
         const int per_group = (int)std::max<int64_t>(1, std::min<int64_t>(t.est_chunks, ((int64_t)p.cu_count + rg - 1) / rg));
         const int grid = per_group * rg;
-        const int delta = ks_delta(p, S);
-        if (f16) return launch_ks<ConvF16, true>(p, a, gt, lds, grid, bf, rg, delta, s);
-        return launch_ks<ConvBF16, false>(p, a, gt, lds, grid, bf, rg, delta, s);
+        const KSplit k = ks_split(p, S);
+        if (f16) return launch_ks<ConvF16, true>(p, a, gt, lds, grid, bf, rg, k, s);
+        return launch_ks<ConvBF16, false>(p, a, gt, lds, grid, bf, rg, k, s);
     }
     if (kind == H16_REGISTER_STAGED) {
         const size_t lds = (size_t)(bf + g.J - 1) * S * 2 * (x3 ? 2 : 1);
