@@ -5,7 +5,8 @@
 //   dx[s]    = sum over (t, n) with start_t + n = s of (G W)[t, n]       (overlap-add)
 //   dW       = G^T X                                                    (learnable basis)
 // Everything is FP32 with MFMA, deterministic (no floating-point atomics):
-//   k_bwd_prep   G and the start sample of every frame
+//   k_bwd_grad   G over every frame (a flat pass over the [T, M] gradient)
+//   k_bwd_fstart the start sample of every frame
 //   k_bwd_dx     owner-computes overlap-add: hop-block row b of dx is sum_j G[b - j] W_j,
 //                W_j = basis columns [jH, jH + H); each sample is written once
 //   k_bwd_dw_tiled  split-K GEMM G^T X over frames into per-split partials (LDS-tiled)
@@ -109,23 +110,40 @@ __global__ void k_fill_i64(int64_t *__restrict__ p, int64_t n, int64_t v) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-// one workgroup per forward chunk: G rows and frame starts of its frames
-__global__ __launch_bounds__(256) void k_bwd_prep(const Chunk *__restrict__ chunks, const int *__restrict__ n_chunks,
-                                                  const float *__restrict__ gout, const float *__restrict__ proj,
-                                                  int64_t n_frames, int M, int H, int kind, float eps,
-                                                  float *__restrict__ G, int64_t *__restrict__ fstart) {
+// G over every frame.  Element e = t M + m of the [T, M] upstream gradient pairs with
+// projections proj[2e], proj[2e + 1] (R, I of Mel bin m) and G entries G[2e], G[2e + 1], so
+// the pass is flat: two elements per thread step with 16-byte projection and G accesses and
+// an 8-byte gradient load when vec (pointers aligned for them), one element otherwise.
+__global__ __launch_bounds__(256) void k_bwd_grad(const float *__restrict__ gout, const float *__restrict__ proj,
+                                                  int64_t n_elems, int kind, float eps, float *__restrict__ G,
+                                                  int vec) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t e0 = 0;
+    if (vec) {
+        const int64_t npairs = n_elems / 2;
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < npairs; i += stride) {
+            const f32x4 y = ((const f32x4 *)proj)[i];
+            const float2 g = ((const float2 *)gout)[i];
+            const float k0 = g.x * map_dS(y[0] * y[0] + y[1] * y[1], kind, eps);
+            const float k1 = g.y * map_dS(y[2] * y[2] + y[3] * y[3], kind, eps);
+            ((f32x4 *)G)[i] = f32x4{2.0f * y[0] * k0, 2.0f * y[1] * k0, 2.0f * y[2] * k1, 2.0f * y[3] * k1};
+        }
+        e0 = 2 * npairs;
+    }
+    for (int64_t e = e0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_elems; e += stride) {
+        const float r = proj[2 * e], im = proj[2 * e + 1];
+        const float k = gout[e] * map_dS(r * r + im * im, kind, eps);
+        G[2 * e] = 2.0f * r * k;
+        G[2 * e + 1] = 2.0f * im * k;
+    }
+}
+
+// one workgroup per forward chunk: the start sample of each of its frames
+__global__ __launch_bounds__(256) void k_bwd_fstart(const Chunk *__restrict__ chunks, const int *__restrict__ n_chunks,
+                                                    int64_t n_frames, int H, int64_t *__restrict__ fstart) {
     const int nch = *n_chunks;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         const Chunk ch = chunks[c];
-        for (int i = threadIdx.x; i < ch.n_frames * M; i += blockDim.x) {
-            const int f = i / M, m = i - f * M;
-            const int64_t t = ch.out_row + f;
-            if (t >= n_frames) continue;
-            const float r = proj[t * 2 * M + 2 * m], im = proj[t * 2 * M + 2 * m + 1];
-            const float k = gout[t * M + m] * map_dS(r * r + im * im, kind, eps);
-            G[t * 2 * M + 2 * m] = 2.0f * r * k;
-            G[t * 2 * M + 2 * m + 1] = 2.0f * im * k;
-        }
         for (int f = threadIdx.x; f < ch.n_frames; f += blockDim.x)
             if (ch.out_row + f < n_frames) fstart[ch.out_row + f] = ch.sample_start + (int64_t)f * H;
     }
@@ -412,9 +430,16 @@ melt_status launch_melt_backward(Plan &p, const float *d_wave, const int64_t *d_
     if (st != MELT_OK) return st;
     const int64_t nchunk_est = n_frames / melt_chunk_frames(p) + n_clips + 1;
     const int grid_prep = (int)std::min<int64_t>(nchunk_est, (int64_t)p.cu_count * 4);
-    k_bwd_prep<<<grid_prep, 256, 0, s>>>(p.d_chunks[0], p.d_nchunks, d_gout, proj, n_frames, M, H, p.kern_out,
-                                         (float)p.cfg.log_eps, G, fstart);
-    st = hip_check(hipGetLastError(), "bwd prep");
+    k_bwd_fstart<<<grid_prep, 256, 0, s>>>(p.d_chunks[0], p.d_nchunks, n_frames, H, fstart);
+    st = hip_check(hipGetLastError(), "bwd frame starts");
+    if (st != MELT_OK) return st;
+    {
+        const int64_t n_elems = n_frames * M;
+        const int vec = ((uintptr_t)proj % 16 == 0) && ((uintptr_t)d_gout % 8 == 0) && ((uintptr_t)G % 16 == 0);
+        const int grid_g = (int)std::max<int64_t>(1, std::min<int64_t>((n_elems / 2 + 255) / 256, (int64_t)p.cu_count * 8));
+        k_bwd_grad<<<grid_g, 256, 0, s>>>(d_gout, proj, n_elems, p.kern_out, (float)p.cfg.log_eps, G, vec);
+    }
+    st = hip_check(hipGetLastError(), "bwd gradient of the projections");
     if (st != MELT_OK) return st;
     if (d_gwave) {
         // rows cover every sample of every clip (samples no frame covers get 0: their G
