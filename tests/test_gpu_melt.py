@@ -129,6 +129,30 @@ def test_many_clips_schedule(torch, melt, orc, prec):
     _check(orc, melt, plan, L, wave, off, prec, label=f"2600 clips {prec}")
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "bf16x3", "fp8"])
+def test_chunk_ring_refill(torch, melt, orc, prec):
+    """20 000 clips of one to four frames, one chunk each: a persistent workgroup of the
+    direct-to-LDS and producer/consumer kernels walks 39 or more chunks, so it reads chunk
+    descriptors through at least one refill of its 32-entry LDS ring.  The default variant
+    is checked against the oracle; every other variant with the ring must give the same
+    bits (they share the per-frame arithmetic)."""
+    rng = np.random.default_rng(41)
+    nfr = rng.integers(1, 5, 20000)
+    lengths = 400 + (nfr - 1) * 160 + rng.integers(0, 160, 20000)
+    wave, off = workloads.random_clips(lengths, seed=42)
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80, precision=prec)
+    L0, _ = _gpu_forward(torch, melt, plan, wave, off)
+    assert L0.shape[0] == int(nfr.sum())
+    _check(orc, melt, plan, L0, wave, off, prec, label=f"20000 clips {prec}")
+    for v in range(1, melt.melt_variant_count(plan.handle)):
+        name = melt.melt_variant_name(plan.handle, v)
+        if "lds-dma" not in name and "producer-consumer" not in name:
+            continue
+        melt.melt_set_variant(plan.handle, v, 0)
+        L, _ = _gpu_forward(torch, melt, plan, wave, off)
+        assert np.array_equal(L, L0), f"{prec} {name} differs from the default variant"
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp8"])
 def test_every_kernel_variant(torch, melt, orc, prec):
     """Every kernel variant of the precision (staging scheme x frames per chunk), pinned with
