@@ -147,8 +147,8 @@ __global__ __launch_bounds__(512) void k_melt_h16_rs(FwdArgs a, const uint4 *__r
 // wait at the end of the iteration is for the copy issued one iteration earlier.
 //
 // The copies are issued by the waves with the least multiply work (those sharing a row tile,
-// or idle ones; all waves when every wave owns a tile).  Only those waves wait for them, so
-// the other waves never wait on their own output stores.
+// or idle ones; the upper half of the waves when every wave owns a tile).  Only those waves
+// wait for them, so the other waves never wait on their own output stores.
 //
 // Wave layout (balanced over the CU's four SIMDs): waves 0..full-1 each own one row tile and
 // sweep every frame tile of the chunk, two at a time; the remaining row tiles (one or two)
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__r
     }
     const int nw = blockDim.x >> 6;
     const int wu = __builtin_amdgcn_readfirstlane(wid);
-    const int dma0 = L.full < nw ? L.full : 0;     // first copying wave
+    const int dma0 = L.full < nw ? L.full : nw / 2;    // first copying wave
     const bool dma_wave = wu >= dma0;
     const int nch = *a.n_chunks;
     const int cstep = gridDim.x / rgroups;         // the grid is a multiple of rgroups
