@@ -153,9 +153,9 @@ __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__re
     for (int r = 0; r < 16; ++r) rinv[r] = rinv_g[rt * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)];
     const int nch = *a.n_chunks;
     // the next chunk's span is copied by the waves with the least multiply work (those
-    // sharing a row tile; all waves when every wave owns one): only they wait for it, so
-    // the other waves never wait on their own output stores
-    const int dma0 = full < nw ? full : 0;
+    // sharing a row tile; the upper half of the waves when every wave owns one): only they
+    // wait for it, so the other waves never wait on their own output stores
+    const int dma0 = full < nw ? full : nw / 2;
     const bool dma_wave = wid >= dma0;
     int c = blockIdx.x;
     if (c < nch) async_span(a, read_chunk(a.chunks, c), scratch);

@@ -195,7 +195,9 @@ def test_other_geometries(torch, melt, orc, geom):
     sr, N, H, M = geom
     lengths = [N - 1, N, 5 * N + 7, 31 * H + N, 2 * 128 * H + N + 3]
     wave, off = workloads.random_clips(lengths, seed=9)
-    for prec in ("fp32", "bf16"):
+    # FP8 too: every geometry here has an FP8 register tile (N 256, 400, 512, 1024), and 128
+    # Mel bins put a row tile on every wave of the FP8 kernel
+    for prec in ("fp32", "bf16", "fp8"):
         plan = melt.MeltPlan(sample_rate=sr, n_fft=N, hop=H, n_mels=M, precision=prec)
         L, _ = _gpu_forward(torch, melt, plan, wave, off)
         _check(orc, melt, plan, L, wave, off, prec, label=f"geometry {geom} {prec}")
