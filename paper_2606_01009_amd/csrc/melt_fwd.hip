@@ -340,7 +340,7 @@ static std::vector<Variant> variant_list(const Plan &p) {
         if (rs_fits(p)) v.push_back({V_H16_RS, 128});
         if (!x3 && !as_fits(p) && ks_fits(p))
             for (int bf : {64, 32})
-                if (ks_lds_bytes(p, bf) <= (size_t)kMaxLds) {
+                if (ks_lds_bytes(p, bf) + kRingBytes <= (size_t)kMaxLds) {
                     v.push_back({V_H16_KS, bf});
                     break;
                 }

@@ -441,7 +441,8 @@ __global__ __launch_bounds__(512) void k_melt_h16_pp(FwdArgs a, const uint4 *__r
 // the first half's, `delta` elements (whole hop rows) further down.  Per pair of frame tiles
 // the second wave hands its partial sums to the first through LDS, which adds them and
 // stores.  A workgroup owns a row group of at most 4 tiles (8 waves); spans are staged as in
-// k_melt_h16_as.
+// k_melt_h16_as: the second-half waves, which store nothing, issue the span copies and wait
+// for them, and chunk descriptors come from the LDS ring.
 template <class Conv, int NS0, int NS1, bool IS_F16>
 __global__ __launch_bounds__(512) void k_melt_h16_ks(FwdArgs a, const uint4 *__restrict__ bhi, GroupTableBig gt,
                                                      int bf, int scr_off, int red_off, int rgroups, int delta) {
@@ -466,15 +467,21 @@ __global__ __launch_bounds__(512) void k_melt_h16_ks(FwdArgs a, const uint4 *__r
         A[s] = (kh == 0 || s < NS1) ? bhi[((size_t)rt * G + kh * NS0 + s) * 64 + lane] : uint4{};
     const int nch = *a.n_chunks;
     const int cstep = gridDim.x / rgroups;
+    const int wu = __builtin_amdgcn_readfirstlane(wid);
+    const bool copier = wu >= gt_n;                // second-half waves: no output stores
     int c = blockIdx.x / rgroups;
     if (c < nch) async_span(a, read_chunk(a.chunks, c), scratch);
     async_wait();
-    for (; c < nch; c += cstep) {
-        const Chunk ch = read_chunk(a.chunks, c);
+    __shared__ ChunkRing ring;
+    for (int it = 0; c < nch; c += cstep, ++it) {
+        const int ri = it % kRing;
+        if (ri == 0) ring_fill(ring, a.chunks, c, cstep, nch);
         __syncthreads();                           // span of chunk c is in scratch; rows are free
+        const Chunk ch = ring_get(ring, ri);
+        const Chunk chn = ring_get(ring, ri + 1);
         convert_span<Conv>(a, ch, scratch, rows, 0);
         __syncthreads();                           // rows ready; scratch is free
-        if (c + cstep < nch) async_span(a, read_chunk(a.chunks, c + cstep), scratch);
+        if (copier && c + cstep < nch) async_span_waves(a, chn, scratch, wu - gt_n, gt_n);
         const int nft = (ch.n_frames + 31) >> 5;
         for (int ft = 0; ft < nft; ft += 2) {      // the same trip count in every wave
             const bool two = ft + 1 < nft;
@@ -512,7 +519,7 @@ __global__ __launch_bounds__(512) void k_melt_h16_ks(FwdArgs a, const uint4 *__r
             }
             __syncthreads();                       // the partial-sum area is free again
         }
-        async_wait();                              // the next chunk's copy has landed
+        if (copier) async_wait();                  // the next chunk's copy has landed
     }
 }
 
@@ -650,7 +657,7 @@ static melt_status launch_rs(Plan &p, const FwdArgs &a, const GroupTableBig &gt,
 template <class Conv, int NS0, int NS1, bool F16>
 static melt_status launch_ks_ns(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
                                 int rg, int delta, hipStream_t s) {
-    allow_lds(k_melt_h16_ks<Conv, NS0, NS1, F16>);
+    allow_lds(k_melt_h16_ks<Conv, NS0, NS1, F16>, kRingBytes);
     const int gt_n = (p.row_tiles + rg - 1) / rg;
     k_melt_h16_ks<Conv, NS0, NS1, F16><<<grid, 128 * gt_n, lds, s>>>(a, (const uint4 *)p.d_pack_h16, gt, bf,
                                                                      (int)(ks_scratch_offset(p, bf) / 4),
@@ -708,7 +715,7 @@ melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf, int
     if (kind == H16_K_SPLIT) {
         if (x3 || !ks_fits(p)) return set_error(MELT_E_UNSUPPORTED, "K-split kernel: unsupported geometry");
         const size_t lds = ks_lds_bytes(p, bf);
-        if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
+        if (lds + kRingBytes > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
         const int rg = ks_row_groups(p);
         const int per_group = (int)std::max<int64_t>(1, std::min<int64_t>(t.est_chunks, ((int64_t)p.cu_count + rg - 1) / rg));
         const int grid = per_group * rg;

@@ -153,6 +153,21 @@ def test_chunk_ring_refill(torch, melt, orc, prec):
         assert np.array_equal(L, L0), f"{prec} {name} differs from the default variant"
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_chunk_ring_refill_ksplit(torch, melt, orc, prec):
+    """The same for the K-split kernel (22.05 kHz, N 1024, H 256, 128 Mel bins: two row
+    groups of four tiles): 20 000 one- to four-frame clips, over 100 chunks per workgroup."""
+    rng = np.random.default_rng(43)
+    nfr = rng.integers(1, 5, 20000)
+    lengths = 1024 + (nfr - 1) * 256 + rng.integers(0, 256, 20000)
+    wave, off = workloads.random_clips(lengths, seed=44)
+    plan = melt.MeltPlan(sample_rate=22050, n_fft=1024, hop=256, n_mels=128, precision=prec)
+    assert "k-split" in melt.melt_variant_name(plan.handle, 0)
+    L, _ = _gpu_forward(torch, melt, plan, wave, off)
+    assert L.shape[0] == int(nfr.sum())
+    _check(orc, melt, plan, L, wave, off, prec, label=f"20000 clips K-split {prec}")
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp8"])
 def test_every_kernel_variant(torch, melt, orc, prec):
     """Every kernel variant of the precision (staging scheme x frames per chunk), pinned with
