@@ -78,6 +78,10 @@ def lib() -> ctypes.CDLL:
         L.oracle_melt_forward_basis.argtypes = [p, p, i, i, i, p, p, i, i, d, p, p, p]
         L.oracle_melt_backward.restype = i64
         L.oracle_melt_backward.argtypes = [p, i64, p, i, i, i, p, p, i, i, d, p, p, p, p]
+        L.oracle_melt_chain.restype = None
+        L.oracle_melt_chain.argtypes = [i64, i, p, p, p, i, d, p, p]
+        L.oracle_melt_backward_linear.restype = i64
+        L.oracle_melt_backward_linear.argtypes = [p, i64, p, i, i, i, p, p, i, p, p, p, p, p]
         L.oracle_power_spectrum.restype = i64
         L.oracle_power_spectrum.argtypes = [p, p, i, i, i, i, p]
         L.oracle_mel_filterbank.argtypes = [i, d, i, d, d, i, i, p]
@@ -238,6 +242,43 @@ def melt_backward(wave, clip_offsets=None, *, n_fft, hop, Wr, Wi, grad_out, out_
     dWi = np.empty_like(Wi)
     lib().oracle_melt_backward(_ptr(x), x.size, _ptr(off), len(off) - 1, n_fft, hop, _ptr(Wr), _ptr(Wi),
                                M, out_kind, float(eps), _ptr(g), _ptr(gx), _ptr(dWr), _ptr(dWi))
+    return gx, dWr, dWi
+
+
+def melt_chain(R, I, grad_out, *, out_kind=OUT_LOG_POWER, eps=1e-10):
+    """Chain rule through the energy and output map (Eqs. meltf, dmp_energy): the gradients
+    (Gr, Gi) of R and I for upstream grad_out, from any projections R, I [T, M]."""
+    R = np.ascontiguousarray(R, np.float64)
+    I = np.ascontiguousarray(I, np.float64)
+    g = np.ascontiguousarray(grad_out, np.float64)
+    if not (R.shape == I.shape == g.shape and R.ndim == 2):
+        raise ValueError("R, I and grad_out must share one [T, M] shape")
+    Gr = np.empty_like(R)
+    Gi = np.empty_like(R)
+    lib().oracle_melt_chain(R.shape[0], R.shape[1], _ptr(R), _ptr(I), _ptr(g), out_kind, float(eps), _ptr(Gr),
+                            _ptr(Gi))
+    return Gr, Gi
+
+
+def melt_backward_linear(wave, clip_offsets=None, *, n_fft, hop, Wr, Wi, Gr, Gi, want_wave=True):
+    """Transpose of the projection (Eq. dmp_projection) applied to the gradients (Gr, Gi) of
+    R and I: (grad_wave, dWr, dWi), grad_wave overlap-added over the frames (None when
+    want_wave is False)."""
+    x = _wave(wave)
+    off = _offsets(clip_offsets, x.size)
+    Wr = np.ascontiguousarray(Wr, np.float64)
+    Wi = np.ascontiguousarray(Wi, np.float64)
+    Gr = np.ascontiguousarray(Gr, np.float64)
+    Gi = np.ascontiguousarray(Gi, np.float64)
+    M = Wr.shape[0]
+    T = total_frames(off, n_fft, hop)
+    if Gr.shape != (T, M) or Gi.shape != (T, M):
+        raise ValueError("Gr and Gi must be [T, M]")
+    gx = np.empty(x.size, np.float64) if want_wave else None
+    dWr = np.empty_like(Wr)
+    dWi = np.empty_like(Wi)
+    lib().oracle_melt_backward_linear(_ptr(x), x.size, _ptr(off), len(off) - 1, n_fft, hop, _ptr(Wr), _ptr(Wi), M,
+                                      _ptr(Gr), _ptr(Gi), _ptr(gx), _ptr(dWr), _ptr(dWi))
     return gx, dWr, dWi
 
 

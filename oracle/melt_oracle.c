@@ -251,44 +251,42 @@ int64_t oracle_melt_forward_basis(const float *wave, const int64_t *clip_off, in
     return T;
 }
 
-/* Gradient of out = map(R^2 + I^2), R = X Wr^T, I = X Wi^T, given the upstream
- * gradient g [T, n_freq] (chain rule; not in the paper):
- *   dR = g * map'(S) * 2R,  dI = g * map'(S) * 2I
- *   dX = dR Wr + dI Wi, overlap-added: dx[start_t + n] += dX[t, n]
- *   dWr = dR^T X,  dWi = dI^T X.
+/* Chain rule through out = map(S), S = R^2 + I^2 (Eqs. meltf, dmp_energy), for given
+ * projections R, I and upstream gradient g, all [T, n_freq]:
+ *   Gr = dL/dR = 2 R g map'(S),  Gi = dL/dI = 2 I g map'(S).
+ * R and I may be the exact projections or those of a reduced-precision forward. */
+void oracle_melt_chain(int64_t T, int n_freq, const double *R, const double *I, const double *g,
+                       int out_kind, double eps, double *Gr, double *Gi)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < T * (int64_t)n_freq; ++e) {
+        double k = g[e] * output_map_dS(R[e] * R[e] + I[e] * I[e], out_kind, eps);
+        Gr[e] = 2.0 * R[e] * k;
+        Gi[e] = 2.0 * I[e] * k;
+    }
+}
+
+/* Transpose of the projection R = X Wr^T, I = X Wi^T (Eq. dmp_projection) applied to
+ * gradients Gr, Gi [T, n_freq] of R and I:
+ *   dX = Gr Wr + Gi Wi, overlap-added over the frames: dx[start_t + n] += dX[t, n]
+ *   dWr = Gr^T X,  dWi = Gi^T X.
  * grad_wave has the length of the whole waveform buffer (samples in no frame get 0).
  * Any of grad_wave, dWr, dWi may be NULL.  Returns T. */
-int64_t oracle_melt_backward(const float *wave, int64_t n_samples, const int64_t *clip_off,
-                             int n_clips, int n_fft, int hop, const double *Wr, const double *Wi,
-                             int n_freq, int out_kind, double eps, const double *grad_out,
-                             double *grad_wave, double *dWr, double *dWi)
+int64_t oracle_melt_backward_linear(const float *wave, int64_t n_samples, const int64_t *clip_off,
+                                    int n_clips, int n_fft, int hop, const double *Wr,
+                                    const double *Wi, int n_freq, const double *Gr,
+                                    const double *Gi, double *grad_wave, double *dWr, double *dWi)
 {
     int64_t *st;
     int64_t T = frame_starts(clip_off, n_clips, n_fft, hop, &st);
-    double *dR = (double *)malloc(sizeof(double) * (size_t)(T > 0 ? T : 1) * (size_t)n_freq);
-    double *dI = (double *)malloc(sizeof(double) * (size_t)(T > 0 ? T : 1) * (size_t)n_freq);
-#pragma omp parallel for schedule(static)
-    for (int64_t t = 0; t < T; ++t) {
-        const float *x = wave + st[t];
-        for (int m = 0; m < n_freq; ++m) {
-            double r = 0.0, i = 0.0;
-            for (int n = 0; n < n_fft; ++n) {
-                r += (double)x[n] * Wr[(size_t)m * n_fft + n];
-                i += (double)x[n] * Wi[(size_t)m * n_fft + n];
-            }
-            double k = grad_out[t * n_freq + m] * output_map_dS(r * r + i * i, out_kind, eps);
-            dR[t * n_freq + m] = 2.0 * r * k;
-            dI[t * n_freq + m] = 2.0 * i * k;
-        }
-    }
     if (grad_wave) {
         for (int64_t s = 0; s < n_samples; ++s) grad_wave[s] = 0.0;
         for (int64_t t = 0; t < T; ++t)            /* serial overlap-add: no races */
             for (int n = 0; n < n_fft; ++n) {
                 double acc = 0.0;
                 for (int m = 0; m < n_freq; ++m)
-                    acc += dR[t * n_freq + m] * Wr[(size_t)m * n_fft + n] +
-                           dI[t * n_freq + m] * Wi[(size_t)m * n_fft + n];
+                    acc += Gr[t * n_freq + m] * Wr[(size_t)m * n_fft + n] +
+                           Gi[t * n_freq + m] * Wi[(size_t)m * n_fft + n];
                 grad_wave[st[t] + n] += acc;
             }
     }
@@ -299,14 +297,37 @@ int64_t oracle_melt_backward(const float *wave, int64_t n_samples, const int64_t
                 double ar = 0.0, ai = 0.0;
                 for (int64_t t = 0; t < T; ++t) {
                     double xv = (double)wave[st[t] + n];
-                    ar += dR[t * n_freq + m] * xv;
-                    ai += dI[t * n_freq + m] * xv;
+                    ar += Gr[t * n_freq + m] * xv;
+                    ai += Gi[t * n_freq + m] * xv;
                 }
                 if (dWr) dWr[(size_t)m * n_fft + n] = ar;
                 if (dWi) dWi[(size_t)m * n_fft + n] = ai;
             }
     }
-    free(st); free(dR); free(dI);
+    free(st);
+    return T;
+}
+
+/* Gradient of out = map(R^2 + I^2), R = X Wr^T, I = X Wi^T, given the upstream
+ * gradient g [T, n_freq] (chain rule; not in the paper): the projections by
+ * oracle_melt_forward_basis, then oracle_melt_chain, then oracle_melt_backward_linear.
+ * grad_wave has the length of the whole waveform buffer (samples in no frame get 0).
+ * Any of grad_wave, dWr, dWi may be NULL.  Returns T. */
+int64_t oracle_melt_backward(const float *wave, int64_t n_samples, const int64_t *clip_off,
+                             int n_clips, int n_fft, int hop, const double *Wr, const double *Wi,
+                             int n_freq, int out_kind, double eps, const double *grad_out,
+                             double *grad_wave, double *dWr, double *dWi)
+{
+    int64_t T = oracle_total_frames(clip_off, n_clips, n_fft, hop);
+    size_t n = (size_t)(T > 0 ? T : 1) * (size_t)n_freq;
+    double *R = (double *)malloc(sizeof(double) * n), *I = (double *)malloc(sizeof(double) * n);
+    double *L = (double *)malloc(sizeof(double) * n);
+    double *Gr = (double *)malloc(sizeof(double) * n), *Gi = (double *)malloc(sizeof(double) * n);
+    oracle_melt_forward_basis(wave, clip_off, n_clips, n_fft, hop, Wr, Wi, n_freq, 2, eps, L, R, I);
+    oracle_melt_chain(T, n_freq, R, I, grad_out, out_kind, eps, Gr, Gi);
+    oracle_melt_backward_linear(wave, n_samples, clip_off, n_clips, n_fft, hop, Wr, Wi, n_freq, Gr, Gi,
+                                grad_wave, dWr, dWi);
+    free(R); free(I); free(L); free(Gr); free(Gi);
     return T;
 }
 

@@ -31,6 +31,50 @@ def test_mel_scale_closed_forms(orc):
             assert orc.mel_to_hz(orc.hz_to_mel(f, form), form) == pytest.approx(f, rel=1e-13, abs=1e-10)
 
 
+def test_slaney_scale_pins(orc):
+    """The Slaney scale (a Mel-formula option of both paths): 3 Mel per 200 Hz below 1 kHz,
+    then 27 Mel per factor 6.4 of frequency.  Closed forms at the break, one and two log
+    steps above it, the constant Mel width of an octave above 1 kHz, and the library routine
+    (transformers.audio_utils.hertz_to_mel / mel_to_hertz, mel_scale="slaney") over 0-11 kHz.
+    A wrong slope, break or log step fails one of them."""
+    from transformers.audio_utils import hertz_to_mel, mel_to_hertz
+    S = orc.MEL_SLANEY
+    assert orc.hz_to_mel(500.0, S) == pytest.approx(7.5, rel=1e-15)
+    assert orc.hz_to_mel(1000.0, S) == pytest.approx(15.0, rel=1e-15)
+    assert orc.hz_to_mel(6400.0, S) == pytest.approx(42.0, rel=1e-15)            # 15 + 27
+    assert orc.hz_to_mel(6400.0 * 6.4, S) == pytest.approx(69.0, rel=1e-15)      # 15 + 2 * 27
+    octave = 27.0 * math.log(2.0) / math.log(6.4)
+    for f in (1000.0, 1500.0, 3000.0, 5512.5):
+        assert orc.hz_to_mel(2 * f, S) - orc.hz_to_mel(f, S) == pytest.approx(octave, rel=1e-13)
+    f = np.linspace(0.0, 11025.0, 301)
+    mu = np.array([orc.hz_to_mel(v, S) for v in f])
+    assert np.allclose(mu, hertz_to_mel(f, mel_scale="slaney"), rtol=1e-14, atol=1e-13)
+    m = np.linspace(0.0, 48.0, 97)
+    assert np.allclose([orc.mel_to_hz(v, S) for v in m], mel_to_hertz(m, mel_scale="slaney"), rtol=1e-13, atol=1e-10)
+
+
+@pytest.mark.parametrize("M,fmin,fmax,sr", [(40, 0.0, 8000.0, 16000.0), (80, 80.0, 7600.0, 16000.0),
+                                             (128, 0.0, 11025.0, 22050.0)])
+def test_slaney_grid_and_filterbank(orc, M, fmin, fmax, sr):
+    """Slaney-scale filter centres and triangles against transformers' routines: the
+    (M+2)-point grid is mel_to_hertz of a uniform Mel grid, the analysis frequencies are its
+    interior points (or the M-point grid for the linspace placement), and the triangular
+    filterbank equals mel_filter_bank(mel_scale="slaney") with and without area norm."""
+    from transformers.audio_utils import hertz_to_mel, mel_filter_bank, mel_to_hertz
+    a, b = hertz_to_mel(fmin, mel_scale="slaney"), hertz_to_mel(fmax, mel_scale="slaney")
+    grid = mel_to_hertz(np.linspace(a, b, M + 2), mel_scale="slaney")
+    assert np.allclose(orc.mel_grid_hz(M, fmin, fmax, orc.MEL_SLANEY), grid, rtol=1e-13, atol=1e-9)
+    assert np.allclose(orc.melt_frequencies(M, fmin, fmax, orc.MEL_SLANEY), grid[1:-1], rtol=1e-13)
+    lin = mel_to_hertz(np.linspace(a, b, M), mel_scale="slaney")
+    assert np.allclose(orc.melt_frequencies(M, fmin, fmax, orc.MEL_SLANEY, orc.PLACE_LINSPACE), lin,
+                       rtol=1e-13, atol=1e-9)
+    N = 512 if sr == 16000.0 else 1024
+    for norm, lib_norm in ((orc.NORM_NONE, None), (orc.NORM_SLANEY, "slaney")):
+        F = orc.mel_filterbank(n_fft=N, sr=sr, n_mels=M, fmin=fmin, fmax=fmax, formula=orc.MEL_SLANEY, norm=norm)
+        ref = mel_filter_bank(N // 2 + 1, M, fmin, fmax, sr, norm=lib_norm, mel_scale="slaney").T
+        assert np.allclose(F, ref, rtol=1e-10, atol=1e-12)
+
+
 def test_mel_grid_and_centres(orc):
     g = orc.mel_grid_hz(80, 0.0, 8000.0)
     assert g[0] == pytest.approx(0.0, abs=1e-9) and g[-1] == pytest.approx(8000.0, rel=1e-14)
@@ -336,6 +380,54 @@ def test_gradient_basis_central_difference(orc):
             om = orc.melt_forward_basis(x, n_fft=N, hop=H, Wr=Wm[0], Wi=Wm[1], eps=1e-3)
             fd = np.sum(g * (op - om)) / (2 * h)
             assert dW[m, n] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+def test_backward_linear_adjoint(orc):
+    """P10 adjoint test: the transposed projection is the adjoint of the projection
+    R = X Wr^T, I = X Wi^T, both in the waveform, <Gr, R(v)> + <Gi, I(v)> = <dx(G), v>, and
+    in the basis, <Gr, X Vr^T> + <Gi, X Vi^T> = <dWr, Vr> + <dWi, Vi>, for random G, v, V on
+    ragged clips (a clip tail that no frame covers gets zero)."""
+    rng = np.random.default_rng(21)
+    lengths = [37, 0, 100, 64, 15]
+    x = rng.standard_normal(sum(lengths)).astype(np.float32)
+    off = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    N, H, M = 16, 5, 3
+    Wr, Wi = rng.standard_normal((M, N)), rng.standard_normal((M, N))
+    T = orc.total_frames(off, N, H)
+    Gr, Gi = rng.standard_normal((T, M)), rng.standard_normal((T, M))
+    gx, dWr, dWi = orc.melt_backward_linear(x, off, n_fft=N, hop=H, Wr=Wr, Wi=Wi, Gr=Gr, Gi=Gi)
+    v = rng.standard_normal(x.size).astype(np.float32)
+    _, Rv, Iv = orc.melt_forward_basis(v, off, n_fft=N, hop=H, Wr=Wr, Wi=Wi, out_kind=orc.OUT_POWER,
+                                       return_ri=True)
+    lhs = np.sum(Gr * Rv) + np.sum(Gi * Iv)
+    assert lhs == pytest.approx(float(np.dot(gx, v.astype(np.float64))), rel=1e-12)
+    Vr, Vi = rng.standard_normal((M, N)), rng.standard_normal((M, N))
+    _, RV, IV = orc.melt_forward_basis(x, off, n_fft=N, hop=H, Wr=Vr, Wi=Vi, out_kind=orc.OUT_POWER,
+                                       return_ri=True)
+    assert np.sum(Gr * RV) + np.sum(Gi * IV) == pytest.approx(np.sum(dWr * Vr) + np.sum(dWi * Vi), rel=1e-12)
+    # samples after the last frame of a clip, and clips shorter than a frame, get zero
+    T0 = orc.num_frames(lengths[0], N, H)
+    tail = off[0] + (T0 - 1) * H + N
+    assert tail < off[1] and np.all(gx[tail:off[1]] == 0.0) and np.all(gx[off[4]:off[5]] == 0.0)
+    assert np.all(gx[:tail] != 0.0)
+
+
+def test_chain_then_linear_is_the_gradient(orc):
+    """The gradient splits into the chain rule through the output map (oracle_melt_chain)
+    and the transposed projection: the composition equals oracle_melt_backward (itself
+    pinned by central differences above) for every output kind."""
+    x, N, H = _tiny()
+    f = np.array([700.0, 2000.0, 5100.0])
+    Wr, Wi = orc.melt_basis(sr=16000.0, n_fft=N, freqs=f)
+    T = orc.num_frames(x.size, N, H)
+    g = np.random.default_rng(14).standard_normal((T, 3))
+    _, R, I = orc.melt_forward_basis(x, n_fft=N, hop=H, Wr=Wr, Wi=Wi, return_ri=True)
+    for kind in (orc.OUT_LOG_POWER, orc.OUT_LOG_MAGNITUDE, orc.OUT_POWER, orc.OUT_MAGNITUDE):
+        Gr, Gi = orc.melt_chain(R, I, g, out_kind=kind, eps=1e-3)
+        a = orc.melt_backward_linear(x, n_fft=N, hop=H, Wr=Wr, Wi=Wi, Gr=Gr, Gi=Gi)
+        b = orc.melt_backward(x, n_fft=N, hop=H, Wr=Wr, Wi=Wi, grad_out=g, out_kind=kind, eps=1e-3)
+        for u, w in zip(a, b):
+            assert np.allclose(u, w, rtol=1e-13, atol=1e-15)
 
 
 # ------------------------------------------------------------------ MFCCT (Eq. mfcct_matrix)
