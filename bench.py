@@ -99,6 +99,13 @@ def sampled_error_db(out, wave, offsets, kind, freqs, n_fft=400, hop=160, n_mels
             "frames_sampled": int(n_sample)}
 
 
+def oracle_freqs(n_mels, fmin=0.0, fmax=8000.0):
+    """The oracle's own HTK Mel centres (Eq. mel_scale, Eq. inverse_mel) for the error check
+    and the CPU baseline: nothing is taken from the plan being measured."""
+    import oracle
+    return oracle.melt_frequencies(n_mels, fmin, fmax, oracle.MEL_HTK, oracle.PLACE_FILTER_CENTRES)
+
+
 def cpu_baseline(wave, offsets, freqs, T, min_seconds=10.0):
     """The FP64 oracle (direct NDFT summation, C + OpenMP) over the whole batch, repeated until
     at least min_seconds of wall time have passed."""
@@ -390,7 +397,7 @@ def main():
         else:
             res["roofline"] = {"bound": "hbm", "frac": bytes_per_launch / (kern_ms * 1e-3) / PEAK["hbm"]}
         if not args.no_check:
-            res["error_vs_fp64_oracle"] = sampled_error_db(out.cpu().numpy(), wave, offsets, "melt", plan.frequencies(),
+            res["error_vs_fp64_oracle"] = sampled_error_db(out.cpu().numpy(), wave, offsets, "melt", oracle_freqs(M),
                                                            n_mels=M)
         log(f"bench: MelT {prec}: {res['frames_per_s'] / 1e6:.1f} M frames/s, kernel {kern_ms * 1e3:.1f} us")
         return res, plan
@@ -481,7 +488,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on the host")
-        line["cpu_baseline"] = cpu_baseline(wave, offsets, plan32.frequencies(), T)
+        line["cpu_baseline"] = cpu_baseline(wave, offsets, oracle_freqs(M), T)
     print(json.dumps(line), flush=True)
     return 0
 

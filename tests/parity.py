@@ -21,6 +21,20 @@ U32 = 2.0 ** -24
 DB_PER_NAT = 10.0 / np.log(10.0)
 
 
+def oracle_basis(orc, cfg):
+    """The oracle's own analysis frequencies and window-folded basis for a plan
+    configuration (a melt_config): Mel centres from the oracle's Mel scale (Eq. mel_scale,
+    Eq. inverse_mel) with the configuration's formula and placement, and the basis of
+    Eq. dmp_weights with its window.  Nothing here is taken from the plan under test, so
+    the placement of the centres is checked too.  Returns (freqs, Wr, Wi)."""
+    formula = {0: orc.MEL_HTK, 1: orc.MEL_SLANEY}[int(cfg.mel_formula)]
+    placement = {0: orc.PLACE_FILTER_CENTRES, 1: orc.PLACE_LINSPACE}[int(cfg.placement)]
+    window = {0: orc.WIN_HANN_SYMMETRIC, 1: orc.WIN_HANN_PERIODIC, 2: orc.WIN_RECT}[int(cfg.window)]
+    f = orc.melt_frequencies(int(cfg.n_mels), float(cfg.fmin), float(cfg.fmax), formula, placement)
+    Wr, Wi = orc.melt_basis(sr=float(cfg.sample_rate), n_fft=int(cfg.n_fft), freqs=f, window_kind=window)
+    return f, Wr, Wi
+
+
 def log_power_bound(R, I, A_r, A_i, n_terms, eps, extra_rel=1.0):
     """Per-bin bound on |L_gpu - L| for L = ln(R^2 + I^2 + eps).  Returns (bound, vacuous)."""
     g = n_terms * U32 / (1 - n_terms * U32) + extra_rel * U32
@@ -178,3 +192,78 @@ def check_stft_log(L_gpu, P, F, pair_norm2, n_fft, eps, c_fft=4.0, label=""):
         hi = np.log(mel + dmel + eps) + 1e-6
         assert np.all(L_gpu[vac] <= hi[vac]) and np.all(L_gpu[vac] >= np.log(eps * (1 - 2 * U32)) - 1e-6), label
     return db_stats(L_gpu, L, mel)
+
+
+# ------------------------------------------------------------------ backward
+
+def _map_dS(S, kind, eps):
+    """d out / dS of the output maps (the same subgradient convention as the oracle)."""
+    S = np.asarray(S, np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        if kind == 0:
+            return 1.0 / (S + eps)
+        if kind == 1:
+            r = np.sqrt(S)
+            return np.where(S > 0, 1.0 / (2.0 * r * (r + eps)), np.inf)
+        if kind == 2:
+            return np.ones_like(S)
+        return np.where(S > 0, 0.5 / np.sqrt(S), np.inf)
+
+
+def grad_proj_error(R, I, eR, eI, g, kind, eps, c_round=8.0):
+    """Per-element bound on the GPU's gradients of the projections, G = 2 (R, I) g map'(S)
+    (chain rule through Eqs. meltf, dmp_energy), computed in FP32 from projections that
+    differ from the reference R, I by at most eR, eI per bin.
+
+    With S = R^2 + I^2 and |S_gpu - S| <= dS (products, sum and their FP32 roundings),
+    map' is positive and non-increasing on [S - dS, S + dS], so it stays within
+    phi_hi = map'(S - dS) and moves by at most dphi = max(map'(S - dS) - map'(S),
+    map'(S) - map'(S + dS)).  Then
+        |G_gpu - G| <= 2|g| (e phi_hi + |R| dphi) + c u 2|g| (|R| + e) phi_hi
+    with c = 8 covering the FP32 evaluation of map' (square root, reciprocal), the products
+    by g and by 2 R, and the rounding of S + eps.  Returns (dGr, dGi, checkable): a bin is
+    checkable where dS < S / 2 (its energy is resolved to better than a factor 2; below
+    that, the forward value is rounding noise and so is any gradient through it)."""
+    R = np.asarray(R, np.float64)
+    I = np.asarray(I, np.float64)
+    S = R * R + I * I
+    dS = (2 * np.abs(R) * eR + eR * eR + 2 * np.abs(I) * eI + eI * eI) * (1 + 2 * U32) + 2 * U32 * S
+    checkable = dS < 0.5 * S
+    if kind == 0:
+        checkable |= (dS < 0.5 * (S + eps)) & (S + eps > 0)
+    S_lo = np.maximum(S - dS, 0.0)
+    S_hi = S + dS
+    phi = _map_dS(S, kind, eps)
+    phi_hi = _map_dS(S_lo, kind, eps)
+    phi_lo = _map_dS(S_hi, kind, eps)
+    with np.errstate(invalid="ignore"):
+        dphi = np.maximum(phi_hi - phi, phi - phi_lo)
+    ag = 2.0 * np.abs(np.asarray(g, np.float64))
+    dGr = ag * (eR * phi_hi + np.abs(R) * dphi) + c_round * U32 * ag * (np.abs(R) + eR) * phi_hi
+    dGi = ag * (eI * phi_hi + np.abs(I) * dphi) + c_round * U32 * ag * (np.abs(I) + eI) * phi_hi
+    dGr = np.where(checkable, dGr, np.inf)
+    dGi = np.where(checkable, dGi, np.inf)
+    return dGr, dGi, checkable
+
+
+def gamma(n):
+    """gamma_n = n u / (1 - n u): the relative bound of an n-term FP32 sum of products in any
+    order."""
+    return n * U32 / (1 - n * U32)
+
+
+def check_within(gpu, ref, bound, label, rel_slack=1e-6):
+    """Element-wise |gpu - ref| <= bound (1 + rel_slack); returns statistics."""
+    gpu = np.asarray(gpu, np.float64)
+    err = np.abs(gpu - ref)
+    bad = ~(err <= bound * (1 + rel_slack) + 1e-300)
+    if np.any(bad):
+        idx = np.flatnonzero(bad)[:8]
+        lines = [f"i={i} gpu={gpu.flat[i]:.9g} ref={ref.flat[i]:.9g} err={err.flat[i]:.3g} bound={bound.flat[i]:.3g}"
+                 for i in idx]
+        raise AssertionError(f"{label}: {int(bad.sum())} of {bad.size} elements beyond the bound\n" + "\n".join(lines))
+    scale = np.abs(ref)
+    nz = scale > 0
+    return {"max_err_over_bound": float(np.max(err / np.maximum(bound, 1e-300))) if err.size else 0.0,
+            "median_rel_err": float(np.median(err[nz] / scale[nz])) if np.any(nz) else 0.0,
+            "median_rel_bound": float(np.median(bound[nz] / scale[nz])) if np.any(nz) else 0.0}

@@ -42,8 +42,8 @@ def _gpu_forward(torch, melt, plan, wave, off, proj=False):
 
 
 def _oracle_fp32(orc, plan, wave, off, eps):
-    f = plan.frequencies()
-    Wr, Wi = orc.melt_basis(sr=plan.cfg.sample_rate, n_fft=plan.n_fft, freqs=f)
+    # centres and basis from the oracle's own Mel scale and placement, not from the plan
+    _, Wr, Wi = parity.oracle_basis(orc, plan.cfg)
     _, R, I = orc.melt_forward_basis(wave, off, n_fft=plan.n_fft, hop=plan.hop, Wr=Wr, Wi=Wi, eps=eps,
                                      return_ri=True)
     _, Ar, Ai = orc.melt_forward_basis(np.abs(wave), off, n_fft=plan.n_fft, hop=plan.hop, Wr=np.abs(Wr),
@@ -310,3 +310,108 @@ def test_config2_full_size_sampled(torch, melt, orc):
                                     np.arange(2997, 191872, 2998)]))
     sub, off = parity.frames_as_clips(cfg["wave"], cfg["offsets"], 400, 160, ids)
     _check(orc, melt, plan, L[ids], sub, off, "fp32", label="config2 full sampled fp32")
+
+
+# ------------------------------------------------------------------ centres, basis and options
+# Eq. mel_scale, Eq. inverse_mel and the filter-centre placement are checked against the
+# oracle's own computation, never against values read back from the plan.
+
+@pytest.mark.parametrize("formula", ["htk", "slaney"])
+@pytest.mark.parametrize("placement", ["centres", "linspace"])
+def test_plan_centres_and_basis_match_oracle(torch, melt, orc, formula, placement):
+    """The plan's analysis frequencies equal the oracle's (its own Mel scale, inverse and
+    placement) to 1e-13 relative, and the plan's FP32 basis is the oracle's FP64 basis of
+    Eq. dmp_weights rounded once: |b - ref| <= 2^-24 |ref| + 2e-12, the second term covering
+    the oracle's FP64 cos/sin of the unreduced argument (at most ~1.3e3 rad here, a few ulp
+    of it).  Over the paper's two bands, 40 to 512 Mel bins and the three windows."""
+    fcode = {"htk": melt.MELT_MEL_HTK, "slaney": melt.MELT_MEL_SLANEY}[formula]
+    pcode = {"centres": melt.MELT_PLACE_FILTER_CENTRES, "linspace": melt.MELT_PLACE_LINSPACE}[placement]
+    cases = [(fmin, fmax, M, melt.MELT_WIN_HANN_SYMMETRIC) for fmin, fmax in ((0.0, 8000.0), (80.0, 7600.0))
+             for M in (40, 80, 128, 512)]
+    cases += [(0.0, 8000.0, 80, melt.MELT_WIN_HANN_PERIODIC), (80.0, 7600.0, 80, melt.MELT_WIN_RECT)]
+    for fmin, fmax, M, win in cases:
+        plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=M, fmin=fmin, fmax=fmax,
+                             mel_formula=fcode, placement=pcode, window=win)
+        f_ref, Wr, Wi = parity.oracle_basis(orc, plan.cfg)
+        f = plan.frequencies()
+        assert np.allclose(f, f_ref, rtol=1e-13, atol=1e-9), (formula, placement, fmin, fmax, M)
+        assert np.all(np.diff(f) > 0)
+        ref = np.vstack([Wr, Wi])
+        B = plan.basis().astype(np.float64)
+        err = np.abs(B - ref) - (2.0 ** -24 * np.abs(ref) + 2e-12)
+        assert np.all(err <= 0), (formula, placement, fmin, fmax, M, win, float(err.max()))
+        plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_window_formula_placement_forward(torch, melt, orc, prec):
+    """The periodic and rectangular windows, the Slaney scale and the M-point placement
+    through the forward kernels on a 1 s clip, against the oracle's own basis."""
+    cfg = workloads.config1(seed=8)
+    opts = [dict(window=melt.MELT_WIN_HANN_PERIODIC), dict(window=melt.MELT_WIN_RECT),
+            dict(mel_formula=melt.MELT_MEL_SLANEY), dict(placement=melt.MELT_PLACE_LINSPACE, fmin=80.0, fmax=7600.0)]
+    for o in opts:
+        kw = dict(sample_rate=16000, n_fft=400, hop=160, n_mels=80, fmin=0.0, fmax=8000.0, precision=prec)
+        kw.update(o)
+        plan = melt.MeltPlan(**kw)
+        L, _ = _gpu_forward(torch, melt, plan, cfg["wave"], cfg["offsets"])
+        _check(orc, melt, plan, L, cfg["wave"], cfg["offsets"], prec, label=f"options {o} {prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp8"])
+def test_spectral_band_80_7600(torch, melt, orc, prec):
+    """The paper's spectral front end (16 kHz, N 400, H 160, 80 Mel bins over 80-7600 Hz;
+    Table "Audio frontend configuration") on config-2 signals, 4 clips x 2.5 s."""
+    cfg = workloads.config2(n_mels=80, n_clips=4, seconds=2.5)
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80, fmin=80.0, fmax=7600.0, precision=prec)
+    L, _ = _gpu_forward(torch, melt, plan, cfg["wave"], cfg["offsets"])
+    _check(orc, melt, plan, L, cfg["wave"], cfg["offsets"], prec, label=f"80-7600 Hz {prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3"])
+def test_512_mel_bins(torch, melt, orc, prec):
+    """The top of the Mel-bin sweep (M = 512, the paper's break-even point; Fig. m_sweep) over
+    80-7600 Hz: 32 row tiles, so four 16-bit row groups and, for FP32, several row-tile
+    blocks per chunk.  2 clips x 2 s (two full chunks and a ragged tail each)."""
+    cfg = workloads.config2(n_mels=512, n_clips=2, seconds=2.0)
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=512, fmin=80.0, fmax=7600.0, precision=prec)
+    L, _ = _gpu_forward(torch, melt, plan, cfg["wave"], cfg["offsets"])
+    _check(orc, melt, plan, L, cfg["wave"], cfg["offsets"], prec, label=f"M=512 {prec}")
+
+
+def test_512_mel_bins_fp8_unsupported(torch, melt):
+    """The FP8 kernel holds at most 8 row tiles (128 Mel bins): more is reported, not run."""
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=512, precision="fp8")
+    wave = torch.zeros(16000, dtype=torch.float32, device="cuda")
+    off = torch.tensor([0, 16000], dtype=torch.int64, device="cuda")
+    with pytest.raises(melt.MeltError) as ei:
+        plan.forward(wave, off, 98)
+    assert ei.value.status == melt.MELT_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_hop_equals_n_fft(torch, melt, orc, prec):
+    """Adjacent frames with no overlap (hop = n_fft = 256): one hop segment per frame."""
+    lengths = [0, 255, 256, 257, 511, 512, 256 * 130 + 7, 256 * 300]
+    wave, off = workloads.random_clips(lengths, seed=256)
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=256, hop=256, n_mels=40, precision=prec)
+    L, _ = _gpu_forward(torch, melt, plan, wave, off)
+    assert L.shape[0] == sum(melt.melt_num_frames(n, 256, 256) for n in lengths)
+    _check(orc, melt, plan, L, wave, off, prec, label=f"hop = n_fft {prec}")
+
+
+def test_frame_offsets(torch, melt, orc):
+    """melt_frame_offsets: the device prefix sums of the per-clip frame counts, against the
+    oracle's frame count per clip, over 2600 ragged clips (prefix sums carried across blocks
+    of 1024 clips), a batch starting part-way into the buffer, and an empty batch."""
+    lengths = np.random.default_rng(51).integers(0, 400 + 30 * 160, 2600)
+    _, off = workloads.random_clips(lengths, seed=52)
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80)
+    for o in (off, off[5:] + 0, off[:1]):
+        d_off = torch.from_numpy(np.ascontiguousarray(o, np.int64)).cuda()
+        d_fo = torch.full((len(o),), -7, dtype=torch.int64, device="cuda")
+        melt.melt_frame_offsets(plan.handle, d_off, d_fo)
+        torch.cuda.synchronize()
+        T_c = [orc.num_frames(int(b - a), 400, 160) for a, b in zip(o[:-1], o[1:])]
+        ref = np.concatenate([[0], np.cumsum(T_c, dtype=np.int64)])
+        assert np.array_equal(d_fo.cpu().numpy(), ref)

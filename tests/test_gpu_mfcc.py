@@ -43,7 +43,7 @@ def _melt_case(torch, melt, orc, wave, off, sr, N, H, M, K, prec, fmin=0.0, fmax
                          output=melt.MELT_OUT_MFCC, n_mfcc=K)
     assert plan.out_cols == K
     C = _gpu(torch, melt, plan, wave, off)
-    Wr, Wi = orc.melt_basis(sr=sr, n_fft=N, freqs=plan.frequencies())
+    _, Wr, Wi = parity.oracle_basis(orc, plan.cfg)     # the oracle's own centres and basis
     eps = 1e-10
     if prec == "fp32":
         _, R, I = orc.melt_forward_basis(wave, off, n_fft=N, hop=H, Wr=Wr, Wi=Wi, eps=eps, return_ri=True)
