@@ -91,7 +91,7 @@ typedef enum {
 typedef struct {
     double  sample_rate;   /* Hz, > 0 */
     int32_t n_fft;         /* frame length N (window length), 2 .. 4096 */
-    int32_t hop;           /* hop H, 1 .. 65536 */
+    int32_t hop;           /* hop H, 1 .. min(n_fft, 65536); hop > n_fft gives MELT_E_UNSUPPORTED */
     int32_t window;        /* melt_window */
     int32_t n_mels;        /* M, 1 .. 512 */
     double  fmin, fmax;    /* 0 <= fmin < fmax <= sample_rate / 2 */
@@ -122,7 +122,8 @@ int64_t melt_num_frames(int64_t n_samples, int32_t n_fft, int32_t hop);
  * filterbank and FFT tables, and a small device workspace.  cfg: host, read only;
  * *out receives the plan (owned by the caller, freed by melt_plan_destroy).  Errors:
  * MELT_E_INVALID_ARG for out-of-range parameters, MELT_E_UNSUPPORTED for sizes the
- * kernels do not handle, MELT_E_HIP / MELT_E_NO_MEMORY on runtime failures. */
+ * kernels do not handle (among them hop > n_fft: frames that skip samples), MELT_E_HIP /
+ * MELT_E_NO_MEMORY on runtime failures.  Parameters are validated before any device call. */
 melt_status melt_plan_create(const melt_config *cfg, int device, melt_plan *out);
 
 /* Frees the plan and its device memory (synchronises the plan's device first).  NULL ok. */
@@ -159,9 +160,12 @@ melt_status melt_frame_offsets(melt_plan plan, const int64_t *d_clip_offsets, in
  *   d_wave         device float32, all clips back to back (read only)
  *   d_clip_offsets device int64 [n_clips + 1] (read only)
  *   n_clips        >= 0 (0 enqueues nothing)
- *   n_frames       T, the number of rows of d_out; the sum of the clips' frame counts must
- *                  equal it (rows past the computed total are left untouched and frames
- *                  beyond n_frames are not written)
+ *   n_frames       T, the number of rows of d_out, which the caller computes as the sum of
+ *                  the clips' frame counts (melt_num_frames per clip).  The library does not
+ *                  read d_clip_offsets on the host, so it cannot check this: if the offsets
+ *                  describe fewer frames, rows past their total are left untouched; if
+ *                  more, frames from row n_frames on are not written.  Either way no
+ *                  memory outside d_out's n_frames rows is written.
  *   d_out          device float32 [n_frames, n_mels] (written); [n_frames, n_mfcc] for
  *                  MELT_OUT_MFCC, which runs the Mel kernel into a plan workspace and then
  *                  the DCT-II product
@@ -188,7 +192,8 @@ melt_status stft_mel_forward(melt_plan plan, const float *d_wave, const int64_t 
  * clips in d_clip_offsets (as in melt_forward); melt_forward_prepared and
  * stft_mel_forward_prepared then launch only the main kernel over that batch.  The
  * tables stay valid until the next melt_forward / melt_forward_proj / stft_mel_forward /
- * melt_batch_prepare call on the plan.  Buffers as in melt_forward_proj / stft_mel_forward
+ * melt_batch_prepare / melt_backward call on the plan (the backward builds its own batch's
+ * tables in the same plan workspace).  Buffers as in melt_forward_proj / stft_mel_forward
  * (d_proj may be NULL). */
 melt_status melt_batch_prepare(melt_plan plan, const int64_t *d_clip_offsets, int32_t n_clips,
                                int64_t n_frames, void *stream);

@@ -39,6 +39,10 @@ static melt_status validate(const melt_config &c) {
         return set_error(MELT_E_INVALID_ARG, "log_eps must be >= 1.18e-38 (the smallest normal FP32)");
     if (c.precision < 0 || c.precision > 4) return set_error(MELT_E_INVALID_ARG, "bad precision");
     if (c.fb_norm < 0 || c.fb_norm > 1) return set_error(MELT_E_INVALID_ARG, "bad fb_norm");
+    // Frames that skip samples (hop > n_fft) are not implemented: the kernels stage a chunk as
+    // hop-block rows whose LDS stride covers min(n_fft, hop) columns, and the streaming carry
+    // keeps n_fft - hop samples.  Rejected here, before any device work.
+    if (c.hop > c.n_fft) return set_error(MELT_E_UNSUPPORTED, "hop > n_fft (frames that skip samples) is not supported");
     return MELT_OK;
 }
 
@@ -49,7 +53,7 @@ static void free_plan(Plan *p) {
     void *bufs[] = {p->d_basis32, p->d_pack_f32, p->d_pack_h16, p->d_pack_lo, p->d_pack_f8, p->d_rowscale,
                     p->d_fb_w, p->d_fb_start, p->d_fb_off, p->d_twiddle, p->d_window, p->d_chunks[0],
                     p->d_chunks[1], p->d_nchunks, p->d_pack_dx, p->d_bwd_ws, p->d_bwd_rows, p->d_dct,
-                    p->d_lmel};
+                    p->d_lmel, p->d_seg32, p->d_col32, p->d_seg16, p->d_col16};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -143,7 +147,9 @@ melt_status melt_plan_create(const melt_config *cfg, int device, melt_plan *out)
         if (st == MELT_OK)
             st = hip_check(hipMemcpy(p->d_dct, D.data(), D.size() * sizeof(float), hipMemcpyHostToDevice), "upload DCT");
     }
+    if (st == MELT_OK) st = pack_tables_upload(*p);
     if (st == MELT_OK) st = pack_basis(*p, nullptr);
+    if (st == MELT_OK) st = hip_check(hipStreamSynchronize(nullptr), "pack basis");
     if (st == MELT_OK) st = stft_plan_build(*p);
     if (st == MELT_OK) st = ensure_chunks(*p, 0, 4096);
     if (st == MELT_OK) st = ensure_chunks(*p, 1, 4096);

@@ -111,6 +111,10 @@ melt_status plan_build_host(Plan &p) {
     p.geo32 = make_geometry(p.N, p.H, 8);
     p.geo16 = make_geometry(p.N, p.H, 16);
     p.geo8 = make_geometry(p.N, p.H, 64);
+    // The staging helpers write every column c < H of a hop-block row at r * S + c, and the
+    // LDS row stride S is at least the padded row length Hp: each row must cover the hop.
+    for (const Geometry *g : {&p.geo32, &p.geo16, &p.geo8})
+        if (g->Hp < p.H) return set_error(MELT_E_UNSUPPORTED, "hop-block row shorter than the hop (hop > n_fft)");
     return MELT_OK;
 }
 

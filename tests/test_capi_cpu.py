@@ -62,6 +62,18 @@ def test_invalid_configs_rejected(lib, field, value):
     assert h.value is None
 
 
+@pytest.mark.parametrize("n_fft,hop", [(400, 401), (256, 270), (16, 65536)])
+def test_hop_beyond_frame_is_unsupported(lib, n_fft, hop):
+    """Frames that skip samples (hop > n_fft) are rejected with MELT_E_UNSUPPORTED before
+    any device call; hop == n_fft (adjacent frames) is a valid configuration."""
+    c = lib.melt_config_default()
+    c.n_fft, c.hop = n_fft, hop
+    h = ctypes.c_void_p()
+    assert lib.load_library().melt_plan_create(ctypes.byref(c), 0, ctypes.byref(h)) == lib.MELT_E_UNSUPPORTED
+    assert h.value is None
+    assert "hop > n_fft" in lib.melt_last_error()
+
+
 def test_null_arguments_rejected(lib):
     L = lib.load_library()
     assert L.melt_plan_create(None, 0, None) == lib.MELT_E_INVALID_ARG
