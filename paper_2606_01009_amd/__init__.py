@@ -340,6 +340,9 @@ class MeltPlan:
         self.n_mels, self.n_fft, self.hop = self.cfg.n_mels, self.cfg.n_fft, self.cfg.hop
         # width of an output row: n_mfcc cepstral coefficients under MELT_OUT_MFCC, else n_mels
         self.out_cols = self.cfg.n_mfcc if self.cfg.output == MELT_OUT_MFCC else self.n_mels
+        # counts set_basis calls, so a backward can tell whether the basis it must
+        # differentiate through is still the plan's
+        self.basis_generation = 0
 
     def close(self):
         if getattr(self, "handle", None) is not None and _lib is not None:
@@ -360,6 +363,7 @@ class MeltPlan:
 
     def set_basis(self, d_basis):
         melt_plan_set_basis(self.handle, d_basis.contiguous())
+        self.basis_generation += 1
 
     def _out(self, n_frames, cols=None):
         import torch
@@ -400,16 +404,28 @@ def _make_function():
                 plan.set_basis(basis_param.detach())
             proj = torch.empty((n_frames, 2 * plan.n_mels), dtype=torch.float32, device=wave.device)
             out = plan.forward(wave.contiguous(), offsets, n_frames, proj=proj)
-            ctx.save_for_backward(wave, proj)
+            # the basis this forward ran with is saved too (autograd's version check then
+            # covers in-place changes to it), with the plan's basis generation
+            ctx.save_for_backward(wave, proj, basis_param)
             ctx.plan, ctx.offsets, ctx.n_frames = plan, offsets, n_frames
             ctx.has_basis = basis_param is not None
+            ctx.generation = plan.basis_generation
             return out
 
         @staticmethod
         def backward(ctx, g):
-            wave, proj = ctx.saved_tensors
-            gw, gb = ctx.plan.backward(wave, ctx.offsets, ctx.n_frames, g, proj=proj,
-                                       want_wave=ctx.needs_input_grad[0], want_basis=ctx.has_basis)
+            wave, proj, basis_param = ctx.saved_tensors
+            plan = ctx.plan
+            if plan.basis_generation != ctx.generation:
+                # another forward changed the plan's basis since this one ran
+                if basis_param is None:
+                    raise RuntimeError("melt_apply: the plan's basis was replaced (set_basis) between this "
+                                       "forward and its backward; pass the basis as basis_param to differentiate "
+                                       "through it")
+                plan.set_basis(basis_param.detach())
+                ctx.generation = plan.basis_generation
+            gw, gb = plan.backward(wave, ctx.offsets, ctx.n_frames, g, proj=proj,
+                                   want_wave=ctx.needs_input_grad[0], want_basis=ctx.has_basis)
             return gw, gb, None, None, None
 
     return MeltFunction

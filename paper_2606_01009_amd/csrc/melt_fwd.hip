@@ -154,38 +154,45 @@ __global__ void k_pack_h16(const float *__restrict__ b32, int M, int N, int H, c
 }
 
 // E4M3 pack of the basis: [rt][group of 64][lane][32 bytes]; lane half h holds k = 64 g + 32 h + byte.
-// Row scales r_j = 448 / max_n |W_j| (FP32); rinv[rt][i] = 1 / r_j of tile row i.
-__global__ void k_pack_f8(const float *__restrict__ b32, int M, int N, int NG, int RT, unsigned *__restrict__ out,
-                          float *__restrict__ rinv) {
+// Row scales r_j = 448 / max_n |W_j| (FP32); rinv[rt][i] = 1 / r_j of tile row i.  One
+// workgroup of 256 threads per row tile: eight threads per tile row share its maximum, then
+// every thread packs whole 4-byte words.
+__global__ __launch_bounds__(256) void k_pack_f8(const float *__restrict__ b32, int M, int N, int NG,
+                                                 unsigned *__restrict__ out, float *__restrict__ rinv) {
     __shared__ float rmax[32];
-    const int rt = blockIdx.x;
-    const int lane = threadIdx.x & 63;
-    if (threadIdx.x < 32) {
+    const int rt = blockIdx.x, t = threadIdx.x;
+    {
+        const int i = t >> 3, sub = t & 7;
         int ml, part;
-        tile_row_to_mel(threadIdx.x, ml, part);
+        tile_row_to_mel(i, ml, part);
         const int mel = rt * 16 + ml;
         float mx = 0.0f;
         if (mel < M)
-            for (int n = 0; n < N; ++n) mx = fmaxf(mx, fabsf(b32[(size_t)(part * M + mel) * N + n]));
-        rmax[threadIdx.x] = mx;
-        rinv[rt * 32 + threadIdx.x] = mx > 0.0f ? 1.0f / __fdiv_rn(448.0f, mx) : 1.0f;
+            for (int n = sub; n < N; n += 8) mx = fmaxf(mx, fabsf(b32[(size_t)(part * M + mel) * N + n]));
+        // the eight threads of a row are consecutive lanes of one wave
+        mx = fmaxf(mx, __shfl_xor(mx, 1, 64));
+        mx = fmaxf(mx, __shfl_xor(mx, 2, 64));
+        mx = fmaxf(mx, __shfl_xor(mx, 4, 64));
+        if (sub == 0) {
+            rmax[i] = mx;
+            rinv[rt * 32 + i] = mx > 0.0f ? 1.0f / __fdiv_rn(448.0f, mx) : 1.0f;
+        }
     }
     __syncthreads();
-    if (threadIdx.x >= 64) return;
-    int ml, part;
-    tile_row_to_mel(lane & 31, ml, part);
-    const int mel = rt * 16 + ml;
-    const float mx = rmax[lane & 31];
-    const float sc = mx > 0.0f ? __fdiv_rn(448.0f, mx) : 1.0f;
-    for (int g = 0; g < NG; ++g)
-        for (int w = 0; w < 8; ++w) {
-            float v[4];
-            for (int e = 0; e < 4; ++e) {
-                const int k = g * 64 + 32 * (lane >> 5) + 4 * w + e;
-                v[e] = (mel < M && k < N) ? __fmul_rn(b32[(size_t)(part * M + mel) * N + k], sc) : 0.0f;
-            }
-            out[(((size_t)rt * NG + g) * 64 + lane) * 8 + w] = fp8x4(v[0], v[1], v[2], v[3]);
+    for (int idx = t; idx < NG * 512; idx += 256) {
+        const int w = idx & 7, lane = (idx >> 3) & 63, g = idx >> 9;
+        int ml, part;
+        tile_row_to_mel(lane & 31, ml, part);
+        const int mel = rt * 16 + ml;
+        const float mx = rmax[lane & 31];
+        const float sc = mx > 0.0f ? __fdiv_rn(448.0f, mx) : 1.0f;
+        float v[4];
+        for (int e = 0; e < 4; ++e) {
+            const int k = g * 64 + 32 * (lane >> 5) + 4 * w + e;
+            v[e] = (mel < M && k < N) ? __fmul_rn(b32[(size_t)(part * M + mel) * N + k], sc) : 0.0f;
         }
+        out[(((size_t)rt * NG + g) * 64 + lane) * 8 + w] = fp8x4(v[0], v[1], v[2], v[3]);
+    }
 }
 
 // ------------------------------------------------------------------ host side
@@ -199,39 +206,37 @@ melt_status upload_ints(const std::vector<int> &v, int **d) {
 
 }  // namespace
 
+melt_status pack_tables_upload(Plan &p) {
+    melt_status st = upload_ints(p.geo32.seg_of_group, &p.d_seg32);
+    if (st == MELT_OK) st = upload_ints(p.geo32.col_of_group, &p.d_col32);
+    if (st == MELT_OK) st = upload_ints(p.geo16.seg_of_group, &p.d_seg16);
+    if (st == MELT_OK) st = upload_ints(p.geo16.col_of_group, &p.d_col16);
+    return st;
+}
+
+// Re-packs the FP32 basis d_basis32 into the layout of the plan's precision (the only one
+// its kernels read) and the backward's dx layout, enqueued on `s`: no allocation and no
+// host synchronisation (the k-group tables were uploaded at plan creation).
 melt_status pack_basis(Plan &p, hipStream_t s) {
-    melt_status st;
-    // per-group segment/column tables for the pack kernels (temporary device copies)
-    auto pack_one = [&](const Geometry &g, auto launch) -> melt_status {
-        int *dseg = nullptr, *dcol = nullptr;
-        melt_status r = upload_ints(g.seg_of_group, &dseg);
-        if (r == MELT_OK) r = upload_ints(g.col_of_group, &dcol);
-        if (r == MELT_OK) {
-            launch(dseg, dcol);
-            r = hip_check(hipGetLastError(), "pack kernel");
-        }
-        if (r == MELT_OK) r = hip_check(hipStreamSynchronize(s), "pack sync");
-        (void)hipFree(dseg);
-        (void)hipFree(dcol);
-        return r;
-    };
     const int RT = p.row_tiles;
-    st = pack_one(p.geo32, [&](int *seg, int *col) {
-        k_pack_f32<<<256, 256, 0, s>>>(p.d_basis32, p.M, p.N, p.H, seg, col, p.geo32.n_groups, RT,
+    switch (p.cfg.precision) {
+    case MELT_PREC_FP32:
+        k_pack_f32<<<256, 256, 0, s>>>(p.d_basis32, p.M, p.N, p.H, p.d_seg32, p.d_col32, p.geo32.n_groups, RT,
                                        (float *)p.d_pack_f32);
-    });
-    if (st != MELT_OK) return st;
-    const int kind_hi = (p.cfg.precision == MELT_PREC_FP16) ? 1 : 0;
-    st = pack_one(p.geo16, [&](int *seg, int *col) {
-        k_pack_h16<<<256, 256, 0, s>>>(p.d_basis32, p.M, p.N, p.H, seg, col, p.geo16.n_groups, RT, kind_hi,
+        break;
+    case MELT_PREC_FP8_E4M3:
+        k_pack_f8<<<RT, 256, 0, s>>>(p.d_basis32, p.M, p.N, (p.N + 63) / 64, (unsigned *)p.d_pack_f8, p.d_rowscale);
+        break;
+    default: {
+        const int kind_hi = (p.cfg.precision == MELT_PREC_FP16) ? 1 : 0;
+        k_pack_h16<<<256, 256, 0, s>>>(p.d_basis32, p.M, p.N, p.H, p.d_seg16, p.d_col16, p.geo16.n_groups, RT, kind_hi,
                                        (unsigned short *)p.d_pack_h16);
-        k_pack_h16<<<256, 256, 0, s>>>(p.d_basis32, p.M, p.N, p.H, seg, col, p.geo16.n_groups, RT, 2,
-                                       (unsigned short *)p.d_pack_lo);
-    });
-    if (st != MELT_OK) return st;
-    const int ng8 = (p.N + 63) / 64;
-    k_pack_f8<<<RT, 64, 0, s>>>(p.d_basis32, p.M, p.N, ng8, RT, (unsigned *)p.d_pack_f8, p.d_rowscale);
-    st = hip_check(hipGetLastError(), "pack f8");
+        if (p.cfg.precision == MELT_PREC_BF16X3)
+            k_pack_h16<<<256, 256, 0, s>>>(p.d_basis32, p.M, p.N, p.H, p.d_seg16, p.d_col16, p.geo16.n_groups, RT, 2,
+                                           (unsigned short *)p.d_pack_lo);
+    }
+    }
+    const melt_status st = hip_check(hipGetLastError(), "pack basis");
     if (st != MELT_OK) return st;
     return pack_basis_dx(p, s);
 }

@@ -61,6 +61,8 @@ struct Plan {
     void *d_pack_f8 = nullptr;         // FP8 E4M3 packed basis
     float *d_rowscale = nullptr;       // FP8 per-row scales (packed row order)
     Geometry geo32, geo16, geo8;
+    int *d_seg32 = nullptr, *d_col32 = nullptr;   // segment / first column of each k-group (device)
+    int *d_seg16 = nullptr, *d_col16 = nullptr;
     // comparator (FFT + CSR filterbank)
     float *d_fb_w = nullptr;           // filter weights, concatenated per Mel bin
     int *d_fb_start = nullptr;         // first bin of each filter
@@ -105,7 +107,8 @@ melt_status plan_build_host(Plan &p);
 void mel_frequencies(const melt_config &cfg, std::vector<double> &f);
 
 // kernels (melt_fwd.hip, stft_mel.hip, melt_bwd.hip)
-melt_status pack_basis(Plan &p, hipStream_t s);
+melt_status pack_tables_upload(Plan &p);         // k-group tables of the pack kernels (plan creation)
+melt_status pack_basis(Plan &p, hipStream_t s);   // enqueue only: no allocation, no synchronisation
 melt_status pack_basis_dx(Plan &p, hipStream_t s);
 melt_status ensure_chunks(Plan &p, int which, int64_t needed);
 melt_status launch_schedule(Plan &p, int which, const int64_t *d_off, int n_clips, int bf, int64_t n_frames,
