@@ -173,6 +173,24 @@ melt_status melt_frame_offsets(melt_plan plan, const int64_t *d_clip_offsets, in
 melt_status melt_forward(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets,
                          int32_t n_clips, int64_t n_frames, float *d_out, void *stream);
 
+/* As melt_forward, for callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the chunk count and chunk
+ * table live in a fixed 1 MiB device array of the library (one per GPU, held until the
+ * process ends) instead of the plan's growable workspace, and the call makes no hipMalloc,
+ * hipFree or other allocating call.  The scratch holds at most 32 760 chunk-table entries:
+ * the call needs n_frames / F + n_clips + 1 of them, F being the frames per chunk of the
+ * plan's kernel variant (the "-bfF" suffix of melt_variant_name; 128 for the default FP32,
+ * BF16 and FP16 kernels), so e.g. up to about 4 million frames in few clips.  Every call on
+ * one GPU shares that GPU's scratch (from every plan): calls that overlap in time on one
+ * GPU (on different streams, or from several host threads) race and must be serialised by
+ * the caller.  Prepared batches of the plan are left untouched.  Arguments as in
+ * melt_forward.
+ * Errors: as melt_forward; MELT_E_SHAPE if the batch needs more chunk entries than the
+ * scratch holds (checked on the host, nothing is enqueued); MELT_E_UNSUPPORTED for
+ * MELT_OUT_MFCC plans (their cepstrum reads a log-Mel workspace the size of the batch). */
+melt_status melt_forward_noalloc(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets,
+                                 int32_t n_clips, int64_t n_frames, float *d_out, void *stream);
+
 /* As melt_forward, also writing the raw projections for the backward pass:
  * d_proj device float32 [n_frames, 2 * n_mels], row t = (R[t,0], I[t,0], R[t,1], I[t,1], ...). */
 melt_status melt_forward_proj(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets,

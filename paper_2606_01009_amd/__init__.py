@@ -66,6 +66,8 @@ _SYMBOLS = {
                                           ctypes.c_void_p]),
     "melt_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                     ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "melt_forward_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "melt_forward_proj": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                          ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "stft_mel_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
@@ -190,6 +192,12 @@ def melt_frame_offsets(plan, d_clip_offsets, d_frame_offsets, stream=None) -> No
 def melt_forward(plan, d_wave, d_clip_offsets, n_frames, d_out, stream=None) -> None:
     _check(load_library().melt_forward(plan, _ptr(d_wave), _ptr(d_clip_offsets), d_clip_offsets.numel() - 1,
                                        int(n_frames), _ptr(d_out), _stream_handle(stream)), "melt_forward")
+
+
+def melt_forward_noalloc(plan, d_wave, d_clip_offsets, n_frames, d_out, stream=None) -> None:
+    _check(load_library().melt_forward_noalloc(plan, _ptr(d_wave), _ptr(d_clip_offsets),
+                                               d_clip_offsets.numel() - 1, int(n_frames), _ptr(d_out),
+                                               _stream_handle(stream)), "melt_forward_noalloc")
 
 
 def melt_forward_proj(plan, d_wave, d_clip_offsets, n_frames, d_out, d_proj, stream=None) -> None:

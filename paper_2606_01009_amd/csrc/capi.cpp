@@ -153,6 +153,7 @@ melt_status melt_plan_create(const melt_config *cfg, int device, melt_plan *out)
     if (st == MELT_OK) st = stft_plan_build(*p);
     if (st == MELT_OK) st = ensure_chunks(*p, 0, 4096);
     if (st == MELT_OK) st = ensure_chunks(*p, 1, 4096);
+    if (st == MELT_OK) st = scratch_init(device);
     if (st == MELT_OK) apply_tune_cache(*p);
     if (st != MELT_OK) {
         free_plan(p);
@@ -228,6 +229,17 @@ melt_status melt_forward_proj(melt_plan plan, const float *d_wave, const int64_t
     st = launch_schedule(*p, 0, d_clip_offsets, n_clips, melt_chunk_frames(*p), n_frames, s);
     if (st != MELT_OK) return st;
     return launch_melt_main(*p, d_wave, d_out, d_proj, s);
+}
+
+melt_status melt_forward_noalloc(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets,
+                                 int32_t n_clips, int64_t n_frames, float *d_out, void *stream) {
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    melt_status st = check_batch(p, d_wave, d_clip_offsets, n_clips, n_frames, d_out);
+    if (st != MELT_OK) return st;
+    if (n_clips == 0 || n_frames == 0) return MELT_OK;
+    st = hip_check(hipSetDevice(p->device), "hipSetDevice");
+    if (st != MELT_OK) return st;
+    return forward_noalloc(*p, d_wave, d_clip_offsets, n_clips, n_frames, d_out, (hipStream_t)stream);
 }
 
 melt_status stft_mel_forward(melt_plan plan, const float *d_wave, const int64_t *d_clip_offsets, int32_t n_clips,

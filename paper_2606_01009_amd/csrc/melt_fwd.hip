@@ -1,6 +1,7 @@
 // MelT forward: chunk schedule of a ragged batch, basis packing for every operand format,
 // the table of kernel variants and the dispatch to them.
 #include <cstdio>
+#include <mutex>
 #include "fwd_common.h"
 
 namespace melt {
@@ -416,6 +417,61 @@ melt_status launch_melt_table(Plan &p, int variant, const Chunk *tab, const int 
     case V_F8_RS: return launch_melt_f8(p, t, false, v.bf);
     }
     return set_error(MELT_E_UNSUPPORTED, "precision not implemented");
+}
+
+// ------------------------------------------------------------------ allocation-free forward
+// melt_forward_noalloc keeps its chunk count and chunk table in a fixed device array instead
+// of the plan's (growable) workspace, for callers that cannot allocate.  Every GPU the
+// library runs on holds its own copy until the process ends; the host side reaches it only
+// through the address hipGetSymbolAddress returns for that device (the array's name in host
+// code is not a device address).  All calls on one GPU share it: calls that overlap in time
+// on one GPU race.
+constexpr size_t kScratchBytes = size_t(1) << 20;    // 1 MiB per device
+constexpr size_t kScratchTable = 256;                // byte offset of the table (count at 0)
+constexpr int64_t kScratchChunks = int64_t((kScratchBytes - kScratchTable) / sizeof(Chunk));
+constexpr int kScratchDevices = 64;
+static_assert(kScratchChunks == 32760, "chunk capacity stated in melt.h");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kScratchDevices] = {};
+
+// Called once per device at plan creation, with `device` current.
+melt_status scratch_init(int device) {
+    if (device < 0 || device >= kScratchDevices) return set_error(MELT_E_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return MELT_OK;
+    void *ptr = nullptr;
+    const melt_status st = hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (st != MELT_OK) return st;
+    g_scratch_ptr[device] = ptr;
+    return MELT_OK;
+}
+
+melt_status forward_noalloc(Plan &p, const float *d_wave, const int64_t *d_off, int n_clips, int64_t n_frames,
+                            float *d_out, hipStream_t s) {
+    if (p.K > 0) return set_error(MELT_E_UNSUPPORTED, "melt_forward_noalloc: MELT_OUT_MFCC needs a log-Mel workspace");
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        base = g_scratch_ptr[p.device];
+    }
+    if (!base) return set_error(MELT_E_HIP, "melt_forward_noalloc: no scratch address for this device");
+    const int v = p.tune_variant;
+    const int bf = melt_chunk_frames(p, v);
+    // every clip ends in at most one partial chunk
+    const int64_t need = n_frames / bf + n_clips + 1;
+    if (need > kScratchChunks)
+        return set_error(MELT_E_SHAPE, "melt_forward_noalloc: n_frames / " + std::to_string(bf) + " + n_clips + 1 = " +
+                                           std::to_string(need) + " chunk entries exceed the 32760 of the scratch");
+    int *n_tab = static_cast<int *>(base);
+    Chunk *tab = reinterpret_cast<Chunk *>(static_cast<unsigned char *>(base) + kScratchTable);
+    // k_schedule writes the count unconditionally, so nothing in the scratch needs clearing
+    k_schedule<<<1, 1024, 0, s>>>(d_off, n_clips, p.N, p.H, bf, tab, kScratchChunks, n_tab);
+    const melt_status st = hip_check(hipGetLastError(), "schedule launch");
+    if (st != MELT_OK) return st;
+    return launch_melt_table(p, v, tab, n_tab, need - 1, n_frames, d_wave, d_out, nullptr, s);
 }
 
 }  // namespace melt

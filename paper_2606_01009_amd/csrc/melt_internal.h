@@ -136,6 +136,10 @@ melt_status launch_row_matmul(const float *in, int64_t rows, int I, int J, const
                               hipStream_t s);
 void dct_matrix(int K, int M, std::vector<float> &D);
 melt_status ensure_lmel(Plan &p, int64_t rows);
+// allocation-free forward (melt_fwd.hip): per-device scratch address, and the forward over it
+melt_status scratch_init(int device);
+melt_status forward_noalloc(Plan &p, const float *d_wave, const int64_t *d_off, int n_clips, int64_t n_frames,
+                            float *d_out, hipStream_t s);
 melt_status launch_melt_backward(Plan &p, const float *d_wave, const int64_t *d_off, int n_clips,
                                  int64_t n_frames, const float *d_gout, const float *d_proj,
                                  float *d_gwave, float *d_gbasis, hipStream_t s);
