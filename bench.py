@@ -79,6 +79,121 @@ def time_launches(torch, fn, steps, warmup, ramp=True):
     return e0.elapsed_time(e1) / steps          # ms per launch
 
 
+def bootstrap_ci(values, level=0.90, resamples=2000, seed=0):
+    """Percentile bootstrap interval of the median of `values` (resampled with replacement)."""
+    v = np.asarray(values, np.float64)
+    rng = np.random.default_rng(seed)
+    meds = np.median(v[rng.integers(0, v.size, size=(resamples, v.size))], axis=1)
+    a = (1.0 - level) / 2.0
+    return [float(np.quantile(meds, a)), float(np.quantile(meds, 1.0 - a))]
+
+
+def trial_stats(torch, fn, calls, trials=20):
+    """The timing protocol of the paper's experiments on this GPU: `trials` trials of `calls`
+    back-to-back calls after a warm-up, each trial timed with HIP events around its calls (an
+    event pair around every call would add its own gaps to sub-100 us kernels, so a trial
+    gives the mean of its calls).  Median over the trials and its bootstrap 90 % interval,
+    in ms per call."""
+    device_ramp(torch)
+    for _ in range(max(5, calls // 4)):
+        fn()
+    per = [time_launches(torch, fn, calls, 1 if t == 0 else 0, ramp=False) for t in range(trials)]
+    return {"median_ms": float(np.median(per)), "ci90_ms": bootstrap_ci(per), "min_ms": float(np.min(per)),
+            "max_ms": float(np.max(per)), "trials": trials, "calls_per_trial": calls}
+
+
+class EnergyMeter:
+    """Board energy from the amdsmi energy accumulator of the GPU torch uses (matched by PCI
+    address).  On MI355X the accumulator (15.3 uJ per count) is republished about once per
+    second with the time it was sampled, so a window runs over whole republication intervals:
+    the first and last snapshots that fall inside a stretch of uninterrupted work (or of
+    idling) bound it, and power = energy delta / sampled-time delta."""
+
+    def __init__(self, torch):
+        import amdsmi
+        self.smi = amdsmi
+        amdsmi.amdsmi_init()
+        props = torch.cuda.get_device_properties(torch.cuda.current_device())
+        want = (getattr(props, "pci_domain_id", 0), getattr(props, "pci_bus_id", -1), getattr(props, "pci_device_id", 0))
+        self.handle = None
+        for h in amdsmi.amdsmi_get_processor_handles():
+            bdf = amdsmi.amdsmi_get_gpu_device_bdf(h)          # "dddd:bb:dd.f"
+            dom, bus, rest = bdf.split(":")
+            if (int(dom, 16), int(bus, 16), int(rest.split(".")[0], 16)) == want:
+                self.handle = h
+        if self.handle is None:
+            raise RuntimeError(f"no amdsmi GPU at PCI {want}")
+        self.res_uj = amdsmi.amdsmi_get_energy_count(self.handle)["counter_resolution"]
+
+    def _read(self):
+        e = self.smi.amdsmi_get_energy_count(self.handle)
+        return time.perf_counter(), e["energy_accumulator"], e["timestamp"]
+
+    def _window(self, step, intervals, lead_s):
+        """Calls step() until `intervals` republications have been seen after lead_s seconds;
+        returns (joules, seconds, counter quanta) between the first and last of them."""
+        t_start = time.perf_counter()
+        last = self._read()
+        snaps = []
+        while len(snaps) < intervals + 1:
+            step()
+            r = self._read()
+            if (r[1], r[2]) != (last[1], last[2]):
+                if r[0] - t_start >= lead_s:
+                    snaps.append(r)
+                last = r
+            if time.perf_counter() - t_start > lead_s + 3.0 * (intervals + 2):
+                raise RuntimeError("energy counter not republished")
+        (h0, a0, s0), (h1, a1, s1) = snaps[0], snaps[-1]
+        dt_host = h1 - h0
+        dt = (s1 - s0) * 1e-9
+        if not (0.8 * dt_host < dt < 1.2 * dt_host):     # a sample time out of sequence: use the host's
+            dt = dt_host
+        return (a1 - a0) * self.res_uj * 1e-6, dt, int(a1 - a0)
+
+    def idle_watts(self, torch, intervals=2):
+        torch.cuda.synchronize()
+        j, dt, q = self._window(lambda: time.sleep(0.0005), intervals, 0.2)
+        return j / dt, dt, q
+
+    def busy_watts(self, torch, fn, call_ms, intervals=3, lead_s=0.5):
+        """Keeps the GPU busy with back-to-back calls of fn (batches of ~20 ms, at most three
+        in flight) and returns the board power over whole republication intervals."""
+        k = max(1, int(round(20.0 / max(call_ms, 1e-3))))
+        inflight = []
+
+        def step():
+            for _ in range(k):
+                fn()
+            ev = torch.cuda.Event()
+            ev.record()
+            inflight.append(ev)
+            if len(inflight) >= 3:
+                inflight.pop(0).synchronize()
+
+        j, dt, q = self._window(step, intervals, lead_s)
+        torch.cuda.synchronize()
+        return j / dt, dt, q
+
+    def close(self):
+        try:
+            self.smi.amdsmi_shut_down()
+        except Exception:
+            pass
+
+
+def energy_per_call(meter, torch, fn, call_ms, idle_w, frames):
+    """Board and active (board minus idle) energy of one call, from the board power while
+    the call runs back to back and its time per call (the paper's method: a counter delta
+    over a window, less the idle baseline)."""
+    w, dt, q = meter.busy_watts(torch, fn, call_ms)
+    board_mj = w * call_ms
+    active_mj = (w - idle_w) * call_ms
+    return {"board_w": w, "idle_w": idle_w, "window_s": dt, "counter_quanta": q,
+            "board_mj_per_call": board_mj, "active_mj_per_call": active_mj,
+            "active_j_per_mframes": active_mj / frames * 1e3, "board_j_per_mframes": board_mj / frames * 1e3}
+
+
 def sampled_error_db(out, wave, offsets, kind, freqs, n_fft=400, hop=160, n_mels=80, n_sample=256, seed=5):
     """dB error against the FP64 oracle on sampled frames (max / rms over bins within 80 dB
     of the sample's peak)."""
@@ -262,16 +377,17 @@ def write_traffic(pmc_dir, T, bytes_algo, wave_bytes):
     log(f"bench: wrote {TRAFFIC_FILE}: {hbm / 1e6:.1f} MB per launch against {bytes_algo / 1e6:.1f} MB algorithmic")
 
 
-def call_ms(torch, fn, calls=20, warmup=5, busy_ms=30.0):
-    """Median over 5 trials of the mean time of `calls` back-to-back calls (HIP events),
-    after about busy_ms of back-to-back calls so that the clocks have ramped up."""
+def call_ms(torch, fn, calls=20, warmup=5, busy_ms=30.0, trials=20):
+    """Median over `trials` trials of the mean time of `calls` back-to-back calls (HIP events)
+    and its bootstrap 90 % interval, after about busy_ms of back-to-back calls so that the
+    clocks have ramped up."""
     t0 = time.perf_counter()
     while (time.perf_counter() - t0) * 1e3 < busy_ms:
         for _ in range(10):
             fn()
         torch.cuda.synchronize()
-    trials = sorted(time_launches(torch, fn, calls, warmup if t == 0 else 1, ramp=False) for t in range(5))
-    return trials[2]
+    per = [time_launches(torch, fn, calls, warmup if t == 0 else 1, ramp=False) for t in range(trials)]
+    return float(np.median(per)), bootstrap_ci(per)
 
 
 def run_workloads(torch, melt, workloads, path):
@@ -294,11 +410,12 @@ def run_workloads(torch, melt, workloads, path):
             try:
                 plan = melt.MeltPlan(sample_rate=sr, n_fft=N, hop=H, n_mels=M, fmin=fmin, fmax=fmax, precision=prec,
                                      output=output, n_mfcc=K)
-                rec[f"melt_{prec}_ms"] = call_ms(torch, lambda: plan.forward(d_wave, d_off, T, out=out))
+                rec[f"melt_{prec}_ms"], rec[f"melt_{prec}_ci90_ms"] = call_ms(
+                    torch, lambda: plan.forward(d_wave, d_off, T, out=out))
             except melt.MeltError as e:
                 rec[f"melt_{prec}_error"] = str(e)
         plan = melt.MeltPlan(sample_rate=sr, n_fft=N, hop=H, n_mels=M, fmin=fmin, fmax=fmax, output=output, n_mfcc=K)
-        rec["fft_ms"] = call_ms(torch, lambda: plan.stft_mel(d_wave, d_off, T, out=out))
+        rec["fft_ms"], rec["fft_ci90_ms"] = call_ms(torch, lambda: plan.stft_mel(d_wave, d_off, T, out=out))
         for prec in precs:
             if f"melt_{prec}_ms" in rec:
                 rec[f"speedup_{prec}_vs_fft"] = rec["fft_ms"] / rec[f"melt_{prec}_ms"]
@@ -335,6 +452,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="time only the FP32 MelT path and the comparator")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled error check")
+    ap.add_argument("--no-energy", action="store_true", help="skip the board-energy windows (amdsmi)")
+    ap.add_argument("--trials", type=int, default=20, help="timing trials per path (median + bootstrap 90%% CI)")
     ap.add_argument("--only", default=None, help="time one path only: fp32|bf16|fp16|bf16x3|fp8|stft|copy (profiling)")
     ap.add_argument("--sweep", action="store_true", help="time every kernel variant of every precision and exit")
     ap.add_argument("--write-traffic", default=None, metavar="PMC_DIR",
@@ -369,6 +488,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     melt.load_library()
     M = args.n_mels
+    full_line = not (args.only or args.sweep or args.workloads or args.systems)
+    meter, idle = None, None
+    if full_line and not args.no_energy:
+        try:
+            meter = EnergyMeter(torch)
+            log("bench: idle board power (before any GPU work of the bench)")
+            idle = meter.idle_watts(torch)
+        except Exception as e:          # no counter on this machine: the line says so
+            meter, idle = None, {"error": f"{type(e).__name__}: {e}"}
     log(f"bench: generating 64 x 30 s synthetic clips (n_mels={M})")
     cfg = workloads.config2(n_mels=M)
     wave, offsets = cfg["wave"], cfg["offsets"]
@@ -388,6 +516,11 @@ def main():
         res = {"frames_per_s": T / (step_ms * 1e-3), "ms_per_step": step_ms, "kernel_ms": kern_ms,
                "tflops": T * flop_per_frame / (kern_ms * 1e-3) / 1e12,
                "hbm_gbps": bytes_per_launch / (kern_ms * 1e-3) / 1e9}
+        if full_line:
+            step = lambda: plan.forward(d_wave, d_off, T, out=out)
+            res["trials"] = trial_stats(torch, step, args.steps, args.trials)
+            if meter is not None:
+                res["energy"] = energy_per_call(meter, torch, step, res["trials"]["median_ms"], idle[0], T)
         # the bound of each precision: FP32 and split-BF16x3 (three products per term) are
         # MFMA-bound, the others HBM-bound (the waveform read once and the output written once)
         if prec in ("fp32", "bf16x3"):
@@ -411,6 +544,11 @@ def main():
         res = {"frames_per_s": T / (step_ms * 1e-3), "ms_per_step": step_ms, "kernel_ms": kern_ms,
                "hbm_gbps": bytes_per_launch / (kern_ms * 1e-3) / 1e9,
                "roofline": {"bound": "hbm", "frac": bytes_per_launch / (kern_ms * 1e-3) / PEAK["hbm"]}}
+        if full_line:
+            step = lambda: plan.stft_mel(d_wave, d_off, T, out=out)
+            res["trials"] = trial_stats(torch, step, args.steps, args.trials)
+            if meter is not None:
+                res["energy"] = energy_per_call(meter, torch, step, res["trials"]["median_ms"], idle[0], T)
         if not args.no_check:
             res["error_vs_fp64_oracle"] = sampled_error_db(out.cpu().numpy(), wave, offsets, "stft", None, n_mels=M)
         log(f"bench: FFT+filterbank: {res['frames_per_s'] / 1e6:.1f} M frames/s, kernel {kern_ms * 1e3:.1f} us")
@@ -485,7 +623,13 @@ def main():
         "melt_fp32_vs_fft": fp32["frames_per_s"] / comparator["frames_per_s"],
         "variants": variants,
         "roofline": roofline,
+        "trials": fp32.get("trials"),
+        "energy": fp32.get("energy") if meter is not None else idle,
     }
+    if meter is not None:
+        line["energy_idle"] = {"board_w": idle[0], "window_s": idle[1], "counter_quanta": idle[2]}
+        line["energy_vs_fft_active"] = comparator["energy"]["active_mj_per_call"] / fp32["energy"]["active_mj_per_call"]
+        meter.close()
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on the host")
         line["cpu_baseline"] = cpu_baseline(wave, offsets, oracle_freqs(M), T)
