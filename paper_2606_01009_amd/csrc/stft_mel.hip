@@ -70,7 +70,9 @@ constexpr CtCis ct_cis(long a, long b) {
 
 // ------------------------------------------------------------------ complex helpers
 
-struct cf {
+// 8-byte aligned, so that moving one value to or from LDS is one 64-bit access with an
+// immediate offset
+struct alignas(8) cf {
     float x, y;
 };
 __device__ __forceinline__ cf cadd(cf a, cf b) { return {a.x + b.x, a.y + b.y}; }
@@ -96,7 +98,29 @@ __device__ __forceinline__ cf twiddle_const(cf a) {
 }
 
 // ------------------------------------------------------------------ small DFTs in registers
-// Forward DFT X[k] = sum_n x[n] exp(-2 pi i n k / L), in place, natural order.
+// Forward DFT X[k] = sum_n x[n] exp(-2 pi i n k / L), in place, natural order.  Sizes with
+// two coprime factors use the prime-factor (Good-Thomas) mapping, which needs no twiddle
+// multiplications between its two stages; prime powers use Cooley-Tukey.  Every index map
+// is a compile-time register renaming.
+
+constexpr int ct_part(int L, int p) {   // largest power of p dividing L
+    int a = 1;
+    while (L % p == 0) {
+        L /= p;
+        a *= p;
+    }
+    return a;
+}
+// first factor A of a coprime split L = A B (the power of 2, else of 3, in L), 0 if none
+constexpr int pfa_factor(int L) {
+    return (ct_part(L, 2) > 1 && ct_part(L, 2) < L) ? ct_part(L, 2)
+           : (ct_part(L, 3) > 1 && ct_part(L, 3) < L) ? ct_part(L, 3) : 0;
+}
+constexpr int ct_inverse(int a, int m) {   // a^-1 mod m (gcd(a, m) = 1)
+    for (int i = 1; i < m; ++i)
+        if ((a * i) % m == 1) return i;
+    return 1;
+}
 
 template <int L>
 struct Radix {
@@ -104,15 +128,15 @@ struct Radix {
                                  : (L % 3 == 0 && L != 3) ? 3 : (L % 5 == 0 && L != 5) ? 5 : L;
 };
 
-template <int L>
+template <int L, int A = pfa_factor(L)>
 struct DFT;
 
 template <>
-struct DFT<1> {
+struct DFT<1, 0> {
     __device__ __forceinline__ static void run(cf *) {}
 };
 template <>
-struct DFT<2> {
+struct DFT<2, 0> {
     __device__ __forceinline__ static void run(cf *x) {
         const cf a = x[0], b = x[1];
         x[0] = cadd(a, b);
@@ -120,7 +144,7 @@ struct DFT<2> {
     }
 };
 template <>
-struct DFT<3> {
+struct DFT<3, 0> {
     __device__ __forceinline__ static void run(cf *x) {
         const float s = 0.86602540378443864676f;   // sin(2 pi / 3)
         const cf a = cadd(x[1], x[2]), b = csub(x[1], x[2]);
@@ -132,7 +156,7 @@ struct DFT<3> {
     }
 };
 template <>
-struct DFT<4> {
+struct DFT<4, 0> {
     __device__ __forceinline__ static void run(cf *x) {
         const cf a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
         const cf c = cadd(x[1], x[3]), d = mul_mi(csub(x[1], x[3]));
@@ -143,7 +167,7 @@ struct DFT<4> {
     }
 };
 template <>
-struct DFT<5> {
+struct DFT<5, 0> {
     __device__ __forceinline__ static void run(cf *x) {
         constexpr CtCis w1 = ct_cis(1, 5), w2 = ct_cis(2, 5);
         const float c1 = (float)w1.c, s1 = (float)w1.s, c2 = (float)w2.c, s2 = (float)w2.s;
@@ -162,9 +186,38 @@ struct DFT<5> {
     }
 };
 
-// composite: L = R m, decimation in time
-template <int L>
+// Good-Thomas, L = A B with gcd(A, B) = 1: input n = (B a + A b) mod L, then B-point DFTs over
+// b for each a, then A-point DFTs over a for each output index kb; output k is the residue
+// pair (ka, kb) by the Chinese remainder theorem, k = (ka eA + kb eB) mod L.
+template <int L, int A>
 struct DFT {
+    static constexpr int B = L / A;
+    static constexpr int eA = B * ct_inverse(B % A, A);   // = 1 mod A, 0 mod B
+    static constexpr int eB = A * ct_inverse(A % B, B);   // = 0 mod A, 1 mod B
+    static_assert(A * B == L && A > 1 && B > 1, "coprime split");
+    __device__ __forceinline__ static void run(cf *x) {
+        cf t[A][B];
+#pragma unroll
+        for (int a = 0; a < A; ++a)
+#pragma unroll
+            for (int b = 0; b < B; ++b) t[a][b] = x[(B * a + A * b) % L];
+#pragma unroll
+        for (int a = 0; a < A; ++a) DFT<B>::run(t[a]);
+#pragma unroll
+        for (int kb = 0; kb < B; ++kb) {
+            cf u[A];
+#pragma unroll
+            for (int a = 0; a < A; ++a) u[a] = t[a][kb];
+            DFT<A>::run(u);
+#pragma unroll
+            for (int ka = 0; ka < A; ++ka) x[(ka * eA + kb * eB) % L] = u[ka];
+        }
+    }
+};
+
+// Cooley-Tukey for prime powers: L = R m, decimation in time
+template <int L>
+struct DFT<L, 0> {
     static constexpr int R = Radix<L>::value;
     static constexpr int Msub = L / R;
     static_assert(R * Msub == L && R <= 5, "DFT size must factor into 2, 3, 4, 5");
@@ -214,13 +267,15 @@ struct StftArgs {
     const int *fb_off;        // [M+1] offsets into fb_w
     int fb_nnz;
     int M, H;
-    int out_kind;
     float eps;
 };
 
-// ln from the hardware base-2 logarithm; v + eps >= eps >= the smallest normal FP32
-__device__ __forceinline__ float stft_out_map(float v, int kind, float eps) {
-    return (kind <= MELT_OUT_LOG_MAGNITUDE) ? __builtin_amdgcn_logf(v + eps) * 0.693147180559945309f : v;
+// output map of kind KIND (a melt_output); ln from the hardware base-2 logarithm, whose
+// argument v + eps >= eps is a normal FP32 number
+template <int KIND>
+__device__ __forceinline__ float stft_out_map(float v, float eps) {
+    if constexpr (KIND <= MELT_OUT_LOG_MAGNITUDE) return __builtin_amdgcn_logf(v + eps) * 0.693147180559945309f;
+    else return v;
 }
 
 // Orders this wave's LDS traffic: everything before is complete and visible to every lane
@@ -233,9 +288,13 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // One wave owns FPW = 64 / TPF complex FFTs (2 FPW frames) per sub-task and runs the whole
-// pipeline for them with wave-local LDS only; a chunk is SUB sub-tasks; the workgroup's
-// waves take chunks independently (persistent loop over the chunk table).
-template <int N1, int N2, int WAVES, int SUB, int WPE>
+// pipeline for them with wave-local LDS only; a chunk is up to SUB sub-tasks; the workgroup's
+// waves take chunks independently (persistent loop over the chunk table).  The wave index,
+// chunk and sub-task are wave-uniform (scalar registers), so the waveform is read through a
+// buffer descriptor held in scalar registers whose bound zero-fills reads past the clip.
+// The samples of the next sub-task are loaded during the current one's power and filter
+// passes when PREFETCH (their registers fit beside those passes).
+template <int N1, int N2, int WAVES, int SUB, int WPE, int KIND>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WPE))) void k_stft_mel(StftArgs a) {
     constexpr int N = N1 * N2;
     constexpr int NB = N / 2 + 1;
@@ -243,35 +302,45 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WPE)
     constexpr int FPW = 64 / TPF;                 // FFTs per wave per sub-task
     constexpr int LDB = N2 + 1;                   // padded row of the [k1][n2] layout
     constexpr int BUF = (N1 * LDB > N ? N1 * LDB : N);
+    constexpr int JT = (NB + 63) / 64;            // bins per lane in the power pass
+    constexpr bool MAG = (KIND == MELT_OUT_LOG_MAGNITUDE || KIND == MELT_OUT_MAGNITUDE);
+    constexpr bool PREFETCH = N1 * N2 < 1200 && N1 != 20;
+    static_assert(2 * NB <= 2 * BUF, "power spectra must fit in the FFT rows");
     extern __shared__ float smem[];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    constexpr int PB = 2 * FPW * NB;              // floats of one wave's power spectra
-    cf *tw = reinterpret_cast<cf *>(smem);                            // [N1][N2]: exp(-2 pi i n2 k1 / N)
-    float *wl = reinterpret_cast<float *>(tw + N);                    // [N] window
-    float *fbw = wl + N;                                              // [nnz]
-    int *fbs = reinterpret_cast<int *>(fbw + a.fb_nnz);               // [M]
-    int *fbo = fbs + a.M;                                             // [M+1]
-    cf *buf = reinterpret_cast<cf *>(fbo + a.M + 2) + wid * FPW * BUF;   // this wave's FFT rows
-    // each wave's 2 FPW power spectra [2 FPW][NB], written over its FFT rows once they are read
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // LDS: twiddles [N1][N2] and every wave's FFT rows (8-byte values first), then the window,
+    // the filter weights (pre-scaled, see below), first bins and offsets
+    cf *tw = reinterpret_cast<cf *>(smem);
+    cf *buf = tw + N + wid * FPW * BUF;
+    float *wl = reinterpret_cast<float *>(tw + N + WAVES * FPW * BUF);
+    float *fbw = wl + N;
+    int *fbs = reinterpret_cast<int *>(fbw + a.fb_nnz);
+    int *fbo = fbs + a.M;
+    // the wave's 2 FPW power spectra [2 FPW][NB] are written over its FFT rows once read
     float *pw = reinterpret_cast<float *>(buf);
-    static_assert(PB * 4 <= FPW * BUF * 8, "power spectra must fit in the FFT rows");
     for (int i = threadIdx.x; i < N; i += 64 * WAVES) {
         const int k1 = i / N2, n2 = i - k1 * N2;
         const float2 t = a.twiddle[(n2 * k1) % N];
         tw[i] = cf{t.x, t.y};
+        wl[i] = a.window[i];
     }
-    for (int i = threadIdx.x; i < N; i += 64 * WAVES) wl[i] = a.window[i];
-    for (int i = threadIdx.x; i < a.fb_nnz; i += 64 * WAVES) fbw[i] = a.fb_w[i];
+    // The spectra below are 4 |X_k|^2 (2 |X_k| for the magnitude kinds): the halving of the
+    // two-for-one separation moves into the weights, exactly (a power of two).
+    for (int i = threadIdx.x; i < a.fb_nnz; i += 64 * WAVES) fbw[i] = a.fb_w[i] * (MAG ? 0.5f : 0.25f);
     for (int i = threadIdx.x; i < a.M; i += 64 * WAVES) fbs[i] = a.fb_start[i];
     for (int i = threadIdx.x; i <= a.M; i += 64 * WAVES) fbo[i] = a.fb_off[i];
     __syncthreads();
 
-    const bool mag = (a.out_kind == MELT_OUT_LOG_MAGNITUDE || a.out_kind == MELT_OUT_MAGNITUDE);
     const int p1 = lane / TPF, n2 = lane - p1 * TPF;                  // step-1 role
     const bool act1 = p1 < FPW && n2 < N2;
+    const int p3 = lane / TPF, k1 = lane - p3 * TPF;                  // step-3 role
+    const bool act3 = p3 < FPW && k1 < N1;
 
     const int nch = *a.n_chunks;
-    const int gw = blockIdx.x * WAVES + wid, nw = gridDim.x * WAVES;
+    const int nw = gridDim.x * WAVES;
+    int c = blockIdx.x * WAVES + wid;
+    if (c >= nch) return;
     // samples of one sub-task for this lane: frames 2 p1 and 2 p1 + 1 at points N2 n1 + n2
     float xa[N1], xb[N1];
     auto load = [&](const Chunk &ch, int sub) {
@@ -287,22 +356,23 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WPE)
             xb[n1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vb, N2 * n1 * 4, 0));
         }
     };
-    int c = gw;
-    Chunk ch;
-    if (c < nch) ch = a.chunks[c];
+    Chunk ch = a.chunks[c];
     int sub = 0;
-    while (c < nch) {
+    if (PREFETCH) load(ch, 0);
+    for (;;) {
         const Chunk cur = ch;
         const int cur_sub = sub;
-        load(cur, cur_sub);
+        if (!PREFETCH) load(cur, cur_sub);
         // advance to the next sub-task (this chunk or the wave's next chunk)
         ++sub;
+        bool more = true;
         if (2 * FPW * sub >= cur.n_frames || sub >= SUB) {
             sub = 0;
             c += nw;
-            if (c < nch) ch = a.chunks[c];
+            more = c < nch;
+            if (more) ch = a.chunks[c];
         }
-        // step 1: N1-point DFTs over n1, four-step twiddle, store as [k1][n2]
+        // step 1: window, N1-point DFTs over n1, four-step twiddle, store as [k1][n2]
         cf z[N1];
 #pragma unroll
         for (int n1 = 0; n1 < N1; ++n1) {
@@ -310,16 +380,14 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WPE)
             z[n1] = cf{xa[n1] * wv, xb[n1] * wv};
         }
         DFT<N1>::run(z);
-        cf *row1 = buf + p1 * BUF;
         if (act1) {
+            cf *row1 = buf + p1 * BUF + n2;
 #pragma unroll
-            for (int k1 = 0; k1 < N1; ++k1) row1[k1 * LDB + n2] = cmul(z[k1], tw[k1 * N2 + n2]);
+            for (int q = 0; q < N1; ++q) row1[q * LDB] = cmul(z[q], tw[q * N2 + n2]);
         }
         wave_sync();
         // step 3: N2-point DFTs over n2, natural order k = k1 + N1 k2
         {
-            const int p3 = lane / TPF, k1 = lane - p3 * TPF;
-            const bool act3 = p3 < FPW && k1 < N1;
             cf y[N2];
             cf *row3 = buf + p3 * BUF;
             if (act3) {
@@ -330,102 +398,89 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WPE)
             if (act3) {
                 DFT<N2>::run(y);
 #pragma unroll
-                for (int k2 = 0; k2 < N2; ++k2) row3[k1 + N1 * k2] = y[k2];
+                for (int q = 0; q < N2; ++q) row3[k1 + N1 * q] = y[q];
             }
         }
         wave_sync();
-        const int f0 = 2 * FPW * cur_sub;
-        // step 4: separate the two real spectra of each FFT, |X_k|^2 (or |X_k|) on every bin
-        // k = 0..N/2, into pw[2 p + {0, 1}][k].  Every lane first reads all its (Z[k], Z[N-k])
-        // pairs, then the wave synchronises and the spectra are written over the FFT rows.
+        // the next sub-task's samples load during the power and filter passes
+        if (PREFETCH && more) load(ch, sub);
+        // step 4: separate the two real spectra of each FFT and form 4 |X_k|^2 (2 |X_k|) on
+        // bins k = lane + 64 j <= N/2: A = (Z[k] + conj Z[N-k]) / 2, B = (Z[k] - conj Z[N-k]) / (2i).
+        // Every value is read before the wave writes the spectra over the FFT rows.
         {
-            constexpr int IT = (FPW * NB + 63) / 64;
-            float pa[IT], pb[IT];
-            int p = 0, k = lane;                   // item lane + 64 i = p NB + k, advanced without division
+            float pa[FPW][JT], pb[FPW][JT];
 #pragma unroll
-            for (int i = 0; i < IT; ++i) {
-                while (k >= NB) {
-                    k -= NB;
-                    ++p;
-                }
-                pa[i] = pb[i] = 0.0f;
-                if (lane + 64 * i < FPW * NB) {
-                    const cf *rowz = buf + p * BUF;
-                    const cf zk = rowz[k], zn = rowz[k == 0 ? 0 : N - k];
-                    // A = (Z[k] + conj Z[N-k]) / 2,  B = (Z[k] - conj Z[N-k]) / (2i)
-                    const float ar = 0.5f * (zk.x + zn.x), ai = 0.5f * (zk.y - zn.y);
-                    const float br = 0.5f * (zk.y + zn.y), bi = -0.5f * (zk.x - zn.x);
-                    pa[i] = ar * ar + ai * ai;
-                    pb[i] = br * br + bi * bi;
-                    if (mag) {
-                        pa[i] = sqrtf(pa[i]);
-                        pb[i] = sqrtf(pb[i]);
+            for (int j = 0; j < JT; ++j) {
+                const int k = lane + 64 * j;
+                const int kn = (k == 0) ? 0 : N - k;
+#pragma unroll
+                for (int p = 0; p < FPW; ++p) {
+                    pa[p][j] = pb[p][j] = 0.0f;
+                    if (64 * j + 64 <= NB || k < NB) {
+                        const cf zk = buf[p * BUF + k], zn = buf[p * BUF + kn];
+                        const float s1 = zk.x + zn.x, s2 = zk.y - zn.y;
+                        const float s3 = zk.y + zn.y, s4 = zk.x - zn.x;
+                        pa[p][j] = s1 * s1 + s2 * s2;
+                        pb[p][j] = s3 * s3 + s4 * s4;
+                        if constexpr (MAG) {
+                            pa[p][j] = __builtin_sqrtf(pa[p][j]);
+                            pb[p][j] = __builtin_sqrtf(pb[p][j]);
+                        }
                     }
                 }
-                k += 64;
             }
-            wave_sync();                           // every FFT row read; pw may overwrite them
-            p = 0;
-            k = lane;
+            wave_sync();
 #pragma unroll
-            for (int i = 0; i < IT; ++i) {
-                while (k >= NB) {
-                    k -= NB;
-                    ++p;
+            for (int j = 0; j < JT; ++j) {
+                const int k = lane + 64 * j;
+                if (64 * j + 64 <= NB || k < NB) {
+#pragma unroll
+                    for (int p = 0; p < FPW; ++p) {
+                        pw[(2 * p) * NB + k] = pa[p][j];
+                        pw[(2 * p + 1) * NB + k] = pb[p][j];
+                    }
                 }
-                if (lane + 64 * i < FPW * NB) {
-                    pw[(2 * p) * NB + k] = pa[i];
-                    pw[(2 * p + 1) * NB + k] = pb[i];
-                }
-                k += 64;
             }
         }
         wave_sync();
-        // step 5: one lane per (Mel filter, half of the 2 FPW spectra): each weight read serves
-        // FPW spectra, bins two at a time; sums in increasing k; output map; coalesced store
+        // step 5: one lane per (Mel filter m, half h of the 2 FPW spectra), m = t / 2, so the
+        // filters of one pass over the lanes have neighbouring widths; each weight read serves
+        // FPW spectra; sums in increasing k; output map; store
         {
-            int h = 0, m = lane;                   // item lane + 64 i = h M + m
+            const int f0 = 2 * FPW * cur_sub;
             for (int t = lane; t < 2 * a.M; t += 64) {
-                while (m >= a.M) {
-                    m -= a.M;
-                    ++h;
-                }
+                const int m = t >> 1, h = t & 1;
                 const float *ps = pw + h * FPW * NB + fbs[m];
-                const int j0 = fbo[m], j1 = fbo[m + 1];
+                const int j0 = fbo[m], nj = fbo[m + 1] - j0;
+                const float *wj = fbw + j0;
                 float acc[FPW];
 #pragma unroll
                 for (int f = 0; f < FPW; ++f) acc[f] = 0.0f;
-                int j = j0;
-                for (; j + 1 < j1; j += 2) {
-                    const float w0 = fbw[j], w1 = fbw[j + 1];
-                    float p0[FPW], p1[FPW];
+                int j = 0;
+                for (; j + 1 < nj; j += 2) {
+                    const float w0 = wj[j], w1 = wj[j + 1];
 #pragma unroll
                     for (int f = 0; f < FPW; ++f) {
-                        p0[f] = ps[f * NB + (j - j0)];
-                        p1[f] = ps[f * NB + (j - j0) + 1];
-                    }
-#pragma unroll
-                    for (int f = 0; f < FPW; ++f) {
-                        acc[f] += w0 * p0[f];
-                        acc[f] += w1 * p1[f];
+                        acc[f] += w0 * ps[f * NB + j];
+                        acc[f] += w1 * ps[f * NB + j + 1];
                     }
                 }
-                if (j < j1) {
-                    const float w0 = fbw[j];
+                if (j < nj) {
+                    const float w0 = wj[j];
 #pragma unroll
-                    for (int f = 0; f < FPW; ++f) acc[f] += w0 * ps[f * NB + (j - j0)];
+                    for (int f = 0; f < FPW; ++f) acc[f] += w0 * ps[f * NB + j];
                 }
 #pragma unroll
                 for (int f = 0; f < FPW; ++f) {
                     const int fa = f0 + h * FPW + f;
                     const int64_t row = cur.out_row + fa;
                     if (fa < cur.n_frames && row < a.n_frames)
-                        a.out[row * a.M + m] = stft_out_map(acc[f], a.out_kind, a.eps);
+                        a.out[row * a.M + m] = stft_out_map<KIND>(acc[f], a.eps);
                 }
-                m += 64;
             }
         }
         wave_sync();
+        if (!more) break;
     }
 }
 
@@ -454,19 +509,31 @@ size_t stft_lds_bytes(const StftShape &s, int M, int nnz) {
     const int N = s.N1 * s.N2;
     const int LDB = s.N2 + 1;
     const int BUF = std::max(s.N1 * LDB, N);
-    const size_t head = (size_t)N * 8 + (size_t)N * 4 + (size_t)nnz * 4 + (size_t)(2 * M + 2) * 4;
-    return ((head + 7) / 8) * 8 + (size_t)kStftWaves * s.FPW * BUF * 8;   // the power spectra reuse the FFT rows
+    // twiddles and FFT rows (the power spectra reuse the rows), window, weights, starts, offsets
+    return (size_t)N * 8 + (size_t)kStftWaves * s.FPW * BUF * 8 + (size_t)N * 4 + (size_t)nnz * 4 +
+           (size_t)(2 * M + 1) * 4;
 }
 
 // waves per SIMD the kernel's registers are sized for: 3 (LDS allows three workgroups per CU),
 // 1 for the 1200-point shape (its 40-point register DFTs need the whole register file)
-template <int N1, int N2, int SUB>
-melt_status launch_shape(const StftArgs &a, size_t lds, int grid, hipStream_t s) {
+template <int N1, int N2, int SUB, int KIND>
+melt_status launch_kind(const StftArgs &a, size_t lds, int grid, hipStream_t s) {
     constexpr int WPE = (N1 * N2 >= 1200) ? 1 : 3;
-    (void)hipFuncSetAttribute((const void *)k_stft_mel<N1, N2, kStftWaves, SUB, WPE>,
+    (void)hipFuncSetAttribute((const void *)k_stft_mel<N1, N2, kStftWaves, SUB, WPE, KIND>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    k_stft_mel<N1, N2, kStftWaves, SUB, WPE><<<grid, 64 * kStftWaves, lds, s>>>(a);
+    k_stft_mel<N1, N2, kStftWaves, SUB, WPE, KIND><<<grid, 64 * kStftWaves, lds, s>>>(a);
     return hip_check(hipGetLastError(), "stft_mel launch");
+}
+
+template <int N1, int N2, int SUB>
+melt_status launch_shape(const StftArgs &a, int kind, size_t lds, int grid, hipStream_t s) {
+    switch (kind) {
+    case MELT_OUT_LOG_POWER: return launch_kind<N1, N2, SUB, MELT_OUT_LOG_POWER>(a, lds, grid, s);
+    case MELT_OUT_LOG_MAGNITUDE: return launch_kind<N1, N2, SUB, MELT_OUT_LOG_MAGNITUDE>(a, lds, grid, s);
+    case MELT_OUT_POWER: return launch_kind<N1, N2, SUB, MELT_OUT_POWER>(a, lds, grid, s);
+    case MELT_OUT_MAGNITUDE: return launch_kind<N1, N2, SUB, MELT_OUT_MAGNITUDE>(a, lds, grid, s);
+    default: return set_error(MELT_E_UNSUPPORTED, "comparator output kind");
+    }
 }
 
 }  // namespace
@@ -568,18 +635,17 @@ melt_status launch_stft_main(Plan &p, const float *d_wave, float *d_out, hipStre
     a.fb_nnz = p.fb_nnz;
     a.M = p.M;
     a.H = p.H;
-    a.out_kind = p.kern_out;
     a.eps = (float)p.cfg.log_eps;
     const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / lds)));
     const int64_t est = (n_frames / bf + p.prepared_clips[1] + kStftWaves - 1) / kStftWaves;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(est, (int64_t)p.cu_count * per_cu));
     melt_status st;
     switch (p.N) {
-    case 400: st = launch_shape<20, 20, 8>(a, lds, grid, s); break;
-    case 512: st = launch_shape<16, 32, 8>(a, lds, grid, s); break;
-    case 1024: st = launch_shape<32, 32, 8>(a, lds, grid, s); break;
-    case 256: st = launch_shape<16, 16, 8>(a, lds, grid, s); break;
-    case 1200: st = launch_shape<30, 40, 16>(a, lds, grid, s); break;
+    case 400: st = launch_shape<20, 20, 8>(a, p.kern_out, lds, grid, s); break;
+    case 512: st = launch_shape<16, 32, 8>(a, p.kern_out, lds, grid, s); break;
+    case 1024: st = launch_shape<32, 32, 8>(a, p.kern_out, lds, grid, s); break;
+    case 256: st = launch_shape<16, 16, 8>(a, p.kern_out, lds, grid, s); break;
+    case 1200: st = launch_shape<30, 40, 16>(a, p.kern_out, lds, grid, s); break;
     default: return set_error(MELT_E_UNSUPPORTED, "n_fft");
     }
     if (st != MELT_OK || p.K == 0) return st;

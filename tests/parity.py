@@ -239,8 +239,10 @@ def grad_proj_error(R, I, eR, eI, g, kind, eps, c_round=8.0):
     with np.errstate(invalid="ignore"):
         dphi = np.maximum(phi_hi - phi, phi - phi_lo)
     ag = 2.0 * np.abs(np.asarray(g, np.float64))
-    dGr = ag * (eR * phi_hi + np.abs(R) * dphi) + c_round * U32 * ag * (np.abs(R) + eR) * phi_hi
-    dGi = ag * (eI * phi_hi + np.abs(I) * dphi) + c_round * U32 * ag * (np.abs(I) + eI) * phi_hi
+    # phi_hi is infinite only where S - dS <= 0 (magnitude kinds), which is never checkable
+    with np.errstate(invalid="ignore"):
+        dGr = ag * (eR * phi_hi + np.abs(R) * dphi) + c_round * U32 * ag * (np.abs(R) + eR) * phi_hi
+        dGi = ag * (eI * phi_hi + np.abs(I) * dphi) + c_round * U32 * ag * (np.abs(I) + eI) * phi_hi
     dGr = np.where(checkable, dGr, np.inf)
     dGi = np.where(checkable, dGi, np.inf)
     return dGr, dGi, checkable
