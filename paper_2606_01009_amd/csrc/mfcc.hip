@@ -1,7 +1,9 @@
 // MFCCT (Eq. mfcct_matrix): C = ln(S + eps) D^T with D the K x M orthonormal DCT-II, and the
-// same cepstrum on the comparator's log-Mel output.  A small dense product over rows,
+// same cepstrum on the comparator's log-Mel output.  A small dense product over rows, on the
+// FP32 matrix cores where its operands fit the LDS staging, else on the vector ALUs,
 // out[r][j] = sum_i in[r][i] A[j][i], used for the forward (A = D, i = Mel bin) and for the
 // backward of the cepstrum (A = D^T, i = cepstral index: dL = dC D).
+#include <algorithm>
 #include <cmath>
 
 #include "melt_internal.h"
@@ -82,14 +84,153 @@ __global__ __launch_bounds__(256) void k_row_matmul(const float *__restrict__ in
     }
 }
 
+// The same product on the FP32 matrix cores (v_mfma_f32_16x16x4f32, FP32 products summed in
+// FP32).  Persistent workgroups of 4 waves stage the matrix once as B-operand fragments,
+//   Bf[((q 4 + e) TJ + t) 64 + lane] = A[j = 16 (jt0 + t) + (lane & 15)][i = 16 q + 4 (lane >> 4) + e],
+// zero outside J x I, then walk blocks of 64 rows: a block is staged in LDS (zero-padded to
+// QI = ceil(I / 16) groups of 16 inputs) and each wave multiplies 16 of its rows while the
+// next block's rows load into registers.  Lane (g = lane >> 4, c = lane & 15) holds inputs
+// 16 q + 4 g .. + 3 of row c, so the four lane groups of one MFMA cover inputs 16 q + e, + 4,
+// + 8, + 12 (the summation order within a group of 16 is permuted, the same for every row).
+// Each wave accumulates TJ output tiles of 16 columns; blockIdx.y selects which TJ tiles.
+// A row's outputs depend on that row only, wherever it sits in the batch.  PRE: the rows are
+// read as 16-byte vectors, at most 8 per thread per block (I <= 128), through registers.
+template <int TJ, bool PRE>
+__global__ __launch_bounds__(256) void k_row_mfma(const float *__restrict__ in, int64_t rows, int I, int J,
+                                                  const float *__restrict__ A, int sj, int si,
+                                                  float *__restrict__ out) {
+    extern __shared__ float sm[];
+    const int QI = (I + 15) >> 4;
+    const int ld = 16 * QI + 4;                    // row stride: 16-byte aligned rows
+    float *tile = sm;                              // [64][ld]
+    float *Bf = sm + 64 * ld;                      // [QI][4][TJ][64]
+    const int jt0 = blockIdx.y * TJ;
+    for (int idx = threadIdx.x; idx < QI * 4 * TJ * 64; idx += blockDim.x) {
+        const int l = idx & 63, t = (idx >> 6) % TJ, qe = (idx >> 6) / TJ;
+        const int j = 16 * (jt0 + t) + (l & 15), i = 16 * (qe >> 2) + 4 * (l >> 4) + (qe & 3);
+        Bf[idx] = (j < J && i < I) ? A[(size_t)j * sj + (size_t)i * si] : 0.0f;
+    }
+    // zero padding inputs of every row (their matrix entries are 0, but LDS may hold
+    // non-finite values); the staging below never writes them
+    const int pad = 16 * QI - I;
+    for (int e = threadIdx.x; e < 64 * pad; e += blockDim.x) {
+        const int r = e / pad;
+        tile[r * ld + I + (e - r * pad)] = 0.0f;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+    const int64_t nblk = (rows + 63) / 64;
+    int64_t blk = blockIdx.x;
+    rm_f32x4 pre[PRE ? 8 : 1];
+    auto fetch = [&](int64_t b) {              // rows of block b into registers
+        const int64_t r0 = b * 64;
+        const int n = (int)(rows - r0 < 64 ? rows - r0 : 64) * I;
+        const float *src = in + r0 * I;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = 4 * (int)threadIdx.x + 1024 * u;
+            if (e < n) pre[u] = *(const rm_f32x4 *)(src + e);
+        }
+    };
+    if (PRE && blk < nblk) fetch(blk);
+    for (; blk < nblk; blk += gridDim.x) {
+        const int64_t r0 = blk * 64;
+        const int nr = (int)(rows - r0 < 64 ? rows - r0 : 64);
+        __syncthreads();                           // the previous block's rows are consumed
+        if constexpr (PRE) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = 4 * (int)threadIdx.x + 1024 * u;
+                if (e < nr * I) {
+                    const int r = e / I, i = e - r * I;
+                    *(rm_f32x4 *)(tile + r * ld + i) = pre[u];
+                }
+            }
+            if (blk + gridDim.x < nblk) fetch(blk + gridDim.x);
+        } else {
+            const float *src = in + r0 * I;
+            for (int e = threadIdx.x; e < nr * I; e += blockDim.x) {
+                const int r = e / I, i = e - r * I;
+                tile[r * ld + i] = src[e];
+            }
+        }
+        __syncthreads();
+        if (16 * wid >= nr) continue;
+        const float *arow = tile + (16 * wid + c) * ld + 4 * g;
+        rm_f32x4 acc[TJ];
+#pragma unroll
+        for (int t = 0; t < TJ; ++t) acc[t] = rm_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int q = 0; q < QI; ++q) {
+            const rm_f32x4 a = *(const rm_f32x4 *)(arow + 16 * q);
+            const float *bq = Bf + q * 4 * TJ * 64 + lane;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int t = 0; t < TJ; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], bq[(e * TJ + t) * 64], acc[t], 0, 0, 0);
+        }
+        // lane holds rows 4 g + v of its wave's 16, column c of each tile
+#pragma unroll
+        for (int t = 0; t < TJ; ++t) {
+            const int j = 16 * (jt0 + t) + c;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = r0 + 16 * wid + 4 * g + v;
+                if (row < rows && j < J) out[row * J + j] = acc[t][v];
+            }
+        }
+    }
+}
+
+namespace {
+
+template <int TJ>
+melt_status launch_mfma(const float *in, int64_t rows, int I, int J, const float *A, int sj, int si, float *out,
+                        bool pre, size_t lds, hipStream_t s) {
+    const void *k = pre ? (const void *)k_row_mfma<TJ, true> : (const void *)k_row_mfma<TJ, false>;
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t nblk = (rows + 63) / 64;
+    const int gy = ((J + 15) / 16 + TJ - 1) / TJ;
+    // two workgroups per CU over all launch columns
+    const int64_t gx = std::max<int64_t>(1, std::min<int64_t>(nblk, (2 * (int64_t)cus + gy - 1) / gy));
+    const dim3 grid((unsigned)gx, (unsigned)gy);
+    if (pre) k_row_mfma<TJ, true><<<grid, 256, lds, s>>>(in, rows, I, J, A, sj, si, out);
+    else k_row_mfma<TJ, false><<<grid, 256, lds, s>>>(in, rows, I, J, A, sj, si, out);
+    return hip_check(hipGetLastError(), "cepstrum launch");
+}
+
+}  // namespace
+
 melt_status launch_row_matmul(const float *in, int64_t rows, int I, int J, const float *A, int sj, int si, float *out,
                               hipStream_t s) {
     if (rows <= 0) return MELT_OK;
+    const int vec = (I % 4 == 0) && (J % 4 == 0) && ((uintptr_t)in % 16 == 0) && ((uintptr_t)out % 16 == 0);
+    // matrix cores when the staged rows and at least one output tile's fragments fit 80 KB
+    // (two workgroups per CU)
+    const int QI = (I + 15) / 16, JT = (J + 15) / 16;
+    const size_t tile_bytes = (size_t)64 * (16 * QI + 4) * sizeof(float);
+    const size_t frag_bytes = (size_t)QI * 4 * 64 * sizeof(float);        // per output tile
+    const size_t budget = 80 * 1024;
+    if (tile_bytes + frag_bytes <= budget) {
+        const int tj = (int)std::min<size_t>(std::min(JT, 8), (budget - tile_bytes) / frag_bytes);
+        const size_t lds = tile_bytes + (size_t)tj * frag_bytes;
+        const bool pre = vec && I <= 128;
+        switch (tj) {
+        case 1: return launch_mfma<1>(in, rows, I, J, A, sj, si, out, pre, lds, s);
+        case 2: return launch_mfma<2>(in, rows, I, J, A, sj, si, out, pre, lds, s);
+        case 3: return launch_mfma<3>(in, rows, I, J, A, sj, si, out, pre, lds, s);
+        case 4: return launch_mfma<4>(in, rows, I, J, A, sj, si, out, pre, lds, s);
+        case 5: return launch_mfma<5>(in, rows, I, J, A, sj, si, out, pre, lds, s);
+        case 6: return launch_mfma<6>(in, rows, I, J, A, sj, si, out, pre, lds, s);
+        case 7: return launch_mfma<7>(in, rows, I, J, A, sj, si, out, pre, lds, s);
+        default: return launch_mfma<8>(in, rows, I, J, A, sj, si, out, pre, lds, s);
+        }
+    }
     const int Jp = (J + kDctJ - 1) / kDctJ * kDctJ;
     const size_t lds = ((size_t)kDctRows * (I + 1) + (size_t)I * Jp) * sizeof(float);
     if (lds > 160 * 1024) return set_error(MELT_E_UNSUPPORTED, "cepstrum input too wide");
     (void)hipFuncSetAttribute((const void *)k_row_matmul, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    const int vec = (I % 4 == 0) && (J % 4 == 0) && ((uintptr_t)in % 16 == 0) && ((uintptr_t)out % 16 == 0);
     const int64_t blocks = (rows + kDctRows - 1) / kDctRows;
     k_row_matmul<<<(unsigned)blocks, 256, lds, s>>>(in, rows, I, J, A, sj, si, out, vec);
     return hip_check(hipGetLastError(), "cepstrum launch");
