@@ -454,7 +454,8 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the sampled error check")
     ap.add_argument("--no-energy", action="store_true", help="skip the board-energy windows (amdsmi)")
     ap.add_argument("--trials", type=int, default=20, help="timing trials per path (median + bootstrap 90%% CI)")
-    ap.add_argument("--only", default=None, help="time one path only: fp32|bf16|fp16|bf16x3|fp8|stft|copy (profiling)")
+    ap.add_argument("--only", default=None,
+                    help="time one path only: fp32|bf16|fp16|bf16x3|fp16x3|fp8|stft|copy (profiling)")
     ap.add_argument("--sweep", action="store_true", help="time every kernel variant of every precision and exit")
     ap.add_argument("--write-traffic", default=None, metavar="PMC_DIR",
                     help="write the committed traffic summary of the FP32 kernel from rocprofv3 --pmc runs "
@@ -521,10 +522,11 @@ def main():
             res["trials"] = trial_stats(torch, step, args.steps, args.trials)
             if meter is not None:
                 res["energy"] = energy_per_call(meter, torch, step, res["trials"]["median_ms"], idle[0], T)
-        # the bound of each precision: FP32 and split-BF16x3 (three products per term) are
-        # MFMA-bound, the others HBM-bound (the waveform read once and the output written once)
-        if prec in ("fp32", "bf16x3"):
-            work = T * flop_per_frame * (3 if prec == "bf16x3" else 1)
+        # the bound of each precision: FP32 and the split 16-bit products (three products per
+        # term) are MFMA-bound, the others HBM-bound (the waveform read once and the output
+        # written once)
+        if prec in ("fp32", "bf16x3", "fp16x3"):
+            work = T * flop_per_frame * (1 if prec == "fp32" else 3)
             peak = PEAK["f32"] if prec == "fp32" else PEAK["bf16"]
             res["roofline"] = {"bound": "mfma", "frac": work / (kern_ms * 1e-3) / peak}
         else:
@@ -562,7 +564,7 @@ def main():
         return 0
 
     if args.sweep:
-        for prec in ("fp32", "bf16", "fp16", "bf16x3", "fp8"):
+        for prec in ("fp32", "bf16", "fp16", "bf16x3", "fp16x3", "fp8"):
             plan = melt.MeltPlan(sample_rate=16000.0, n_fft=400, hop=160, n_mels=M, precision=prec)
             desc = melt.melt_autotune(plan.handle, T)
             log(f"bench: autotune {prec}: {desc}")
@@ -587,7 +589,7 @@ def main():
     comparator = run_stft()
     variants = {}
     if not args.no_variants:
-        for prec in ("bf16x3", "bf16", "fp16", "fp8"):
+        for prec in ("fp16x3", "bf16x3", "bf16", "fp16", "fp8"):
             try:
                 variants[prec] = run_melt(prec)[0]
             except melt.MeltError as e:

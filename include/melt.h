@@ -81,9 +81,17 @@ typedef enum {
  *   FP16     - binary16 operands
  *   FP8_E4M3 - OCP E4M3 operands; each frame scaled by 448 / max|x_t| and each basis row by
  *              448 / max|row| before rounding, undone in FP32 after the product
- *   BF16X3   - split-bfloat16 compensated product xh*Wh + xh*Wl + xl*Wh */
+ *   BF16X3   - split-bfloat16 compensated product xh*Wh + xh*Wl + xl*Wh: two 8-bit
+ *              significands per operand, about 17 significant bits per product term
+ *   FP16X3   - split-binary16 compensated product xh*Wh + xh*Wl + xl*Wh, products exact in
+ *              FP32: two 11-bit significands per operand, about 22 significant bits per term
+ *              (FP32-level).  The waveform is pre-scaled by 2^10 (exact) so that the low parts
+ *              of quiet samples stay normal; the scale is undone on the FP32 projections.
+ *              Samples must satisfy |x| < 63.9 (2^10 |x| within binary16's range); a
+ *              larger sample overflows and the frames that contain it come out non-finite. */
 typedef enum {
-    MELT_PREC_FP32 = 0, MELT_PREC_BF16 = 1, MELT_PREC_FP16 = 2, MELT_PREC_FP8_E4M3 = 3, MELT_PREC_BF16X3 = 4
+    MELT_PREC_FP32 = 0, MELT_PREC_BF16 = 1, MELT_PREC_FP16 = 2, MELT_PREC_FP8_E4M3 = 3, MELT_PREC_BF16X3 = 4,
+    MELT_PREC_FP16X3 = 5
 } melt_precision;
 
 /* Frontend parameters (Experiments, Table "Audio frontend configuration": 16 kHz,

@@ -32,7 +32,7 @@ WIN_HANN_SYMMETRIC, WIN_HANN_PERIODIC, WIN_RECT = 0, 1, 2
 MEL_HTK, MEL_SLANEY = 0, 1
 PLACE_FILTER_CENTRES, PLACE_LINSPACE = 0, 1
 NORM_NONE, NORM_SLANEY = 0, 1
-PREC_FP32, PREC_BF16, PREC_FP16, PREC_FP8_E4M3, PREC_BF16X3 = 0, 1, 2, 3, 4
+PREC_FP32, PREC_BF16, PREC_FP16, PREC_FP8_E4M3, PREC_BF16X3, PREC_FP16X3 = 0, 1, 2, 3, 4, 5
 
 
 def build(force: bool = False) -> Path:

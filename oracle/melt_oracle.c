@@ -495,6 +495,9 @@ double oracle_round_e4m3(float x)
  *       by s_t r_j.  A silent frame (max 0) uses s_t = 1.
  *   prec 4 (BF16x3): x = xh + xl, W = Wh + Wl with xh = bf16(x), xl = bf16(x - xh) (FP32
  *       difference, exact) and the same for W; the product is xh Wh + xh Wl + xl Wh.
+ *   prec 5 (FP16x3): as prec 4 with binary16 parts, the frame samples first multiplied by
+ *       2^10 in FP32 (exact) and the product sum divided by 2^10; a sample whose scaled
+ *       value exceeds binary16's range becomes infinite.
  * Wr, Wi are the FP64 basis; out / R / I as in oracle_melt_forward_basis.  Returns T. */
 int64_t oracle_melt_forward_quant(const float *wave, const int64_t *clip_off, int n_clips,
                                   int n_fft, int hop, const double *Wr, const double *Wi,
@@ -523,6 +526,7 @@ int64_t oracle_melt_forward_quant(const float *wave, const int64_t *clip_off, in
             if (prec == 1) h = oracle_round_bf16(v);
             else if (prec == 2) h = oracle_round_fp16(v);
             else if (prec == 3) { volatile float vs = v * rs[j]; h = oracle_round_e4m3(vs); }
+            else if (prec == 5) { h = oracle_round_fp16(v); l = oracle_round_fp16((float)(v - (float)h)); }
             else { h = oracle_round_bf16(v); l = oracle_round_bf16((float)(v - (float)h)); }
             Bh[(size_t)j * n_fft + n] = h;
             Bl[(size_t)j * n_fft + n] = l;
@@ -547,6 +551,11 @@ int64_t oracle_melt_forward_quant(const float *wave, const int64_t *clip_off, in
                 if (prec == 1) { xh[n] = oracle_round_bf16(v); xl[n] = 0.0; }
                 else if (prec == 2) { xh[n] = oracle_round_fp16(v); xl[n] = 0.0; }
                 else if (prec == 3) { volatile float vs = v * s_t; xh[n] = oracle_round_e4m3(vs); xl[n] = 0.0; }
+                else if (prec == 5) {
+                    volatile float vs = v * 1024.0f;
+                    xh[n] = oracle_round_fp16(vs);
+                    xl[n] = isfinite(xh[n]) ? oracle_round_fp16((float)(vs - (float)xh[n])) : 0.0;
+                }
                 else { xh[n] = oracle_round_bf16(v); xl[n] = oracle_round_bf16((float)(v - (float)xh[n])); }
             }
             for (int m = 0; m < n_freq; ++m) {
@@ -557,9 +566,10 @@ int64_t oracle_melt_forward_quant(const float *wave, const int64_t *clip_off, in
                     double a = 0.0;
                     for (int n = 0; n < n_fft; ++n) {
                         a += xh[n] * bh[n];
-                        if (prec == 4) a += xh[n] * bl[n] + xl[n] * bh[n];
+                        if (prec >= 4) a += xh[n] * bl[n] + xl[n] * bh[n];
                     }
                     if (prec == 3) a /= (double)s_t * (double)rs[j];
+                    if (prec == 5) a /= 1024.0;
                     acc[h] = a;
                 }
                 out[t * n_freq + m] = output_map(acc[0] * acc[0] + acc[1] * acc[1], out_kind, eps);

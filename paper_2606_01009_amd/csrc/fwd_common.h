@@ -74,6 +74,7 @@ __device__ inline unsigned short f32_to_f16_bits(float x) {
 __device__ inline float bf16_bits_to_f32(unsigned short u) {
     return __builtin_bit_cast(float, (unsigned)u << 16);
 }
+__device__ inline float f16_bits_to_f32(unsigned short u) { return (float)__builtin_bit_cast(_Float16, u); }
 
 // four FP32 values -> four E4M3 bytes (round to nearest even, saturating)
 __device__ __forceinline__ unsigned fp8x4(float a, float b, float c, float d) {
@@ -113,6 +114,7 @@ struct FwdArgs {
     int out_kind;
     float eps;
     float invH;            // 1 / H rounded to FP32 (row index of a span position)
+    float acc_scale;       // multiplies the accumulated projections (exact power of two; 1 unless FP16X3)
 };
 
 // Chunk descriptors of a persistent workgroup's iterations, staged in LDS.  Reading each
@@ -182,8 +184,13 @@ __device__ __forceinline__ void map8(const f32x16 &acc, int kind, float eps, flo
 // `f_local` of the chunk).  Register pairs (4g, 4g+1), (4g+2, 4g+3) are (R, I) of Mel bins
 // 8h + 2g and 8h + 2g + 1 of the tile.
 __device__ inline void store_tile(const FwdArgs &a, const Chunk &ch, int rt, int f_local, int lane,
-                                  const f32x16 &acc) {
+                                  const f32x16 &acc_in) {
     if (f_local >= ch.n_frames) return;
+    f32x16 acc = acc_in;
+    if (a.acc_scale != 1.0f) {          // FP16X3: undo the waveform's pre-scale (exact)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[e] *= a.acc_scale;
+    }
     const int64_t row = ch.out_row + f_local;
     if (row >= a.n_frames) return;
     const int h = lane >> 5;
@@ -261,6 +268,26 @@ struct ConvBF16X3 {
         const float r2 = v[2] - __builtin_bit_cast(float, h23 << 16), r3 = v[3] - __builtin_bit_cast(float, h23 & 0xffff0000u);
         *(uint2 *)(l + i) = uint2{h01, h23};
         *(uint2 *)(l + i + lo_off) = uint2{pk_bf16(r0, r1), pk_bf16(r2, r3)};
+    }
+};
+
+// split-binary16 of the waveform pre-scaled by 2^10 (exact): the high part at [i], the low part
+// (the FP32 residual, exact, rounded to binary16) at [i + lo_off]
+struct ConvF16X3 {
+    typedef unsigned short elem_t;
+    __device__ static void store(unsigned short *l, int i, float v, int lo_off) {
+        const float u = v * kF16x3Scale;
+        const unsigned short hb = f32_to_f16_bits(u);
+        l[i] = hb;
+        l[i + lo_off] = f32_to_f16_bits(u - f16_bits_to_f32(hb));
+    }
+    __device__ static void store4(unsigned short *l, int i, f32x4 v, int lo_off) {
+        const f32x4 u = v * kF16x3Scale;
+        const unsigned h01 = pk_f16(u[0], u[1]), h23 = pk_f16(u[2], u[3]);
+        const cv_f32x2 b01 = __builtin_convertvector(__builtin_bit_cast(cv_f16x2, h01), cv_f32x2);
+        const cv_f32x2 b23 = __builtin_convertvector(__builtin_bit_cast(cv_f16x2, h23), cv_f32x2);
+        *(uint2 *)(l + i) = uint2{h01, h23};
+        *(uint2 *)(l + i + lo_off) = uint2{pk_f16(u[0] - b01[0], u[1] - b01[1]), pk_f16(u[2] - b23[0], u[3] - b23[1])};
     }
 };
 
@@ -581,6 +608,7 @@ inline FwdArgs make_args(const Plan &p, const Geometry &g, int S, const FwdTask 
     a.out_kind = p.kern_out;
     a.eps = (float)p.cfg.log_eps;
     a.invH = (float)(1.0 / p.H);
+    a.acc_scale = p.cfg.precision == MELT_PREC_FP16X3 ? 1.0f / kF16x3Scale : 1.0f;
     return a;
 }
 
@@ -604,7 +632,7 @@ inline bool as_fits(const Plan &p) { return rs_supported(p.geo16.n_groups); }
 
 // LDS of the direct-to-LDS 16-bit kernel: operand rows, then the FP32 span scratch (16-byte aligned)
 inline size_t as_rows_bytes(const Plan &p, int bf) {
-    const bool x3 = p.cfg.precision == MELT_PREC_BF16X3;
+    const bool x3 = prec_split(p);
     return (size_t)(bf + p.geo16.J - 1) * lds_stride(p.geo16.Hp, 2) * 2 * (x3 ? 2 : 1);
 }
 // ... then nbuf FP32 spans the chunks' copies land in (each 16-byte aligned)

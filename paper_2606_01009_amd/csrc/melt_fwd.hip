@@ -131,7 +131,8 @@ __global__ void k_pack_f32(const float *__restrict__ b32, int M, int N, int H, c
     }
 }
 
-// 16-bit pack: [rt][group][lane][8]; kind 0 = bf16, 1 = fp16, 2 = bf16 low part of the split
+// 16-bit pack: [rt][group][lane][8]; kind 0 = bf16, 1 = fp16, 2 = bf16 low part of the split,
+// 3 = fp16 low part of the split
 __global__ void k_pack_h16(const float *__restrict__ b32, int M, int N, int H, const int *__restrict__ seg,
                            const int *__restrict__ col, int NG, int RT, int kind, unsigned short *__restrict__ out) {
     const int64_t total = (int64_t)RT * NG * 64 * 8;
@@ -146,6 +147,9 @@ __global__ void k_pack_h16(const float *__restrict__ b32, int M, int N, int H, c
             r = f32_to_bf16_bits(v);
         } else if (kind == 1) {
             r = f32_to_f16_bits(v);
+        } else if (kind == 3) {
+            const float hi = f16_bits_to_f32(f32_to_f16_bits(v));
+            r = f32_to_f16_bits(v - hi);
         } else {
             const float hi = bf16_bits_to_f32(f32_to_bf16_bits(v));
             r = f32_to_bf16_bits(v - hi);
@@ -229,12 +233,12 @@ melt_status pack_basis(Plan &p, hipStream_t s) {
         k_pack_f8<<<RT, 256, 0, s>>>(p.d_basis32, p.M, p.N, (p.N + 63) / 64, (unsigned *)p.d_pack_f8, p.d_rowscale);
         break;
     default: {
-        const int kind_hi = (p.cfg.precision == MELT_PREC_FP16) ? 1 : 0;
+        const int kind_hi = prec_f16(p) ? 1 : 0;
         k_pack_h16<<<256, 256, 0, s>>>(p.d_basis32, p.M, p.N, p.H, p.d_seg16, p.d_col16, p.geo16.n_groups, RT, kind_hi,
                                        (unsigned short *)p.d_pack_h16);
-        if (p.cfg.precision == MELT_PREC_BF16X3)
-            k_pack_h16<<<256, 256, 0, s>>>(p.d_basis32, p.M, p.N, p.H, p.d_seg16, p.d_col16, p.geo16.n_groups, RT, 2,
-                                           (unsigned short *)p.d_pack_lo);
+        if (prec_split(p))
+            k_pack_h16<<<256, 256, 0, s>>>(p.d_basis32, p.M, p.N, p.H, p.d_seg16, p.d_col16, p.geo16.n_groups, RT,
+                                           kind_hi == 1 ? 3 : 2, (unsigned short *)p.d_pack_lo);
     }
     }
     const melt_status st = hip_check(hipGetLastError(), "pack basis");
@@ -291,7 +295,7 @@ melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H
 //              chunks; then two span buffers), producer/consumer row-split (one span, then
 //              two; only with producer waves), row-split with register staging, frame-split
 //              (the only one when the frame is too long for a register tile)
-//   BF16X3     the same, with one-span chunks of 96 then 64 frames
+//   BF16X3 / FP16X3  the same, with one-span chunks of 96 then 64 frames
 //   FP8        row-split with direct-to-LDS staging (the largest chunk that fits LDS),
 //              row-split with register staging
 enum VariantKind { V_F32_WS, V_F32_FS, V_H16_PP, V_H16_AS, V_H16_RS, V_H16_KS, V_H16_FS, V_F8_AS, V_F8_RS };
@@ -317,7 +321,7 @@ static std::vector<Variant> variant_list(const Plan &p) {
         v.push_back({V_F8_RS, kBF32});
         break;
     default: {
-        const bool x3 = p.cfg.precision == MELT_PREC_BF16X3;
+        const bool x3 = prec_split(p);
         if (as_fits(p)) {
             // one span buffer (128 then 64 frames per chunk; 96 then 64 for BF16X3), then two
             for (int bf : {128, 96, 64}) {

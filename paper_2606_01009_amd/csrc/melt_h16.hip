@@ -10,7 +10,8 @@ namespace melt {
 // NS k-groups of 16, one v_mfma_f32_32x32x16 per tile and group.  The frame fragments are
 // read D groups ahead into a ring of registers, and scheduling barriers keep each group's
 // reads above the multiplies they overlap, so LDS latency hides behind D groups of MFMAs.
-// X3 adds hi*lo + lo*hi products from the low parts (basis in Al, frames at lo_off).  D is
+// X3 adds hi*lo + lo*hi products from the low parts (basis in Al, frames at lo_off), in
+// bfloat16 or binary16 as the operands.  D is
 // the depth of the fragment ring (a shallower ring frees registers for a longer basis tile).
 template <int NS, bool X3, bool IS_F16, int D = (X3 ? 1 : 4)>
 __device__ __forceinline__ void mfma_sweep(const uint4 (&A)[NS], const uint4 (&Al)[X3 ? NS : 1],
@@ -36,6 +37,13 @@ __device__ __forceinline__ void mfma_sweep(const uint4 (&A)[NS], const uint4 (&A
             const f16x8 av = __builtin_bit_cast(f16x8, A[s]);
             acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, __builtin_bit_cast(f16x8, b0[slot]), acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, __builtin_bit_cast(f16x8, b1[slot]), acc1, 0, 0, 0);
+            if constexpr (X3) {
+                const f16x8 al = __builtin_bit_cast(f16x8, Al[s]);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, __builtin_bit_cast(f16x8, b0[slot]), acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, __builtin_bit_cast(f16x8, b1[slot]), acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, __builtin_bit_cast(f16x8, c0[slot]), acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, __builtin_bit_cast(f16x8, c1[slot]), acc1, 0, 0, 0);
+            }
         } else {
             const bf16x8 av = __builtin_bit_cast(bf16x8, A[s]);
             acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, b0[slot]), acc0, 0, 0, 0);
@@ -54,7 +62,7 @@ __device__ __forceinline__ void mfma_sweep(const uint4 (&A)[NS], const uint4 (&A
 }
 
 // Sweep over one 32-frame tile into one accumulator (back-to-back MFMAs on the same
-// accumulator forward their result).  X3: hi*hi, lo*hi and hi*lo per k-group, which keeps
+// accumulator forward their result).  X3 (split bfloat16 or binary16): hi*hi, lo*hi and hi*lo per k-group, which keeps
 // the hi and lo basis tiles (8 NS VGPRs) beside a single tile's 16 accumulators.
 template <int NS, bool X3, bool IS_F16>
 __device__ __forceinline__ void mfma_sweep1(const uint4 (&A)[NS], const uint4 (&Al)[X3 ? NS : 1],
@@ -74,8 +82,13 @@ __device__ __forceinline__ void mfma_sweep1(const uint4 (&A)[NS], const uint4 (&
         const int slot = s % D;
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (IS_F16) {
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, A[s]),
-                                                         __builtin_bit_cast(f16x8, b[slot]), acc, 0, 0, 0);
+            const f16x8 ah = __builtin_bit_cast(f16x8, A[s]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, __builtin_bit_cast(f16x8, b[slot]), acc, 0, 0, 0);
+            if constexpr (X3) {
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, Al[s]),
+                                                             __builtin_bit_cast(f16x8, b[slot]), acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, __builtin_bit_cast(f16x8, c[slot]), acc, 0, 0, 0);
+            }
         } else {
             const bf16x8 ah = __builtin_bit_cast(bf16x8, A[s]);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, __builtin_bit_cast(bf16x8, b[slot]), acc, 0, 0, 0);
@@ -680,8 +693,8 @@ melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf, int
     const int prec = p.cfg.precision;
     const Geometry &g = p.geo16;
     const int S = lds_stride(g.Hp, 2);
-    const bool f16 = prec == MELT_PREC_FP16;
-    const bool x3 = prec == MELT_PREC_BF16X3;
+    const bool f16 = prec_f16(p);
+    const bool x3 = prec_split(p);
     if (g.n_groups > 512) return set_error(MELT_E_UNSUPPORTED, "frame too long");
     const FwdArgs a = make_args(p, g, S, t);
     const GroupTableBig gt = make_table(g, S);
@@ -696,6 +709,7 @@ melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf, int
         const int per_cu = std::min(std::max(1, (int)(kMaxLds / (lds + kRingBytes))), 2);
         const int per_group = (int)std::max<int64_t>(1, std::min<int64_t>(t.est_chunks, ((int64_t)p.cu_count * per_cu + rg - 1) / rg));
         const int grid = per_group * rg;
+        if (x3 && f16) return launch_as<ConvF16X3, true, true>(p, a, gt, lds, grid, bf, sb, s);
         if (x3) return launch_as<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, sb, s);
         if (f16) return launch_as<ConvF16, false, true>(p, a, gt, lds, grid, bf, sb, s);
         return launch_as<ConvBF16, false, false>(p, a, gt, lds, grid, bf, sb, s);
@@ -708,6 +722,7 @@ melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf, int
         const int rg = row_groups(p);
         const int per_group = (int)std::max<int64_t>(1, std::min<int64_t>(t.est_chunks, ((int64_t)p.cu_count + rg - 1) / rg));
         const int grid = per_group * rg;
+        if (x3 && f16) return launch_pp<ConvF16X3, true, true>(p, a, gt, lds, grid, bf, nbuf, s);
         if (x3) return launch_pp<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, nbuf, s);
         if (f16) return launch_pp<ConvF16, false, true>(p, a, gt, lds, grid, bf, nbuf, s);
         return launch_pp<ConvBF16, false, false>(p, a, gt, lds, grid, bf, nbuf, s);
@@ -727,11 +742,12 @@ melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf, int
         const size_t lds = (size_t)(bf + g.J - 1) * S * 2 * (x3 ? 2 : 1);
         if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
         const int grid = persistent_grid(p, t.est_chunks, std::min(std::max(1, (int)(kMaxLds / lds)), 2));
+        if (x3 && f16) return launch_rs<ConvF16X3, true, true>(p, a, gt, lds, grid, bf, s);
         if (x3) return launch_rs<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, s);
         if (f16) return launch_rs<ConvF16, false, true>(p, a, gt, lds, grid, bf, s);
         return launch_rs<ConvBF16, false, false>(p, a, gt, lds, grid, bf, s);
     }
-    if (x3) return set_error(MELT_E_UNSUPPORTED, "BF16X3 needs the register-tile kernel (frame too long)");
+    if (x3) return set_error(MELT_E_UNSUPPORTED, "split 16-bit precisions need the register-tile kernel (frame too long)");
     const size_t lds = (size_t)(kBF32 + g.J - 1) * S * 2;
     if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
     const int grid = persistent_grid(p, t.est_chunks, 2);

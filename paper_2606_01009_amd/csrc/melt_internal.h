@@ -98,6 +98,17 @@ struct Plan {
     std::string last_tune;
 };
 
+// compensated (split) 16-bit precisions: a high and a low part per operand, three products
+inline bool prec_split(const Plan &p) {
+    return p.cfg.precision == MELT_PREC_BF16X3 || p.cfg.precision == MELT_PREC_FP16X3;
+}
+// 16-bit precisions whose operands are binary16
+inline bool prec_f16(const Plan &p) {
+    return p.cfg.precision == MELT_PREC_FP16 || p.cfg.precision == MELT_PREC_FP16X3;
+}
+// exact power-of-two pre-scale of the waveform under FP16X3 (keeps the low parts normal)
+constexpr float kF16x3Scale = 1024.0f;
+
 // status plumbing (capi.cpp)
 melt_status set_error(melt_status s, const std::string &msg);
 melt_status hip_check(hipError_t e, const char *what);

@@ -30,7 +30,7 @@ def _proj(torch, plan, d_wave, d_off, T):
     return out, P
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp16x3", "fp8"])
 def test_set_basis_repacks_the_plan_precision(torch, melt, prec):
     """A basis scaled by 2 is exact in FP32, BF16, split BF16 and scaled FP8 (whose row
     scales halve exactly), so after set_basis the projections are exactly twice the original
@@ -48,7 +48,7 @@ def test_set_basis_repacks_the_plan_precision(torch, melt, prec):
     plan.set_basis(b)
     out2, P2 = _proj(torch, plan, d_wave, d_off, 98)
     torch.cuda.synchronize()
-    if prec == "fp16":
+    if prec in ("fp16", "fp16x3"):
         assert torch.allclose(P1, 2.0 * P0, rtol=1e-3, atol=1e-4 * float(P0.abs().max()))
     else:
         assert torch.equal(P1, 2.0 * P0)

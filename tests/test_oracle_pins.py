@@ -487,6 +487,53 @@ def test_quant_models_are_consistent(orc):
     assert np.median(np.abs(q8[loud] / exact[loud] - 1)) < 0.1
 
 
+def test_split_fp16_model_against_numpy_float16(orc):
+    """The split-binary16 operand model (waveform pre-scaled by 2^10, hi + lo parts of the
+    waveform and of the FP32 basis, xh Wh + xh Wl + xl Wh, unscaled) equals the same steps
+    written with numpy's IEEE binary16 casts; its error against the exact projection stays
+    within 3 2^-21 of sum |x W| (about 22 significant bits, FP32-level), at least 16 times
+    below split bfloat16's where the samples are above 1e-4; a sample beyond binary16's range after the pre-scale makes its frames
+    non-finite."""
+    N, H, sr = 400, 160, 16000.0
+    f = orc.melt_frequencies(16, 0, 8000)
+    Wr, Wi = orc.melt_basis(sr=sr, n_fft=N, freqs=f)
+    # amplitudes over 100 dB, so that low parts of quiet samples are exercised
+    x = (_frame(2400, 31) * np.repeat(10.0 ** np.linspace(-5, 0, 6), 400)).astype(np.float32)
+    off = np.array([0, x.size], np.int64)
+    _, R, I = orc.melt_forward_quant(x, off, n_fft=N, hop=H, Wr=Wr, Wi=Wi, prec=orc.PREC_FP16X3, return_ri=True)
+
+    def split(v):
+        hi = v.astype(np.float16)
+        lo = (v - hi.astype(np.float32)).astype(np.float16)
+        return hi.astype(np.float64), lo.astype(np.float64)
+
+    xs = x * np.float32(1024.0)
+    T = 1 + (x.size - N) // H
+    for W, P in ((Wr, R), (Wi, I)):
+        Wh, Wl = split(W.astype(np.float32))
+        for t in range(T):
+            xh, xl = split(xs[t * H:t * H + N])
+            terms = xh * Wh + xh * Wl + xl * Wh
+            ref = terms.sum(axis=1) / 1024.0
+            scale = np.abs(terms).sum(axis=1) / 1024.0
+            assert np.all(np.abs(P[t] - ref) <= 1e-12 * scale)
+    exact = orc.melt_forward_basis(x, off, n_fft=N, hop=H, Wr=Wr, Wi=Wi, return_ri=True)[1]
+    _, Rb, _ = orc.melt_forward_quant(x, off, n_fft=N, hop=H, Wr=Wr, Wi=Wi, prec=orc.PREC_BF16X3, return_ri=True)
+    sumabs = np.stack([np.abs(x[t * H:t * H + N].astype(np.float64)) @ np.abs(Wr).T for t in range(T)])
+    e16 = np.abs(R - exact) / sumabs
+    eb16 = np.abs(Rb - exact) / sumabs
+    assert e16.max() <= 3 * 2.0 ** -21
+    # frames from the third on hold samples of at least 1e-4 (the first straddle 1e-5, where the
+    # binary16 low parts fall below the normal range and the error nears split bfloat16's)
+    print(f"max error / sum|xW| from frame 3: split binary16 {e16[3:].max():.3g}, split bfloat16 {eb16[3:].max():.3g}")
+    assert e16[3:].max() < eb16[3:].max() / 16
+    # overflow: a sample of 64 is beyond binary16's range after the 2^10 pre-scale
+    xo = x.copy()
+    xo[500] = 64.0
+    qo = orc.melt_forward_quant(xo, off, n_fft=N, hop=H, Wr=Wr, Wi=Wi, prec=orc.PREC_FP16X3, out_kind=orc.OUT_POWER)
+    assert not np.all(np.isfinite(qo[:3])) and np.all(np.isfinite(qo[4:]))
+
+
 # ------------------------------------------------------------------ values the paper prints
 
 def test_paper_log_convention(orc):
