@@ -294,7 +294,8 @@ melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H
 //   BF16/FP16  row-split with direct-to-LDS staging (one span buffer: 128- then 64-frame
 //              chunks; then two span buffers), producer/consumer row-split (one span, then
 //              two; only with producer waves), row-split with register staging, frame-split
-//              (the only one when the frame is too long for a register tile)
+//              (the only one when the frame is too long for a register tile; for the split
+//              precisions only then)
 //   BF16X3 / FP16X3  the same, with one-span chunks of 96 then 64 frames
 //   FP8        row-split with direct-to-LDS staging (the largest chunk that fits LDS),
 //              row-split with register staging
@@ -354,7 +355,9 @@ static std::vector<Variant> variant_list(const Plan &p) {
                     v.push_back({V_H16_KS, bf});
                     break;
                 }
-        if (!x3) v.push_back({V_H16_FS, kBF32});
+        // frame-split: the fallback for every 16-bit precision (the split ones only where no
+        // register-tile kernel applies)
+        if (!x3 || v.empty()) v.push_back({V_H16_FS, kBF32});
     }
     }
     return v;

@@ -538,19 +538,22 @@ __global__ __launch_bounds__(512) void k_melt_h16_ks(FwdArgs a, const uint4 *__r
 
 // ------------------------------------------------------------------ 16-bit frame-split kernel
 // Fallback for frame lengths whose basis tile does not fit in registers: as the FP32
-// frame-split kernel, one 32x32x16 MFMA per k-group.
-template <class Conv, int RTB, bool IS_F16>
+// frame-split kernel, one 32x32x16 MFMA per k-group, the basis fragments read from L2.
+// X3 (split precisions): the frames' low parts are staged at lo_off and the basis low parts
+// streamed beside the high ones, hi*hi + lo*hi + hi*lo per k-group.
+template <class Conv, int RTB, bool IS_F16, bool X3>
 __global__ __launch_bounds__(256, 1) void k_melt_h16_fs(FwdArgs a, const uint4 *__restrict__ bpack,
-                                                        GroupTableBig gt) {
+                                                        const uint4 *__restrict__ blo, GroupTableBig gt) {
     extern __shared__ unsigned short lds16[];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int nch = *a.n_chunks;
     const int NG = gt.n;
-    zero_pad_columns<Conv>(a, kChunkF32 + a.J - 1, lds16, 256, 0);
+    const int lo_off = X3 ? a.S * (kChunkF32 + a.J - 1) : 0;
+    zero_pad_columns<Conv>(a, kChunkF32 + a.J - 1, lds16, 256, lo_off);
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         const Chunk ch = read_chunk(a.chunks, c);
         __syncthreads();
-        stage_span<Conv, 8>(a, ch, lds16, 256, 0);
+        stage_span<Conv, 8>(a, ch, lds16, 256, lo_off);
         __syncthreads();
         const int fbase = wid * 32;
         if (fbase >= ch.n_frames) continue;
@@ -560,18 +563,34 @@ __global__ __launch_bounds__(256, 1) void k_melt_h16_fs(FwdArgs a, const uint4 *
 #pragma unroll
             for (int r = 0; r < RTB; ++r) acc[r] = f32x16{};
             const uint4 *bp = bpack + (size_t)rb * NG * 64 + lane;
+            const uint4 *bl = blo + (size_t)rb * NG * 64 + lane;
             for (int g = 0; g < NG; ++g) {
                 const uint4 b = *(const uint4 *)(lp + gt.lds_off[g]);
+                uint4 bx = {};
+                if constexpr (X3) bx = *(const uint4 *)(lp + lo_off + gt.lds_off[g]);
 #pragma unroll
                 for (int r = 0; r < RTB; ++r) {
                     if (rb + r >= a.row_tiles) continue;
                     const uint4 av = bp[((size_t)r * NG + g) * 64];
-                    if constexpr (IS_F16)
-                        acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, av),
-                                                                        __builtin_bit_cast(f16x8, b), acc[r], 0, 0, 0);
-                    else
-                        acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
-                                                                         __builtin_bit_cast(bf16x8, b), acc[r], 0, 0, 0);
+                    uint4 ax = {};
+                    if constexpr (X3) ax = bl[((size_t)r * NG + g) * 64];
+                    if constexpr (IS_F16) {
+                        const f16x8 ah = __builtin_bit_cast(f16x8, av);
+                        acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, __builtin_bit_cast(f16x8, b), acc[r], 0, 0, 0);
+                        if constexpr (X3) {
+                            acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, ax),
+                                                                            __builtin_bit_cast(f16x8, b), acc[r], 0, 0, 0);
+                            acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, __builtin_bit_cast(f16x8, bx), acc[r], 0, 0, 0);
+                        }
+                    } else {
+                        const bf16x8 ah = __builtin_bit_cast(bf16x8, av);
+                        acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, __builtin_bit_cast(bf16x8, b), acc[r], 0, 0, 0);
+                        if constexpr (X3) {
+                            acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ax),
+                                                                             __builtin_bit_cast(bf16x8, b), acc[r], 0, 0, 0);
+                            acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, __builtin_bit_cast(bf16x8, bx), acc[r], 0, 0, 0);
+                        }
+                    }
                 }
             }
 #pragma unroll
@@ -583,12 +602,25 @@ __global__ __launch_bounds__(256, 1) void k_melt_h16_fs(FwdArgs a, const uint4 *
 
 // ------------------------------------------------------------------ launch
 
-template <class Conv, bool F16, int RTB>
+template <class Conv, bool F16, int RTB, bool X3 = false>
 static melt_status launch_h16fs_rtb(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid,
                                     hipStream_t s) {
-    allow_lds(k_melt_h16_fs<Conv, RTB, F16>);
-    k_melt_h16_fs<Conv, RTB, F16><<<grid, 256, lds, s>>>(a, (const uint4 *)p.d_pack_h16, gt);
+    allow_lds(k_melt_h16_fs<Conv, RTB, F16, X3>);
+    k_melt_h16_fs<Conv, RTB, F16, X3><<<grid, 256, lds, s>>>(a, (const uint4 *)p.d_pack_h16,
+                                                             (const uint4 *)p.d_pack_lo, gt);
     return hip_check(hipGetLastError(), "melt h16 fs launch");
+}
+
+// the split precisions on the frame-split kernel: four row tiles per sweep (the low-part
+// loads double the basis traffic)
+template <class Conv, bool F16>
+static melt_status launch_h16fs_x3(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid,
+                                   hipStream_t s) {
+    switch (std::min(p.row_tiles, 4)) {
+    case 1: return launch_h16fs_rtb<Conv, F16, 1, true>(p, a, gt, lds, grid, s);
+    case 2: return launch_h16fs_rtb<Conv, F16, 2, true>(p, a, gt, lds, grid, s);
+    default: return launch_h16fs_rtb<Conv, F16, 4, true>(p, a, gt, lds, grid, s);
+    }
 }
 
 template <class Conv, int NS, bool X3, bool F16>
@@ -747,10 +779,11 @@ melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf, int
         if (f16) return launch_rs<ConvF16, false, true>(p, a, gt, lds, grid, bf, s);
         return launch_rs<ConvBF16, false, false>(p, a, gt, lds, grid, bf, s);
     }
-    if (x3) return set_error(MELT_E_UNSUPPORTED, "split 16-bit precisions need the register-tile kernel (frame too long)");
-    const size_t lds = (size_t)(kBF32 + g.J - 1) * S * 2;
+    const size_t lds = (size_t)(kBF32 + g.J - 1) * S * 2 * (x3 ? 2 : 1);
     if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
     const int grid = persistent_grid(p, t.est_chunks, 2);
+    if (x3) return f16 ? launch_h16fs_x3<ConvF16X3, true>(p, a, gt, lds, grid, s)
+                       : launch_h16fs_x3<ConvBF16X3, false>(p, a, gt, lds, grid, s);
     switch (std::min(p.row_tiles, 8)) {
     case 1: return f16 ? launch_h16fs_rtb<ConvF16, true, 1>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 1>(p, a, gt, lds, grid, s);
     case 2: return f16 ? launch_h16fs_rtb<ConvF16, true, 2>(p, a, gt, lds, grid, s) : launch_h16fs_rtb<ConvBF16, false, 2>(p, a, gt, lds, grid, s);

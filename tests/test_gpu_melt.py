@@ -205,6 +205,22 @@ def test_every_kernel_variant(torch, melt, orc, prec):
             melt.melt_set_variant(plan.handle, n, 0)
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
+@pytest.mark.parametrize("geom", [(22050, 1024, 256, 128), (16000, 1200, 160, 128), (16000, 1024, 256, 40)])
+def test_split_precisions_long_frames(torch, melt, orc, prec, geom):
+    """The split precisions at frame lengths whose hi and lo basis tiles do not fit in a
+    wave's registers (N 1024: 64 k-groups, N 1200 at hop 160: 75): the frame-split kernel
+    with the basis streamed from L2, on ragged clips that end 128-frame chunks exactly, one
+    frame past them and mid-way; one to eight row tiles."""
+    sr, N, H, M = geom
+    plan = melt.MeltPlan(sample_rate=sr, n_fft=N, hop=H, n_mels=M, precision=prec)
+    assert "frame-split" in melt.melt_variant_name(plan.handle, 0)
+    lengths = [N - 1, N, (127 * H + N), (128 * H + N), (200 * H + N + 5), 3 * N + 17]
+    wave, off = workloads.random_clips(lengths, seed=N + M)
+    L, _ = _gpu_forward(torch, melt, plan, wave, off)
+    _check(orc, melt, plan, L, wave, off, prec, label=f"long frames {geom} {prec}")
+
+
 @pytest.mark.parametrize("geom", [(16000, 512, 128, 128), (22050, 1024, 256, 128), (16000, 400, 100, 40),
                                   (8000, 256, 80, 24)])
 def test_other_geometries(torch, melt, orc, geom):
