@@ -122,9 +122,11 @@ __global__ __launch_bounds__(512) void k_melt_f8_rs(FwdArgs a, const i32x8 *__re
 //
 // As k_melt_f8_rs, with the chunk's sample span copied HBM -> LDS by direct-to-LDS loads
 // (async_span) while the previous chunk multiplies.  Frame t of the chunk is span samples
-// [tH, tH + N), so each frame's maximum and E4M3 image come straight from the contiguous
-// span (no hop-block rows, no division per element), in one pass per frame.  Positions at
-// or past the valid span (clip end) count as 0.  Outputs are stored straight from the
+// [tH, tH + N): its maximum comes from 16-sample block maxima when hop and frame are whole
+// blocks, else from per-row maxima (no reduction per frame either way), and its E4M3
+// image from one flat pass over every (frame, 4-sample word) of the chunk, 16-byte reads
+// straight from the contiguous span.  Positions at or past the valid span (clip end) count
+// as 0.  Outputs are stored straight from the
 // accumulators.  Waves map to row tiles and frame tiles as in the 16-bit kernel
 // (wave_layout: one or two leftover row tiles are shared by four waves, by frame tiles).
 template <int NG>
@@ -144,6 +146,9 @@ __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__re
     constexpr int SQ = KP + 16;             // row stride (bytes): 4 x odd dwords -> conflict-free 16-byte reads
     unsigned char *xq = reinterpret_cast<unsigned char *>(lds_f8);              // [bf][SQ] E4M3
     float *sinv = reinterpret_cast<float *>(xq + bf * SQ);                       // [bf] s_t
+    float *mfull = sinv + bf;                                                    // [bf + J - 1] row maxima
+    float *mpre = mfull + bf + a.J - 1;                                          // [bf + J - 1] prefix maxima
+    float *bmax = sinv + bf;                   // or [(bf + J - 1) H / 16] block maxima (same area)
     float *scratch = lds_f8 + scr_off;                                           // FP32 span
     i32x8 A[NG];
 #pragma unroll
@@ -168,38 +173,142 @@ __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__re
         const Chunk ch = ring_get(ring, ri);
         const Chunk chn = ring_get(ring, ri + 1);
         const int valid = span_valid(a, ch);
-        // one wave per frame: its samples (span [tH, tH + N), 0 at or past the clip end) are
-        // read once into registers, max |x| is reduced across the wave, then the frame is
-        // scaled by s_t = 448 / max and rounded to E4M3 straight from the registers
-        constexpr int KW = (KP / 4 + 63) / 64;     // 4-sample words per lane
-        const bool vec = (a.H & 3) == 0 && (N & 3) == 0;
-        for (int t = wid; t < ch.n_frames; t += nw) {
-            const int base = t * a.H;
-            const bool whole = vec && base + N <= valid;    // every sample of the frame present
-            f32x4 x[KW];
-            float mx = 0.0f;
+        if ((a.H & 15) == 0 && (N & 15) == 0) {
+            // Frame maxima from 16-sample block maxima (frames start and end on block
+            // boundaries).  A wave reads 1024 contiguous samples as four 1 KB rows of 16-byte
+            // reads (consecutive lanes, consecutive addresses); two quad permutations combine
+            // the four lanes that hold one block.
+            const int span_len = (ch.n_frames + a.J - 1) * a.H;
+            const int nblk = span_len >> 4;
+            for (int base = 1024 * wid; base < span_len; base += 1024 * nw) {
+                float bmx[4];
 #pragma unroll
-            for (int k = 0; k < KW; ++k) {
-                const int n0 = 4 * (lane + 64 * k), o = base + n0;
-                if (whole) {
-                    x[k] = n0 < N ? *(const f32x4 *)(scratch + o) : f32x4{};
-                } else {
+                for (int k = 0; k < 4; ++k) {
+                    const int o = base + 256 * k + 4 * lane;
+                    f32x4 v;
+                    if (o + 4 <= valid) {
+                        v = *(const f32x4 *)(scratch + o);
+                    } else {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) x[k][e] = (n0 + e < N && o + e < valid) ? scratch[o + e] : 0.0f;
+                        for (int e = 0; e < 4; ++e) v[e] = o + e < valid ? scratch[o + e] : 0.0f;
+                    }
+                    float m = fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
+                    m = fmaxf(m, __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, m), 0xB1, 0xF, 0xF, false)));
+                    m = fmaxf(m, __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, m), 0x4E, 0xF, 0xF, false)));
+                    bmx[k] = m;
                 }
-                mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x[k][0]), fabsf(x[k][1])), fmaxf(fabsf(x[k][2]), fabsf(x[k][3]))));
+                if ((lane & 3) == 0) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int blk = (base >> 4) + 16 * k + (lane >> 2);
+                        if (blk < nblk) bmax[blk] = bmx[k];
+                    }
+                }
             }
+            __syncthreads();
+            // four consecutive lanes per frame, each over every fourth of its blocks
+            const int bpf = N >> 4, bph = a.H >> 4;           // blocks per frame, per hop
+            for (int i = threadIdx.x; i < 4 * ch.n_frames; i += nthreads) {
+                const int t = i >> 2, q = i & 3;
+                float mx = 0.0f;
+                for (int j = q; j < bpf; j += 4) mx = fmaxf(mx, bmax[t * bph + j]);
+                mx = fmaxf(mx, __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, mx), 0xB1, 0xF, 0xF, false)));
+                mx = fmaxf(mx, __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, mx), 0x4E, 0xF, 0xF, false)));
+                if (q == 0) sinv[t] = mx > 0.0f ? __fdiv_rn(448.0f, mx) : 1.0f;   // the scale; inverted in the epilogue
+            }
+            __syncthreads();
+        } else {
+            // Per-frame scales from per-row maxima: row r (span samples [rH, rH + H), 0 at or
+            // past the clip end) gets the maximum of |x| over the whole row and over the prefix
+            // of Llast samples that the last segment of a frame uses, four lanes per row.  Frame
+            // t's maximum is then that of rows t .. t + J - 2 and the prefix of row t + J - 1.
+            const int rows = ch.n_frames + a.J - 1;
+            const int Llast = N - (a.J - 1) * a.H;
+            for (int idx = threadIdx.x; idx < 4 * rows; idx += nthreads) {
+                const int r = idx >> 2, q = idx & 3;
+                const int c0 = (q * a.H) >> 2, c1 = ((q + 1) * a.H) >> 2;
+                const int o0 = r * a.H;
+                float mf = 0.0f, mp = 0.0f;
+                if ((a.H & 15) == 0 && o0 + c1 <= valid) {
+                    // quarter rows of a multiple of 4 samples, 16-byte aligned, all present
+                    for (int col = c0; col < c1; col += 4) {
+                        const f32x4 v = *(const f32x4 *)(scratch + o0 + col);
+                        const float m4 = fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
+                        mf = fmaxf(mf, m4);
+                        if (col + 4 <= Llast) mp = fmaxf(mp, m4);
+                        else if (col < Llast)
+                            for (int e = 0; e < Llast - col; ++e) mp = fmaxf(mp, fabsf(v[e]));
+                    }
+                } else {
+                    for (int col = c0; col < c1; ++col) {
+                        const float v = o0 + col < valid ? fabsf(scratch[o0 + col]) : 0.0f;
+                        mf = fmaxf(mf, v);
+                        if (col < Llast) mp = fmaxf(mp, v);
+                    }
+                }
+                // the four lanes of a row are consecutive and active together
+                mf = fmaxf(mf, __shfl_xor(mf, 1));
+                mp = fmaxf(mp, __shfl_xor(mp, 1));
+                mf = fmaxf(mf, __shfl_xor(mf, 2));
+                mp = fmaxf(mp, __shfl_xor(mp, 2));
+                if (q == 0) {
+                    mfull[r] = mf;
+                    mpre[r] = mp;
+                }
+            }
+            __syncthreads();
+            for (int t = threadIdx.x; t < ch.n_frames; t += nthreads) {
+                float mx = mpre[t + a.J - 1];
+                for (int j = 0; j + 1 < a.J; ++j) mx = fmaxf(mx, mfull[t + j]);
+                sinv[t] = mx > 0.0f ? __fdiv_rn(448.0f, mx) : 1.0f;   // the scale; inverted in the epilogue
+            }
+            __syncthreads();
+        }
+        // E4M3 image: one wave per frame, lane words u = lane + 64 k (samples 4u .. 4u + 3 of the
+        // frame scaled by s_t -> one 32-bit word, 0 past N and past the clip end), the loads of
+        // four frames of the wave in flight together
+        {
+            constexpr int WPF = KP / 4;               // words per frame
+            constexpr int KW = (WPF + 63) / 64;       // words per lane
+            constexpr int FT = 4;                     // frames in flight per wave
+            const bool vec = (a.H & 3) == 0 && (N & 3) == 0;
+            for (int t0 = wid; t0 < ch.n_frames; t0 += FT * nw) {
+                f32x4 x[FT][KW];
+                float sc[FT];
 #pragma unroll
-            for (int d = 32; d > 0; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d));
-            const float s = mx > 0.0f ? __fdiv_rn(448.0f, mx) : 1.0f;     // the scale; inverted in the epilogue
-            if (lane == 0) sinv[t] = s;
-            unsigned *dst = reinterpret_cast<unsigned *>(xq + t * SQ);
+                for (int h = 0; h < FT; ++h) {
+                    const int t = t0 + h * nw;
+                    sc[h] = 0.0f;
 #pragma unroll
-            for (int k = 0; k < KW; ++k) {
-                const int u = lane + 64 * k;
-                if (u < KP / 4)
-                    dst[u] = fp8x4(__fmul_rn(x[k][0], s), __fmul_rn(x[k][1], s), __fmul_rn(x[k][2], s),
-                                   __fmul_rn(x[k][3], s));
+                    for (int k = 0; k < KW; ++k) x[h][k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                    if (t >= ch.n_frames) continue;
+                    sc[h] = sinv[t];
+                    const int base = t * a.H;
+                    const bool whole = vec && base + N <= valid;    // every sample of the frame present
+#pragma unroll
+                    for (int k = 0; k < KW; ++k) {
+                        const int n0 = 4 * (lane + 64 * k), o = base + n0;
+                        if (whole) {
+                            if (n0 < N) x[h][k] = *(const f32x4 *)(scratch + o);
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) x[h][k][e] = (n0 + e < N && o + e < valid) ? scratch[o + e] : 0.0f;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < FT; ++h) {
+                    const int t = t0 + h * nw;
+                    if (t >= ch.n_frames) break;
+                    unsigned *dst = reinterpret_cast<unsigned *>(xq + t * SQ);
+#pragma unroll
+                    for (int k = 0; k < KW; ++k) {
+                        const int u = lane + 64 * k;
+                        if (u < WPF)
+                            dst[u] = fp8x4(__fmul_rn(x[h][k][0], sc[h]), __fmul_rn(x[h][k][1], sc[h]),
+                                           __fmul_rn(x[h][k][2], sc[h]), __fmul_rn(x[h][k][3], sc[h]));
+                    }
+                }
             }
         }
         __syncthreads();                           // image ready; scratch is free
@@ -262,11 +371,13 @@ static melt_status launch_f8(Plan &p, const FwdArgs &a, size_t lds, int grid, in
     return hip_check(hipGetLastError(), "melt f8 launch");
 }
 
-// LDS of the direct-to-LDS FP8 kernel at bf frames per chunk: the E4M3 image, the scales
-// and row maxima, the FP32 span (16-byte aligned), then the epilogue areas
+// LDS of the direct-to-LDS FP8 kernel at bf frames per chunk: the E4M3 image, the scales,
+// the row and prefix maxima, the FP32 span (16-byte aligned), then the epilogue areas
 size_t f8_as_scratch_offset(const Plan &p, int bf) {
     const int ng8 = (p.N + 63) / 64;
-    const size_t img = (size_t)bf * (ng8 * 64 + 16) + (size_t)bf * 4;
+    const size_t rows = (size_t)(bf + p.geo32.J - 1);
+    const size_t maxima = std::max(2 * rows, (rows * p.H + 15) / 16);    // row or block maxima
+    const size_t img = (size_t)bf * (ng8 * 64 + 16) + (size_t)bf * 4 + maxima * 4;
     return (img + 15) & ~size_t(15);
 }
 size_t f8_as_lds_bytes(const Plan &p, int bf) {
@@ -288,11 +399,12 @@ melt_status launch_melt_f8(Plan &p, const FwdTask &t, bool lds_dma, int bf) {
     const int ng8 = (p.N + 63) / 64;
     if (p.row_tiles > 8) return set_error(MELT_E_UNSUPPORTED, "too many Mel bins for the FP8 kernel");
     const FwdArgs a = make_args(p, g, S, t);
-    const int grid = persistent_grid(p, t.est_chunks, 1);
     const hipStream_t s = t.stream;
     if (lds_dma) {
         const size_t lds = f8_as_lds_bytes(p, bf);
         if (lds + kRingBytes > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS for the FP8 kernel");
+        // as many workgroups per CU as LDS holds, at most two
+        const int grid = persistent_grid(p, t.est_chunks, std::min(2, (int)(kMaxLds / (lds + kRingBytes))));
         switch (ng8) {
         case 4: return launch_f8_as<4>(p, a, lds, grid, bf, s);
         case 7: return launch_f8_as<7>(p, a, lds, grid, bf, s);
@@ -301,6 +413,7 @@ melt_status launch_melt_f8(Plan &p, const FwdTask &t, bool lds_dma, int bf) {
         default: return set_error(MELT_E_UNSUPPORTED, "FP8 kernel supports n_fft in (192, 256], (384, 512], (960, 1024]");
         }
     }
+    const int grid = persistent_grid(p, t.est_chunks, 1);
     const int rows_max = bf + g.J - 1;
     const size_t lds = (size_t)rows_max * S * 4 + (size_t)bf * (ng8 * 64 + 16) + (size_t)bf * 4 + 2 * (size_t)rows_max * 4;
     if (lds > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS for the FP8 kernel");

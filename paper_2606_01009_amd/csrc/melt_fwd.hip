@@ -314,11 +314,15 @@ static std::vector<Variant> variant_list(const Plan &p) {
         v.push_back({V_F32_FS, kBF32});
         break;
     case MELT_PREC_FP8_E4M3:
+        // the largest chunk that fits LDS (one workgroup per CU), then 64-frame chunks with two
+        // workgroups per CU (one quantises while the other multiplies)
         for (int bf : {128, 96, 64, 32})
             if (f8_as_lds_bytes(p, bf) + kRingBytes <= (size_t)kMaxLds) {
                 v.push_back({V_F8_AS, bf});
                 break;
             }
+        if (!v.empty() && v.back().bf > 64 && 2 * (f8_as_lds_bytes(p, 64) + kRingBytes) <= (size_t)kMaxLds)
+            v.push_back({V_F8_AS, 64});
         v.push_back({V_F8_RS, kBF32});
         break;
     default: {
