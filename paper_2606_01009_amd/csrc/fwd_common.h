@@ -629,6 +629,11 @@ inline bool rs_supported(int NS) { return NS == 25 || NS == 32 || NS == 20 || NS
 inline bool rs_fits(const Plan &p) { return rs_supported(p.geo16.n_groups) && p.row_tiles <= 8; }
 // the direct-to-LDS kernel: any Mel count (row groups of at most 8 tiles)
 inline bool as_fits(const Plan &p) { return rs_supported(p.geo16.n_groups); }
+// the row-pair kernel: two basis tiles per wave (16 or 20 k-groups), 4, 5 or 8 row tiles
+inline bool ap_fits(const Plan &p) {
+    const int ng = p.geo16.n_groups;
+    return (ng == 16 || ng == 20) && (p.row_tiles == 4 || p.row_tiles == 5 || p.row_tiles == 8);
+}
 
 // LDS of the direct-to-LDS 16-bit kernel: operand rows, then the FP32 span scratch (16-byte aligned)
 inline size_t as_rows_bytes(const Plan &p, int bf) {
@@ -718,7 +723,8 @@ inline size_t ks_lds_bytes(const Plan &p, int bf) {
 
 // per-family launchers (melt_f32.hip, melt_h16.hip, melt_f8.hip)
 melt_status launch_melt_f32(Plan &p, const FwdTask &t, bool warp_specialised);
-enum H16Kind { H16_LDS_DMA = 0, H16_REGISTER_STAGED = 1, H16_FRAME_SPLIT = 2, H16_K_SPLIT = 3, H16_PIPELINED = 4 };
+enum H16Kind { H16_LDS_DMA = 0, H16_REGISTER_STAGED = 1, H16_FRAME_SPLIT = 2, H16_K_SPLIT = 3, H16_PIPELINED = 4,
+               H16_ROW_PAIR = 5 };
 melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf, int nbuf = 1);
 melt_status launch_melt_f8(Plan &p, const FwdTask &t, bool lds_dma, int bf);
 size_t f8_as_lds_bytes(const Plan &p, int bf);   // LDS of the direct-to-LDS FP8 kernel

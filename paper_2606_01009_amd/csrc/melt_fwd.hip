@@ -291,15 +291,16 @@ melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H
 // Kernel variants of a plan, in the order the autotuner times them (p.tune_variant selects;
 // the first one is the default):
 //   FP32       frame-split with staging waves, frame-split with register prefetch
-//   BF16/FP16  row-split with direct-to-LDS staging (one span buffer: 128- then 64-frame
+//   BF16/FP16  row pairs (two basis tiles per wave) where they fit; row-split with direct-to-LDS
+//              staging (one span buffer: 128- then 64-frame
 //              chunks; then two span buffers), producer/consumer row-split (one span, then
 //              two; only with producer waves), row-split with register staging, frame-split
 //              (the only one when the frame is too long for a register tile; for the split
 //              precisions only then)
-//   BF16X3 / FP16X3  the same, with one-span chunks of 96 then 64 frames
+//   BF16X3 / FP16X3  the same without row pairs, with one-span chunks of 96 then 64 frames
 //   FP8        row-split with direct-to-LDS staging (the largest chunk that fits LDS),
 //              row-split with register staging
-enum VariantKind { V_F32_WS, V_F32_FS, V_H16_PP, V_H16_AS, V_H16_RS, V_H16_KS, V_H16_FS, V_F8_AS, V_F8_RS };
+enum VariantKind { V_F32_WS, V_F32_FS, V_H16_PP, V_H16_AS, V_H16_AP, V_H16_RS, V_H16_KS, V_H16_FS, V_F8_AS, V_F8_RS };
 struct Variant {
     VariantKind kind;
     int bf;          // frames per chunk
@@ -327,6 +328,8 @@ static std::vector<Variant> variant_list(const Plan &p) {
         break;
     default: {
         const bool x3 = prec_split(p);
+        // row pairs first where they fit (two basis tiles per wave, 128 frames per chunk)
+        if (!x3 && ap_fits(p) && as_lds_bytes(p, 128) + kRingBytes <= (size_t)kMaxLds) v.push_back({V_H16_AP, 128});
         if (as_fits(p)) {
             // one span buffer (128 then 64 frames per chunk; 96 then 64 for BF16X3), then two
             for (int bf : {128, 96, 64}) {
@@ -339,6 +342,7 @@ static std::vector<Variant> variant_list(const Plan &p) {
                     break;
                 }
         }
+        // row pairs (two basis tiles per wave, 128 frames per chunk)
         if (pp_fits(p)) {
             // producer/consumer: one span (96 or 64 frames per chunk), then two spans
             for (int bf : {96, 64})
@@ -383,6 +387,7 @@ const char *forward_variant_name(const Plan &p, int i) {
                     : v[i].kind == V_F32_WS ? "f32-frame-split-warp-specialised"
                     : v[i].kind == V_F32_FS ? "f32-frame-split"
                     : v[i].kind == V_H16_AS ? (v[i].nbuf == 2 ? "h16-row-split-lds-dma2" : "h16-row-split-lds-dma")
+                    : v[i].kind == V_H16_AP ? "h16-row-pair-lds-dma"
                     : v[i].kind == V_H16_RS ? "h16-row-split"
                     : v[i].kind == V_H16_KS ? "h16-k-split-lds-dma"
                     : v[i].kind == V_H16_FS ? "h16-frame-split"
@@ -421,6 +426,7 @@ melt_status launch_melt_table(Plan &p, int variant, const Chunk *tab, const int 
     case V_F32_FS: return launch_melt_f32(p, t, false);
     case V_H16_PP: return launch_melt_h16(p, t, H16_PIPELINED, v.bf, v.nbuf);
     case V_H16_AS: return launch_melt_h16(p, t, H16_LDS_DMA, v.bf, v.nbuf);
+    case V_H16_AP: return launch_melt_h16(p, t, H16_ROW_PAIR, v.bf);
     case V_H16_RS: return launch_melt_h16(p, t, H16_REGISTER_STAGED, v.bf);
     case V_H16_KS: return launch_melt_h16(p, t, H16_K_SPLIT, v.bf);
     case V_H16_FS: return launch_melt_h16(p, t, H16_FRAME_SPLIT, v.bf);

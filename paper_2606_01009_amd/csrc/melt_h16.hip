@@ -269,6 +269,109 @@ __global__ __launch_bounds__(512) void k_melt_h16_as(FwdArgs a, const uint4 *__r
     }
 }
 
+// ------------------------------------------------------------------ 16-bit row-pair kernel, direct-to-LDS staging
+//
+// As k_melt_h16_as (one span buffer), with waves that hold the basis tiles of two row tiles in
+// registers, so each frame fragment read from LDS feeds two MFMAs: the multiply phase reads
+// half as many fragments.  With 2 NS uint4 of basis per lane and eight waves (two per SIMD,
+// 256 registers each) it fits up to NS = 20 k-groups (at 25 the two tiles spill).  A variant
+// with four waves holding two or three tiles each (one per SIMD) was slower at every shape
+// measured: the second wave per SIMD hides more than the halved fragment reads save.  Roles
+// for a group of cnt row tiles (pair_role):
+//   cnt 8: wave w takes the pair (2 (w/2), 2 (w/2) + 1) on frame tiles of parity w % 2;
+//   cnt 5: waves 0-3 take the pairs (0, 1) and (2, 3) on alternate frame tiles, waves 4-7
+//          the single tile 4 on every fourth frame tile (each SIMD: 4 + 1 tile products);
+//   cnt 4: wave w takes the pair (2 (w/4), 2 (w/4) + 1) on every fourth frame tile.
+// Waves 4-7 copy the next chunk's span (the single-tile ones when cnt = 5).
+struct PairRole {
+    int ta, tb, part, P;    // first tile, second tile (-1: none), first frame tile, frame-tile stride
+};
+__host__ __device__ inline bool pair_layout_ok(int cnt) { return cnt == 4 || cnt == 5 || cnt == 8; }
+__device__ __forceinline__ PairRole pair_role(int cnt, int w) {
+    if (cnt == 8) return {2 * (w >> 1), 2 * (w >> 1) + 1, w & 1, 2};
+    if (cnt == 4) return {2 * (w >> 2), 2 * (w >> 2) + 1, w & 3, 4};
+    if (w < 4) return {2 * (w >> 1), 2 * (w >> 1) + 1, w & 1, 2};
+    return {4, -1, w - 4, 4};
+}
+
+// one 32-frame tile against two basis tiles: per k-group one fragment read, two MFMAs
+template <int NS, bool IS_F16, int D = 2>
+__device__ __forceinline__ void mfma_sweep_pair(const uint4 (&A0)[NS], const uint4 (&A1)[NS], const unsigned short *l0,
+                                                const GroupTableBig &gt, f32x16 &acc0, f32x16 &acc1) {
+    uint4 b[D];
+#pragma unroll
+    for (int s = 0; s < D && s < NS; ++s) b[s] = *(const uint4 *)(l0 + gt.lds_off[s]);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int slot = s % D;
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (IS_F16) {
+            const f16x8 bv = __builtin_bit_cast(f16x8, b[slot]);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, A0[s]), bv, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, A1[s]), bv, acc1, 0, 0, 0);
+        } else {
+            const bf16x8 bv = __builtin_bit_cast(bf16x8, b[slot]);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, A0[s]), bv, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, A1[s]), bv, acc1, 0, 0, 0);
+        }
+        if (s + D < NS) b[slot] = *(const uint4 *)(l0 + gt.lds_off[s + D]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <class Conv, int NS, bool IS_F16>
+__global__ __launch_bounds__(512, 1) void k_melt_h16_ap(FwdArgs a, const uint4 *__restrict__ bhi, GroupTableBig gt,
+                                                        int bf, int scr_off) {
+    extern __shared__ float lds_ap[];
+    const int lane = threadIdx.x & 63;
+    const int wu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const PairRole R = pair_role(a.row_tiles, wu);
+    unsigned short *rows = reinterpret_cast<unsigned short *>(lds_ap);
+    float *span = lds_ap + scr_off;
+    zero_pad_columns<Conv>(a, bf + a.J - 1, rows, blockDim.x, 0);
+    uint4 A0[NS], A1[NS];
+    const uint4 Al[1] = {};
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        A0[s] = bhi[((size_t)R.ta * NS + s) * 64 + lane];
+        A1[s] = R.tb >= 0 ? bhi[((size_t)R.tb * NS + s) * 64 + lane] : uint4{};
+    }
+    const bool dma_wave = wu >= 4;
+    const int nch = *a.n_chunks;
+    int c = blockIdx.x;
+    if (c < nch) async_span(a, read_chunk(a.chunks, c), span);
+    async_wait();
+    __shared__ ChunkRing ring;
+    for (int it = 0; c < nch; c += gridDim.x, ++it) {
+        const int ri = it % kRing;
+        if (ri == 0) ring_fill(ring, a.chunks, c, gridDim.x, nch);
+        __syncthreads();                           // span of chunk c has landed; rows are free
+        const Chunk ch = ring_get(ring, ri);
+        const Chunk chn = ring_get(ring, ri + 1);
+        convert_span<Conv>(a, ch, span, rows, 0);
+        __syncthreads();                           // rows ready; the span is free
+        if (dma_wave && c + (int)gridDim.x < nch) async_span_waves(a, chn, span, wu - 4, 4);
+        const int nft = (ch.n_frames + 31) >> 5;
+        // a copying wave waits ahead of its last tile's stores, or after the loop
+        bool waited = !dma_wave;
+        for (int ft = R.part; ft < nft; ft += R.P) {
+            f32x16 acc0 = f32x16{}, acc1 = f32x16{};
+            int off = (ft * 32 + (lane & 31)) * a.S + 8 * (lane >> 5);
+            asm volatile("" : "+v"(off));
+            const unsigned short *l0 = rows + off;
+            if (R.tb >= 0) mfma_sweep_pair<NS, IS_F16>(A0, A1, l0, gt, acc0, acc1);
+            else mfma_sweep1<NS, false, IS_F16>(A0, Al, l0, gt, 0, acc0);
+            if (!waited && ft + R.P >= nft) {
+                async_wait();
+                waited = true;
+            }
+            store_tile(a, ch, R.ta, ft * 32 + (lane & 31), lane, acc0);
+            if (R.tb >= 0) store_tile(a, ch, R.tb, ft * 32 + (lane & 31), lane, acc1);
+        }
+        if (!waited) async_wait();                 // no tile for this wave (or a frameless chunk)
+    }
+}
+
 // ------------------------------------------------------------------ 16-bit row-split kernel, producer/consumer
 //
 // The same wave layout and multiplies as k_melt_h16_as, with the staging taken off the
@@ -660,6 +763,25 @@ static melt_status launch_as(Plan &p, const FwdArgs &a, const GroupTableBig &gt,
     }
 }
 
+template <class Conv, int NS, bool F16>
+static melt_status launch_ap_ns(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+                                hipStream_t s) {
+    allow_lds(k_melt_h16_ap<Conv, NS, F16>, kRingBytes);
+    k_melt_h16_ap<Conv, NS, F16><<<grid, 512, lds, s>>>(a, (const uint4 *)p.d_pack_h16, gt, bf,
+                                                          (int)(as_scratch_offset(p, bf) / 4));
+    return hip_check(hipGetLastError(), "melt h16 row-pair launch");
+}
+
+template <class Conv, bool F16>
+static melt_status launch_ap(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+                             hipStream_t s) {
+    switch (p.geo16.n_groups) {
+    case 16: return launch_ap_ns<Conv, 16, F16>(p, a, gt, lds, grid, bf, s);
+    case 20: return launch_ap_ns<Conv, 20, F16>(p, a, gt, lds, grid, bf, s);
+    default: return set_error(MELT_E_UNSUPPORTED, "row-pair kernel: no register tile for this frame length");
+    }
+}
+
 template <class Conv, int NS, bool X3, bool F16>
 static melt_status launch_pp_ns(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
                                 int nscr, hipStream_t s) {
@@ -745,6 +867,14 @@ melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf, int
         if (x3) return launch_as<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, sb, s);
         if (f16) return launch_as<ConvF16, false, true>(p, a, gt, lds, grid, bf, sb, s);
         return launch_as<ConvBF16, false, false>(p, a, gt, lds, grid, bf, sb, s);
+    }
+    if (kind == H16_ROW_PAIR) {
+        if (x3 || !ap_fits(p)) return set_error(MELT_E_UNSUPPORTED, "row-pair kernel: unsupported geometry");
+        const size_t lds = as_lds_bytes(p, bf, 1);
+        if (lds + kRingBytes > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(t.est_chunks, (int64_t)p.cu_count));
+        if (f16) return launch_ap<ConvF16, true>(p, a, gt, lds, grid, bf, s);
+        return launch_ap<ConvBF16, false>(p, a, gt, lds, grid, bf, s);
     }
     if (kind == H16_PIPELINED) {
         if (!pp_fits(p)) return set_error(MELT_E_UNSUPPORTED, "producer/consumer kernel: no producer waves");

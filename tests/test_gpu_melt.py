@@ -189,7 +189,10 @@ def test_every_kernel_variant(torch, melt, orc, prec):
         # N 1024: 64 k-groups, the K-split kernel (two waves per row tile); 128 and 80 Mel bins
         # (row groups of 4 + 4 and 3 + 2 tiles).  N 1200 at hop 160 (the cepstral front end):
         # 75 k-groups, split unevenly into 40 + 35 at the fifth hop segment
-        geoms = geoms + [(22050, 1024, 256, 128), (16000, 1024, 256, 80), (16000, 1200, 160, 128)]
+        geoms = geoms + [(22050, 1024, 256, 128), (16000, 1024, 256, 80), (16000, 1200, 160, 128),
+                         # 16 and 20 k-groups with 80, 128 and 64 Mel bins: the row-pair kernel (two
+                         # basis tiles per wave; 5, 8 and 4 row tiles)
+                         (16000, 256, 128, 80), (16000, 320, 160, 128), (16000, 256, 128, 64)]
     for sr, N, H, M in geoms:
         lengths = [0, N - 1, N, N + 1] + [(f - 1) * H + N + d for f in (64, 65, 96, 97, 128, 129, 200) for d in (0, 3)]
         wave, off = workloads.random_clips(lengths, seed=N + H)
