@@ -147,6 +147,7 @@ melt_status melt_plan_create(const melt_config *cfg, int device, melt_plan *out)
         if (st == MELT_OK)
             st = hip_check(hipMemcpy(p->d_dct, D.data(), D.size() * sizeof(float), hipMemcpyHostToDevice), "upload DCT");
     }
+    if (st == MELT_OK) init_variants(*p);
     if (st == MELT_OK) st = pack_tables_upload(*p);
     if (st == MELT_OK) st = pack_basis(*p, nullptr);
     if (st == MELT_OK) st = hip_check(hipStreamSynchronize(nullptr), "pack basis");

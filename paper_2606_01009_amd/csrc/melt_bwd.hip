@@ -109,6 +109,9 @@ __device__ __forceinline__ float map_dS(float S, int kind, float eps) {
 __global__ void k_fill_i64(int64_t *__restrict__ p, int64_t n, int64_t v) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
+__global__ void k_fill_f32(float *__restrict__ p, int64_t n, float v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
 
 // G over every frame.  Element e = t M + m of the [T, M] upstream gradient pairs with
 // projections proj[2e], proj[2e + 1] (R, I of Mel bin m) and G entries G[2e], G[2e + 1], so
@@ -384,7 +387,11 @@ melt_status launch_melt_backward(Plan &p, const float *d_wave, const int64_t *d_
                                  const float *d_gout, const float *d_proj, float *d_gwave, float *d_gbasis,
                                  hipStream_t s) {
     if (n_clips == 0 || n_frames == 0) {
-        if (d_gbasis) return hip_check(hipMemsetAsync(d_gbasis, 0, sizeof(float) * 2 * p.M * p.N, s), "memset");
+        // a fill kernel rather than a memset, so that the call can be captured in a HIP graph
+        if (d_gbasis) {
+            k_fill_f32<<<64, 256, 0, s>>>(d_gbasis, (int64_t)2 * p.M * p.N, 0.0f);
+            return hip_check(hipGetLastError(), "bwd fill");
+        }
         return MELT_OK;
     }
     const int M = p.M, N = p.N, H = p.H, J = p.geo32.J, Q = 2 * M;

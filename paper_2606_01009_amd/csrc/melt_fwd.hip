@@ -371,29 +371,39 @@ static std::vector<Variant> variant_list(const Plan &p) {
     return v;
 }
 
-static Variant variant_at(const Plan &p, int i) {
+void init_variants(Plan &p) {
     const std::vector<Variant> v = variant_list(p);
-    if (v.empty()) return {V_H16_FS, kBF32};      // unsupported geometry: the launch reports it
-    return v[i >= 0 && (size_t)i < v.size() ? i : 0];
+    p.n_variants = (int)std::min<size_t>(v.size(), Plan::kMaxVariants);
+    for (int i = 0; i < p.n_variants; ++i) {
+        p.var_kind[i] = v[i].kind;
+        p.var_bf[i] = v[i].bf;
+        p.var_nbuf[i] = v[i].nbuf;
+    }
 }
 
-int forward_variants(const Plan &p) { return (int)variant_list(p).size(); }
+static Variant variant_at(const Plan &p, int i) {
+    if (p.n_variants == 0) return {V_H16_FS, kBF32};    // unsupported geometry: the launch reports it
+    const int k = i >= 0 && i < p.n_variants ? i : 0;
+    return {(VariantKind)p.var_kind[k], p.var_bf[k], p.var_nbuf[k]};
+}
+
+int forward_variants(const Plan &p) { return p.n_variants; }
 
 const char *forward_variant_name(const Plan &p, int i) {
     static thread_local char buf[64];
-    const std::vector<Variant> v = variant_list(p);
-    if (i < 0 || (size_t)i >= v.size()) return "none";
-    const char *k = v[i].kind == V_H16_PP   ? (v[i].nbuf == 2 ? "h16-producer-consumer-2span" : "h16-producer-consumer")
-                    : v[i].kind == V_F32_WS ? "f32-frame-split-warp-specialised"
-                    : v[i].kind == V_F32_FS ? "f32-frame-split"
-                    : v[i].kind == V_H16_AS ? (v[i].nbuf == 2 ? "h16-row-split-lds-dma2" : "h16-row-split-lds-dma")
-                    : v[i].kind == V_H16_AP ? "h16-row-pair-lds-dma"
-                    : v[i].kind == V_H16_RS ? "h16-row-split"
-                    : v[i].kind == V_H16_KS ? "h16-k-split-lds-dma"
-                    : v[i].kind == V_H16_FS ? "h16-frame-split"
-                    : v[i].kind == V_F8_AS  ? "f8-row-split-lds-dma"
+    if (i < 0 || i >= p.n_variants) return "none";
+    const Variant v = variant_at(p, i);
+    const char *k = v.kind == V_H16_PP   ? (v.nbuf == 2 ? "h16-producer-consumer-2span" : "h16-producer-consumer")
+                    : v.kind == V_F32_WS ? "f32-frame-split-warp-specialised"
+                    : v.kind == V_F32_FS ? "f32-frame-split"
+                    : v.kind == V_H16_AS ? (v.nbuf == 2 ? "h16-row-split-lds-dma2" : "h16-row-split-lds-dma")
+                    : v.kind == V_H16_AP ? "h16-row-pair-lds-dma"
+                    : v.kind == V_H16_RS ? "h16-row-split"
+                    : v.kind == V_H16_KS ? "h16-k-split-lds-dma"
+                    : v.kind == V_H16_FS ? "h16-frame-split"
+                    : v.kind == V_F8_AS  ? "f8-row-split-lds-dma"
                                             : "f8-row-split";
-    std::snprintf(buf, sizeof(buf), "%s-bf%d", k, v[i].bf);
+    std::snprintf(buf, sizeof(buf), "%s-bf%d", k, v.bf);
     return buf;
 }
 

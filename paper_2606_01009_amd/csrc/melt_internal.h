@@ -91,6 +91,11 @@ struct Plan {
     float *d_dct = nullptr;
     float *d_lmel = nullptr;
     size_t lmel_cap = 0;
+    // kernel variants of the forward for this plan, fixed at plan creation (init_variants):
+    // kind, frames per chunk, span buffers; read without allocating by every forward call
+    static constexpr int kMaxVariants = 16;
+    int n_variants = 0;
+    int var_kind[kMaxVariants] = {}, var_bf[kMaxVariants] = {}, var_nbuf[kMaxVariants] = {};
     // tuning
     int cu_count = 256;
     int tune_variant = 0;                          // index of the chosen kernel variant
@@ -138,6 +143,7 @@ melt_status launch_stft_main(Plan &p, const float *d_wave, float *d_out, hipStre
 // size (streaming); est_chunks sizes the grid
 melt_status launch_melt_table(Plan &p, int variant, const Chunk *tab, const int *n_tab, int64_t est_chunks,
                               int64_t n_frames, const float *d_wave, float *d_out, float *d_proj, hipStream_t s);
+void init_variants(Plan &p);             // melt_fwd.hip: fills the plan's variant table
 int forward_variants(const Plan &p);
 void apply_tune_cache(Plan &p);          // stream.hip: apply a MELT_AUTOTUNE_CACHE entry
 const char *forward_variant_name(const Plan &p, int variant);

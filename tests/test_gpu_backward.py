@@ -250,3 +250,43 @@ def test_autograd_function(torch, melt, orc):
     basis2 = (basis.detach() * 2.0).contiguous()
     out2 = melt.melt_apply(wave.detach(), plan, d_off, 98, basis_param=basis2)
     assert torch.allclose(out2, out.detach() + 2 * np.log(2.0), atol=1e-3)
+
+
+def test_empty_batch_and_graph_replay(torch, melt):
+    """An empty batch writes d/dbasis = 0 with a fill kernel (no memset node, so the call can
+    be captured).  The backward captured in a HIP graph and replayed gives the eager result
+    bit for bit on every replay, with eager work and synchronisations between the replays."""
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80)
+    gb0 = torch.full((160, 400), float("nan"), dtype=torch.float32, device="cuda")
+    none_off = torch.zeros(1, dtype=torch.int64, device="cuda")
+    melt.melt_backward(plan.handle, torch.zeros(8, device="cuda"), none_off, 0,
+                       torch.zeros((1, 80), device="cuda"), None, None, gb0)
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(gb0)) == 0
+    cfg = workloads.config1(seed=17)
+    d_wave = torch.from_numpy(cfg["wave"]).cuda()
+    d_off = torch.from_numpy(cfg["offsets"]).cuda()
+    out = torch.empty((98, 80), device="cuda")
+    proj = torch.empty((98, 160), device="cuda")
+    plan.forward(d_wave, d_off, 98, out=out, proj=proj)
+    gout = torch.randn((98, 80), device="cuda")
+    gw = torch.empty_like(d_wave)
+    gb = torch.empty((160, 400), device="cuda")
+    melt.melt_backward(plan.handle, d_wave, d_off, 98, gout, proj, gw, gb)   # sizes the workspaces
+    torch.cuda.synchronize()
+    ref_w, ref_b = gw.clone(), gb.clone()
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            melt.melt_backward(plan.handle, d_wave, d_off, 98, gout, proj, gw, gb)
+    torch.cuda.synchronize()
+    for k in range(4):
+        gw.fill_(float("nan"))
+        gb.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(gw, ref_w) and torch.equal(gb, ref_b), f"replay {k}"
+        _ = (gout * 2.0).sum().item()      # eager work between replays
