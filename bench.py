@@ -455,7 +455,7 @@ def main():
     ap.add_argument("--no-energy", action="store_true", help="skip the board-energy windows (amdsmi)")
     ap.add_argument("--trials", type=int, default=20, help="timing trials per path (median + bootstrap 90%% CI)")
     ap.add_argument("--only", default=None,
-                    help="time one path only: fp32|bf16|fp16|bf16x3|fp16x3|fp8|stft|copy (profiling)")
+                    help="time one path only: fp32|bf16|fp16|bf16x3|fp16x3|fp8|fp8b|stft|copy (profiling)")
     ap.add_argument("--sweep", action="store_true", help="time every kernel variant of every precision and exit")
     ap.add_argument("--write-traffic", default=None, metavar="PMC_DIR",
                     help="write the committed traffic summary of the FP32 kernel from rocprofv3 --pmc runs "
@@ -564,7 +564,7 @@ def main():
         return 0
 
     if args.sweep:
-        for prec in ("fp32", "bf16", "fp16", "bf16x3", "fp16x3", "fp8"):
+        for prec in ("fp32", "bf16", "fp16", "bf16x3", "fp16x3", "fp8", "fp8b"):
             plan = melt.MeltPlan(sample_rate=16000.0, n_fft=400, hop=160, n_mels=M, precision=prec)
             desc = melt.melt_autotune(plan.handle, T)
             log(f"bench: autotune {prec}: {desc}")
@@ -589,7 +589,7 @@ def main():
     comparator = run_stft()
     variants = {}
     if not args.no_variants:
-        for prec in ("fp16x3", "bf16x3", "bf16", "fp16", "fp8"):
+        for prec in ("fp16x3", "bf16x3", "bf16", "fp16", "fp8", "fp8b"):
             try:
                 variants[prec] = run_melt(prec)[0]
             except melt.MeltError as e:

@@ -88,10 +88,21 @@ typedef enum {
  *              (FP32-level).  The waveform is pre-scaled by 2^10 (exact) so that the low parts
  *              of quiet samples stay normal; the scale is undone on the FP32 projections.
  *              Samples must satisfy |x| < 63.9 (2^10 |x| within binary16's range); a
- *              larger sample overflows and the frames that contain it come out non-finite. */
+ *              larger sample overflows and the frames that contain it come out non-finite.
+ *   FP8_E4M3_BLOCK32 - OCP E4M3 operands with power-of-two block scales instead of frame
+ *              scales: the waveform of each clip is cut into 32-sample blocks from its first
+ *              sample, block b is scaled by 2^e_b with e_b the largest integer such that
+ *              2^e_b max|x_b| <= 448 (e_b = 0 for a silent block, clamped to [-127, 127])
+ *              and rounded to E4M3 once; every frame reads its samples from that one image,
+ *              and the matrix cores undo 2^-e_b per 32-sample block of the product (E8M0
+ *              block scales of v_mfma_scale_f32_32x32x64_f8f6f4).  Basis rows are scaled as
+ *              for FP8_E4M3.  This is block scaling, not per-frame scaling: a sample gets the
+ *              scale of its own block whatever frame reads it.  Needs hop % 32 == 0
+ *              (else MELT_E_UNSUPPORTED at plan creation) and, as FP8_E4M3, n_fft in
+ *              (192, 256], (384, 512] or (960, 1024] (else MELT_E_UNSUPPORTED at the call). */
 typedef enum {
     MELT_PREC_FP32 = 0, MELT_PREC_BF16 = 1, MELT_PREC_FP16 = 2, MELT_PREC_FP8_E4M3 = 3, MELT_PREC_BF16X3 = 4,
-    MELT_PREC_FP16X3 = 5
+    MELT_PREC_FP16X3 = 5, MELT_PREC_FP8_E4M3_BLOCK32 = 6
 } melt_precision;
 
 /* Frontend parameters (Experiments, Table "Audio frontend configuration": 16 kHz,

@@ -32,7 +32,7 @@ WIN_HANN_SYMMETRIC, WIN_HANN_PERIODIC, WIN_RECT = 0, 1, 2
 MEL_HTK, MEL_SLANEY = 0, 1
 PLACE_FILTER_CENTRES, PLACE_LINSPACE = 0, 1
 NORM_NONE, NORM_SLANEY = 0, 1
-PREC_FP32, PREC_BF16, PREC_FP16, PREC_FP8_E4M3, PREC_BF16X3, PREC_FP16X3 = 0, 1, 2, 3, 4, 5
+PREC_FP32, PREC_BF16, PREC_FP16, PREC_FP8_E4M3, PREC_BF16X3, PREC_FP16X3, PREC_FP8_E4M3_BLOCK32 = 0, 1, 2, 3, 4, 5, 6
 
 
 def build(force: bool = False) -> Path:
@@ -91,6 +91,8 @@ def lib() -> ctypes.CDLL:
         for name in ("oracle_round_bf16", "oracle_round_fp16", "oracle_round_e4m3"):
             getattr(L, name).restype = d
             getattr(L, name).argtypes = [ctypes.c_float]
+        L.oracle_block_exponent.restype = i
+        L.oracle_block_exponent.argtypes = [ctypes.c_float]
         L.oracle_melt_forward_quant.restype = i64
         L.oracle_melt_forward_quant.argtypes = [p, p, i, i, i, p, p, i, i, i, d, p, p, p]
         L.oracle_num_threads.restype = i
@@ -165,6 +167,12 @@ def round_fp16(x) -> np.ndarray:
 def round_e4m3(x) -> np.ndarray:
     f = lib().oracle_round_e4m3
     return np.array([f(float(v)) for v in np.asarray(x, np.float32).ravel()]).reshape(np.shape(x))
+
+
+def block_exponent(m) -> np.ndarray:
+    """Largest integer e with 2^e |m| <= 448, within [-127, 127]; 0 for m = 0."""
+    f = lib().oracle_block_exponent
+    return np.array([f(float(v)) for v in np.asarray(m, np.float32).ravel()], np.int64).reshape(np.shape(m))
 
 
 # ---------------------------------------------------------------- MelT

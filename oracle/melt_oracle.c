@@ -498,7 +498,27 @@ double oracle_round_e4m3(float x)
  *   prec 5 (FP16x3): as prec 4 with binary16 parts, the frame samples first multiplied by
  *       2^10 in FP32 (exact) and the product sum divided by 2^10; a sample whose scaled
  *       value exceeds binary16's range becomes infinite.
+ *   prec 6 (FP8 E4M3 with 32-sample block scales): each clip is cut into blocks of 32
+ *       samples from its first sample (samples past the clip end count as 0); block b gets
+ *       the exponent e_b of block_exponent(max |x| over the block), every sample of the
+ *       block is multiplied by 2^e_b in FP32 and rounded to E4M3, and a frame uses the
+ *       values q 2^-e_b of its samples' blocks.  The basis is rounded as for prec 3 and the
+ *       exact product sum divided by r_j.
  * Wr, Wi are the FP64 basis; out / R / I as in oracle_melt_forward_basis.  Returns T. */
+/* The largest integer e with 2^e m <= 448 (the largest finite E4M3 value), m > 0, limited
+ * to [-127, 127] (the exponents an E8M0 scale can undo); 0 for m = 0.  Found by stepping e
+ * from 0, each comparison exact in double. */
+static int block_exponent(double m)
+{
+    if (m == 0.0) return 0;
+    int e = 0;
+    while (e > -127 && ldexp(m, e) > 448.0) --e;
+    while (e < 127 && ldexp(m, e + 1) <= 448.0) ++e;
+    return e;
+}
+
+int oracle_block_exponent(float m) { return block_exponent(fabs((double)m)); }
+
 int64_t oracle_melt_forward_quant(const float *wave, const int64_t *clip_off, int n_clips,
                                   int n_fft, int hop, const double *Wr, const double *Wi,
                                   int n_freq, int prec, int out_kind, double eps, double *out,
@@ -525,12 +545,26 @@ int64_t oracle_melt_forward_quant(const float *wave, const int64_t *clip_off, in
             double h = 0.0, l = 0.0;
             if (prec == 1) h = oracle_round_bf16(v);
             else if (prec == 2) h = oracle_round_fp16(v);
-            else if (prec == 3) { volatile float vs = v * rs[j]; h = oracle_round_e4m3(vs); }
+            else if (prec == 3 || prec == 6) { volatile float vs = v * rs[j]; h = oracle_round_e4m3(vs); }
             else if (prec == 5) { h = oracle_round_fp16(v); l = oracle_round_fp16((float)(v - (float)h)); }
             else { h = oracle_round_bf16(v); l = oracle_round_bf16((float)(v - (float)h)); }
             Bh[(size_t)j * n_fft + n] = h;
             Bl[(size_t)j * n_fft + n] = l;
         }
+    }
+    /* prec 6: the block exponent of every sample of every clip */
+    int *bexp = NULL;
+    if (prec == 6) {
+        int64_t total = n_clips > 0 ? clip_off[n_clips] : 0;
+        bexp = (int *)malloc(sizeof(int) * (size_t)(total > 0 ? total : 1));
+        for (int c = 0; c < n_clips; ++c)
+            for (int64_t b0 = clip_off[c]; b0 < clip_off[c + 1]; b0 += 32) {
+                int64_t b1 = b0 + 32 < clip_off[c + 1] ? b0 + 32 : clip_off[c + 1];
+                double mx = 0.0;
+                for (int64_t i = b0; i < b1; ++i) if (fabs((double)wave[i]) > mx) mx = fabs((double)wave[i]);
+                int e = block_exponent(mx);
+                for (int64_t i = b0; i < b1; ++i) bexp[i] = e;
+            }
     }
 #pragma omp parallel
     {
@@ -551,6 +585,12 @@ int64_t oracle_melt_forward_quant(const float *wave, const int64_t *clip_off, in
                 if (prec == 1) { xh[n] = oracle_round_bf16(v); xl[n] = 0.0; }
                 else if (prec == 2) { xh[n] = oracle_round_fp16(v); xl[n] = 0.0; }
                 else if (prec == 3) { volatile float vs = v * s_t; xh[n] = oracle_round_e4m3(vs); xl[n] = 0.0; }
+                else if (prec == 6) {
+                    int e = bexp[st[t] + n];
+                    volatile float vs = ldexpf(v, e);
+                    xh[n] = ldexp(oracle_round_e4m3(vs), -e);
+                    xl[n] = 0.0;
+                }
                 else if (prec == 5) {
                     volatile float vs = v * 1024.0f;
                     xh[n] = oracle_round_fp16(vs);
@@ -566,9 +606,10 @@ int64_t oracle_melt_forward_quant(const float *wave, const int64_t *clip_off, in
                     double a = 0.0;
                     for (int n = 0; n < n_fft; ++n) {
                         a += xh[n] * bh[n];
-                        if (prec >= 4) a += xh[n] * bl[n] + xl[n] * bh[n];
+                        if (prec == 4 || prec == 5) a += xh[n] * bl[n] + xl[n] * bh[n];
                     }
                     if (prec == 3) a /= (double)s_t * (double)rs[j];
+                    if (prec == 6) a /= (double)rs[j];
                     if (prec == 5) a /= 1024.0;
                     acc[h] = a;
                 }
@@ -579,7 +620,7 @@ int64_t oracle_melt_forward_quant(const float *wave, const int64_t *clip_off, in
         }
         free(xh); free(xl);
     }
-    free(st); free(Bh); free(Bl); free(rs);
+    free(st); free(Bh); free(Bl); free(rs); free(bexp);
     return T;
 }
 

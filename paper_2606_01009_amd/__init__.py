@@ -28,9 +28,12 @@ MELT_MEL_HTK, MELT_MEL_SLANEY = range(2)
 MELT_PLACE_FILTER_CENTRES, MELT_PLACE_LINSPACE = range(2)
 MELT_FB_NORM_NONE, MELT_FB_NORM_SLANEY = range(2)
 MELT_OUT_LOG_POWER, MELT_OUT_LOG_MAGNITUDE, MELT_OUT_POWER, MELT_OUT_MAGNITUDE, MELT_OUT_MFCC = range(5)
-MELT_PREC_FP32, MELT_PREC_BF16, MELT_PREC_FP16, MELT_PREC_FP8_E4M3, MELT_PREC_BF16X3, MELT_PREC_FP16X3 = range(6)
+(MELT_PREC_FP32, MELT_PREC_BF16, MELT_PREC_FP16, MELT_PREC_FP8_E4M3, MELT_PREC_BF16X3, MELT_PREC_FP16X3,
+ MELT_PREC_FP8_E4M3_BLOCK32) = range(7)
+# "fp8b": E4M3 with power-of-two scales per 32-sample block of the waveform
 PRECISIONS = {"fp32": MELT_PREC_FP32, "bf16": MELT_PREC_BF16, "fp16": MELT_PREC_FP16,
-              "fp8": MELT_PREC_FP8_E4M3, "bf16x3": MELT_PREC_BF16X3, "fp16x3": MELT_PREC_FP16X3}
+              "fp8": MELT_PREC_FP8_E4M3, "bf16x3": MELT_PREC_BF16X3, "fp16x3": MELT_PREC_FP16X3,
+              "fp8b": MELT_PREC_FP8_E4M3_BLOCK32}
 
 
 class MeltLibraryMissing(RuntimeError):

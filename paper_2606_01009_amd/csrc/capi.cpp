@@ -37,7 +37,10 @@ static melt_status validate(const melt_config &c) {
     // the log epilogues take the hardware logarithm of S + eps, which needs a normal FP32 argument
     if (!(c.log_eps >= 1.1754943508222875e-38) || !std::isfinite(c.log_eps))
         return set_error(MELT_E_INVALID_ARG, "log_eps must be >= 1.18e-38 (the smallest normal FP32)");
-    if (c.precision < 0 || c.precision > 5) return set_error(MELT_E_INVALID_ARG, "bad precision");
+    if (c.precision < 0 || c.precision > 6) return set_error(MELT_E_INVALID_ARG, "bad precision");
+    // block-scaled FP8: a frame's 32-sample blocks must be blocks of the clip (hop a multiple of 32)
+    if (c.precision == MELT_PREC_FP8_E4M3_BLOCK32 && c.hop % 32 != 0)
+        return set_error(MELT_E_UNSUPPORTED, "FP8 with 32-sample block scales needs hop % 32 == 0");
     if (c.fb_norm < 0 || c.fb_norm > 1) return set_error(MELT_E_INVALID_ARG, "bad fb_norm");
     // Frames that skip samples (hop > n_fft) are not implemented: the kernels stage a chunk as
     // hop-block rows whose LDS stride covers min(n_fft, hop) columns, and the streaming carry

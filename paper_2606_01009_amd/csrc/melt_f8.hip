@@ -362,6 +362,463 @@ __global__ __launch_bounds__(512) void k_melt_f8_as(FwdArgs a, const i32x8 *__re
     }
 }
 
+// ------------------------------------------------------------------ FP8 kernel, 32-sample block scales
+//
+// MELT_PREC_FP8_E4M3_BLOCK32.  The waveform is quantised once.  With the hop a multiple of 32,
+// a chunk's span is whole 32-sample blocks of its clip, and so is every 32-sample k-block of a
+// frame.  Block b gets the power-of-two scale 2^e_b (e_b the largest integer with
+// 2^e_b max|x_b| <= 448; 0 for a silent block) and its samples are rounded to E4M3 into
+// hop-block rows in LDS, one byte per sample, beside one E8M0 code 127 - e_b per block.  A
+// frame's 64-sample k-group is two blocks, and v_mfma_scale_f32_32x32x64_f8f6f4 scales each:
+// for column j of B the code of lane j covers k 0..31 and that of lane j + 32 covers k
+// 32..63, while a lane's 32 operand bytes are k 16 h .. 16 h + 15 (bytes 0-15) and k 32 + 16 h
+// .. (bytes 16-31), h = lane / 32.  So lane half h reads samples 16 h .. 16 h + 15 of block
+// 2g and of block 2g + 1 (two 16-byte reads) and passes the code of block 2g + h; the basis
+// is packed in the same order (k_pack_f8 with blocks = 1).  The product sums 2^-e_b q W_q
+// over every block with no per-frame copy of the samples.  Basis rows keep the FP8_E4M3 row
+// scales (unit scale in the MFMA, 1 / r_j in the epilogue).  Row groups, wave layout, chunk
+// ring and span copies are those of k_melt_h16_as.
+
+// byte offset, in the hop-block rows, of block i of a frame (samples 32 i .. 32 i + 31):
+// row 32 i / H, column 32 i % H; blocks past the frame (32 i >= N, zero basis) read block 0
+struct F8BlockTable {
+    int off[32];
+};
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+// largest e with 2^e m <= 448 (m > 0 finite), clamped to [-127, 127]; 0 for m = 0.
+// m = f 2^E with f in [0.5, 1): 2^e m <= 448 = 0.875 2^9 holds for e = 9 - E when f <= 0.875,
+// else for e = 8 - E.
+__device__ __forceinline__ int block_exp(float m) {
+    if (!(m > 0.0f)) return 0;
+    const int E = __builtin_amdgcn_frexp_expf(m);
+    const float f = __builtin_amdgcn_frexp_mantf(m);
+    const int e = (f <= 0.875f ? 9 : 8) - E;
+    return e < -127 ? -127 : (e > 127 ? 127 : e);
+}
+
+// One lane's 32-sample block fb of a chunk's span, all in that lane: the block maximum, its
+// exponent and the 32 E4M3 bytes.  The lane's eight 16-byte reads start at slot
+// rot = (lane / 2) mod 8 of its 128-byte block and wrap, so that the 16 lanes of an LDS pass
+// (blocks 128 bytes apart, or 4 KB apart in pairs of eight) touch 16 distinct 4-bank groups;
+// each 4-sample group is written to its own 4-byte slot of the block's row bytes at `dst`.
+// `whole` (wave-uniform): every active lane's block lies before `valid`; otherwise samples at
+// or past `valid` (clip end) read as 0.  TWO_PASS reads the block twice (maximum, then
+// conversion) to keep eight fewer vectors live, for kernels that hold more registers.
+template <bool TWO_PASS>
+__device__ __forceinline__ void convert_lane_block(const float *span, int valid, bool whole, int fb,
+                                                   unsigned char *dst, int *codes) {
+    const int rot = (threadIdx.x >> 1) & 7;
+    const float *s1 = span + 32 * fb + 4 * rot, *s2 = s1 - 32;
+    auto load = [&](int k) -> f32x4 {
+        if (whole) return *(const f32x4 *)((k < 8 - rot ? s1 : s2) + 4 * k);
+        f32x4 v;
+        const int o = 32 * fb + 4 * ((k + rot) & 7);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = o + e < valid ? span[o + e] : 0.0f;
+        return v;
+    };
+    auto amax = [](f32x4 v) { return fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))); };
+    f32x4 v[TWO_PASS ? 1 : 8];
+    float m = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if constexpr (TWO_PASS) {
+            m = fmaxf(m, amax(load(k)));
+        } else {
+            v[k] = load(k);
+            m = fmaxf(m, amax(v[k]));
+        }
+    }
+    const int e = block_exp(m);
+    unsigned char *d1 = dst + 4 * rot, *d2 = d1 - 32;
+    auto store = [&](int k, unsigned w) { *(unsigned *)((k < 8 - rot ? d1 : d2) + 4 * k) = w; };
+    // v_cvt_scalef32_pk_fp8_f32 rounds x / 2^floor(log2 s) to E4M3 in one step, so s = 2^-e
+    // gives the E4M3 value of 2^e x.  2^-127 (e = 127, a block below 448 2^-127 but not
+    // silent) is not a normal FP32 scale: a wave holding such a block takes ldexp and the
+    // plain conversion.
+    if (__builtin_amdgcn_ballot_w64(e >= 127) == 0) {
+        const float sc = __builtin_bit_cast(float, (127 - e) << 23);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const f32x4 x = TWO_PASS ? load(k) : v[TWO_PASS ? 0 : k];
+            const s16x2 lo = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(s16x2{0, 0}, x[0], x[1], sc, false);
+            store(k, __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(lo, x[2], x[3], sc, true)));
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const f32x4 x = TWO_PASS ? load(k) : v[TWO_PASS ? 0 : k];
+            store(k, fp8x4(__builtin_ldexpf(x[0], e), __builtin_ldexpf(x[1], e), __builtin_ldexpf(x[2], e),
+                           __builtin_ldexpf(x[3], e)));
+        }
+    }
+    codes[fb] = 127 - e;
+}
+
+// byte offset of E4M3 block fb in the hop-block rows: row r = fb / bph (from the FP32 product
+// (fb + 1/2) (1 / bph), exact while fb < 2^16: its error stays far below the 1 / (2 bph)
+// margin), at 32 fb + r (S8 - H)
+__device__ __forceinline__ int block_row_byte(int fb, float inv_bph, int pad) {
+    return 32 * fb + (int)(((float)fb + 0.5f) * inv_bph) * pad;
+}
+
+// The chunk's FP32 span -> E4M3 hop-block rows (stride S8 bytes) and block codes, one block per
+// lane, consecutive blocks over the lanes and waves.
+__device__ __forceinline__ void convert_blocks(const FwdArgs &a, const Chunk &ch, const float *span,
+                                               unsigned char *rows8, int S8, int *codes, float inv_bph) {
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
+    const int nblk = ((ch.n_frames + a.J - 1) * a.H) >> 5;
+    const int valid = span_valid(a, ch);
+    const int pad = S8 - a.H;
+    for (int f0 = 64 * wid; f0 < nblk; f0 += 64 * nw) {
+        const int fb = f0 + lane;
+        if (fb < nblk)
+            convert_lane_block<true>(span, valid, 32 * (f0 + 64) <= valid, fb, rows8 + block_row_byte(fb, inv_bph, pad),
+                                     codes);
+    }
+}
+
+// One or two 32-frame tiles (q0, q1: the tiles' frame rows of this lane, plus 16 h; s0, s1:
+// their block codes at the lane's half) against a wave's E4M3 basis tile: per k-group two
+// 16-byte reads (blocks 2g and 2g + 1) and one code per tile, read D groups ahead.
+template <int NG, bool TWO, int D = 2>
+__device__ __forceinline__ void f8b_sweep(const i32x8 (&A)[NG], const F8BlockTable &bt, const unsigned char *q0,
+                                          const unsigned char *q1, const int *s0, const int *s1, f32x16 &acc0,
+                                          f32x16 &acc1) {
+    i32x8 b0[D], b1[D];
+    int c0[D], c1[D];
+    auto fetch = [&](int g, int slot) {
+        const int o0 = bt.off[2 * g], o1 = bt.off[2 * g + 1];
+        const uint4 l0 = *(const uint4 *)(q0 + o0), h0 = *(const uint4 *)(q0 + o1);
+        b0[slot] = i32x8{(int)l0.x, (int)l0.y, (int)l0.z, (int)l0.w, (int)h0.x, (int)h0.y, (int)h0.z, (int)h0.w};
+        c0[slot] = s0[2 * g];
+        if constexpr (TWO) {
+            const uint4 l1 = *(const uint4 *)(q1 + o0), h1 = *(const uint4 *)(q1 + o1);
+            b1[slot] = i32x8{(int)l1.x, (int)l1.y, (int)l1.z, (int)l1.w, (int)h1.x, (int)h1.y, (int)h1.z, (int)h1.w};
+            c1[slot] = s1[2 * g];
+        }
+    };
+#pragma unroll
+    for (int g = 0; g < D && g < NG; ++g) fetch(g, g);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const int slot = g % D;
+        __builtin_amdgcn_sched_barrier(0);
+        acc0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[g], b0[slot], acc0, 0, 0, 0, 127, 0, c0[slot]);
+        if constexpr (TWO)
+            acc1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[g], b1[slot], acc1, 0, 0, 0, 127, 0, c1[slot]);
+        if (g + D < NG) fetch(g + D, slot);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int NG>
+__global__ __launch_bounds__(512) void k_melt_f8b_as(
+    FwdArgs a, const i32x8 *__restrict__ bq, const float *__restrict__ rinv_g, F8BlockTable bt, int S8, int code_off,
+    int n_codes, int scr_off, int rgroups) {
+    extern __shared__ float lds_f8b[];
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
+    const int grp = blockIdx.x % rgroups, gt_n = (a.row_tiles + rgroups - 1) / rgroups;
+    const int r0 = grp * gt_n, cnt = min(a.row_tiles - r0, gt_n);
+    const WaveLayout L = layout_for(cnt);
+    const bool idle = wid >= L.waves;
+    int rt = wid, part = 0, P = 1;
+    if (wid >= L.full) {
+        rt = L.full + (wid - L.full) / L.psplit;
+        part = (wid - L.full) % L.psplit;
+        P = L.psplit;
+    }
+    rt = idle ? r0 : r0 + rt;
+    unsigned char *rows8 = reinterpret_cast<unsigned char *>(lds_f8b);
+    int *codes = reinterpret_cast<int *>(lds_f8b) + code_off;
+    float *span = lds_f8b + scr_off;
+    const int bph = a.H >> 5;
+    const float inv_bph = 1.0f / (float)bph;
+    // codes past the chunk's blocks (read for blocks past a frame, or frames past the chunk)
+    // are finite from the start
+    for (int i = threadIdx.x; i < n_codes; i += blockDim.x) codes[i] = 127;
+    i32x8 A[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) A[g] = bq[((size_t)rt * NG + g) * 64 + lane];
+    float rinv[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) rinv[r] = rinv_g[rt * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)];
+    const int dma0 = L.full < nw ? L.full : nw / 2;    // first copying wave
+    const bool dma_wave = wid >= dma0;
+    const int nch = *a.n_chunks;
+    const int cstep = gridDim.x / rgroups;
+    int c = blockIdx.x / rgroups;
+    if (c < nch) async_span(a, read_chunk(a.chunks, c), span);
+    async_wait();
+    __shared__ ChunkRing ring;
+    for (int it = 0; c < nch; c += cstep, ++it) {
+        const int ri = it % kRing;
+        if (ri == 0) ring_fill(ring, a.chunks, c, cstep, nch);
+        __syncthreads();                           // span of chunk c has landed; rows are free
+        const Chunk ch = ring_get(ring, ri);
+        const Chunk chn = ring_get(ring, ri + 1);
+        convert_blocks(a, ch, span, rows8, S8, codes, inv_bph);
+        __syncthreads();                           // rows and codes ready; the span is free
+        if (dma_wave && c + cstep < nch) async_span_waves(a, chn, span, wid - dma0, nw - dma0);
+        const int nft = idle ? 0 : (ch.n_frames + 31) >> 5;
+        bool waited = !dma_wave;
+        const int step = P == 1 ? 2 : P;
+        for (int ft = part; ft < nft; ft += step) {
+            f32x16 acc0 = f32x16{}, acc1 = f32x16{};
+            const int f0 = ft * 32 + (lane & 31);
+            const unsigned char *q0 = rows8 + f0 * S8 + 16 * (lane >> 5);
+            const int *s0 = codes + f0 * bph + (lane >> 5);
+            const bool two = step == 2 && ft + 1 < nft;
+            if (two) {
+                f8b_sweep<NG, true>(A, bt, q0, q0 + 32 * S8, s0, s0 + 32 * bph, acc0, acc1);
+            } else {
+                f8b_sweep<NG, false>(A, bt, q0, q0, s0, s0, acc0, acc1);
+            }
+            if (!waited && ft + step >= nft) {
+                async_wait();
+                waited = true;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (u == 1 && !two) break;
+                f32x16 &acc = u ? acc1 : acc0;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[r] *= rinv[r];
+                store_tile(a, ch, rt, (ft + u) * 32 + (lane & 31), lane, acc);
+            }
+        }
+        if (!waited) async_wait();                 // no tile for this wave (or a frameless chunk)
+    }
+}
+
+// ------------------------------------------------------------------ FP8 block-scaled, producer/consumer
+//
+// The arithmetic of k_melt_f8b_as, with a chunk's conversion and its multiplies on different
+// waves so that they overlap (the conversion is vector-ALU work, the multiplies matrix-core
+// and LDS work).  Waves 4-7 (producers) own the 256-sample blocks b = w, w + 4, ... of every
+// chunk's span (w = wave - 4): each copies its blocks HBM -> LDS (direct-to-LDS) and converts
+// exactly those into E4M3 rows and block codes, so no producer waits for another.  Waves 0-3
+// (consumers) multiply.  Two row/code buffers alternate: in iteration k the consumers multiply
+// chunk k from one while the producers convert chunk k + 1 into the other and start the copy
+// of chunk k + 2, with one barrier per chunk.  Consumer c owns row tile c and, past four tiles,
+// a share of the rest (f8_role); a frame tile it holds two row tiles of is swept once for both,
+// each fragment read feeding two MFMAs.  Chunk descriptors pass through a four-slot LDS ring:
+// wave 4 loads descriptor k + 3 in iteration k and stores it before the barrier (slot
+// (k + 3) mod 4 was last read in iteration k - 1).
+
+struct F8Role {
+    int t0, t1, part, P;    // own tile (-1: none), second tile on frame tiles = part mod P (-1: none)
+};
+__device__ __forceinline__ F8Role f8_role(int cnt, int c) {
+    if (c >= cnt) return {-1, -1, 0, 1};
+    if (cnt <= 4) return {c, -1, 0, 1};
+    if (cnt == 5) return {c, 4, c, 4};
+    if (cnt == 6) return {c, 4 + (c >> 1), c & 1, 2};
+    return {c, 4 + c < cnt ? 4 + c : -1, 0, 1};
+}
+
+// one 32-frame tile against two basis tiles: per k-group one fragment (two 16-byte reads) and
+// one code, two MFMAs
+template <int NG, int D = 2>
+__device__ __forceinline__ void f8b_sweep_pair(const i32x8 (&A0)[NG], const i32x8 (&A1)[NG], const F8BlockTable &bt,
+                                               const unsigned char *q0, const int *s0, f32x16 &acc0, f32x16 &acc1) {
+    i32x8 b[D];
+    int cd[D];
+    auto fetch = [&](int g, int slot) {
+        const uint4 l = *(const uint4 *)(q0 + bt.off[2 * g]), h = *(const uint4 *)(q0 + bt.off[2 * g + 1]);
+        b[slot] = i32x8{(int)l.x, (int)l.y, (int)l.z, (int)l.w, (int)h.x, (int)h.y, (int)h.z, (int)h.w};
+        cd[slot] = s0[2 * g];
+    };
+#pragma unroll
+    for (int g = 0; g < D && g < NG; ++g) fetch(g, g);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const int slot = g % D;
+        __builtin_amdgcn_sched_barrier(0);
+        acc0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A0[g], b[slot], acc0, 0, 0, 0, 127, 0, cd[slot]);
+        acc1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A1[g], b[slot], acc1, 0, 0, 0, 127, 0, cd[slot]);
+        if (g + D < NG) fetch(g + D, slot);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// the copies of one 256-sample block b of the chunk's valid span into the span: one 16-byte
+// copy if the block is whole, else 4-byte copies of its valid samples
+__device__ __forceinline__ void copy_block(const float *src, unsigned base, int valid, int b) {
+    const int lane = threadIdx.x & 63;
+    if (256 * (b + 1) <= valid) {
+        lds_dma_x4(src + b * 256 + 4 * lane, base + b * 1024);
+    } else {
+        for (int q = 4 * b; q * 64 < valid; ++q) {
+            const int o = q * 64 + lane;
+            if (o < valid) lds_dma_x1(src + o, base + q * 256);
+        }
+    }
+}
+
+// A producer's conversion of its 256-sample blocks b = pw, pw + 4, ... of a chunk's span: per
+// wave step eight of them, one E4M3 block per lane (convert_lane_block).  With NEXT, each
+// step's blocks are then copied for the next chunk (`nx`) into the span, and after the loop
+// those of this producer's blocks past this chunk's span.
+template <bool NEXT>
+__device__ __forceinline__ void convert_owned8(const FwdArgs &a, const Chunk &ch, float *span,
+                                               unsigned char *rows8, int S8, int *codes, float inv_bph, int pw,
+                                               const Chunk &nx) {
+    const int lane = threadIdx.x & 63;
+    const int span_len = (ch.n_frames + a.J - 1) * a.H;
+    const int nblk = span_len >> 5, n256 = (span_len + 255) >> 8;
+    const int valid = span_valid(a, ch);
+    const int pad = S8 - a.H;
+    const float *nsrc = a.wave + nx.sample_start;
+    const int nvalid = NEXT ? span_valid(a, nx) : 0;
+    const unsigned base = __builtin_amdgcn_readfirstlane(lds_addr(span));
+    int b0 = pw;
+    for (; b0 < n256; b0 += 32) {
+        const int fb = 8 * (b0 + 4 * (lane >> 3)) + (lane & 7);
+        // every lane's block before the clip end: the last lane's block is 8 (b0 + 28) + 7
+        const bool whole = 256 * (b0 + 29) <= valid;
+        if (fb < nblk) convert_lane_block<false>(span, valid, whole, fb, rows8 + block_row_byte(fb, inv_bph, pad), codes);
+        if constexpr (NEXT) {
+            // the blocks just read may be overwritten by the next chunk's copies
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (256 * (b0 + 4 * u) < nvalid) copy_block(nsrc, base, nvalid, b0 + 4 * u);
+        }
+    }
+    if constexpr (NEXT) {
+        for (; 256 * b0 < nvalid; b0 += 4) copy_block(nsrc, base, nvalid, b0);
+    }
+}
+
+// a producer's copies of its blocks of a chunk's valid span (no conversion pending)
+__device__ __forceinline__ void copy_owned(const FwdArgs &a, const Chunk &ch, float *span, int pw) {
+    const int valid = span_valid(a, ch);
+    const float *src = a.wave + ch.sample_start;
+    const unsigned base = __builtin_amdgcn_readfirstlane(lds_addr(span));
+    for (int b = pw; 256 * b < valid; b += 4) copy_block(src, base, valid, b);
+}
+
+__device__ __forceinline__ Chunk slot_get(const Chunk *slots, int i) {
+    Chunk e = slots[i];
+    e.sample_start = uniform64(e.sample_start);
+    e.sample_end = uniform64(e.sample_end);
+    e.out_row = uniform64(e.out_row);
+    e.n_frames = __builtin_amdgcn_readfirstlane(e.n_frames);
+    e.clip = __builtin_amdgcn_readfirstlane(e.clip);
+    return e;
+}
+
+template <int NG>
+__global__ __launch_bounds__(512) void k_melt_f8b_pc(FwdArgs a, const i32x8 *__restrict__ bq,
+                                                    const float *__restrict__ rinv_g, F8BlockTable bt, int S8,
+                                                    int buf_bytes, int code_off, int n_codes, int scr_off,
+                                                    int rgroups) {
+    extern __shared__ float lds_pc[];
+    __shared__ Chunk dslot[4];
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int grp = blockIdx.x % rgroups, gt_n = (a.row_tiles + rgroups - 1) / rgroups;
+    const int r0 = grp * gt_n, cnt = min(a.row_tiles - r0, gt_n);
+    const bool producer = wid >= 4;
+    const int pw = wid - 4;
+    unsigned char *buf0 = reinterpret_cast<unsigned char *>(lds_pc);
+    float *span = lds_pc + scr_off;
+    const int bph = a.H >> 5;
+    const float inv_bph = 1.0f / (float)bph;
+    const int nch = *a.n_chunks;
+    const int cstep = gridDim.x / rgroups;
+    const int c0 = blockIdx.x / rgroups;
+    // codes past a chunk's blocks (read for blocks past a frame, or frames past the chunk) are
+    // finite from the start, in both buffers
+    for (int i = threadIdx.x; i < n_codes; i += blockDim.x) {
+        reinterpret_cast<int *>(buf0 + code_off)[i] = 127;
+        reinterpret_cast<int *>(buf0 + buf_bytes + code_off)[i] = 127;
+    }
+    // prologue: descriptors 0..2 in their slots; the producers copy and convert chunk 0 into
+    // buffer 0 and start the copy of chunk 1.  Producers and consumers then run loops of their
+    // own (so that neither role's registers are live in the other's), with one barrier per
+    // chunk in both.
+    if (wid == 4 && lane < 3 && c0 + lane * cstep < nch) dslot[lane] = a.chunks[c0 + lane * cstep];
+    if (producer) {
+        if (c0 < nch) {
+            const Chunk ch = read_chunk(a.chunks, c0);
+            copy_owned(a, ch, span, pw);
+            async_wait();
+            if (c0 + cstep < nch)
+                convert_owned8<true>(a, ch, span, buf0, S8, reinterpret_cast<int *>(buf0 + code_off), inv_bph, pw,
+                                     read_chunk(a.chunks, c0 + cstep));
+            else
+                convert_owned8<false>(a, ch, span, buf0, S8, reinterpret_cast<int *>(buf0 + code_off), inv_bph, pw,
+                                      ch);
+        }
+        for (int it = 0; c0 + it * cstep < nch; ++it) {
+            __syncthreads();                       // chunk it converted; buffer (it + 1) & 1 free
+            const int c = c0 + it * cstep;
+            if (c + cstep >= nch) continue;
+            Chunk nd{};
+            const bool load_desc = wid == 4 && c + 3 * cstep < nch;
+            async_wait();                          // this producer's copies of chunk it + 1
+            if (load_desc) nd = a.chunks[c + 3 * cstep];
+            const Chunk ch1 = slot_get(dslot, (it + 1) & 3);
+            unsigned char *rows = buf0 + ((it + 1) & 1) * buf_bytes;
+            int *codes = reinterpret_cast<int *>(rows + code_off);
+            if (c + 2 * cstep < nch)
+                convert_owned8<true>(a, ch1, span, rows, S8, codes, inv_bph, pw, slot_get(dslot, (it + 2) & 3));
+            else
+                convert_owned8<false>(a, ch1, span, rows, S8, codes, inv_bph, pw, ch1);
+            if (load_desc && lane == 0) dslot[(it + 3) & 3] = nd;
+        }
+        return;
+    }
+    const F8Role R = f8_role(cnt, wid);
+    i32x8 A0[NG], A1[NG];
+    float ri0[16], ri1[16];
+    if (R.t0 >= 0) {
+        const int t0 = r0 + R.t0, t1 = r0 + (R.t1 >= 0 ? R.t1 : R.t0);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            A0[g] = bq[((size_t)t0 * NG + g) * 64 + lane];
+            A1[g] = bq[((size_t)t1 * NG + g) * 64 + lane];
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            ri0[r] = rinv_g[t0 * 32 + i];
+            ri1[r] = rinv_g[t1 * 32 + i];
+        }
+    }
+    for (int it = 0; c0 + it * cstep < nch; ++it) {
+        __syncthreads();                           // chunk it converted; buffer (it + 1) & 1 free
+        if (R.t0 < 0) continue;
+        const Chunk ch = slot_get(dslot, it & 3);
+        const unsigned char *rows = buf0 + (it & 1) * buf_bytes;
+        const int *codes = reinterpret_cast<const int *>(rows + code_off);
+        const int nft = (ch.n_frames + 31) >> 5;
+        for (int ft = 0; ft < nft; ++ft) {
+            const int f0 = ft * 32 + (lane & 31);
+            int off = f0 * S8 + 16 * (lane >> 5);
+            asm volatile("" : "+v"(off));
+            const unsigned char *q0 = rows + off;
+            const int *s0 = codes + f0 * bph + (lane >> 5);
+            f32x16 acc0 = f32x16{}, acc1 = f32x16{};
+            const bool pair = R.t1 >= 0 && (ft & (R.P - 1)) == R.part;
+            if (pair) f8b_sweep_pair<NG>(A0, A1, bt, q0, s0, acc0, acc1);
+            else f8b_sweep<NG, false>(A0, bt, q0, q0, s0, s0, acc0, acc1);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc0[r] *= ri0[r];
+            store_tile(a, ch, r0 + R.t0, f0, lane, acc0);
+            if (pair) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc1[r] *= ri1[r];
+                store_tile(a, ch, r0 + R.t1, f0, lane, acc1);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launch
 
 template <int NG>
@@ -391,6 +848,91 @@ static melt_status launch_f8_as(Plan &p, const FwdArgs &a, size_t lds, int grid,
     k_melt_f8_as<NG><<<grid, 64 * w.waves, lds, s>>>(a, (const i32x8 *)p.d_pack_f8, p.d_rowscale, p.N, bf,
                                                      (int)(f8_as_scratch_offset(p, bf) / 4), w.full, w.psplit);
     return hip_check(hipGetLastError(), "melt f8 lds-dma launch");
+}
+
+// LDS of the block-scaled FP8 kernel at bf frames per chunk: E4M3 hop-block rows (stride
+// f8b_stride bytes), block codes, then the FP32 span (16-byte aligned)
+int f8b_stride(const Plan &p) { return lds_stride(p.H, 1); }
+static size_t f8b_codes(const Plan &p, int bf) {
+    const int bph = p.H / 32, ng8 = (p.N + 63) / 64;
+    // the chunk's blocks, and the codes read for blocks past the last frame of a tile
+    return (size_t)std::max((bf + p.geo32.J - 1) * bph, (bf - 1) * bph + 2 * ng8);
+}
+static size_t f8b_codes_offset(const Plan &p, int bf) {
+    return ((size_t)(bf + p.geo32.J - 1) * f8b_stride(p) + 15) & ~size_t(15);
+}
+static size_t f8b_span_offset(const Plan &p, int bf) {
+    return (f8b_codes_offset(p, bf) + f8b_codes(p, bf) * 4 + 15) & ~size_t(15);
+}
+size_t f8b_lds_bytes(const Plan &p, int bf) {
+    return f8b_span_offset(p, bf) + (size_t)(bf + p.geo32.J - 1) * p.H * 4;
+}
+
+template <int NG>
+static melt_status launch_f8b_ng(Plan &p, const FwdArgs &a, const F8BlockTable &bt, size_t lds, int grid, int bf,
+                                 int rg, hipStream_t s) {
+    allow_lds(k_melt_f8b_as<NG>, kRingBytes);
+    const WaveLayout w = wave_layout(p);
+    k_melt_f8b_as<NG><<<grid, 64 * w.waves, lds, s>>>(
+        a, (const i32x8 *)p.d_pack_f8, p.d_rowscale, bt, f8b_stride(p), (int)(f8b_codes_offset(p, bf) / 4),
+        (int)f8b_codes(p, bf), (int)(f8b_span_offset(p, bf) / 4), rg);
+    return hip_check(hipGetLastError(), "melt f8 block-scaled launch");
+}
+
+// LDS of the producer/consumer form: two row/code buffers, then the FP32 span
+static size_t f8b_buf_bytes(const Plan &p, int bf) {
+    return f8b_codes_offset(p, bf) + ((f8b_codes(p, bf) * 4 + 15) & ~size_t(15));
+}
+size_t f8b_pc_lds_bytes(const Plan &p, int bf) {
+    return 2 * f8b_buf_bytes(p, bf) + (size_t)(bf + p.geo32.J - 1) * p.H * 4;
+}
+
+template <int NG>
+static melt_status launch_f8b_pc_ng(Plan &p, const FwdArgs &a, const F8BlockTable &bt, size_t lds, int grid, int bf,
+                                    int rg, hipStream_t s) {
+    allow_lds(k_melt_f8b_pc<NG>, (int)(4 * sizeof(Chunk)));
+    k_melt_f8b_pc<NG><<<grid, 512, lds, s>>>(a, (const i32x8 *)p.d_pack_f8, p.d_rowscale, bt, f8b_stride(p),
+                                             (int)f8b_buf_bytes(p, bf), (int)f8b_codes_offset(p, bf),
+                                             (int)f8b_codes(p, bf), (int)(2 * f8b_buf_bytes(p, bf) / 4), rg);
+    return hip_check(hipGetLastError(), "melt f8 block-scaled producer/consumer launch");
+}
+
+melt_status launch_melt_f8b(Plan &p, const FwdTask &t, int bf, bool pc) {
+    if (p.H % 32 != 0) return set_error(MELT_E_UNSUPPORTED, "FP8 with 32-sample block scales needs hop % 32 == 0");
+    const int ng8 = (p.N + 63) / 64;
+    if (ng8 != 4 && ng8 != 7 && ng8 != 8 && ng8 != 16)
+        return set_error(MELT_E_UNSUPPORTED, "FP8 kernel supports n_fft in (192, 256], (384, 512], (960, 1024]");
+    const Geometry &g = p.geo32;
+    const FwdArgs a = make_args(p, g, lds_stride(g.Hp, 4), t);
+    const size_t lds = pc ? f8b_pc_lds_bytes(p, bf) : f8b_lds_bytes(p, bf);
+    if (lds + kRingBytes > (size_t)kMaxLds)
+        return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS for the FP8 kernel");
+    F8BlockTable bt{};
+    const int S8 = f8b_stride(p);
+    for (int i = 0; i < 2 * ng8; ++i) {
+        const int n = 32 * i;
+        bt.off[i] = n < p.N ? (n / p.H) * S8 + n % p.H : 0;
+    }
+    // one persistent set of workgroups per row group, one workgroup per CU (its eight waves
+    // take two waves' registers per SIMD)
+    const int rg = row_groups(p);
+    const int per_group =
+        (int)std::max<int64_t>(1, std::min<int64_t>(t.est_chunks, ((int64_t)p.cu_count + rg - 1) / rg));
+    const int grid = per_group * rg;
+    if (pc) {
+        switch (ng8) {
+        case 4: return launch_f8b_pc_ng<4>(p, a, bt, lds, grid, bf, rg, t.stream);
+        case 7: return launch_f8b_pc_ng<7>(p, a, bt, lds, grid, bf, rg, t.stream);
+        case 8: return launch_f8b_pc_ng<8>(p, a, bt, lds, grid, bf, rg, t.stream);
+        default: return set_error(MELT_E_UNSUPPORTED, "producer/consumer FP8 kernel: n_fft above 512");
+        }
+    }
+    switch (ng8) {
+    case 4: return launch_f8b_ng<4>(p, a, bt, lds, grid, bf, rg, t.stream);
+    case 7: return launch_f8b_ng<7>(p, a, bt, lds, grid, bf, rg, t.stream);
+    case 8: return launch_f8b_ng<8>(p, a, bt, lds, grid, bf, rg, t.stream);
+    default: return launch_f8b_ng<16>(p, a, bt, lds, grid, bf, rg, t.stream);
+    }
 }
 
 melt_status launch_melt_f8(Plan &p, const FwdTask &t, bool lds_dma, int bf) {

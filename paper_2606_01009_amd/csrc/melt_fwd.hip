@@ -158,11 +158,14 @@ __global__ void k_pack_h16(const float *__restrict__ b32, int M, int N, int H, c
     }
 }
 
-// E4M3 pack of the basis: [rt][group of 64][lane][32 bytes]; lane half h holds k = 64 g + 32 h + byte.
-// Row scales r_j = 448 / max_n |W_j| (FP32); rinv[rt][i] = 1 / r_j of tile row i.  One
-// workgroup of 256 threads per row tile: eight threads per tile row share its maximum, then
-// every thread packs whole 4-byte words.
-__global__ __launch_bounds__(256) void k_pack_f8(const float *__restrict__ b32, int M, int N, int NG,
+// E4M3 pack of the basis: [rt][group of 64][lane][32 bytes].  blocks = 0: lane half h holds
+// k = 64 g + 32 h + byte (any k order serves a product with unit block scales, as long as the
+// frames use the same).  blocks = 1: the order in which the 32x32x64 MFMA's two 32-k scale
+// blocks are whole: bytes 0-15 of half h are k = 64 g + 16 h + byte (block 0), bytes 16-31
+// are k = 64 g + 32 + 16 h + byte - 16 (block 1).  Row scales r_j = 448 / max_n |W_j| (FP32);
+// rinv[rt][i] = 1 / r_j of tile row i.  One workgroup of 256 threads per row tile: eight
+// threads per tile row share its maximum, then every thread packs whole 4-byte words.
+__global__ __launch_bounds__(256) void k_pack_f8(const float *__restrict__ b32, int M, int N, int NG, int blocks,
                                                  unsigned *__restrict__ out, float *__restrict__ rinv) {
     __shared__ float rmax[32];
     const int rt = blockIdx.x, t = threadIdx.x;
@@ -193,7 +196,8 @@ __global__ __launch_bounds__(256) void k_pack_f8(const float *__restrict__ b32, 
         const float sc = mx > 0.0f ? __fdiv_rn(448.0f, mx) : 1.0f;
         float v[4];
         for (int e = 0; e < 4; ++e) {
-            const int k = g * 64 + 32 * (lane >> 5) + 4 * w + e;
+            const int bb = 4 * w + e, h = lane >> 5;
+            const int k = blocks ? g * 64 + 32 * (bb >> 4) + 16 * h + (bb & 15) : g * 64 + 32 * h + bb;
             v[e] = (mel < M && k < N) ? __fmul_rn(b32[(size_t)(part * M + mel) * N + k], sc) : 0.0f;
         }
         out[(((size_t)rt * NG + g) * 64 + lane) * 8 + w] = fp8x4(v[0], v[1], v[2], v[3]);
@@ -230,7 +234,10 @@ melt_status pack_basis(Plan &p, hipStream_t s) {
                                        (float *)p.d_pack_f32);
         break;
     case MELT_PREC_FP8_E4M3:
-        k_pack_f8<<<RT, 256, 0, s>>>(p.d_basis32, p.M, p.N, (p.N + 63) / 64, (unsigned *)p.d_pack_f8, p.d_rowscale);
+    case MELT_PREC_FP8_E4M3_BLOCK32:
+        k_pack_f8<<<RT, 256, 0, s>>>(p.d_basis32, p.M, p.N, (p.N + 63) / 64,
+                                     p.cfg.precision == MELT_PREC_FP8_E4M3_BLOCK32 ? 1 : 0, (unsigned *)p.d_pack_f8,
+                                     p.d_rowscale);
         break;
     default: {
         const int kind_hi = prec_f16(p) ? 1 : 0;
@@ -300,7 +307,10 @@ melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H
 //   BF16X3 / FP16X3  the same without row pairs, with one-span chunks of 96 then 64 frames
 //   FP8        row-split with direct-to-LDS staging (the largest chunk that fits LDS),
 //              row-split with register staging
-enum VariantKind { V_F32_WS, V_F32_FS, V_H16_PP, V_H16_AS, V_H16_AP, V_H16_RS, V_H16_KS, V_H16_FS, V_F8_AS, V_F8_RS };
+//   FP8 with 32-sample block scales  producer/consumer block-scaled kernel, then the
+//              one-buffer block-scaled kernel with 160- and 128-frame chunks
+enum VariantKind { V_F32_WS, V_F32_FS, V_H16_PP, V_H16_AS, V_H16_AP, V_H16_RS, V_H16_KS, V_H16_FS, V_F8_AS, V_F8_RS,
+                   V_F8B_AS, V_F8B_PC };
 struct Variant {
     VariantKind kind;
     int bf;          // frames per chunk
@@ -325,6 +335,19 @@ static std::vector<Variant> variant_list(const Plan &p) {
         if (!v.empty() && v.back().bf > 64 && 2 * (f8_as_lds_bytes(p, 64) + kRingBytes) <= (size_t)kMaxLds)
             v.push_back({V_F8_AS, 64});
         v.push_back({V_F8_RS, kBF32});
+        break;
+    case MELT_PREC_FP8_E4M3_BLOCK32:
+        // producer/consumer (the largest chunk whose two row buffers fit; its waves hold two
+        // basis tiles, so at most 8 k-groups of 64), then the one-buffer kernel at 160- and
+        // 128-frame chunks
+        for (int bf : {128, 96, 64})
+            if ((p.N + 63) / 64 <= 8 && f8b_pc_lds_bytes(p, bf) + kRingBytes <= (size_t)kMaxLds) {
+                v.push_back({V_F8B_PC, bf});
+                break;
+            }
+        for (int bf : {160, 128})
+            if (f8b_lds_bytes(p, bf) + kRingBytes <= (size_t)kMaxLds) v.push_back({V_F8B_AS, bf});
+        if (v.empty()) v.push_back({V_F8B_AS, 32});    // unsupported geometry: the launch reports it
         break;
     default: {
         const bool x3 = prec_split(p);
@@ -402,6 +425,8 @@ const char *forward_variant_name(const Plan &p, int i) {
                     : v.kind == V_H16_KS ? "h16-k-split-lds-dma"
                     : v.kind == V_H16_FS ? "h16-frame-split"
                     : v.kind == V_F8_AS  ? "f8-row-split-lds-dma"
+                    : v.kind == V_F8B_AS ? "f8-block-scaled-lds-dma"
+                    : v.kind == V_F8B_PC ? "f8-block-scaled-producer-consumer-lds-dma"
                                             : "f8-row-split";
     std::snprintf(buf, sizeof(buf), "%s-bf%d", k, v.bf);
     return buf;
@@ -442,6 +467,8 @@ melt_status launch_melt_table(Plan &p, int variant, const Chunk *tab, const int 
     case V_H16_FS: return launch_melt_h16(p, t, H16_FRAME_SPLIT, v.bf);
     case V_F8_AS: return launch_melt_f8(p, t, true, v.bf);
     case V_F8_RS: return launch_melt_f8(p, t, false, v.bf);
+    case V_F8B_AS: return launch_melt_f8b(p, t, v.bf, false);
+    case V_F8B_PC: return launch_melt_f8b(p, t, v.bf, true);
     }
     return set_error(MELT_E_UNSUPPORTED, "precision not implemented");
 }

@@ -30,7 +30,7 @@ def _proj(torch, plan, d_wave, d_off, T):
     return out, P
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp16x3", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp16x3", "fp8", "fp8b"])
 def test_set_basis_repacks_the_plan_precision(torch, melt, prec):
     """A basis scaled by 2 is exact in FP32, BF16, split BF16 and scaled FP8 (whose row
     scales halve exactly), so after set_basis the projections are exactly twice the original

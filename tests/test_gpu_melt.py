@@ -1,7 +1,8 @@
 """GPU parity of the MelT forward (melt_forward / melt_forward_proj) against the FP64 oracle.
 
-FP32: against the plain FP64 oracle (direct NDFT summation).  BF16 / FP16 / split-BF16x3:
-against the oracle's operand model of the same precision (operands rounded exactly as the
+FP32: against the plain FP64 oracle (direct NDFT summation).  BF16 / FP16 / split-BF16x3 /
+split-FP16x3 / FP8 (per-frame and 32-sample block scales): against the oracle's operand model
+of the same precision (operands rounded exactly as the
 format defines, products and sums exact), so the only difference left is FP32
 accumulation.  The pass condition is the per-bin bound of tests/parity.py; the dB error
 against the plain FP64 oracle is reported for every precision.
@@ -58,7 +59,7 @@ def _check(orc, melt, plan, L, wave, off, prec, eps=1e-10, label=""):
         st = parity.check_log_power(L, R, I, Ar, Ai, N, eps, extra_rel=1.0, label=label)
     else:
         code = {"bf16": orc.PREC_BF16, "fp16": orc.PREC_FP16, "bf16x3": orc.PREC_BF16X3,
-                "fp16x3": orc.PREC_FP16X3, "fp8": orc.PREC_FP8_E4M3}[prec]
+                "fp16x3": orc.PREC_FP16X3, "fp8": orc.PREC_FP8_E4M3, "fp8b": orc.PREC_FP8_E4M3_BLOCK32}[prec]
         _, Rq, Iq = orc.melt_forward_quant(wave, off, n_fft=N, hop=plan.hop, Wr=Wr, Wi=Wi, prec=code, eps=eps,
                                            return_ri=True)
         if prec in ("bf16x3", "fp16x3"):
@@ -67,14 +68,16 @@ def _check(orc, melt, plan, L, wave, off, prec, eps=1e-10, label=""):
             _, Aq_r, Aq_i = orc.melt_forward_quant(np.abs(wave), off, n_fft=N, hop=plan.hop, Wr=np.abs(Wr),
                                                    Wi=np.abs(Wi), prec=code, eps=eps, return_ri=True)
             nt = N
-        # FP8: the FP32 epilogue multiplies by 1/s_t and 1/r_j (three more roundings)
-        parity.check_log_power(L, Rq, Iq, Aq_r, Aq_i, nt, eps, extra_rel=4.0 if prec == "fp8" else 0.0, label=label)
+        # FP8: the FP32 epilogue multiplies by 1/s_t and 1/r_j (three more roundings); block-scaled
+        # FP8 by 1/r_j
+        parity.check_log_power(L, Rq, Iq, Aq_r, Aq_i, nt, eps, extra_rel=4.0 if prec in ("fp8", "fp8b") else 0.0,
+                               label=label)
         st = parity.db_stats(L, np.log(R * R + I * I + eps), R * R + I * I)
     print(f"{label}: dB error vs FP64 oracle on active bins: max {st['max_db']:.3g} rms {st['rms_db']:.3g}")
     return st
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp16x3", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp16x3", "fp8", "fp8b"])
 def test_config1_tiny(torch, melt, orc, prec):
     """One 1 s clip at 16 kHz, N=400, H=160, 80 HTK bins, 0-8 kHz: 98 frames."""
     cfg = workloads.config1()
@@ -91,7 +94,7 @@ def test_config1_tiny(torch, melt, orc, prec):
         assert st["max_db"] < 0.5
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3", "fp16x3", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3", "fp16x3", "fp8", "fp8b"])
 @pytest.mark.parametrize("n_mels", [80, 128])
 def test_config2_reduced(torch, melt, orc, prec, n_mels):
     """Config-2 signals at reduced size (4 clips x 2.5 s = 4 x 248 frames: two full 128-frame
@@ -102,7 +105,7 @@ def test_config2_reduced(torch, melt, orc, prec, n_mels):
     _check(orc, melt, plan, L, cfg["wave"], cfg["offsets"], prec, label=f"config2-reduced M={n_mels} {prec}")
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "fp8", "fp8b"])
 def test_ragged_edge_cases(torch, melt, orc, prec):
     """Empty clips, clips shorter than a frame, exactly one frame, one sample more, and
     lengths that end chunks at every residue."""
@@ -130,7 +133,7 @@ def test_many_clips_schedule(torch, melt, orc, prec):
     _check(orc, melt, plan, L, wave, off, prec, label=f"2600 clips {prec}")
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp16", "bf16x3", "fp16x3", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "bf16x3", "fp16x3", "fp8", "fp8b"])
 def test_chunk_ring_refill(torch, melt, orc, prec):
     """20 000 clips of one to four frames, one chunk each: a persistent workgroup of the
     direct-to-LDS and producer/consumer kernels walks 39 or more chunks, so it reads chunk
@@ -169,7 +172,7 @@ def test_chunk_ring_refill_ksplit(torch, melt, orc, prec):
     _check(orc, melt, plan, L, wave, off, prec, label=f"20000 clips K-split {prec}")
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp16x3", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp16x3", "fp8", "fp8b"])
 def test_every_kernel_variant(torch, melt, orc, prec):
     """Every kernel variant of the precision (staging scheme x frames per chunk), pinned with
     melt_set_variant, on clips that end chunks of 64, 96 and 128 frames exactly, one frame
@@ -183,6 +186,10 @@ def test_every_kernel_variant(torch, melt, orc, prec):
              (16000, 400, 160, 144), (16000, 400, 160, 256)]
     if prec == "fp8":
         geoms = geoms[:1]
+    elif prec == "fp8b":
+        # hops that are whole 32-sample blocks; 9 and 16 row tiles are row groups of 5 + 4 and
+        # 8 + 8; N 1024 (16 k-groups of 64) and N 256 (4)
+        geoms = [g for g in geoms if g[2] % 32 == 0] + [(22050, 1024, 256, 128), (16000, 256, 128, 80)]
     elif prec == "fp32":
         geoms = geoms[:3]
     elif prec in ("bf16", "fp16"):
@@ -231,8 +238,9 @@ def test_other_geometries(torch, melt, orc, geom):
     lengths = [N - 1, N, 5 * N + 7, 31 * H + N, 2 * 128 * H + N + 3]
     wave, off = workloads.random_clips(lengths, seed=9)
     # FP8 too: every geometry here has an FP8 register tile (N 256, 400, 512, 1024), and 128
-    # Mel bins put a row tile on every wave of the FP8 kernel
-    for prec in ("fp32", "bf16", "fp8"):
+    # Mel bins put a row tile on every wave of the FP8 kernel; block-scaled FP8 where the hop
+    # is whole 32-sample blocks
+    for prec in ("fp32", "bf16", "fp8") + (("fp8b",) if H % 32 == 0 else ()):
         plan = melt.MeltPlan(sample_rate=sr, n_fft=N, hop=H, n_mels=M, precision=prec)
         L, _ = _gpu_forward(torch, melt, plan, wave, off)
         _check(orc, melt, plan, L, wave, off, prec, label=f"geometry {geom} {prec}")
@@ -243,7 +251,7 @@ def test_config3_precision_sweep(torch, melt, orc):
     4 clips x 2 s: every precision against its operand model (pass condition) and the dB
     error against the FP64 oracle per 10 dB band below each frame's peak (reported)."""
     cfg = workloads.config3(n_clips=4, seconds=2.0)
-    for prec in ("fp32", "fp16x3", "bf16x3", "fp16", "bf16", "fp8"):
+    for prec in ("fp32", "fp16x3", "bf16x3", "fp16", "bf16", "fp8", "fp8b"):
         plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80, precision=prec)
         L, _ = _gpu_forward(torch, melt, plan, cfg["wave"], cfg["offsets"])
         st = _check(orc, melt, plan, L, cfg["wave"], cfg["offsets"], prec, label=f"config3 {prec}")
@@ -365,7 +373,7 @@ def test_plan_centres_and_basis_match_oracle(torch, melt, orc, formula, placemen
         plan.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "fp8b"])
 def test_window_formula_placement_forward(torch, melt, orc, prec):
     """The periodic and rectangular windows, the Slaney scale and the M-point placement
     through the forward kernels on a 1 s clip, against the oracle's own basis."""
@@ -380,7 +388,7 @@ def test_window_formula_placement_forward(torch, melt, orc, prec):
         _check(orc, melt, plan, L, cfg["wave"], cfg["offsets"], prec, label=f"options {o} {prec}")
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp8", "fp8b"])
 def test_spectral_band_80_7600(torch, melt, orc, prec):
     """The paper's spectral front end (16 kHz, N 400, H 160, 80 Mel bins over 80-7600 Hz;
     Table "Audio frontend configuration") on config-2 signals, 4 clips x 2.5 s."""
@@ -390,11 +398,11 @@ def test_spectral_band_80_7600(torch, melt, orc, prec):
     _check(orc, melt, plan, L, cfg["wave"], cfg["offsets"], prec, label=f"80-7600 Hz {prec}")
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp8b"])
 def test_512_mel_bins(torch, melt, orc, prec):
     """The top of the Mel-bin sweep (M = 512, the paper's break-even point; Fig. m_sweep) over
-    80-7600 Hz: 32 row tiles, so four 16-bit row groups and, for FP32, several row-tile
-    blocks per chunk.  2 clips x 2 s (two full chunks and a ragged tail each)."""
+    80-7600 Hz: 32 row tiles, so four 16-bit (and block-scaled FP8) row groups and, for FP32,
+    several row-tile blocks per chunk.  2 clips x 2 s (two full chunks and a ragged tail each)."""
     cfg = workloads.config2(n_mels=512, n_clips=2, seconds=2.0)
     plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=512, fmin=80.0, fmax=7600.0, precision=prec)
     L, _ = _gpu_forward(torch, melt, plan, cfg["wave"], cfg["offsets"])
@@ -411,7 +419,7 @@ def test_512_mel_bins_fp8_unsupported(torch, melt):
     assert ei.value.status == melt.MELT_E_UNSUPPORTED
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "fp8b"])
 def test_hop_equals_n_fft(torch, melt, orc, prec):
     """Adjacent frames with no overlap (hop = n_fft = 256): one hop segment per frame."""
     lengths = [0, 255, 256, 257, 511, 512, 256 * 130 + 7, 256 * 300]
@@ -420,6 +428,47 @@ def test_hop_equals_n_fft(torch, melt, orc, prec):
     L, _ = _gpu_forward(torch, melt, plan, wave, off)
     assert L.shape[0] == sum(melt.melt_num_frames(n, 256, 256) for n in lengths)
     _check(orc, melt, plan, L, wave, off, prec, label=f"hop = n_fft {prec}")
+
+
+def test_block_scaled_fp8_extreme_blocks(torch, melt, orc):
+    """Block-scaled FP8 over the whole exponent range: a clip at 1e-37 (blocks whose exponent is
+    the largest allowed, 127: the kernel's plain-conversion path), one at 3e3 (negative
+    exponents), one of normal level with silent stretches (exponent 0), checked through the
+    raw projections, clip by clip, against the operand model within the FP32 accumulation bound
+    (the projections of the quiet clip are far below the log floor)."""
+    rng = np.random.default_rng(61)
+    lens = [4000, 4000, 4000]
+    x = rng.standard_normal(sum(lens)).astype(np.float32)
+    # the quiet clip stays in FP32's normal range (|x| >= 3e-38)
+    x[:4000] = np.where(np.abs(x[:4000]) < 0.3, np.copysign(0.3, x[:4000]), x[:4000]) * np.float32(1e-37)
+    x[4000:8000] *= np.float32(3e3)
+    x[8000 + 1000:8000 + 2000] = 0.0
+    off = np.array([0, 4000, 8000, 12000], np.int64)
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80, precision="fp8b")
+    _, P = _gpu_forward(torch, melt, plan, x, off, proj=True)
+    _, Wr, Wi = parity.oracle_basis(orc, plan.cfg)
+    _, Rq, Iq = orc.melt_forward_quant(x, off, n_fft=400, hop=160, Wr=Wr, Wi=Wi, prec=orc.PREC_FP8_E4M3_BLOCK32,
+                                       return_ri=True)
+    _, Ar, Ai = orc.melt_forward_quant(np.abs(x), off, n_fft=400, hop=160, Wr=np.abs(Wr), Wi=np.abs(Wi),
+                                       prec=orc.PREC_FP8_E4M3_BLOCK32, return_ri=True)
+    g = 405 * parity.U32
+    assert np.all(np.abs(P[:, 0::2] - Rq) <= g * Ar + 1e-45)
+    assert np.all(np.abs(P[:, 1::2] - Iq) <= g * Ai + 1e-45)
+    assert np.abs(Rq[:20]).max() > 0 and np.abs(P[:20, 0::2]).max() < 1e-30
+
+
+def test_block_scaled_fp8_needs_whole_block_hops(torch, melt):
+    """Block-scaled FP8 needs a hop of whole 32-sample blocks (reported at plan creation); the
+    frame length needs an FP8 register tile (reported at the call)."""
+    with pytest.raises(melt.MeltError) as ei:
+        melt.MeltPlan(sample_rate=16000, n_fft=400, hop=100, n_mels=80, precision="fp8b")
+    assert ei.value.status == melt.MELT_E_UNSUPPORTED
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=1200, hop=160, n_mels=80, precision="fp8b")
+    wave = torch.zeros(16000, dtype=torch.float32, device="cuda")
+    off = torch.tensor([0, 16000], dtype=torch.int64, device="cuda")
+    with pytest.raises(melt.MeltError) as ei:
+        plan.forward(wave, off, melt.melt_num_frames(16000, 1200, 160))
+    assert ei.value.status == melt.MELT_E_UNSUPPORTED
 
 
 def test_frame_offsets(torch, melt, orc):

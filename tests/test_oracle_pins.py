@@ -534,6 +534,81 @@ def test_split_fp16_model_against_numpy_float16(orc):
     assert not np.all(np.isfinite(qo[:3])) and np.all(np.isfinite(qo[4:]))
 
 
+def test_block_exponent_is_the_largest_fitting_power_of_two(orc):
+    """The block exponent is the largest integer e with 2^e m <= 448 (so 2^(e+1) m > 448),
+    within the E8M0-undoable range [-127, 127], and 0 for a silent block."""
+    rng = np.random.default_rng(5)
+    m = np.concatenate([10.0 ** rng.uniform(-30, 30, 4000),
+                        [448.0, 449.0, 224.0, 1.0, 1.75, 1.76, 3.5, 2.0 ** -100, 1e-37, 3e38]]).astype(np.float32)
+    e = orc.block_exponent(m)
+    m64 = m.astype(np.float64)
+    assert np.all(np.ldexp(m64, e) <= 448.0)
+    free = (e > -127) & (e < 127)
+    assert np.all(np.ldexp(m64[free], e[free] + 1) > 448.0)
+    assert orc.block_exponent(np.float32(0.0)) == 0
+    assert list(orc.block_exponent(np.array([448, 449, 1.0, 1.76], np.float32))) == [0, -1, 8, 7]
+
+
+def test_block_scaled_fp8_model_against_torch_float8(orc):
+    """The FP8 block-scaled operand model (32-sample blocks from each clip's first sample,
+    samples scaled by 2^e_b and cast to E4M3, basis rows scaled by 448 / max|row| and cast)
+    equals the same steps written with torch's float8_e4m3fn casts and numpy block maxima, on
+    two clips of uneven length and 80 dB of dynamics; scaling the waveform by a power of two
+    scales R and I by exactly that power; on loud bins its error against the exact projection
+    is that of 3-bit significands."""
+    import torch
+    N, H, sr = 400, 160, 16000.0
+    f = orc.melt_frequencies(16, 0, 8000)
+    Wr, Wi = orc.melt_basis(sr=sr, n_fft=N, freqs=f)
+    lens = [2000, 1333]
+    gains = np.concatenate([np.repeat(10.0 ** np.linspace(-4, 0, 5), 400), np.full(1333, 0.3)])
+    x = (_frame(sum(lens), 17) * gains).astype(np.float32)
+    off = np.array([0, lens[0], sum(lens)], np.int64)
+    _, R, I = orc.melt_forward_quant(x, off, n_fft=N, hop=H, Wr=Wr, Wi=Wi, prec=orc.PREC_FP8_E4M3_BLOCK32,
+                                     return_ri=True)
+
+    def e4m3(v):
+        return torch.from_numpy(np.ascontiguousarray(v, np.float32)).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+
+    def block_exp(mx):
+        # largest e with 2^e mx <= 448, by brute force over the whole range
+        es = np.arange(-127, 128)
+        ok = np.ldexp(mx[:, None], es[None, :]) <= 448.0
+        return np.where(mx > 0, es[np.where(ok, es[None, :], -999).argmax(axis=1)], 0)
+
+    xq = np.zeros(x.size)
+    for c in range(2):
+        seg = x[off[c]:off[c + 1]]
+        nb = (seg.size + 31) // 32
+        pad = np.zeros(nb * 32, np.float32)
+        pad[:seg.size] = seg
+        e = block_exp(np.abs(pad.reshape(nb, 32)).max(axis=1).astype(np.float64))
+        ee = np.repeat(e, 32)[:seg.size]
+        scaled = (seg.astype(np.float64) * np.ldexp(1.0, ee)).astype(np.float32)    # exact
+        xq[off[c]:off[c + 1]] = np.ldexp(e4m3(scaled), -ee)
+    row = 0
+    for c in range(2):
+        T = 1 + (lens[c] - N) // H
+        for W, P in ((Wr, R), (Wi, I)):
+            W32 = W.astype(np.float32)
+            rs = np.float32(448.0) / np.abs(W32).max(axis=1)
+            Wq = e4m3(W32 * rs[:, None]) / rs[:, None].astype(np.float64)
+            for t in range(T):
+                terms = Wq * xq[off[c] + t * H:off[c] + t * H + N]
+                ref = terms.sum(axis=1)
+                assert np.all(np.abs(P[row + t] - ref) <= 1e-12 * np.abs(terms).sum(axis=1) + 1e-300)
+        row += T
+    # power-of-two equivariance: every block exponent shifts, the E4M3 codes stay the same
+    for k in (-7, 5):
+        _, R2, I2 = orc.melt_forward_quant(np.ldexp(x, k).astype(np.float32), off, n_fft=N, hop=H, Wr=Wr, Wi=Wi,
+                                           prec=orc.PREC_FP8_E4M3_BLOCK32, return_ri=True)
+        assert np.array_equal(R2, np.ldexp(R, k)) and np.array_equal(I2, np.ldexp(I, k))
+    exact = orc.melt_forward_basis(x, off, n_fft=N, hop=H, Wr=Wr, Wi=Wi, out_kind=orc.OUT_POWER)
+    q = R ** 2 + I ** 2
+    loud = exact > 1e-2 * exact.max(axis=1, keepdims=True)
+    assert np.median(np.abs(q[loud] / exact[loud] - 1)) < 0.1
+
+
 # ------------------------------------------------------------------ values the paper prints
 
 def test_paper_log_convention(orc):

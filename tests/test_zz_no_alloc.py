@@ -44,6 +44,7 @@ def _both(torch, melt, plan, wave, off):
 
 @pytest.mark.parametrize("prec,geom", [("fp32", (16000, 400, 160, 80)), ("bf16", (16000, 400, 160, 80)),
                                        ("fp16", (16000, 512, 128, 128)), ("fp8", (16000, 400, 160, 80)),
+                                       ("fp8b", (16000, 400, 160, 80)),
                                        ("bf16x3", (16000, 400, 160, 80)), ("fp16x3", (16000, 400, 160, 80)),
                                        ("bf16", (22050, 1024, 256, 128))])
 def test_noalloc_equals_forward(torch, melt, prec, geom):
