@@ -730,6 +730,7 @@ melt_status launch_melt_f8(Plan &p, const FwdTask &t, bool lds_dma, int bf);
 size_t f8_as_lds_bytes(const Plan &p, int bf);   // LDS of the direct-to-LDS FP8 kernel
 melt_status launch_melt_f8b(Plan &p, const FwdTask &t, int bf, bool pc);   // FP8 with 32-sample block scales
 size_t f8b_lds_bytes(const Plan &p, int bf);
-size_t f8b_pc_lds_bytes(const Plan &p, int bf);   // its producer/consumer form
+size_t f8b_pc_lds_bytes(const Plan &p, int bf);   // its producer/consumer form (dynamic LDS)
+size_t f8b_pc_static_bytes();
 
 }  // namespace melt

@@ -597,53 +597,17 @@ __global__ __launch_bounds__(512) void k_melt_f8b_as(
 // ------------------------------------------------------------------ FP8 block-scaled, producer/consumer
 //
 // The arithmetic of k_melt_f8b_as, with a chunk's conversion and its multiplies on different
-// waves so that they overlap (the conversion is vector-ALU work, the multiplies matrix-core
-// and LDS work).  Waves 4-7 (producers) own the 256-sample blocks b = w, w + 4, ... of every
-// chunk's span (w = wave - 4): each copies its blocks HBM -> LDS (direct-to-LDS) and converts
-// exactly those into E4M3 rows and block codes, so no producer waits for another.  Waves 0-3
-// (consumers) multiply.  Two row/code buffers alternate: in iteration k the consumers multiply
+// waves so that they overlap (the conversion is vector-ALU and LDS work, the multiplies
+// matrix-core and LDS work).  A workgroup of 12 waves: the first NC = (row tiles of the group)
+// are consumers, one basis tile each, the other NP = 12 - NC producers.  Producer w owns the
+// 256-sample blocks b = w, w + NP, ... of every chunk's span: it copies its blocks HBM -> LDS
+// (direct-to-LDS) and converts exactly those into E4M3 rows and block codes, so no producer
+// waits for another.  Two row/code buffers alternate: in iteration k the consumers multiply
 // chunk k from one while the producers convert chunk k + 1 into the other and start the copy
-// of chunk k + 2, with one barrier per chunk.  Consumer c owns row tile c and, past four tiles,
-// a share of the rest (f8_role); a frame tile it holds two row tiles of is swept once for both,
-// each fragment read feeding two MFMAs.  Chunk descriptors pass through a four-slot LDS ring:
-// wave 4 loads descriptor k + 3 in iteration k and stores it before the barrier (slot
-// (k + 3) mod 4 was last read in iteration k - 1).
-
-struct F8Role {
-    int t0, t1, part, P;    // own tile (-1: none), second tile on frame tiles = part mod P (-1: none)
-};
-__device__ __forceinline__ F8Role f8_role(int cnt, int c) {
-    if (c >= cnt) return {-1, -1, 0, 1};
-    if (cnt <= 4) return {c, -1, 0, 1};
-    if (cnt == 5) return {c, 4, c, 4};
-    if (cnt == 6) return {c, 4 + (c >> 1), c & 1, 2};
-    return {c, 4 + c < cnt ? 4 + c : -1, 0, 1};
-}
-
-// one 32-frame tile against two basis tiles: per k-group one fragment (two 16-byte reads) and
-// one code, two MFMAs
-template <int NG, int D = 2>
-__device__ __forceinline__ void f8b_sweep_pair(const i32x8 (&A0)[NG], const i32x8 (&A1)[NG], const F8BlockTable &bt,
-                                               const unsigned char *q0, const int *s0, f32x16 &acc0, f32x16 &acc1) {
-    i32x8 b[D];
-    int cd[D];
-    auto fetch = [&](int g, int slot) {
-        const uint4 l = *(const uint4 *)(q0 + bt.off[2 * g]), h = *(const uint4 *)(q0 + bt.off[2 * g + 1]);
-        b[slot] = i32x8{(int)l.x, (int)l.y, (int)l.z, (int)l.w, (int)h.x, (int)h.y, (int)h.z, (int)h.w};
-        cd[slot] = s0[2 * g];
-    };
-#pragma unroll
-    for (int g = 0; g < D && g < NG; ++g) fetch(g, g);
-#pragma unroll
-    for (int g = 0; g < NG; ++g) {
-        const int slot = g % D;
-        __builtin_amdgcn_sched_barrier(0);
-        acc0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A0[g], b[slot], acc0, 0, 0, 0, 127, 0, cd[slot]);
-        acc1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A1[g], b[slot], acc1, 0, 0, 0, 127, 0, cd[slot]);
-        if (g + D < NG) fetch(g + D, slot);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-}
+// of chunk k + 2, with one barrier per chunk.  Three waves per SIMD: a consumer holds one
+// basis tile (8 NG registers) and sweeps one frame tile at a time.  Chunk descriptors pass
+// through a four-slot LDS ring: the first producer loads descriptor k + 3 in iteration k and
+// stores it before the barrier (slot (k + 3) mod 4 was last read in iteration k - 1).
 
 // the copies of one 256-sample block b of the chunk's valid span into the span: one 16-byte
 // copy if the block is whole, else 4-byte copies of its valid samples
@@ -666,7 +630,7 @@ __device__ __forceinline__ void copy_block(const float *src, unsigned base, int 
 template <bool NEXT>
 __device__ __forceinline__ void convert_owned8(const FwdArgs &a, const Chunk &ch, float *span,
                                                unsigned char *rows8, int S8, int *codes, float inv_bph, int pw,
-                                               const Chunk &nx) {
+                                               int np, const Chunk &nx) {
     const int lane = threadIdx.x & 63;
     const int span_len = (ch.n_frames + a.J - 1) * a.H;
     const int nblk = span_len >> 5, n256 = (span_len + 255) >> 8;
@@ -676,29 +640,29 @@ __device__ __forceinline__ void convert_owned8(const FwdArgs &a, const Chunk &ch
     const int nvalid = NEXT ? span_valid(a, nx) : 0;
     const unsigned base = __builtin_amdgcn_readfirstlane(lds_addr(span));
     int b0 = pw;
-    for (; b0 < n256; b0 += 32) {
-        const int fb = 8 * (b0 + 4 * (lane >> 3)) + (lane & 7);
-        // every lane's block before the clip end: the last lane's block is 8 (b0 + 28) + 7
-        const bool whole = 256 * (b0 + 29) <= valid;
+    for (; b0 < n256; b0 += 8 * np) {
+        const int fb = 8 * (b0 + np * (lane >> 3)) + (lane & 7);
+        // every lane's block before the clip end: the last lane's block is 8 (b0 + 7 np) + 7
+        const bool whole = 256 * (b0 + 7 * np + 1) <= valid;
         if (fb < nblk) convert_lane_block<false>(span, valid, whole, fb, rows8 + block_row_byte(fb, inv_bph, pad), codes);
         if constexpr (NEXT) {
             // the blocks just read may be overwritten by the next chunk's copies
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (256 * (b0 + 4 * u) < nvalid) copy_block(nsrc, base, nvalid, b0 + 4 * u);
+                if (256 * (b0 + np * u) < nvalid) copy_block(nsrc, base, nvalid, b0 + np * u);
         }
     }
     if constexpr (NEXT) {
-        for (; 256 * b0 < nvalid; b0 += 4) copy_block(nsrc, base, nvalid, b0);
+        for (; 256 * b0 < nvalid; b0 += np) copy_block(nsrc, base, nvalid, b0);
     }
 }
 
 // a producer's copies of its blocks of a chunk's valid span (no conversion pending)
-__device__ __forceinline__ void copy_owned(const FwdArgs &a, const Chunk &ch, float *span, int pw) {
+__device__ __forceinline__ void copy_owned(const FwdArgs &a, const Chunk &ch, float *span, int pw, int np) {
     const int valid = span_valid(a, ch);
     const float *src = a.wave + ch.sample_start;
     const unsigned base = __builtin_amdgcn_readfirstlane(lds_addr(span));
-    for (int b = pw; 256 * b < valid; b += 4) copy_block(src, base, valid, b);
+    for (int b = pw; 256 * b < valid; b += np) copy_block(src, base, valid, b);
 }
 
 __device__ __forceinline__ Chunk slot_get(const Chunk *slots, int i) {
@@ -712,18 +676,21 @@ __device__ __forceinline__ Chunk slot_get(const Chunk *slots, int i) {
 }
 
 template <int NG>
-__global__ __launch_bounds__(512) void k_melt_f8b_pc(FwdArgs a, const i32x8 *__restrict__ bq,
+__global__ __launch_bounds__(768) void k_melt_f8b_pc(FwdArgs a, const i32x8 *__restrict__ bq,
                                                     const float *__restrict__ rinv_g, F8BlockTable bt, int S8,
                                                     int buf_bytes, int code_off, int n_codes, int scr_off,
                                                     int rgroups) {
     extern __shared__ float lds_pc[];
     __shared__ Chunk dslot[4];
+    __shared__ float rinv_s[8 * 32];
     const int lane = threadIdx.x & 63;
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
     const int grp = blockIdx.x % rgroups, gt_n = (a.row_tiles + rgroups - 1) / rgroups;
     const int r0 = grp * gt_n, cnt = min(a.row_tiles - r0, gt_n);
-    const bool producer = wid >= 4;
-    const int pw = wid - 4;
+    for (int i = threadIdx.x; i < 32 * cnt; i += blockDim.x) rinv_s[i] = rinv_g[32 * r0 + i];
+    const int nc = cnt, np = nw - cnt;             // consumers (one row tile each), producers
+    const bool producer = wid >= nc;
+    const int pw = wid - nc;
     unsigned char *buf0 = reinterpret_cast<unsigned char *>(lds_pc);
     float *span = lds_pc + scr_off;
     const int bph = a.H >> 5;
@@ -741,58 +708,47 @@ __global__ __launch_bounds__(512) void k_melt_f8b_pc(FwdArgs a, const i32x8 *__r
     // buffer 0 and start the copy of chunk 1.  Producers and consumers then run loops of their
     // own (so that neither role's registers are live in the other's), with one barrier per
     // chunk in both.
-    if (wid == 4 && lane < 3 && c0 + lane * cstep < nch) dslot[lane] = a.chunks[c0 + lane * cstep];
+    if (wid == nc && lane < 3 && c0 + lane * cstep < nch) dslot[lane] = a.chunks[c0 + lane * cstep];
     if (producer) {
         if (c0 < nch) {
             const Chunk ch = read_chunk(a.chunks, c0);
-            copy_owned(a, ch, span, pw);
+            copy_owned(a, ch, span, pw, np);
             async_wait();
             if (c0 + cstep < nch)
                 convert_owned8<true>(a, ch, span, buf0, S8, reinterpret_cast<int *>(buf0 + code_off), inv_bph, pw,
-                                     read_chunk(a.chunks, c0 + cstep));
+                                     np, read_chunk(a.chunks, c0 + cstep));
             else
                 convert_owned8<false>(a, ch, span, buf0, S8, reinterpret_cast<int *>(buf0 + code_off), inv_bph, pw,
-                                      ch);
+                                      np, ch);
         }
         for (int it = 0; c0 + it * cstep < nch; ++it) {
             __syncthreads();                       // chunk it converted; buffer (it + 1) & 1 free
             const int c = c0 + it * cstep;
             if (c + cstep >= nch) continue;
             Chunk nd{};
-            const bool load_desc = wid == 4 && c + 3 * cstep < nch;
+            const bool load_desc = wid == nc && c + 3 * cstep < nch;
             async_wait();                          // this producer's copies of chunk it + 1
             if (load_desc) nd = a.chunks[c + 3 * cstep];
             const Chunk ch1 = slot_get(dslot, (it + 1) & 3);
             unsigned char *rows = buf0 + ((it + 1) & 1) * buf_bytes;
             int *codes = reinterpret_cast<int *>(rows + code_off);
             if (c + 2 * cstep < nch)
-                convert_owned8<true>(a, ch1, span, rows, S8, codes, inv_bph, pw, slot_get(dslot, (it + 2) & 3));
+                convert_owned8<true>(a, ch1, span, rows, S8, codes, inv_bph, pw, np, slot_get(dslot, (it + 2) & 3));
             else
-                convert_owned8<false>(a, ch1, span, rows, S8, codes, inv_bph, pw, ch1);
+                convert_owned8<false>(a, ch1, span, rows, S8, codes, inv_bph, pw, np, ch1);
             if (load_desc && lane == 0) dslot[(it + 3) & 3] = nd;
         }
         return;
     }
-    const F8Role R = f8_role(cnt, wid);
-    i32x8 A0[NG], A1[NG];
-    float ri0[16], ri1[16];
-    if (R.t0 >= 0) {
-        const int t0 = r0 + R.t0, t1 = r0 + (R.t1 >= 0 ? R.t1 : R.t0);
+    const int rt = r0 + wid;
+    i32x8 A[NG];
 #pragma unroll
-        for (int g = 0; g < NG; ++g) {
-            A0[g] = bq[((size_t)t0 * NG + g) * 64 + lane];
-            A1[g] = bq[((size_t)t1 * NG + g) * 64 + lane];
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            ri0[r] = rinv_g[t0 * 32 + i];
-            ri1[r] = rinv_g[t1 * 32 + i];
-        }
-    }
+    for (int g = 0; g < NG; ++g) A[g] = bq[((size_t)rt * NG + g) * 64 + lane];
+    // the tile's row unscaling factors in LDS (read in the epilogue, not held in registers):
+    // lane half h uses rows 8 q + 4 h .. + 3 of the tile, four consecutive floats per q
+    const float *ri = rinv_s + 32 * wid + 4 * (lane >> 5);
     for (int it = 0; c0 + it * cstep < nch; ++it) {
         __syncthreads();                           // chunk it converted; buffer (it + 1) & 1 free
-        if (R.t0 < 0) continue;
         const Chunk ch = slot_get(dslot, it & 3);
         const unsigned char *rows = buf0 + (it & 1) * buf_bytes;
         const int *codes = reinterpret_cast<const int *>(rows + code_off);
@@ -803,18 +759,15 @@ __global__ __launch_bounds__(512) void k_melt_f8b_pc(FwdArgs a, const i32x8 *__r
             asm volatile("" : "+v"(off));
             const unsigned char *q0 = rows + off;
             const int *s0 = codes + f0 * bph + (lane >> 5);
-            f32x16 acc0 = f32x16{}, acc1 = f32x16{};
-            const bool pair = R.t1 >= 0 && (ft & (R.P - 1)) == R.part;
-            if (pair) f8b_sweep_pair<NG>(A0, A1, bt, q0, s0, acc0, acc1);
-            else f8b_sweep<NG, false>(A0, bt, q0, q0, s0, s0, acc0, acc1);
+            f32x16 acc = f32x16{}, unused = f32x16{};
+            f8b_sweep<NG, false>(A, bt, q0, q0, s0, s0, acc, unused);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc0[r] *= ri0[r];
-            store_tile(a, ch, r0 + R.t0, f0, lane, acc0);
-            if (pair) {
+            for (int q = 0; q < 4; ++q) {
+                const f32x4 r4 = *(const f32x4 *)(ri + 8 * q);
 #pragma unroll
-                for (int r = 0; r < 16; ++r) acc1[r] *= ri1[r];
-                store_tile(a, ch, r0 + R.t1, f0, lane, acc1);
+                for (int e = 0; e < 4; ++e) acc[4 * q + e] *= r4[e];
             }
+            store_tile(a, ch, rt, f0, lane, acc);
         }
     }
 }
@@ -886,12 +839,14 @@ static size_t f8b_buf_bytes(const Plan &p, int bf) {
 size_t f8b_pc_lds_bytes(const Plan &p, int bf) {
     return 2 * f8b_buf_bytes(p, bf) + (size_t)(bf + p.geo32.J - 1) * p.H * 4;
 }
+// its static LDS: the descriptor slots and the row unscaling factors of a row group
+size_t f8b_pc_static_bytes() { return 4 * sizeof(Chunk) + 8 * 32 * sizeof(float); }
 
 template <int NG>
 static melt_status launch_f8b_pc_ng(Plan &p, const FwdArgs &a, const F8BlockTable &bt, size_t lds, int grid, int bf,
                                     int rg, hipStream_t s) {
-    allow_lds(k_melt_f8b_pc<NG>, (int)(4 * sizeof(Chunk)));
-    k_melt_f8b_pc<NG><<<grid, 512, lds, s>>>(a, (const i32x8 *)p.d_pack_f8, p.d_rowscale, bt, f8b_stride(p),
+    allow_lds(k_melt_f8b_pc<NG>, (int)f8b_pc_static_bytes());
+    k_melt_f8b_pc<NG><<<grid, 768, lds, s>>>(a, (const i32x8 *)p.d_pack_f8, p.d_rowscale, bt, f8b_stride(p),
                                              (int)f8b_buf_bytes(p, bf), (int)f8b_codes_offset(p, bf),
                                              (int)f8b_codes(p, bf), (int)(2 * f8b_buf_bytes(p, bf) / 4), rg);
     return hip_check(hipGetLastError(), "melt f8 block-scaled producer/consumer launch");
@@ -905,7 +860,7 @@ melt_status launch_melt_f8b(Plan &p, const FwdTask &t, int bf, bool pc) {
     const Geometry &g = p.geo32;
     const FwdArgs a = make_args(p, g, lds_stride(g.Hp, 4), t);
     const size_t lds = pc ? f8b_pc_lds_bytes(p, bf) : f8b_lds_bytes(p, bf);
-    if (lds + kRingBytes > (size_t)kMaxLds)
+    if (lds + (pc ? f8b_pc_static_bytes() : (size_t)kRingBytes) > (size_t)kMaxLds)
         return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS for the FP8 kernel");
     F8BlockTable bt{};
     const int S8 = f8b_stride(p);

@@ -337,11 +337,11 @@ static std::vector<Variant> variant_list(const Plan &p) {
         v.push_back({V_F8_RS, kBF32});
         break;
     case MELT_PREC_FP8_E4M3_BLOCK32:
-        // producer/consumer (the largest chunk whose two row buffers fit; its waves hold two
-        // basis tiles, so at most 8 k-groups of 64), then the one-buffer kernel at 160- and
+        // producer/consumer (the largest chunk whose two row buffers fit; three waves per SIMD,
+        // so a basis tile of at most 8 k-groups of 64), then the one-buffer kernel at 160- and
         // 128-frame chunks
         for (int bf : {128, 96, 64})
-            if ((p.N + 63) / 64 <= 8 && f8b_pc_lds_bytes(p, bf) + kRingBytes <= (size_t)kMaxLds) {
+            if ((p.N + 63) / 64 <= 8 && f8b_pc_lds_bytes(p, bf) + f8b_pc_static_bytes() <= (size_t)kMaxLds) {
                 v.push_back({V_F8B_PC, bf});
                 break;
             }
