@@ -682,6 +682,19 @@ inline bool pp_fits(const Plan &p) {
     return true;
 }
 
+// 12-wave producer/consumer 16-bit kernel: two operand-row buffers (16-byte aligned each), then
+// the FP32 span; consumers hold one basis tile of at most 25 k-groups (three waves per SIMD)
+inline size_t pc_rows_bytes(const Plan &p, int bf) {
+    return ((size_t)(bf + p.geo16.J - 1) * lds_stride(p.geo16.Hp, 2) * 2 + 15) & ~size_t(15);
+}
+inline size_t pc_lds_bytes(const Plan &p, int bf) {
+    return 2 * pc_rows_bytes(p, bf) + (size_t)(bf + p.geo16.J - 1) * p.H * 4;
+}
+inline bool pc_fits(const Plan &p) {
+    const int ng = p.geo16.n_groups;
+    return ng == 10 || ng == 16 || ng == 20 || ng == 25;
+}
+
 // K-split 16-bit kernel (frames too long for one wave's basis tile): two waves per row tile,
 // the first holding the k-groups of the first J0 hop segments (ns0 groups), the second the
 // rest (ns1 <= ns0 groups).  The split must leave the second half's groups at the first
@@ -724,7 +737,7 @@ inline size_t ks_lds_bytes(const Plan &p, int bf) {
 // per-family launchers (melt_f32.hip, melt_h16.hip, melt_f8.hip)
 melt_status launch_melt_f32(Plan &p, const FwdTask &t, bool warp_specialised);
 enum H16Kind { H16_LDS_DMA = 0, H16_REGISTER_STAGED = 1, H16_FRAME_SPLIT = 2, H16_K_SPLIT = 3, H16_PIPELINED = 4,
-               H16_ROW_PAIR = 5 };
+               H16_ROW_PAIR = 5, H16_PC12 = 6 };
 melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf, int nbuf = 1);
 melt_status launch_melt_f8(Plan &p, const FwdTask &t, bool lds_dma, int bf);
 size_t f8_as_lds_bytes(const Plan &p, int bf);   // LDS of the direct-to-LDS FP8 kernel

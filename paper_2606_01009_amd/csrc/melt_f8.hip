@@ -658,7 +658,7 @@ __device__ __forceinline__ void convert_owned8(const FwdArgs &a, const Chunk &ch
 }
 
 // a producer's copies of its blocks of a chunk's valid span (no conversion pending)
-__device__ __forceinline__ void copy_owned(const FwdArgs &a, const Chunk &ch, float *span, int pw, int np) {
+__device__ __forceinline__ void copy_owned8(const FwdArgs &a, const Chunk &ch, float *span, int pw, int np) {
     const int valid = span_valid(a, ch);
     const float *src = a.wave + ch.sample_start;
     const unsigned base = __builtin_amdgcn_readfirstlane(lds_addr(span));
@@ -709,18 +709,17 @@ __global__ __launch_bounds__(768) void k_melt_f8b_pc(FwdArgs a, const i32x8 *__r
     // own (so that neither role's registers are live in the other's), with one barrier per
     // chunk in both.
     if (wid == nc && lane < 3 && c0 + lane * cstep < nch) dslot[lane] = a.chunks[c0 + lane * cstep];
+    // the first chunk is copied and converted by every wave (blocks w, w + 12, ...); after a
+    // barrier the producers start the copy of the second
+    if (c0 < nch) {
+        const Chunk ch = read_chunk(a.chunks, c0);
+        copy_owned8(a, ch, span, wid, nw);
+        async_wait();
+        convert_owned8<false>(a, ch, span, buf0, S8, reinterpret_cast<int *>(buf0 + code_off), inv_bph, wid, nw, ch);
+    }
+    __syncthreads();
     if (producer) {
-        if (c0 < nch) {
-            const Chunk ch = read_chunk(a.chunks, c0);
-            copy_owned(a, ch, span, pw, np);
-            async_wait();
-            if (c0 + cstep < nch)
-                convert_owned8<true>(a, ch, span, buf0, S8, reinterpret_cast<int *>(buf0 + code_off), inv_bph, pw,
-                                     np, read_chunk(a.chunks, c0 + cstep));
-            else
-                convert_owned8<false>(a, ch, span, buf0, S8, reinterpret_cast<int *>(buf0 + code_off), inv_bph, pw,
-                                      np, ch);
-        }
+        if (c0 + cstep < nch) copy_owned8(a, read_chunk(a.chunks, c0 + cstep), span, pw, np);
         for (int it = 0; c0 + it * cstep < nch; ++it) {
             __syncthreads();                       // chunk it converted; buffer (it + 1) & 1 free
             const int c = c0 + it * cstep;

@@ -310,7 +310,7 @@ melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H
 //   FP8 with 32-sample block scales  producer/consumer block-scaled kernel, then the
 //              one-buffer block-scaled kernel with 160- and 128-frame chunks
 enum VariantKind { V_F32_WS, V_F32_FS, V_H16_PP, V_H16_AS, V_H16_AP, V_H16_RS, V_H16_KS, V_H16_FS, V_F8_AS, V_F8_RS,
-                   V_F8B_AS, V_F8B_PC };
+                   V_F8B_AS, V_F8B_PC, V_H16_PC };
 struct Variant {
     VariantKind kind;
     int bf;          // frames per chunk
@@ -351,7 +351,14 @@ static std::vector<Variant> variant_list(const Plan &p) {
         break;
     default: {
         const bool x3 = prec_split(p);
-        // row pairs first where they fit (two basis tiles per wave, 128 frames per chunk)
+        // 12-wave producer/consumer first where it fits (96 then 64 frames per chunk), then row
+        // pairs (two basis tiles per wave, 128 frames per chunk)
+        if (!x3 && pc_fits(p))
+            for (int bf : {96, 64})
+                if (pc_lds_bytes(p, bf) + 4 * sizeof(Chunk) <= (size_t)kMaxLds) {
+                    v.push_back({V_H16_PC, bf});
+                    break;
+                }
         if (!x3 && ap_fits(p) && as_lds_bytes(p, 128) + kRingBytes <= (size_t)kMaxLds) v.push_back({V_H16_AP, 128});
         if (as_fits(p)) {
             // one span buffer (128 then 64 frames per chunk; 96 then 64 for BF16X3), then two
@@ -421,6 +428,7 @@ const char *forward_variant_name(const Plan &p, int i) {
                     : v.kind == V_F32_FS ? "f32-frame-split"
                     : v.kind == V_H16_AS ? (v.nbuf == 2 ? "h16-row-split-lds-dma2" : "h16-row-split-lds-dma")
                     : v.kind == V_H16_AP ? "h16-row-pair-lds-dma"
+                    : v.kind == V_H16_PC ? "h16-producer-consumer-12w-lds-dma"
                     : v.kind == V_H16_RS ? "h16-row-split"
                     : v.kind == V_H16_KS ? "h16-k-split-lds-dma"
                     : v.kind == V_H16_FS ? "h16-frame-split"
@@ -462,6 +470,7 @@ melt_status launch_melt_table(Plan &p, int variant, const Chunk *tab, const int 
     case V_H16_PP: return launch_melt_h16(p, t, H16_PIPELINED, v.bf, v.nbuf);
     case V_H16_AS: return launch_melt_h16(p, t, H16_LDS_DMA, v.bf, v.nbuf);
     case V_H16_AP: return launch_melt_h16(p, t, H16_ROW_PAIR, v.bf);
+    case V_H16_PC: return launch_melt_h16(p, t, H16_PC12, v.bf);
     case V_H16_RS: return launch_melt_h16(p, t, H16_REGISTER_STAGED, v.bf);
     case V_H16_KS: return launch_melt_h16(p, t, H16_K_SPLIT, v.bf);
     case V_H16_FS: return launch_melt_h16(p, t, H16_FRAME_SPLIT, v.bf);

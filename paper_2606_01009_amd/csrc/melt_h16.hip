@@ -103,6 +103,17 @@ __device__ __forceinline__ void mfma_sweep1(const uint4 (&A)[NS], const uint4 (&
     __builtin_amdgcn_sched_barrier(0);
 }
 
+// a chunk descriptor from an LDS slot, its fields made wave-uniform
+__device__ __forceinline__ Chunk ring_slot(const Chunk *slots, int i) {
+    Chunk e = slots[i];
+    e.sample_start = uniform64(e.sample_start);
+    e.sample_end = uniform64(e.sample_end);
+    e.out_row = uniform64(e.out_row);
+    e.n_frames = __builtin_amdgcn_readfirstlane(e.n_frames);
+    e.clip = __builtin_amdgcn_readfirstlane(e.clip);
+    return e;
+}
+
 // ------------------------------------------------------------------ 16-bit row-split kernel
 //
 // One wave per 32-row basis tile (16 Mel bins); the wave keeps its whole basis tile in
@@ -549,6 +560,88 @@ __global__ __launch_bounds__(512) void k_melt_h16_pp(FwdArgs a, const uint4 *__r
     }
 }
 
+// ------------------------------------------------------------------ 16-bit producer/consumer kernel, 12 waves
+//
+// The arrangement of the block-scaled FP8 producer/consumer kernel (melt_f8.hip) for BF16 and
+// FP16: a chunk's conversion and its multiplies on different waves, so that they overlap.  A
+// workgroup of 12 waves (three per SIMD): the first NC = (row tiles of the group) are
+// consumers, each holding one basis tile in registers (NS k-groups of 16) and sweeping one
+// frame tile at a time; the other NP = 12 - NC are producers.  Producer w owns the 256-sample
+// blocks w, w + NP, ... of every chunk's span: it copies them HBM -> LDS (direct-to-LDS),
+// waits for its own copies only and converts exactly those into the 16-bit hop-block rows of
+// the other row buffer, then issues its copies of the chunk after next.  In iteration k the
+// consumers multiply chunk k from one buffer while the producers fill the other with chunk
+// k + 1; one barrier per chunk.  Chunk descriptors pass through a four-slot LDS ring: the first
+// producer loads descriptor k + 3 in iteration k and stores it before the barrier (slot
+// (k + 3) mod 4 was last read in iteration k - 1).  The first chunk is copied and converted by
+// all twelve waves.
+template <class Conv, int NS, bool IS_F16>
+__global__ __launch_bounds__(768) void k_melt_h16_pc(FwdArgs a, const uint4 *__restrict__ bhi, GroupTableBig gt,
+                                                     int bf, int rows_len, int scr_off, int rgroups) {
+    extern __shared__ float lds_hpc[];
+    __shared__ Chunk dslot[4];
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
+    const int grp = blockIdx.x % rgroups, gt_n = (a.row_tiles + rgroups - 1) / rgroups;
+    const int r0 = grp * gt_n, cnt = min(a.row_tiles - r0, gt_n);
+    const int nc = cnt, np = nw - cnt;             // consumers (one row tile each), producers
+    const bool producer = wid >= nc;
+    const int pw = wid - nc;
+    unsigned short *rows0 = reinterpret_cast<unsigned short *>(lds_hpc);
+    unsigned short *rows1 = rows0 + rows_len;
+    float *span = lds_hpc + scr_off;
+    const int nch = *a.n_chunks;
+    const int cstep = gridDim.x / rgroups;
+    const int c0 = blockIdx.x / rgroups;
+    zero_pad_columns<Conv>(a, bf + a.J - 1, rows0, blockDim.x, 0);
+    zero_pad_columns<Conv>(a, bf + a.J - 1, rows1, blockDim.x, 0);
+    if (wid == nc && lane < 3 && c0 + lane * cstep < nch) dslot[lane] = a.chunks[c0 + lane * cstep];
+    // the first chunk is copied and converted by every wave (blocks w, w + 12, ...); after a
+    // barrier the producers start the copy of the second
+    if (c0 < nch) {
+        const Chunk ch = read_chunk(a.chunks, c0);
+        copy_owned(a, ch, span, wid, nw);
+        async_wait();
+        convert_owned<Conv>(a, ch, span, rows0, 0, wid, nw);
+    }
+    __syncthreads();
+    if (producer) {
+        if (c0 + cstep < nch) copy_owned(a, read_chunk(a.chunks, c0 + cstep), span, pw, np);
+        for (int it = 0; c0 + it * cstep < nch; ++it) {
+            __syncthreads();                       // chunk it converted; buffer (it + 1) & 1 free
+            const int c = c0 + it * cstep;
+            if (c + cstep >= nch) continue;
+            Chunk nd{};
+            const bool load_desc = wid == nc && c + 3 * cstep < nch;
+            async_wait();                          // this producer's copies of chunk it + 1
+            if (load_desc) nd = a.chunks[c + 3 * cstep];
+            const Chunk ch1 = ring_slot(dslot, (it + 1) & 3);
+            convert_owned<Conv>(a, ch1, span, ((it + 1) & 1) ? rows1 : rows0, 0, pw, np);
+            if (load_desc && lane == 0) dslot[(it + 3) & 3] = nd;
+            if (c + 2 * cstep < nch) copy_owned(a, ring_slot(dslot, (it + 2) & 3), span, pw, np);
+        }
+        return;
+    }
+    const int rt = r0 + wid;
+    uint4 A[NS];
+    const uint4 Al[1] = {};
+#pragma unroll
+    for (int s = 0; s < NS; ++s) A[s] = bhi[((size_t)rt * NS + s) * 64 + lane];
+    for (int it = 0; c0 + it * cstep < nch; ++it) {
+        __syncthreads();                           // chunk it converted; buffer (it + 1) & 1 free
+        const Chunk ch = ring_slot(dslot, it & 3);
+        const unsigned short *rows = (it & 1) ? rows1 : rows0;
+        const int nft = (ch.n_frames + 31) >> 5;
+        for (int ft = 0; ft < nft; ++ft) {
+            int off = (ft * 32 + (lane & 31)) * a.S + 8 * (lane >> 5);
+            asm volatile("" : "+v"(off));
+            f32x16 acc = f32x16{};
+            mfma_sweep1<NS, false, IS_F16>(A, Al, rows + off, gt, 0, acc);
+            store_tile(a, ch, rt, ft * 32 + (lane & 31), lane, acc);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ 16-bit K-split kernel
 //
 // For frames whose basis tile is too long for one wave's registers (N = 1024: 64 k-groups;
@@ -821,6 +914,29 @@ static melt_status launch_rs(Plan &p, const FwdArgs &a, const GroupTableBig &gt,
     }
 }
 
+template <class Conv, int NS, bool F16>
+static melt_status launch_pc_ns(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+                                hipStream_t s) {
+    allow_lds(k_melt_h16_pc<Conv, NS, F16>, (int)(4 * sizeof(Chunk)));
+    const int rg = row_groups(p);
+    k_melt_h16_pc<Conv, NS, F16><<<grid, 768, lds, s>>>(a, (const uint4 *)p.d_pack_h16, gt, bf,
+                                                         (int)(pc_rows_bytes(p, bf) / 2),
+                                                         (int)(2 * pc_rows_bytes(p, bf) / 4), rg);
+    return hip_check(hipGetLastError(), "melt h16 12-wave producer/consumer launch");
+}
+
+template <class Conv, bool F16>
+static melt_status launch_pc(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+                             hipStream_t s) {
+    switch (p.geo16.n_groups) {
+    case 10: return launch_pc_ns<Conv, 10, F16>(p, a, gt, lds, grid, bf, s);
+    case 16: return launch_pc_ns<Conv, 16, F16>(p, a, gt, lds, grid, bf, s);
+    case 20: return launch_pc_ns<Conv, 20, F16>(p, a, gt, lds, grid, bf, s);
+    case 25: return launch_pc_ns<Conv, 25, F16>(p, a, gt, lds, grid, bf, s);
+    default: return set_error(MELT_E_UNSUPPORTED, "12-wave producer/consumer kernel: no register tile for this frame length");
+    }
+}
+
 template <class Conv, int NS0, int NS1, bool F16>
 static melt_status launch_ks_ns(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
                                 int rg, int delta, hipStream_t s) {
@@ -875,6 +991,16 @@ melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf, int
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(t.est_chunks, (int64_t)p.cu_count));
         if (f16) return launch_ap<ConvF16, true>(p, a, gt, lds, grid, bf, s);
         return launch_ap<ConvBF16, false>(p, a, gt, lds, grid, bf, s);
+    }
+    if (kind == H16_PC12) {
+        if (x3 || !pc_fits(p)) return set_error(MELT_E_UNSUPPORTED, "12-wave producer/consumer kernel: unsupported geometry");
+        const size_t lds = pc_lds_bytes(p, bf);
+        if (lds + 4 * sizeof(Chunk) > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
+        const int rg = row_groups(p);
+        const int per_group = (int)std::max<int64_t>(1, std::min<int64_t>(t.est_chunks, ((int64_t)p.cu_count + rg - 1) / rg));
+        const int grid = per_group * rg;
+        if (f16) return launch_pc<ConvF16, true>(p, a, gt, lds, grid, bf, s);
+        return launch_pc<ConvBF16, false>(p, a, gt, lds, grid, bf, s);
     }
     if (kind == H16_PIPELINED) {
         if (!pp_fits(p)) return set_error(MELT_E_UNSUPPORTED, "producer/consumer kernel: no producer waves");
