@@ -56,7 +56,7 @@ static void free_plan(Plan *p) {
     void *bufs[] = {p->d_basis32, p->d_pack_f32, p->d_pack_h16, p->d_pack_lo, p->d_pack_f8, p->d_rowscale,
                     p->d_fb_w, p->d_fb_start, p->d_fb_off, p->d_twiddle, p->d_window, p->d_chunks[0],
                     p->d_chunks[1], p->d_nchunks, p->d_pack_dx, p->d_bwd_ws, p->d_bwd_rows, p->d_dct,
-                    p->d_lmel, p->d_seg32, p->d_col32, p->d_seg16, p->d_col16};
+                    p->d_dct_x3, p->d_lmel, p->d_seg32, p->d_col32, p->d_seg16, p->d_col16};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -149,6 +149,10 @@ melt_status melt_plan_create(const melt_config *cfg, int device, melt_plan *out)
         st = alloc((void **)&p->d_dct, D.size() * sizeof(float));
         if (st == MELT_OK)
             st = hip_check(hipMemcpy(p->d_dct, D.data(), D.size() * sizeof(float), hipMemcpyHostToDevice), "upload DCT");
+        const int prec = cfg->precision;
+        if (st == MELT_OK && (prec == MELT_PREC_BF16 || prec == MELT_PREC_FP16 || prec == MELT_PREC_FP8_E4M3 ||
+                              prec == MELT_PREC_FP8_E4M3_BLOCK32))
+            st = pack_dct_x3(*p);
     }
     if (st == MELT_OK) init_variants(*p);
     if (st == MELT_OK) st = pack_tables_upload(*p);

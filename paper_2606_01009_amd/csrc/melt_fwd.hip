@@ -457,7 +457,7 @@ melt_status launch_melt_main(Plan &p, const float *d_wave, float *d_out, float *
     if (st == MELT_OK)
         st = launch_melt_table(p, v, p.d_chunks[0], p.d_nchunks, est, n_frames, d_wave, p.d_lmel, d_proj, s);
     if (st != MELT_OK) return st;
-    return launch_row_matmul(p.d_lmel, n_frames, p.M, p.K, p.d_dct, p.M, 1, d_out, s);
+    return launch_cepstrum(p, p.d_lmel, n_frames, d_out, s);
 }
 
 melt_status launch_melt_table(Plan &p, int variant, const Chunk *tab, const int *n_tab, int64_t est_chunks,

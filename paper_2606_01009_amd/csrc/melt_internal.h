@@ -89,6 +89,7 @@ struct Plan {
     int K = 0;                         // cepstral coefficients (MELT_OUT_MFCC), else 0
     int kern_out = 0;                  // output map of the Mel kernels (log power under MFCC)
     float *d_dct = nullptr;
+    void *d_dct_x3 = nullptr;          // its split binary16 fragments (16-bit / FP8 plans, K <= 64)
     float *d_lmel = nullptr;
     size_t lmel_cap = 0;
     // kernel variants of the forward for this plan, fixed at plan creation (init_variants):
@@ -149,6 +150,8 @@ void apply_tune_cache(Plan &p);          // stream.hip: apply a MELT_AUTOTUNE_CA
 const char *forward_variant_name(const Plan &p, int variant);
 melt_status stft_plan_build(Plan &p);
 // MFCCT (mfcc.hip): out[r][j] = sum_i in[r][i] A[j sj + i si]; the DCT-II; the workspace
+melt_status launch_cepstrum(const Plan &p, const float *lmel, int64_t rows, float *out, hipStream_t s);
+melt_status pack_dct_x3(Plan &p);        // plan creation, after the DCT upload
 melt_status launch_row_matmul(const float *in, int64_t rows, int I, int J, const float *A, int sj, int si, float *out,
                               hipStream_t s);
 void dct_matrix(int K, int M, std::vector<float> &D);

@@ -1,5 +1,6 @@
 // MFCCT (Eq. mfcct_matrix): C = ln(S + eps) D^T with D the K x M orthonormal DCT-II, and the
-// same cepstrum on the comparator's log-Mel output.  A small dense product over rows, on the
+// same cepstrum on the comparator's log-Mel output.  A small dense product over rows: after a
+// 16-bit or FP8 projection a split binary16 product on the 32x32x16 matrix cores, else on the
 // FP32 matrix cores where its operands fit the LDS staging, else on the vector ALUs,
 // out[r][j] = sum_i in[r][i] A[j][i], used for the forward (A = D, i = Mel bin) and for the
 // backward of the cepstrum (A = D^T, i = cepstral index: dL = dC D).
@@ -181,6 +182,104 @@ __global__ __launch_bounds__(256) void k_row_mfma(const float *__restrict__ in, 
     }
 }
 
+// The cepstrum after a 16-bit or FP8 MelT projection, on the binary16 matrix cores as the
+// split product Lh Dh + Lh Dl + Ll Dh (two 11-bit significands per operand; products exact in
+// FP32, each term about 22 significant bits, far below the projection's own error).  The
+// log-Mel values are pre-scaled by 2^9 (with eps at least the smallest normal, |L| <= 89, so
+// 2^9 L stays below binary16's 65504) and the DCT by 2^10 (|D| <= 1), both exact, so that the
+// low parts of small values stay normal; the FP32 sums are divided by 2^19.
+// v_mfma_f32_32x32x16_f16 with the DCT as A and 32 log-Mel rows as B: lane (c = lane % 32,
+// h = lane / 32) loads inputs 8 u + 4 h .. + 3 of row c for u < 2 NI (16-byte loads, the two
+// halves of a wave reading adjacent 16 bytes of a row, all issued before the multiplies), so
+// k-slot (h, e) of group g is input 16 g + 8 (e / 4) + 4 h + e % 4 on both operands.  The DCT
+// fragments (TJ tiles of 32 coefficients by NI groups, hi and lo) are packed once per plan
+// (k_pack_dct_x3) and held in registers for the wave's life.  Lane (c, h) ends with
+// coefficients 32 t + 8 q + 4 h .. + 3 of row c.  Waves walk 32-row tiles.  The host
+// guarantees I % 8 == 0, I <= 16 NI, J <= 32 TJ and 16-byte aligned input rows; vec: output
+// rows 16-byte aligned too (J % 4 == 0).
+typedef _Float16 cx_h16x8 __attribute__((ext_vector_type(8)));
+typedef float cx_f32x16 __attribute__((ext_vector_type(16)));
+
+// F[((t NI + g) 2 + part) 64 + lane][e] = part 0: hi, 1: lo of 2^10 D[32 t + lane % 32][i],
+// i = 16 g + 8 (e / 4) + 4 (lane / 32) + e % 4, zero outside K x M
+__global__ void k_pack_dct_x3(const float *__restrict__ D, int K, int M, int NI, int TJ, cx_h16x8 *__restrict__ F) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= TJ * NI * 2 * 64) return;
+    const int lane = idx & 63, part = (idx >> 6) & 1, tg = idx >> 7, g = tg % NI, t = tg / NI;
+    cx_h16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int j = 32 * t + (lane & 31), i = 16 * g + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        const float d = (j < K && i < M) ? D[(size_t)j * M + i] * 1024.0f : 0.0f;
+        const _Float16 dh = (_Float16)d;
+        v[e] = part ? (_Float16)(d - (float)dh) : dh;
+    }
+    F[idx] = v;
+}
+
+template <int NI, int TJ>
+__global__ __launch_bounds__(256) void k_cepstrum_x3(const float *__restrict__ in, int64_t rows, int I, int J,
+                                                     const cx_h16x8 *__restrict__ F, float *__restrict__ out,
+                                                     int vec) {
+    const int lane = threadIdx.x & 63, c = lane & 31, h = lane >> 5;
+    cx_h16x8 Dh[TJ][NI], Dl[TJ][NI];
+#pragma unroll
+    for (int t = 0; t < TJ; ++t)
+#pragma unroll
+        for (int g = 0; g < NI; ++g) {
+            Dh[t][g] = F[((t * NI + g) * 2) * 64 + lane];
+            Dl[t][g] = F[((t * NI + g) * 2 + 1) * 64 + lane];
+        }
+    const int64_t ntile = (rows + 31) >> 5;
+    const int64_t wstep = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); tile < ntile; tile += wstep) {
+        const int64_t r = tile * 32 + c;
+        const bool live = r < rows;
+        const float *src = in + r * I + 4 * h;
+        rm_f32x4 x[2 * NI];
+#pragma unroll
+        for (int u = 0; u < 2 * NI; ++u)
+            x[u] = (live && 8 * u < I) ? *(const rm_f32x4 *)(src + 8 * u) : rm_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        cx_f32x16 acc[TJ];
+#pragma unroll
+        for (int t = 0; t < TJ; ++t) acc[t] = cx_f32x16{};
+#pragma unroll
+        for (int g = 0; g < NI; ++g) {
+            cx_h16x8 lh, ll;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float v = x[2 * g + (e >> 2)][e & 3] * 512.0f;
+                const _Float16 vh = (_Float16)v;
+                lh[e] = vh;
+                ll[e] = (_Float16)(v - (float)vh);
+            }
+#pragma unroll
+            for (int t = 0; t < TJ; ++t) {
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Dh[t][g], lh, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Dl[t][g], lh, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Dh[t][g], ll, acc[t], 0, 0, 0);
+            }
+        }
+        if (!live) continue;
+        float *o = out + r * J;
+#pragma unroll
+        for (int t = 0; t < TJ; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j0 = 32 * t + 8 * q + 4 * h;
+                const rm_f32x4 v = rm_f32x4{acc[t][4 * q], acc[t][4 * q + 1], acc[t][4 * q + 2], acc[t][4 * q + 3]} *
+                                   (1.0f / 524288.0f);
+                if (vec && j0 + 4 <= J) {
+                    *(rm_f32x4 *)(o + j0) = v;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (j0 + e < J) o[j0 + e] = v[e];
+                }
+            }
+    }
+}
+
 namespace {
 
 template <int TJ>
@@ -201,6 +300,59 @@ melt_status launch_mfma(const float *in, int64_t rows, int I, int J, const float
 }
 
 }  // namespace
+
+// the split binary16 cepstrum takes K <= 64 (one or two tiles of 32) and M <= 128, M % 8 == 0
+static bool x3_fits(int K, int M) { return K >= 1 && K <= 64 && M % 8 == 0 && M >= 8 && M <= 128; }
+
+melt_status pack_dct_x3(Plan &p) {
+    if (!x3_fits(p.K, p.M)) return MELT_OK;
+    const int ni = (p.M + 15) / 16, tj = (p.K + 31) / 32;
+    const size_t n = (size_t)tj * ni * 2 * 64;
+    if (hipMalloc(&p.d_dct_x3, n * 16) != hipSuccess) return set_error(MELT_E_NO_MEMORY, "DCT fragments");
+    k_pack_dct_x3<<<(unsigned)((n + 255) / 256), 256>>>(p.d_dct, p.K, p.M, ni, tj, (cx_h16x8 *)p.d_dct_x3);
+    melt_status st = hip_check(hipGetLastError(), "pack DCT fragments");
+    if (st == MELT_OK) st = hip_check(hipStreamSynchronize(nullptr), "pack DCT fragments");
+    return st;
+}
+
+template <int NI, int TJ>
+static melt_status launch_x3(const Plan &p, const float *in, int64_t rows, float *out, hipStream_t s) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t ntile = (rows + 31) / 32;
+    const int vec = p.K % 4 == 0 && (uintptr_t)out % 16 == 0;
+    // two workgroups of four waves per CU: the fragments and the rows in flight take ~250 VGPRs
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((ntile + 3) / 4, 2 * (int64_t)cus));
+    k_cepstrum_x3<NI, TJ><<<(unsigned)grid, 256, 0, s>>>(in, rows, p.M, p.K, (const cx_h16x8 *)p.d_dct_x3, out, vec);
+    return hip_check(hipGetLastError(), "cepstrum (split binary16) launch");
+}
+
+template <int TJ>
+static melt_status launch_x3_tj(const Plan &p, const float *in, int64_t rows, float *out, hipStream_t s) {
+    switch ((p.M + 15) / 16) {
+    case 1: return launch_x3<1, TJ>(p, in, rows, out, s);
+    case 2: return launch_x3<2, TJ>(p, in, rows, out, s);
+    case 3: return launch_x3<3, TJ>(p, in, rows, out, s);
+    case 4: return launch_x3<4, TJ>(p, in, rows, out, s);
+    case 5: return launch_x3<5, TJ>(p, in, rows, out, s);
+    case 6: return launch_x3<6, TJ>(p, in, rows, out, s);
+    case 7: return launch_x3<7, TJ>(p, in, rows, out, s);
+    default: return launch_x3<8, TJ>(p, in, rows, out, s);
+    }
+}
+
+// the cepstrum of the plan's MelT forward: split binary16 matrix cores after a 16-bit or FP8
+// projection (when the fragments were packed), FP32 matrix cores otherwise
+melt_status launch_cepstrum(const Plan &p, const float *lmel, int64_t rows, float *out, hipStream_t s) {
+    const int prec = p.cfg.precision;
+    const bool low = prec == MELT_PREC_BF16 || prec == MELT_PREC_FP16 || prec == MELT_PREC_FP8_E4M3 ||
+                     prec == MELT_PREC_FP8_E4M3_BLOCK32;
+    if (rows <= 0) return MELT_OK;
+    if (low && p.d_dct_x3 && (uintptr_t)lmel % 16 == 0) {
+        return p.K <= 32 ? launch_x3_tj<1>(p, lmel, rows, out, s) : launch_x3_tj<2>(p, lmel, rows, out, s);
+    }
+    return launch_row_matmul(lmel, rows, p.M, p.K, p.d_dct, p.M, 1, out, s);
+}
 
 melt_status launch_row_matmul(const float *in, int64_t rows, int I, int J, const float *A, int sj, int si, float *out,
                               hipStream_t s) {

@@ -295,7 +295,7 @@ melt_status melt_stream_push(melt_stream_state S, const float *d_chunk, int32_t 
     if (p.K > 0) {
         // MFCCT over the whole slot block (rows past a stream's emitted count carry no meaning)
         const int64_t rows = (int64_t)S->n_streams * S->max_frames;
-        st = launch_row_matmul(S->d_lmel, rows, p.M, p.K, p.d_dct, p.M, 1, d_out, s);
+        st = launch_cepstrum(p, S->d_lmel, rows, d_out, s);
     }
     return st;
 }

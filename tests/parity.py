@@ -126,15 +126,26 @@ def log_error_radius(R, I, A_r, A_i, n_terms, eps, extra_rel=1.0):
     return np.where(vac, width, bound), L
 
 
-def check_cepstrum(C_gpu, L, bL, D, label=""):
+def check_cepstrum(C_gpu, L, bL, D, label="", split=False):
     """C = L D^T (Eq. mfcct_matrix) from log-Mel rows L with per-bin error radius bL: the
     FP32 product adds gamma_M sum |D||L| plus the FP32 rounding of D (u sum |D||L|), so
-        |C_gpu - C| <= |D| bL + (gamma_M + u) |D| |L| + u |C|."""
+        |C_gpu - C| <= |D| bL + (gamma_M + u) |D| |L| + u |C|.
+    split: the product runs as Lh Dh + Lh Dl + Ll Dh on binary16 operands (hi + lo of the
+    FP32 values scaled by 2^9 and 2^10).  Each lo rounds to 11 bits (|x - xh - xl| <= 2^-22 |x|
+    on either side), the dropped Ll Dl is at most 2^-22 |L||D|, and 3M exact products are
+    summed in FP32: (gamma_3M + u + 4 * 2^-22) |D| |L|, plus M times half a binary16 subnormal
+    step per operand (2^-25 in the scaled units) for the lo parts that fall below the normal
+    range."""
     C_gpu = np.asarray(C_gpu, np.float64)
     M = D.shape[1]
     C = L @ D.T
-    g = M * U32 / (1 - M * U32) + U32
-    bound = bL @ np.abs(D).T + g * (np.abs(L) @ np.abs(D).T) + U32 * np.abs(C) + 1e-30
+    if split:
+        g = 3 * M * U32 / (1 - 3 * M * U32) + U32 + 4 * 2.0 ** -22
+        tiny = M * (2.0 ** -25 / 2 ** 10 * np.abs(L).max(initial=0.0) + 2.0 ** -25 / 2 ** 9 + 2.0 ** -44)
+    else:
+        g = M * U32 / (1 - M * U32) + U32
+        tiny = 0.0
+    bound = bL @ np.abs(D).T + g * (np.abs(L) @ np.abs(D).T) + U32 * np.abs(C) + tiny + 1e-30
     err = np.abs(C_gpu - C)
     bad = err > bound
     if np.any(bad):

@@ -51,21 +51,43 @@ def _melt_case(torch, melt, orc, wave, off, sr, N, H, M, K, prec, fmin=0.0, fmax
                                            return_ri=True)
         bL, L = parity.log_error_radius(R, I, Ar, Ai, N, eps, extra_rel=1.0)
     else:
-        code = {"bf16": orc.PREC_BF16, "fp16": orc.PREC_FP16}[prec]
+        code = {"bf16": orc.PREC_BF16, "fp16": orc.PREC_FP16, "fp8": orc.PREC_FP8_E4M3,
+                "fp8b": orc.PREC_FP8_E4M3_BLOCK32}[prec]
         _, R, I = orc.melt_forward_quant(wave, off, n_fft=N, hop=H, Wr=Wr, Wi=Wi, prec=code, eps=eps, return_ri=True)
         _, Ar, Ai = orc.melt_forward_quant(np.abs(wave), off, n_fft=N, hop=H, Wr=np.abs(Wr), Wi=np.abs(Wi), prec=code,
                                            eps=eps, return_ri=True)
-        bL, L = parity.log_error_radius(R, I, Ar, Ai, N, eps, extra_rel=0.0)
+        # FP8: the epilogue's unscaling adds up to four FP32 roundings
+        bL, L = parity.log_error_radius(R, I, Ar, Ai, N, eps, extra_rel=4.0 if prec in ("fp8", "fp8b") else 0.0)
     D = orc.dct2_ortho(K, M)
-    st = parity.check_cepstrum(C, L, bL, D, label=f"MFCCT {prec} N={N} M={M} K={K}")
+    # after a 16-bit or FP8 projection the cepstrum runs as a split binary16 product
+    st = parity.check_cepstrum(C, L, bL, D, label=f"MFCCT {prec} N={N} M={M} K={K}", split=prec != "fp32")
     print(f"MFCCT {prec} N={N} M={M} K={K}: max |dC| {st['max_abs']:.3g} (bound up to {st['max_bound']:.3g})")
     return C
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "fp8", "fp8b"])
 def test_mfcct_config1(torch, melt, orc, prec):
     cfg = workloads.config1()
     _melt_case(torch, melt, orc, cfg["wave"], cfg["offsets"], 16000.0, 400, 160, 80, 40, prec, fmax=8000.0)
+
+
+@pytest.mark.parametrize("K", [1, 13, 31, 33, 40, 64, 80])
+def test_mfcct_split_cepstrum_shapes(torch, melt, orc, K):
+    """The split binary16 cepstrum over its coefficient tiles (one or two of 32, ragged) and
+    Mel widths (80: five groups of 16; 128: eight), on a ragged batch whose row count is not
+    a multiple of the 32-row tile.  K = 80 is past two tiles: the FP32 product takes it."""
+    lengths = [400, 400 + 160 * 37 + 3, 16000 + 77]
+    wave, off = workloads.random_clips(lengths, seed=40 + K)
+    M = 128 if K == 64 else 80
+    _melt_case(torch, melt, orc, wave, off, 16000.0, 400, 160, M, min(K, M), "bf16", fmax=8000.0)
+
+
+def test_mfcct_cepstral_configuration_bf16(torch, melt, orc):
+    """The cepstral configuration (N = 1200, M = 128, K = 40) at BF16: the K-split projection
+    kernel, then the split binary16 cepstrum."""
+    lengths = [1199, 1200, 16000, 5 * 160 + 1200 + 7, 32000]
+    wave, off = workloads.random_clips(lengths, seed=13)
+    _melt_case(torch, melt, orc, wave, off, 16000.0, 1200, 160, 128, 40, "bf16", fmax=8000.0)
 
 
 def test_mfcct_cepstral_configuration(torch, melt, orc):
