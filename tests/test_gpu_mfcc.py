@@ -82,12 +82,49 @@ def test_mfcct_split_cepstrum_shapes(torch, melt, orc, K):
     _melt_case(torch, melt, orc, wave, off, 16000.0, 400, 160, M, min(K, M), "bf16", fmax=8000.0)
 
 
-def test_mfcct_cepstral_configuration_bf16(torch, melt, orc):
-    """The cepstral configuration (N = 1200, M = 128, K = 40) at BF16: the K-split projection
-    kernel, then the split binary16 cepstrum."""
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_mfcct_cepstral_configuration_16bit(torch, melt, orc, prec):
+    """The cepstral configuration (N = 1200, M = 128, K = 40) at 16 bits: the K-split
+    projection kernel (two row groups), then the split binary16 cepstrum."""
     lengths = [1199, 1200, 16000, 5 * 160 + 1200 + 7, 32000]
     wave, off = workloads.random_clips(lengths, seed=13)
-    _melt_case(torch, melt, orc, wave, off, 16000.0, 1200, 160, 128, 40, "bf16", fmax=8000.0)
+    _melt_case(torch, melt, orc, wave, off, 16000.0, 1200, 160, 128, 40, prec, fmax=8000.0)
+
+
+@pytest.mark.parametrize("M,K", [(16, 13), (64, 40), (64, 64), (80, 13), (128, 33), (128, 64), (112, 1)])
+def test_mfcct_k_split_shapes(torch, melt, orc, M, K):
+    """MFCCT at N = 1200 (the K-split projection kernel) over one row group (M <= 64) and
+    two, one or two coefficient tiles of the split cepstrum, ragged clips whose chunks end in
+    a partial frame tile."""
+    lengths = [1200 + 160 * 70 + 5, 1200 + 160 * 33, 4000]
+    wave, off = workloads.random_clips(lengths, seed=60 + M + K)
+    plan = melt.MeltPlan(sample_rate=16000.0, n_fft=1200, hop=160, n_mels=M, fmax=8000.0, precision="bf16",
+                         output=melt.MELT_OUT_MFCC, n_mfcc=K)
+    assert "k-split" in melt.melt_variant_name(plan.handle, 0)
+    _melt_case(torch, melt, orc, wave, off, 16000.0, 1200, 160, M, K, "bf16", fmax=8000.0)
+
+
+def test_mfcct_is_deterministic_and_keeps_projections(torch, melt):
+    """Two MFCCT calls are bit-identical, and the projections an MFCC plan stores for the
+    backward equal those of the log-power plan."""
+    wave, off = workloads.random_clips([16000, 23456, 1200], seed=71)
+    kw = dict(sample_rate=16000.0, n_fft=1200, hop=160, n_mels=128, fmax=8000.0, precision="bf16")
+    mf = melt.MeltPlan(output=melt.MELT_OUT_MFCC, n_mfcc=40, **kw)
+    lp = melt.MeltPlan(**kw)
+    T = melt.total_frames(off, 1200, 160)
+    d_wave = torch.from_numpy(np.ascontiguousarray(wave)).cuda()
+    d_off = torch.from_numpy(np.asarray(off, np.int64)).cuda()
+    outs, projs = [], []
+    for plan, cols in ((mf, 40), (mf, 40), (lp, 128)):
+        out = torch.full((T, cols), float("nan"), dtype=torch.float32, device="cuda")
+        P = torch.full((T, 256), float("nan"), dtype=torch.float32, device="cuda")
+        plan.forward(d_wave, d_off, T, out=out, proj=P)
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy())
+        projs.append(P.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+    assert np.all(np.isfinite(outs[0]))
+    assert np.array_equal(projs[0], projs[2]) and np.array_equal(projs[1], projs[2])
 
 
 def test_mfcct_cepstral_configuration(torch, melt, orc):
