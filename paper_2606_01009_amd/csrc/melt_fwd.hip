@@ -18,6 +18,62 @@ __device__ __forceinline__ int64_t wave_scan(int64_t v, int lane) {
     return v;
 }
 
+// a / b for 0 <= a, 0 < b < 2^31: 32-bit division when a fits (the 64-bit one is a long
+// software sequence)
+__device__ __forceinline__ int64_t udiv_nonneg(int64_t a, int b) {
+    return a <= 0x7fffffff ? (int64_t)((uint32_t)a / (uint32_t)b) : a / b;
+}
+
+// Chunk table for at most 64 clips, with no barrier: every wave holds the clips in its lanes
+// (lane = clip) and scans their frame and chunk counts in registers; entry q (taken by lane
+// q % 64 of wave (q / 64) % 16) finds its clip by a binary search over the lanes' chunk
+// prefix sums (shuffles, every lane active).  n_chunks receives min(total, cap).
+__global__ __launch_bounds__(1024) void k_schedule64(const int64_t *__restrict__ off, int n_clips, int N, int H,
+                                                     int bf, Chunk *__restrict__ tab, int64_t cap,
+                                                     int *__restrict__ n_out) {
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int64_t st = 0, L = 0;
+    if (lane < n_clips) {
+        st = off[lane];
+        L = off[lane + 1] - st;
+    }
+    const int64_t T = (L >= N) ? 1 + udiv_nonneg(L - N, H) : 0;
+    const int64_t K = udiv_nonneg(T + bf - 1, bf);
+    const int64_t pf = wave_scan(T, lane), pc = wave_scan(K, lane);
+    const int64_t total = __shfl(pc, 63, 64);
+    const int64_t nv = total < cap ? total : cap;
+    // the same on every lane; made scalar so the loop below keeps every lane active
+    const int64_t n = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(nv >> 32)) << 32) |
+                                (uint32_t)__builtin_amdgcn_readfirstlane((int)nv));
+    for (int64_t q0 = 64 * w; q0 < n; q0 += 1024) {      // wave-uniform trip count
+        const int64_t q = q0 + lane;
+        int t = 0;                                       // clips whose chunks all precede q
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1)
+            if (__shfl(pc, t + d - 1, 64) <= q) t += d;
+        // every shuffle runs on all lanes: a lane left out of one (a shuffle under a
+        // condition) would read as zero to the lanes that source from it
+        const int tp = t > 0 ? t - 1 : 0;
+        const int64_t pc_p = __shfl(pc, tp, 64), pf_p = __shfl(pf, tp, 64);
+        const int64_t pf_t = __shfl(pf, t & 63, 64);
+        const int64_t st_t = __shfl(st, t & 63, 64), L_t = __shfl(L, t & 63, 64);
+        const int64_t kc0 = t > 0 ? pc_p : 0;
+        const int64_t fb = t > 0 ? pf_p : 0;
+        const int64_t Tt = pf_t - fb;
+        if (q < n) {
+            const int64_t k = q - kc0;
+            Chunk e;
+            e.sample_start = st_t + k * bf * (int64_t)H;
+            e.sample_end = st_t + L_t;
+            e.out_row = fb + k * bf;
+            e.n_frames = (int)((Tt - k * bf) < bf ? (Tt - k * bf) : bf);
+            e.clip = t;
+            tab[q] = e;
+        }
+    }
+    if (threadIdx.x == 0) *n_out = (int)n;
+}
+
 // One workgroup: prefix sums over the clips of frame counts and chunk counts, then the
 // chunk table.  n_chunks receives min(total, cap).
 __global__ __launch_bounds__(1024) void k_schedule(const int64_t *__restrict__ off, int n_clips, int N,
@@ -35,8 +91,8 @@ __global__ __launch_bounds__(1024) void k_schedule(const int64_t *__restrict__ o
             st = off[c];
             L = off[c + 1] - st;
         }
-        const int64_t T = (L >= N) ? 1 + (L - N) / H : 0;
-        const int64_t K = (T + bf - 1) / bf;
+        const int64_t T = (L >= N) ? 1 + udiv_nonneg(L - N, H) : 0;
+        const int64_t K = udiv_nonneg(T + bf - 1, bf);
         // inclusive prefix sums of T and K over the block: within each wave, then across the
         // 16 wave totals
         const int64_t pf = wave_scan(T, lane), pc = wave_scan(K, lane);
@@ -278,8 +334,12 @@ melt_status launch_schedule(Plan &p, int which, const int64_t *d_off, int n_clip
     const int64_t need = n_frames / bf + n_clips + 1;
     melt_status st = ensure_chunks(p, which, need);
     if (st != MELT_OK) return st;
-    k_schedule<<<1, 1024, 0, s>>>(d_off, n_clips, p.N, p.H, bf, p.d_chunks[which], p.chunk_cap[which],
-                                  p.d_nchunks + which);
+    if (n_clips <= 64)
+        k_schedule64<<<1, 1024, 0, s>>>(d_off, n_clips, p.N, p.H, bf, p.d_chunks[which], p.chunk_cap[which],
+                                        p.d_nchunks + which);
+    else
+        k_schedule<<<1, 1024, 0, s>>>(d_off, n_clips, p.N, p.H, bf, p.d_chunks[which], p.chunk_cap[which],
+                                      p.d_nchunks + which);
     st = hip_check(hipGetLastError(), "schedule launch");
     if (st == MELT_OK) {
         p.prepared_frames[which] = n_frames;
@@ -530,8 +590,9 @@ melt_status forward_noalloc(Plan &p, const float *d_wave, const int64_t *d_off, 
                                            std::to_string(need) + " chunk entries exceed the 32760 of the scratch");
     int *n_tab = static_cast<int *>(base);
     Chunk *tab = reinterpret_cast<Chunk *>(static_cast<unsigned char *>(base) + kScratchTable);
-    // k_schedule writes the count unconditionally, so nothing in the scratch needs clearing
-    k_schedule<<<1, 1024, 0, s>>>(d_off, n_clips, p.N, p.H, bf, tab, kScratchChunks, n_tab);
+    // the schedule kernels write the count unconditionally, so nothing in the scratch needs clearing
+    if (n_clips <= 64) k_schedule64<<<1, 1024, 0, s>>>(d_off, n_clips, p.N, p.H, bf, tab, kScratchChunks, n_tab);
+    else k_schedule<<<1, 1024, 0, s>>>(d_off, n_clips, p.N, p.H, bf, tab, kScratchChunks, n_tab);
     const melt_status st = hip_check(hipGetLastError(), "schedule launch");
     if (st != MELT_OK) return st;
     return launch_melt_table(p, v, tab, n_tab, need - 1, n_frames, d_wave, d_out, nullptr, s);

@@ -105,6 +105,24 @@ def test_config2_reduced(torch, melt, orc, prec, n_mels):
     _check(orc, melt, plan, L, cfg["wave"], cfg["offsets"], prec, label=f"config2-reduced M={n_mels} {prec}")
 
 
+@pytest.mark.parametrize("n_clips", [1, 63, 64, 65, 300])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_schedule_clip_counts(torch, melt, orc, prec, n_clips):
+    """Chunk schedules of up to 64 clips (one wave's lanes, no barrier) and of more (the
+    block-scan kernel): ragged clips with empty ones, clips shorter than a frame and clips of
+    several chunks, against the oracle frame by frame (the output starts as NaN, so a frame
+    no chunk covers fails)."""
+    rng = np.random.default_rng(80 + n_clips)
+    lengths = rng.integers(0, 400 + 300 * 160, n_clips)
+    lengths[5::7] = 0
+    lengths[3::11] = 399
+    wave, off = workloads.random_clips(lengths, seed=81 + n_clips)
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80, precision=prec)
+    L, _ = _gpu_forward(torch, melt, plan, wave, off)
+    assert L.shape[0] == sum(melt.melt_num_frames(int(n), 400, 160) for n in lengths)
+    _check(orc, melt, plan, L, wave, off, prec, label=f"{n_clips} clips {prec}")
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "fp8", "fp8b"])
 def test_ragged_edge_cases(torch, melt, orc, prec):
     """Empty clips, clips shorter than a frame, exactly one frame, one sample more, and
