@@ -681,7 +681,7 @@ __global__ __launch_bounds__(768) void k_melt_f8b_pc(FwdArgs a, const i32x8 *__r
                                                     int buf_bytes, int code_off, int n_codes, int scr_off,
                                                     int rgroups) {
     extern __shared__ float lds_pc[];
-    __shared__ Chunk dslot[4];
+    __shared__ __align__(16) Chunk dslot[4];
     __shared__ float rinv_s[8 * 32];
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
@@ -724,10 +724,17 @@ __global__ __launch_bounds__(768) void k_melt_f8b_pc(FwdArgs a, const i32x8 *__r
             __syncthreads();                       // chunk it converted; buffer (it + 1) & 1 free
             const int c = c0 + it * cstep;
             if (c + cstep >= nch) continue;
-            Chunk nd{};
+            // the next descriptor as two 16-byte values in registers (a Chunk variable
+            // assigned under this condition was placed in scratch memory: per-iteration stores
+            // that reached HBM and a wait for every outstanding memory operation)
+            uint4 nd0 = {}, nd1 = {};
             const bool load_desc = wid == nc && c + 3 * cstep < nch;
             async_wait();                          // this producer's copies of chunk it + 1
-            if (load_desc) nd = a.chunks[c + 3 * cstep];
+            if (load_desc) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(a.chunks + (c + 3 * cstep));
+                nd0 = src[0];
+                nd1 = src[1];
+            }
             const Chunk ch1 = slot_get(dslot, (it + 1) & 3);
             unsigned char *rows = buf0 + ((it + 1) & 1) * buf_bytes;
             int *codes = reinterpret_cast<int *>(rows + code_off);
@@ -735,7 +742,11 @@ __global__ __launch_bounds__(768) void k_melt_f8b_pc(FwdArgs a, const i32x8 *__r
                 convert_owned8<true>(a, ch1, span, rows, S8, codes, inv_bph, pw, np, slot_get(dslot, (it + 2) & 3));
             else
                 convert_owned8<false>(a, ch1, span, rows, S8, codes, inv_bph, pw, np, ch1);
-            if (load_desc && lane == 0) dslot[(it + 3) & 3] = nd;
+            if (load_desc && lane == 0) {
+                uint4 *dst = reinterpret_cast<uint4 *>(dslot + ((it + 3) & 3));
+                dst[0] = nd0;
+                dst[1] = nd1;
+            }
         }
         return;
     }

@@ -579,7 +579,7 @@ template <class Conv, int NS, bool IS_F16>
 __global__ __launch_bounds__(768) void k_melt_h16_pc(FwdArgs a, const uint4 *__restrict__ bhi, GroupTableBig gt,
                                                      int bf, int rows_len, int scr_off, int rgroups) {
     extern __shared__ float lds_hpc[];
-    __shared__ Chunk dslot[4];
+    __shared__ __align__(16) Chunk dslot[4];
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
     const int grp = blockIdx.x % rgroups, gt_n = (a.row_tiles + rgroups - 1) / rgroups;
@@ -611,13 +611,24 @@ __global__ __launch_bounds__(768) void k_melt_h16_pc(FwdArgs a, const uint4 *__r
             __syncthreads();                       // chunk it converted; buffer (it + 1) & 1 free
             const int c = c0 + it * cstep;
             if (c + cstep >= nch) continue;
-            Chunk nd{};
+            // the next descriptor as two 16-byte values in registers (a Chunk variable
+            // assigned under this condition was placed in scratch memory: per-iteration stores
+            // that reached HBM and a wait for every outstanding memory operation)
+            uint4 nd0 = {}, nd1 = {};
             const bool load_desc = wid == nc && c + 3 * cstep < nch;
             async_wait();                          // this producer's copies of chunk it + 1
-            if (load_desc) nd = a.chunks[c + 3 * cstep];
+            if (load_desc) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(a.chunks + (c + 3 * cstep));
+                nd0 = src[0];
+                nd1 = src[1];
+            }
             const Chunk ch1 = ring_slot(dslot, (it + 1) & 3);
             convert_owned<Conv>(a, ch1, span, ((it + 1) & 1) ? rows1 : rows0, 0, pw, np);
-            if (load_desc && lane == 0) dslot[(it + 3) & 3] = nd;
+            if (load_desc && lane == 0) {
+                uint4 *dst = reinterpret_cast<uint4 *>(dslot + ((it + 3) & 3));
+                dst[0] = nd0;
+                dst[1] = nd1;
+            }
             if (c + 2 * cstep < nch) copy_owned(a, ring_slot(dslot, (it + 2) & 3), span, pw, np);
         }
         return;
