@@ -740,6 +740,8 @@ enum H16Kind { H16_LDS_DMA = 0, H16_REGISTER_STAGED = 1, H16_FRAME_SPLIT = 2, H1
                H16_ROW_PAIR = 5, H16_PC12 = 6 };
 melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf, int nbuf = 1);
 melt_status launch_melt_f8(Plan &p, const FwdTask &t, bool lds_dma, int bf);
+melt_status launch_melt_f8_pc(Plan &p, const FwdTask &t, int bf);
+size_t f8_pc_lds_bytes(const Plan &p, int bf);
 size_t f8_as_lds_bytes(const Plan &p, int bf);   // LDS of the direct-to-LDS FP8 kernel
 melt_status launch_melt_f8b(Plan &p, const FwdTask &t, int bf, bool pc);   // FP8 with 32-sample block scales
 size_t f8b_lds_bytes(const Plan &p, int bf);

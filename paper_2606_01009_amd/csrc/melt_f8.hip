@@ -782,6 +782,175 @@ __global__ __launch_bounds__(768) void k_melt_f8b_pc(FwdArgs a, const i32x8 *__r
     }
 }
 
+// ------------------------------------------------------------------ FP8 per-frame scales, producer/consumer
+//
+// The per-frame FP8 kernel on 12 waves (three per SIMD), arranged as k_melt_f8b_pc: the first
+// NC waves (NC = row tiles of the group) are consumers holding one E4M3 basis tile each, the
+// other 12 - NC are producers that quantise the next chunk while the consumers multiply this
+// one.  A producer takes whole frames (frames p, p + NP, ..., four in flight): frame t of the
+// chunk is span samples [tH, tH + N), samples past the clip end 0; a lane holds samples
+// 4 u .. 4 u + 3 for its words u = lane + 64 k, the wave reduces max|x| over them, forms
+// s_t = 448 / max (1 for a silent frame) and writes the frame's E4M3 image row (zeros past N).
+// The FP32 span and the image are double buffered (chunk k in buffer k % 2): the copies of
+// chunk it + 2 (256-sample blocks p, p + NP, ...) are issued at the start of iteration it into
+// the buffer of chunk it, which every producer finished before the barrier that started the
+// iteration, and each producer waits for its own at the end of the iteration (a producer
+// reads samples other producers copied, so the wait precedes the next barrier).  One barrier
+// per chunk; descriptors through a four-slot LDS ring.  The scales and the unscaling epilogue
+// are those of k_melt_f8_as.  Per chunk the quantisation of whole frames (a wave-wide maximum
+// per frame) costs the producers more than the all-wave kernel's block-maxima passes: at
+// 80 Mel bins and n_fft 400 this kernel is slower than k_melt_f8_as, so it is the variant for
+// row groups (more than 128 Mel bins), which k_melt_f8_as does not take.  Needs hop and frame
+// multiples of 4 samples.
+template <int NG>
+__global__ __launch_bounds__(768) void k_melt_f8_pc(FwdArgs a, const i32x8 *__restrict__ bq,
+                                                   const float *__restrict__ rinv_g, int N, int bf, int img_bytes,
+                                                   int span_off, int span_bytes, int rgroups) {
+    extern __shared__ float lds_fpc[];
+    __shared__ __align__(16) Chunk dslot[4];
+    __shared__ __align__(16) float rinv_s[8 * 32];
+    constexpr int KP = NG * 64;             // padded frame length in the E4M3 image
+    constexpr int SQ = KP + 16;             // row stride (bytes): conflict-free 16-byte reads
+    constexpr int WPF = KP / 4;             // image words per frame
+    constexpr int KW = (WPF + 63) / 64;     // words per lane
+    constexpr int FT = 4;                   // frames in flight per producer wave
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
+    const int grp = blockIdx.x % rgroups, gt_n = (a.row_tiles + rgroups - 1) / rgroups;
+    const int r0 = grp * gt_n, cnt = min(a.row_tiles - r0, gt_n);
+    const int nc = cnt, np = nw - cnt;             // consumers (one row tile each), producers
+    const bool producer = wid >= nc;
+    const int pw = wid - nc;
+    for (int i = threadIdx.x; i < 32 * cnt; i += blockDim.x) rinv_s[i] = rinv_g[32 * r0 + i];
+    unsigned char *img0 = reinterpret_cast<unsigned char *>(lds_fpc);
+    float *span0 = reinterpret_cast<float *>(img0 + span_off);
+    const bool vec = (a.H & 3) == 0 && (N & 3) == 0;
+    const int nch = *a.n_chunks;
+    const int cstep = gridDim.x / rgroups;
+    const int c0 = blockIdx.x / rgroups;
+    // image rows of chunk frames [w0, ...) step ws, of buffer `img` (scales after the rows)
+    auto quantise = [&](const Chunk &ch, const float *span, unsigned char *img, int w0, int ws) {
+        const int valid = span_valid(a, ch);
+        float *sinv = reinterpret_cast<float *>(img + bf * SQ);
+        for (int t0 = w0; t0 < ch.n_frames; t0 += FT * ws) {
+            f32x4 x[FT][KW];
+#pragma unroll
+            for (int h = 0; h < FT; ++h) {
+                const int t = t0 + h * ws;
+#pragma unroll
+                for (int k = 0; k < KW; ++k) x[h][k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                if (t >= ch.n_frames) continue;
+                const int base = t * a.H;
+                const bool whole = vec && base + N <= valid;
+#pragma unroll
+                for (int k = 0; k < KW; ++k) {
+                    const int n0 = 4 * (lane + 64 * k), o = base + n0;
+                    if (whole) {
+                        if (n0 < N) x[h][k] = *(const f32x4 *)(span + o);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) x[h][k][e] = (n0 + e < N && o + e < valid) ? span[o + e] : 0.0f;
+                    }
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < FT; ++h) {
+                const int t = t0 + h * ws;              // wave-uniform
+                if (t >= ch.n_frames) break;
+                float m = 0.0f;
+#pragma unroll
+                for (int k = 0; k < KW; ++k)
+                    m = fmaxf(m, fmaxf(fmaxf(fabsf(x[h][k][0]), fabsf(x[h][k][1])),
+                                       fmaxf(fabsf(x[h][k][2]), fabsf(x[h][k][3]))));
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
+                const float sc = m > 0.0f ? __fdiv_rn(448.0f, m) : 1.0f;   // inverted in the epilogue
+                if (lane == 0) sinv[t] = sc;
+                unsigned *dst = reinterpret_cast<unsigned *>(img + t * SQ);
+#pragma unroll
+                for (int k = 0; k < KW; ++k) {
+                    const int u = lane + 64 * k;
+                    if (u < WPF)
+                        dst[u] = fp8x4(__fmul_rn(x[h][k][0], sc), __fmul_rn(x[h][k][1], sc),
+                                       __fmul_rn(x[h][k][2], sc), __fmul_rn(x[h][k][3], sc));
+                }
+            }
+        }
+    };
+    // prologue: descriptors 0..2 in their slots; every wave copies chunk 0 (blocks w, w + 12,
+    // ...) into span 0, the producers also chunk 1 into span 1; after a barrier every wave
+    // quantises frames of chunk 0 into image 0
+    if (wid == nc && lane < 3 && c0 + lane * cstep < nch) dslot[lane] = a.chunks[c0 + lane * cstep];
+    if (c0 < nch) copy_owned8(a, read_chunk(a.chunks, c0), span0, wid, nw);
+    if (producer && c0 + cstep < nch)
+        copy_owned8(a, read_chunk(a.chunks, c0 + cstep), reinterpret_cast<float *>(img0 + span_off + span_bytes), pw,
+                    np);
+    async_wait();
+    __syncthreads();
+    if (c0 < nch) quantise(read_chunk(a.chunks, c0), span0, img0, wid, nw);
+    if (producer) {
+        for (int it = 0; c0 + it * cstep < nch; ++it) {
+            __syncthreads();                       // chunk it quantised; image (it + 1) & 1 free
+            const int c = c0 + it * cstep;
+            if (c + cstep >= nch) continue;
+            float *span_nx = reinterpret_cast<float *>(img0 + span_off + (it & 1) * span_bytes);
+            const float *span_cur = reinterpret_cast<const float *>(img0 + span_off + ((it + 1) & 1) * span_bytes);
+            // chunk it + 2 into the span chunk it used
+            if (c + 2 * cstep < nch) copy_owned8(a, slot_get(dslot, (it + 2) & 3), span_nx, pw, np);
+            uint4 nd0 = {}, nd1 = {};              // the next descriptor, in registers
+            const bool load_desc = wid == nc && c + 3 * cstep < nch;
+            if (load_desc) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(a.chunks + (c + 3 * cstep));
+                nd0 = src[0];
+                nd1 = src[1];
+            }
+            quantise(slot_get(dslot, (it + 1) & 3), span_cur, img0 + ((it + 1) & 1) * img_bytes, pw, np);
+            if (load_desc && lane == 0) {
+                uint4 *dst = reinterpret_cast<uint4 *>(dslot + ((it + 3) & 3));
+                dst[0] = nd0;
+                dst[1] = nd1;
+            }
+            async_wait();                          // this producer's copies of chunk it + 2
+        }
+        return;
+    }
+    const int rt = r0 + wid;
+    i32x8 A[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) A[g] = bq[((size_t)rt * NG + g) * 64 + lane];
+    // the tile's row unscaling factors in LDS (read in the epilogue, not held in registers):
+    // lane half h uses rows 8 q + 4 h .. + 3 of the tile, four consecutive floats per q
+    const float *ri = rinv_s + 32 * wid + 4 * (lane >> 5);
+    for (int it = 0; c0 + it * cstep < nch; ++it) {
+        __syncthreads();                           // chunk it quantised; image (it + 1) & 1 free
+        const Chunk ch = slot_get(dslot, it & 3);
+        const unsigned char *xq = img0 + (it & 1) * img_bytes;
+        const float *sinv = reinterpret_cast<const float *>(xq + bf * SQ);
+        const int nft = (ch.n_frames + 31) >> 5;
+        for (int ft = 0; ft < nft; ++ft) {
+            const int f = ft * 32 + (lane & 31);
+            int off = f * SQ + 32 * (lane >> 5);
+            asm volatile("" : "+v"(off));
+            const unsigned char *q0 = xq + off;
+            f32x16 acc = f32x16{};
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const uint4 bl = *(const uint4 *)(q0 + 64 * g), bh = *(const uint4 *)(q0 + 64 * g + 16);
+                const i32x8 B = {(int)bl.x, (int)bl.y, (int)bl.z, (int)bl.w, (int)bh.x, (int)bh.y, (int)bh.z, (int)bh.w};
+                acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[g], B, acc, 0, 0, 0, 127, 0, 127);
+            }
+            const float is = f < ch.n_frames ? 1.0f / sinv[f] : 0.0f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const f32x4 r4 = *(const f32x4 *)(ri + 8 * q);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[4 * q + e] = acc[4 * q + e] * (is * r4[e]);
+            }
+            store_tile(a, ch, rt, f, lane, acc);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launch
 
 template <int NG>
@@ -802,6 +971,26 @@ size_t f8_as_scratch_offset(const Plan &p, int bf) {
 }
 size_t f8_as_lds_bytes(const Plan &p, int bf) {
     return (f8_as_scratch_offset(p, bf) + (size_t)(bf + p.geo32.J - 1) * p.H * 4 + 15) & ~size_t(15);
+}
+
+// LDS of the per-frame producer/consumer kernel: two images (rows then the frame scales) and
+// two FP32 spans, each 16-byte aligned
+static size_t f8_pc_img_bytes(const Plan &p, int bf) {
+    const int ng8 = (p.N + 63) / 64;
+    return ((size_t)bf * (ng8 * 64 + 16) + (size_t)bf * 4 + 15) & ~size_t(15);
+}
+static size_t f8_pc_span_bytes(const Plan &p, int bf) {
+    return ((size_t)(bf + p.geo32.J - 1) * p.H * 4 + 15) & ~size_t(15);
+}
+size_t f8_pc_lds_bytes(const Plan &p, int bf) { return 2 * f8_pc_img_bytes(p, bf) + 2 * f8_pc_span_bytes(p, bf); }
+
+template <int NG>
+static melt_status launch_f8_pc_ng(Plan &p, const FwdArgs &a, size_t lds, int grid, int bf, int rg, hipStream_t s) {
+    allow_lds(k_melt_f8_pc<NG>, 4 * sizeof(Chunk) + 8 * 32 * 4);
+    const size_t img = f8_pc_img_bytes(p, bf);
+    k_melt_f8_pc<NG><<<grid, 768, lds, s>>>(a, (const i32x8 *)p.d_pack_f8, p.d_rowscale, p.N, bf, (int)img,
+                                            (int)(2 * img), (int)f8_pc_span_bytes(p, bf), rg);
+    return hip_check(hipGetLastError(), "melt f8 producer/consumer launch");
 }
 
 template <int NG>
@@ -897,6 +1086,29 @@ melt_status launch_melt_f8b(Plan &p, const FwdTask &t, int bf, bool pc) {
     case 7: return launch_f8b_ng<7>(p, a, bt, lds, grid, bf, rg, t.stream);
     case 8: return launch_f8b_ng<8>(p, a, bt, lds, grid, bf, rg, t.stream);
     default: return launch_f8b_ng<16>(p, a, bt, lds, grid, bf, rg, t.stream);
+    }
+}
+
+melt_status launch_melt_f8_pc(Plan &p, const FwdTask &t, int bf) {
+    const int ng8 = (p.N + 63) / 64;
+    if (p.H % 4 != 0 || p.N % 4 != 0)
+        return set_error(MELT_E_UNSUPPORTED, "producer/consumer FP8 kernel: hop and n_fft must be multiples of 4");
+    const int rg = row_groups(p), gt_n = (p.row_tiles + rg - 1) / rg;
+    if (gt_n > 8) return set_error(MELT_E_UNSUPPORTED, "producer/consumer FP8 kernel: row group too large");
+    const size_t lds = f8_pc_lds_bytes(p, bf);
+    if (lds + 4 * sizeof(Chunk) + 8 * 32 * 4 > (size_t)kMaxLds)
+        return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS for the FP8 kernel");
+    const Geometry &g = p.geo32;
+    const FwdArgs a = make_args(p, g, lds_stride(g.Hp, 4), t);
+    // one persistent set of workgroups per row group, one workgroup per CU
+    const int per_group =
+        (int)std::max<int64_t>(1, std::min<int64_t>(t.est_chunks, ((int64_t)p.cu_count + rg - 1) / rg));
+    const int grid = per_group * rg;
+    switch (ng8) {
+    case 4: return launch_f8_pc_ng<4>(p, a, lds, grid, bf, rg, t.stream);
+    case 7: return launch_f8_pc_ng<7>(p, a, lds, grid, bf, rg, t.stream);
+    case 8: return launch_f8_pc_ng<8>(p, a, lds, grid, bf, rg, t.stream);
+    default: return set_error(MELT_E_UNSUPPORTED, "producer/consumer FP8 kernel: n_fft in (192, 256] or (384, 512]");
     }
 }
 

@@ -370,7 +370,7 @@ melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H
 //   FP8 with 32-sample block scales  producer/consumer block-scaled kernel, then the
 //              one-buffer block-scaled kernel with 160- and 128-frame chunks
 enum VariantKind { V_F32_WS, V_F32_FS, V_H16_PP, V_H16_AS, V_H16_AP, V_H16_RS, V_H16_KS, V_H16_FS, V_F8_AS, V_F8_RS,
-                   V_F8B_AS, V_F8B_PC, V_H16_PC };
+                   V_F8B_AS, V_F8B_PC, V_H16_PC, V_F8_PC };
 struct Variant {
     VariantKind kind;
     int bf;          // frames per chunk
@@ -384,9 +384,14 @@ static std::vector<Variant> variant_list(const Plan &p) {
         v.push_back({V_F32_WS, kBF32});
         v.push_back({V_F32_FS, kBF32});
         break;
-    case MELT_PREC_FP8_E4M3:
-        // the largest chunk that fits LDS (one workgroup per CU), then 64-frame chunks with two
-        // workgroups per CU (one quantises while the other multiplies)
+    case MELT_PREC_FP8_E4M3: {
+        // up to 8 row tiles: the largest all-wave chunk that fits LDS (one workgroup per CU),
+        // then 64-frame chunks with two workgroups per CU; the producer/consumer kernel (two
+        // images and two spans of 64-frame chunks) first beyond 8 row tiles, last otherwise
+        const int ng8 = (p.N + 63) / 64;
+        const bool pc = (ng8 == 4 || ng8 == 7 || ng8 == 8) && p.H % 4 == 0 && p.N % 4 == 0 &&
+                        f8_pc_lds_bytes(p, 64) + 4 * sizeof(Chunk) + 8 * 32 * 4 <= (size_t)kMaxLds;
+        if (pc && p.row_tiles > 8) v.push_back({V_F8_PC, 64});
         for (int bf : {128, 96, 64, 32})
             if (f8_as_lds_bytes(p, bf) + kRingBytes <= (size_t)kMaxLds) {
                 v.push_back({V_F8_AS, bf});
@@ -395,7 +400,9 @@ static std::vector<Variant> variant_list(const Plan &p) {
         if (!v.empty() && v.back().bf > 64 && 2 * (f8_as_lds_bytes(p, 64) + kRingBytes) <= (size_t)kMaxLds)
             v.push_back({V_F8_AS, 64});
         v.push_back({V_F8_RS, kBF32});
+        if (pc && p.row_tiles <= 8) v.push_back({V_F8_PC, 64});
         break;
+    }
     case MELT_PREC_FP8_E4M3_BLOCK32:
         // producer/consumer (the largest chunk whose two row buffers fit; three waves per SIMD,
         // so a basis tile of at most 8 k-groups of 64), then the one-buffer kernel at 160- and
@@ -493,6 +500,7 @@ const char *forward_variant_name(const Plan &p, int i) {
                     : v.kind == V_H16_KS ? "h16-k-split-lds-dma"
                     : v.kind == V_H16_FS ? "h16-frame-split"
                     : v.kind == V_F8_AS  ? "f8-row-split-lds-dma"
+                    : v.kind == V_F8_PC  ? "f8-producer-consumer-lds-dma"
                     : v.kind == V_F8B_AS ? "f8-block-scaled-lds-dma"
                     : v.kind == V_F8B_PC ? "f8-block-scaled-producer-consumer-lds-dma"
                                             : "f8-row-split";
@@ -535,6 +543,7 @@ melt_status launch_melt_table(Plan &p, int variant, const Chunk *tab, const int 
     case V_H16_KS: return launch_melt_h16(p, t, H16_K_SPLIT, v.bf);
     case V_H16_FS: return launch_melt_h16(p, t, H16_FRAME_SPLIT, v.bf);
     case V_F8_AS: return launch_melt_f8(p, t, true, v.bf);
+    case V_F8_PC: return launch_melt_f8_pc(p, t, v.bf);
     case V_F8_RS: return launch_melt_f8(p, t, false, v.bf);
     case V_F8B_AS: return launch_melt_f8b(p, t, v.bf, false);
     case V_F8B_PC: return launch_melt_f8b(p, t, v.bf, true);

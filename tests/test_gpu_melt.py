@@ -416,25 +416,33 @@ def test_spectral_band_80_7600(torch, melt, orc, prec):
     _check(orc, melt, plan, L, cfg["wave"], cfg["offsets"], prec, label=f"80-7600 Hz {prec}")
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp8b"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp8", "fp8b"])
 def test_512_mel_bins(torch, melt, orc, prec):
     """The top of the Mel-bin sweep (M = 512, the paper's break-even point; Fig. m_sweep) over
-    80-7600 Hz: 32 row tiles, so four 16-bit (and block-scaled FP8) row groups and, for FP32,
-    several row-tile blocks per chunk.  2 clips x 2 s (two full chunks and a ragged tail each)."""
+    80-7600 Hz: 32 row tiles, so four 16-bit (and FP8) row groups and, for FP32, several
+    row-tile blocks per chunk.  2 clips x 2 s (two full chunks and a ragged tail each)."""
     cfg = workloads.config2(n_mels=512, n_clips=2, seconds=2.0)
     plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=512, fmin=80.0, fmax=7600.0, precision=prec)
     L, _ = _gpu_forward(torch, melt, plan, cfg["wave"], cfg["offsets"])
     _check(orc, melt, plan, L, cfg["wave"], cfg["offsets"], prec, label=f"M=512 {prec}")
 
 
-def test_512_mel_bins_fp8_unsupported(torch, melt):
-    """The FP8 kernel holds at most 8 row tiles (128 Mel bins): more is reported, not run."""
+def test_512_mel_bins_fp8_all_wave_unsupported(torch, melt):
+    """The all-wave per-frame FP8 kernels hold at most 8 row tiles (128 Mel bins): pinned at
+    512 Mel bins they report the error and run nothing (the producer/consumer kernel, the
+    default, takes row groups)."""
     plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=512, precision="fp8")
     wave = torch.zeros(16000, dtype=torch.float32, device="cuda")
     off = torch.tensor([0, 16000], dtype=torch.int64, device="cuda")
-    with pytest.raises(melt.MeltError) as ei:
-        plan.forward(wave, off, 98)
-    assert ei.value.status == melt.MELT_E_UNSUPPORTED
+    names = [melt.melt_variant_name(plan.handle, v) for v in range(melt.melt_variant_count(plan.handle))]
+    assert "producer-consumer" in names[0]
+    others = [v for v, n in enumerate(names) if "producer-consumer" not in n]
+    assert others
+    for v in others:
+        melt.melt_set_variant(plan.handle, v)
+        with pytest.raises(melt.MeltError) as ei:
+            plan.forward(wave, off, 98)
+        assert ei.value.status == melt.MELT_E_UNSUPPORTED
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8", "fp8b"])
