@@ -472,6 +472,18 @@ __device__ __forceinline__ int async_span(const FwdArgs &a, const Chunk &ch, flo
     return async_span_waves(a, ch, scratch, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), blockDim.x >> 6);
 }
 
+// Chunk descriptor i of the table (i wave-uniform) through the scalar data cache (the table is
+// read-only in the forward kernels): the wait for it is on the scalar-memory counter, so it
+// never includes the wave's direct-to-LDS copies, which the compiler does not track (the
+// wait it places for a vector load issued before such copies is a full vmcnt(0)).
+__device__ __forceinline__ void load_chunk_scalar(const Chunk *tab, int i, uint4 &lo, uint4 &hi) {
+    typedef unsigned cu32x8 __attribute__((ext_vector_type(8)));
+    typedef const __attribute__((address_space(4))) cu32x8 *cptr;
+    const cu32x8 v = *(cptr)(tab + i);
+    lo = make_uint4(v[0], v[1], v[2], v[3]);
+    hi = make_uint4(v[4], v[5], v[6], v[7]);
+}
+
 __device__ __forceinline__ void async_wait() {
     __builtin_amdgcn_s_waitcnt(0);     // this wave's direct-to-LDS copies have landed
 }

@@ -726,15 +726,12 @@ __global__ __launch_bounds__(768) void k_melt_f8b_pc(FwdArgs a, const i32x8 *__r
             if (c + cstep >= nch) continue;
             // the next descriptor as two 16-byte values in registers (a Chunk variable
             // assigned under this condition was placed in scratch memory: per-iteration stores
-            // that reached HBM and a wait for every outstanding memory operation)
+            // that reached HBM and a wait for every outstanding memory operation), loaded
+            // through the scalar cache so that storing it waits for no copy
             uint4 nd0 = {}, nd1 = {};
             const bool load_desc = wid == nc && c + 3 * cstep < nch;
             async_wait();                          // this producer's copies of chunk it + 1
-            if (load_desc) {
-                const uint4 *src = reinterpret_cast<const uint4 *>(a.chunks + (c + 3 * cstep));
-                nd0 = src[0];
-                nd1 = src[1];
-            }
+            if (load_desc) load_chunk_scalar(a.chunks, c + 3 * cstep, nd0, nd1);
             const Chunk ch1 = slot_get(dslot, (it + 1) & 3);
             unsigned char *rows = buf0 + ((it + 1) & 1) * buf_bytes;
             int *codes = reinterpret_cast<int *>(rows + code_off);
@@ -897,13 +894,9 @@ __global__ __launch_bounds__(768) void k_melt_f8_pc(FwdArgs a, const i32x8 *__re
             const float *span_cur = reinterpret_cast<const float *>(img0 + span_off + ((it + 1) & 1) * span_bytes);
             // chunk it + 2 into the span chunk it used
             if (c + 2 * cstep < nch) copy_owned8(a, slot_get(dslot, (it + 2) & 3), span_nx, pw, np);
-            uint4 nd0 = {}, nd1 = {};              // the next descriptor, in registers
+            uint4 nd0 = {}, nd1 = {};              // the next descriptor (scalar loads), in registers
             const bool load_desc = wid == nc && c + 3 * cstep < nch;
-            if (load_desc) {
-                const uint4 *src = reinterpret_cast<const uint4 *>(a.chunks + (c + 3 * cstep));
-                nd0 = src[0];
-                nd1 = src[1];
-            }
+            if (load_desc) load_chunk_scalar(a.chunks, c + 3 * cstep, nd0, nd1);
             quantise(slot_get(dslot, (it + 1) & 3), span_cur, img0 + ((it + 1) & 1) * img_bytes, pw, np);
             if (load_desc && lane == 0) {
                 uint4 *dst = reinterpret_cast<uint4 *>(dslot + ((it + 3) & 3));

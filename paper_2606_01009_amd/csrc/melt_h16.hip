@@ -613,15 +613,12 @@ __global__ __launch_bounds__(768) void k_melt_h16_pc(FwdArgs a, const uint4 *__r
             if (c + cstep >= nch) continue;
             // the next descriptor as two 16-byte values in registers (a Chunk variable
             // assigned under this condition was placed in scratch memory: per-iteration stores
-            // that reached HBM and a wait for every outstanding memory operation)
+            // that reached HBM and a wait for every outstanding memory operation), loaded
+            // through the scalar cache so that storing it waits for no copy
             uint4 nd0 = {}, nd1 = {};
             const bool load_desc = wid == nc && c + 3 * cstep < nch;
             async_wait();                          // this producer's copies of chunk it + 1
-            if (load_desc) {
-                const uint4 *src = reinterpret_cast<const uint4 *>(a.chunks + (c + 3 * cstep));
-                nd0 = src[0];
-                nd1 = src[1];
-            }
+            if (load_desc) load_chunk_scalar(a.chunks, c + 3 * cstep, nd0, nd1);
             const Chunk ch1 = ring_slot(dslot, (it + 1) & 3);
             convert_owned<Conv>(a, ch1, span, ((it + 1) & 1) ? rows1 : rows0, 0, pw, np);
             if (load_desc && lane == 0) {
