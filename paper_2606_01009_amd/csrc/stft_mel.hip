@@ -19,6 +19,8 @@
 
 namespace melt {
 
+typedef float sm_f32x4 __attribute__((ext_vector_type(4)));
+
 void build_filterbank(const melt_config &c, std::vector<int> &start, std::vector<int> &off, std::vector<float> &w);
 
 // ------------------------------------------------------------------ compile-time cos/sin
@@ -305,7 +307,12 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WPE)
     constexpr int JT = (NB + 63) / 64;            // bins per lane in the power pass
     constexpr bool MAG = (KIND == MELT_OUT_LOG_MAGNITUDE || KIND == MELT_OUT_MAGNITUDE);
     constexpr bool PREFETCH = N1 * N2 < 1200 && N1 != 20;
-    static_assert(2 * NB <= 2 * BUF, "power spectra must fit in the FFT rows");
+    // power spectra interleaved by bin: bin k holds the FPW spectra of half 0, then those of
+    // half 1, each half padded to FP4 floats, so a step-5 lane reads its FPW values of one bin
+    // in one access (16 bytes for FPW 3 and 4)
+    constexpr int FP4 = FPW == 3 ? 4 : FPW;
+    constexpr int PST = 2 * FP4;                  // floats per bin
+    static_assert(NB * PST <= 2 * FPW * BUF, "power spectra must fit in the FFT rows");
     extern __shared__ float smem[];
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -317,7 +324,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WPE)
     float *fbw = wl + N;
     int *fbs = reinterpret_cast<int *>(fbw + a.fb_nnz);
     int *fbo = fbs + a.M;
-    // the wave's 2 FPW power spectra [2 FPW][NB] are written over its FFT rows once read
+    // the wave's 2 FPW power spectra [NB][2][FP4] are written over its FFT rows once read
     float *pw = reinterpret_cast<float *>(buf);
     for (int i = threadIdx.x; i < N; i += 64 * WAVES) {
         const int k1 = i / N2, n2 = i - k1 * N2;
@@ -434,10 +441,22 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WPE)
             for (int j = 0; j < JT; ++j) {
                 const int k = lane + 64 * j;
                 if (64 * j + 64 <= NB || k < NB) {
+                    // spectrum q = 2 p (A of FFT p) or 2 p + 1 (B); half h holds q = h FPW + f
 #pragma unroll
-                    for (int p = 0; p < FPW; ++p) {
-                        pw[(2 * p) * NB + k] = pa[p][j];
-                        pw[(2 * p + 1) * NB + k] = pb[p][j];
+                    for (int h = 0; h < 2; ++h) {
+                        float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                        for (int f = 0; f < FPW; ++f) {
+                            const int q = h * FPW + f;
+                            v[f] = (q & 1) ? pb[q >> 1][j] : pa[q >> 1][j];
+                        }
+                        float *d = pw + k * PST + h * FP4;
+                        if constexpr (FP4 == 4) {
+                            *reinterpret_cast<sm_f32x4 *>(d) = sm_f32x4{v[0], v[1], v[2], v[3]};
+                        } else {
+#pragma unroll
+                            for (int f = 0; f < FPW; ++f) d[f] = v[f];
+                        }
                     }
                 }
             }
@@ -450,25 +469,41 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WPE)
             const int f0 = 2 * FPW * cur_sub;
             for (int t = lane; t < 2 * a.M; t += 64) {
                 const int m = t >> 1, h = t & 1;
-                const float *ps = pw + h * FPW * NB + fbs[m];
+                const float *ps = pw + fbs[m] * PST + h * FP4;
                 const int j0 = fbo[m], nj = fbo[m + 1] - j0;
                 const float *wj = fbw + j0;
                 float acc[FPW];
 #pragma unroll
                 for (int f = 0; f < FPW; ++f) acc[f] = 0.0f;
+                // the FPW values of bin fbs[m] + j
+                auto bin = [&](int j, float (&x)[FPW]) {
+                    if constexpr (FP4 == 4) {
+                        const sm_f32x4 v = *reinterpret_cast<const sm_f32x4 *>(ps + j * PST);
+#pragma unroll
+                        for (int f = 0; f < FPW; ++f) x[f] = v[f];
+                    } else {
+#pragma unroll
+                        for (int f = 0; f < FPW; ++f) x[f] = ps[j * PST + f];
+                    }
+                };
                 int j = 0;
                 for (; j + 1 < nj; j += 2) {
                     const float w0 = wj[j], w1 = wj[j + 1];
+                    float x0[FPW], x1[FPW];
+                    bin(j, x0);
+                    bin(j + 1, x1);
 #pragma unroll
                     for (int f = 0; f < FPW; ++f) {
-                        acc[f] += w0 * ps[f * NB + j];
-                        acc[f] += w1 * ps[f * NB + j + 1];
+                        acc[f] += w0 * x0[f];
+                        acc[f] += w1 * x1[f];
                     }
                 }
                 if (j < nj) {
                     const float w0 = wj[j];
+                    float x0[FPW];
+                    bin(j, x0);
 #pragma unroll
-                    for (int f = 0; f < FPW; ++f) acc[f] += w0 * ps[f * NB + j];
+                    for (int f = 0; f < FPW; ++f) acc[f] += w0 * x0[f];
                 }
 #pragma unroll
                 for (int f = 0; f < FPW; ++f) {
@@ -507,8 +542,7 @@ constexpr int kStftWaves = 4;
 
 size_t stft_lds_bytes(const StftShape &s, int M, int nnz) {
     const int N = s.N1 * s.N2;
-    const int LDB = s.N2 + 1;
-    const int BUF = std::max(s.N1 * LDB, N);
+    const int BUF = std::max(s.N1 * (s.N2 + 1), N);
     // twiddles and FFT rows (the power spectra reuse the rows), window, weights, starts, offsets
     return (size_t)N * 8 + (size_t)kStftWaves * s.FPW * BUF * 8 + (size_t)N * 4 + (size_t)nnz * 4 +
            (size_t)(2 * M + 1) * 4;
