@@ -233,6 +233,25 @@ def test_every_kernel_variant(torch, melt, orc, prec):
             melt.melt_set_variant(plan.handle, n, 0)
 
 
+@pytest.mark.parametrize("geom", [(16000, 256, 128, 80), (16000, 400, 160, 144), (16000, 512, 128, 96),
+                                  (16000, 400, 160, 256)])
+def test_fp8_producer_consumer(torch, melt, orc, geom):
+    """The per-frame FP8 producer/consumer kernel pinned by name: 4, 7 and 8 k-groups of 64
+    (n_fft 256, 400, 512), one row group and row groups of 5 + 4 and 8 + 8 tiles, on ragged
+    clips that end its 64-frame chunks exactly, one frame past them and mid-way (the span and
+    image buffers alternate per chunk)."""
+    sr, N, H, M = geom
+    plan = melt.MeltPlan(sample_rate=sr, n_fft=N, hop=H, n_mels=M, precision="fp8")
+    names = [melt.melt_variant_name(plan.handle, v) for v in range(melt.melt_variant_count(plan.handle))]
+    pc = [v for v, n in enumerate(names) if "producer-consumer" in n]
+    assert len(pc) == 1
+    melt.melt_set_variant(plan.handle, pc[0], 0)
+    lengths = [0, N - 1, N] + [(f - 1) * H + N + d for f in (63, 64, 65, 128, 129, 200, 257) for d in (0, 3)]
+    wave, off = workloads.random_clips(lengths, seed=N + M + 7)
+    L, _ = _gpu_forward(torch, melt, plan, wave, off)
+    _check(orc, melt, plan, L, wave, off, "fp8", label=f"fp8 producer/consumer {geom}")
+
+
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
 @pytest.mark.parametrize("geom", [(22050, 1024, 256, 128), (16000, 1200, 160, 128), (16000, 1024, 256, 40)])
 def test_split_precisions_long_frames(torch, melt, orc, prec, geom):
