@@ -82,20 +82,23 @@ def db_stats(L_gpu, L_ref, S_ref, active_db=80.0):
                 active_frac=float(act.mean()) if act.size else 0.0)
 
 
-def frames_as_clips(wave, offsets, n_fft, hop, frame_ids):
+def frames_as_clips(wave, offsets, n_fft, hop, frame_ids, tail=0):
     """Re-expresses selected global frames as one-frame clips (start offsets), so the oracle
-    can evaluate just those frames of a large batch."""
+    can evaluate just those frames of a large batch.  tail (< hop) keeps up to that many
+    samples past each frame, within its clip: the rest of the frame's last 32-sample block, on
+    which the block-scaled FP8 scale of that block depends."""
+    assert 0 <= tail < hop
     offsets = np.asarray(offsets, np.int64)
-    starts = []
+    segs = []
     T_c = np.array([max(0, 1 + (b - a - n_fft) // hop) if b - a >= n_fft else 0
                     for a, b in zip(offsets[:-1], offsets[1:])], np.int64)
     fo = np.concatenate([[0], np.cumsum(T_c)])
     for f in frame_ids:
         c = int(np.searchsorted(fo, f, side="right") - 1)
-        starts.append(offsets[c] + (f - fo[c]) * hop)
-    segs = [wave[s:s + n_fft] for s in starts]
+        s = offsets[c] + (f - fo[c]) * hop
+        segs.append(wave[s:min(s + n_fft + tail, offsets[c + 1])])
     sub = np.concatenate(segs).astype(np.float32)
-    off = np.arange(len(segs) + 1, dtype=np.int64) * n_fft
+    off = np.concatenate([[0], np.cumsum([len(g) for g in segs])]).astype(np.int64)
     return sub, off
 
 

@@ -363,20 +363,24 @@ def test_empty_calls(torch, melt):
         melt.melt_forward(plan.handle, None, d_off2, 5, out)
 
 
-def test_config2_full_size_sampled(torch, melt, orc):
-    """The benchmark's workload and launch: 64 clips x 30 s (191 872 frames, M=80), FP32.
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp16x3", "fp8", "fp8b"])
+def test_config2_full_size_sampled(torch, melt, orc, prec):
+    """The benchmark's workload and launch: 64 clips x 30 s (191 872 frames, M=80), at every
+    precision the benchmark times (each plan's default kernel, as the benchmark runs it).
     256 frames sampled across the batch (first/last of every clip included) are checked
-    against the oracle evaluated on exactly those frames."""
+    against the oracle evaluated on exactly those frames (with the rest of the last 32-sample
+    block for block-scaled FP8)."""
     cfg = workloads.config2(n_mels=80)
-    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80, precision="fp32")
+    plan = melt.MeltPlan(sample_rate=16000, n_fft=400, hop=160, n_mels=80, precision=prec)
     L, _ = _gpu_forward(torch, melt, plan, cfg["wave"], cfg["offsets"])
     assert L.shape == (191872, 80)
     assert np.all(np.isfinite(L))
     rng = np.random.default_rng(77)
     ids = np.unique(np.concatenate([rng.integers(0, L.shape[0], 128), np.arange(0, 191872, 2998),
                                     np.arange(2997, 191872, 2998)]))
-    sub, off = parity.frames_as_clips(cfg["wave"], cfg["offsets"], 400, 160, ids)
-    _check(orc, melt, plan, L[ids], sub, off, "fp32", label="config2 full sampled fp32")
+    tail = (-400) % 32 if prec == "fp8b" else 0
+    sub, off = parity.frames_as_clips(cfg["wave"], cfg["offsets"], 400, 160, ids, tail=tail)
+    _check(orc, melt, plan, L[ids], sub, off, prec, label=f"config2 full sampled {prec}")
 
 
 # ------------------------------------------------------------------ centres, basis and options
