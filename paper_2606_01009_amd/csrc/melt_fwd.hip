@@ -358,15 +358,19 @@ melt_status launch_frame_offsets(const int64_t *d_off, int n_clips, int N, int H
 // Kernel variants of a plan, in the order the autotuner times them (p.tune_variant selects;
 // the first one is the default):
 //   FP32       frame-split with staging waves, frame-split with register prefetch
-//   BF16/FP16  row pairs (two basis tiles per wave) where they fit; row-split with direct-to-LDS
-//              staging (one span buffer: 128- then 64-frame
+//   BF16/FP16  the 12-wave producer/consumer kernel (96- or 64-frame chunks) where its
+//              register tiles and LDS fit; row pairs (two basis tiles per wave) where they fit;
+//              row-split with direct-to-LDS staging (one span buffer: 128- then 64-frame
 //              chunks; then two span buffers), producer/consumer row-split (one span, then
-//              two; only with producer waves), row-split with register staging, frame-split
-//              (the only one when the frame is too long for a register tile; for the split
-//              precisions only then)
-//   BF16X3 / FP16X3  the same without row pairs, with one-span chunks of 96 then 64 frames
-//   FP8        row-split with direct-to-LDS staging (the largest chunk that fits LDS),
-//              row-split with register staging
+//              two; only with producer waves), row-split with register staging, K-split (frames
+//              too long for one wave's tile), frame-split (the fallback; for the split
+//              precisions only where no register-tile kernel applies)
+//   BF16X3 / FP16X3  the 8-wave producer/consumer kernel (hi and lo tiles, 64-frame chunks)
+//              where it fits, then as above without row pairs and K-split, with one-span
+//              chunks of 96 then 64 frames
+//   FP8        row-split with direct-to-LDS staging (the largest chunk that fits LDS; 64-frame
+//              chunks at two workgroups per CU), row-split with register staging, then the
+//              producer/consumer kernel (first beyond 8 row tiles, which the others do not take)
 //   FP8 with 32-sample block scales  producer/consumer block-scaled kernel, then the
 //              one-buffer block-scaled kernel with 160- and 128-frame chunks
 enum VariantKind { V_F32_WS, V_F32_FS, V_H16_PP, V_H16_AS, V_H16_AP, V_H16_RS, V_H16_KS, V_H16_FS, V_F8_AS, V_F8_RS,
@@ -426,6 +430,10 @@ static std::vector<Variant> variant_list(const Plan &p) {
                     v.push_back({V_H16_PC, bf});
                     break;
                 }
+        // the split precisions' producer/consumer form (8 waves, hi and lo rows; 64-frame
+        // chunks): their default where it fits
+        if (x3 && pc_fits(p) && pc_x3_lds_bytes(p, 64) + 4 * sizeof(Chunk) <= (size_t)kMaxLds)
+            v.push_back({V_H16_PC, 64});
         if (!x3 && ap_fits(p) && as_lds_bytes(p, 128) + kRingBytes <= (size_t)kMaxLds) v.push_back({V_H16_AP, 128});
         if (as_fits(p)) {
             // one span buffer (128 then 64 frames per chunk; 96 then 64 for BF16X3), then two
@@ -495,7 +503,9 @@ const char *forward_variant_name(const Plan &p, int i) {
                     : v.kind == V_F32_FS ? "f32-frame-split"
                     : v.kind == V_H16_AS ? (v.nbuf == 2 ? "h16-row-split-lds-dma2" : "h16-row-split-lds-dma")
                     : v.kind == V_H16_AP ? "h16-row-pair-lds-dma"
-                    : v.kind == V_H16_PC ? "h16-producer-consumer-12w-lds-dma"
+                    : v.kind == V_H16_PC ? (p.cfg.precision == MELT_PREC_BF16X3 || p.cfg.precision == MELT_PREC_FP16X3
+                                                ? "h16-producer-consumer-8w-lds-dma"
+                                                : "h16-producer-consumer-12w-lds-dma")
                     : v.kind == V_H16_RS ? "h16-row-split"
                     : v.kind == V_H16_KS ? "h16-k-split-lds-dma"
                     : v.kind == V_H16_FS ? "h16-frame-split"

@@ -575,9 +575,11 @@ __global__ __launch_bounds__(512) void k_melt_h16_pp(FwdArgs a, const uint4 *__r
 // producer loads descriptor k + 3 in iteration k and stores it before the barrier (slot
 // (k + 3) mod 4 was last read in iteration k - 1).  The first chunk is copied and converted by
 // all twelve waves.
-template <class Conv, int NS, bool IS_F16>
-__global__ __launch_bounds__(768) void k_melt_h16_pc(FwdArgs a, const uint4 *__restrict__ bhi, GroupTableBig gt,
-                                                     int bf, int rows_len, int scr_off, int rgroups) {
+template <class Conv, int NS, bool X3, bool IS_F16>
+__global__ __launch_bounds__(X3 ? 512 : 768) void k_melt_h16_pc(FwdArgs a, const uint4 *__restrict__ bhi,
+                                                               const uint4 *__restrict__ blo, GroupTableBig gt,
+                                                               int bf, int rows_len, int lo_off, int scr_off,
+                                                               int rgroups) {
     extern __shared__ float lds_hpc[];
     __shared__ __align__(16) Chunk dslot[4];
     const int lane = threadIdx.x & 63;
@@ -593,16 +595,16 @@ __global__ __launch_bounds__(768) void k_melt_h16_pc(FwdArgs a, const uint4 *__r
     const int nch = *a.n_chunks;
     const int cstep = gridDim.x / rgroups;
     const int c0 = blockIdx.x / rgroups;
-    zero_pad_columns<Conv>(a, bf + a.J - 1, rows0, blockDim.x, 0);
-    zero_pad_columns<Conv>(a, bf + a.J - 1, rows1, blockDim.x, 0);
+    zero_pad_columns<Conv>(a, bf + a.J - 1, rows0, blockDim.x, lo_off);
+    zero_pad_columns<Conv>(a, bf + a.J - 1, rows1, blockDim.x, lo_off);
     if (wid == nc && lane < 3 && c0 + lane * cstep < nch) dslot[lane] = a.chunks[c0 + lane * cstep];
-    // the first chunk is copied and converted by every wave (blocks w, w + 12, ...); after a
+    // the first chunk is copied and converted by every wave (blocks w, w + nw, ...); after a
     // barrier the producers start the copy of the second
     if (c0 < nch) {
         const Chunk ch = read_chunk(a.chunks, c0);
         copy_owned(a, ch, span, wid, nw);
         async_wait();
-        convert_owned<Conv>(a, ch, span, rows0, 0, wid, nw);
+        convert_owned<Conv>(a, ch, span, rows0, lo_off, wid, nw);
     }
     __syncthreads();
     if (producer) {
@@ -620,7 +622,7 @@ __global__ __launch_bounds__(768) void k_melt_h16_pc(FwdArgs a, const uint4 *__r
             async_wait();                          // this producer's copies of chunk it + 1
             if (load_desc) load_chunk_scalar(a.chunks, c + 3 * cstep, nd0, nd1);
             const Chunk ch1 = ring_slot(dslot, (it + 1) & 3);
-            convert_owned<Conv>(a, ch1, span, ((it + 1) & 1) ? rows1 : rows0, 0, pw, np);
+            convert_owned<Conv>(a, ch1, span, ((it + 1) & 1) ? rows1 : rows0, lo_off, pw, np);
             if (load_desc && lane == 0) {
                 uint4 *dst = reinterpret_cast<uint4 *>(dslot + ((it + 3) & 3));
                 dst[0] = nd0;
@@ -631,10 +633,15 @@ __global__ __launch_bounds__(768) void k_melt_h16_pc(FwdArgs a, const uint4 *__r
         return;
     }
     const int rt = r0 + wid;
-    uint4 A[NS];
-    const uint4 Al[1] = {};
+    uint4 A[NS], Al[X3 ? NS : 1];
 #pragma unroll
     for (int s = 0; s < NS; ++s) A[s] = bhi[((size_t)rt * NS + s) * 64 + lane];
+    if constexpr (X3) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) Al[s] = blo[((size_t)rt * NS + s) * 64 + lane];
+    } else {
+        Al[0] = uint4{};
+    }
     for (int it = 0; c0 + it * cstep < nch; ++it) {
         __syncthreads();                           // chunk it converted; buffer (it + 1) & 1 free
         const Chunk ch = ring_slot(dslot, it & 3);
@@ -644,7 +651,7 @@ __global__ __launch_bounds__(768) void k_melt_h16_pc(FwdArgs a, const uint4 *__r
             int off = (ft * 32 + (lane & 31)) * a.S + 8 * (lane >> 5);
             asm volatile("" : "+v"(off));
             f32x16 acc = f32x16{};
-            mfma_sweep1<NS, false, IS_F16>(A, Al, rows + off, gt, 0, acc);
+            mfma_sweep1<NS, X3, IS_F16>(A, Al, rows + off, gt, lo_off, acc);
             store_tile(a, ch, rt, ft * 32 + (lane & 31), lane, acc);
         }
     }
@@ -922,26 +929,36 @@ static melt_status launch_rs(Plan &p, const FwdArgs &a, const GroupTableBig &gt,
     }
 }
 
-template <class Conv, int NS, bool F16>
-static melt_status launch_pc_ns(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
-                                hipStream_t s) {
-    allow_lds(k_melt_h16_pc<Conv, NS, F16>, (int)(4 * sizeof(Chunk)));
-    const int rg = row_groups(p);
-    k_melt_h16_pc<Conv, NS, F16><<<grid, 768, lds, s>>>(a, (const uint4 *)p.d_pack_h16, gt, bf,
-                                                         (int)(pc_rows_bytes(p, bf) / 2),
-                                                         (int)(2 * pc_rows_bytes(p, bf) / 4), rg);
-    return hip_check(hipGetLastError(), "melt h16 12-wave producer/consumer launch");
+// The split precisions on the producer/consumer kernel: a consumer holds the hi and lo basis
+// tiles (2 NS fragments), so the workgroup has 8 waves (two per SIMD, 256 registers each) and
+// row groups of at most 5 tiles (at least 3 producers); each row buffer holds the hi rows then
+// the lo rows.
+static int pc_x3_row_groups(const Plan &p) { return (p.row_tiles + 4) / 5; }
+size_t pc_x3_lds_bytes(const Plan &p, int bf) {
+    return 4 * pc_rows_bytes(p, bf) + (size_t)(bf + p.geo16.J - 1) * p.H * 4;
 }
 
-template <class Conv, bool F16>
-static melt_status launch_pc(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+template <class Conv, int NS, bool X3, bool F16>
+static melt_status launch_pc_ns(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf,
+                                int rg, hipStream_t s) {
+    allow_lds(k_melt_h16_pc<Conv, NS, X3, F16>, (int)(4 * sizeof(Chunk)));
+    const int part = (int)(pc_rows_bytes(p, bf) / 2);            // elements of one row image
+    const int rows_len = X3 ? 2 * part : part;
+    k_melt_h16_pc<Conv, NS, X3, F16><<<grid, X3 ? 512 : 768, lds, s>>>(
+        a, (const uint4 *)p.d_pack_h16, (const uint4 *)p.d_pack_lo, gt, bf, rows_len, X3 ? part : 0,
+        (int)(2 * rows_len * 2 / 4), rg);
+    return hip_check(hipGetLastError(), "melt h16 producer/consumer launch");
+}
+
+template <class Conv, bool X3, bool F16>
+static melt_status launch_pc(Plan &p, const FwdArgs &a, const GroupTableBig &gt, size_t lds, int grid, int bf, int rg,
                              hipStream_t s) {
     switch (p.geo16.n_groups) {
-    case 10: return launch_pc_ns<Conv, 10, F16>(p, a, gt, lds, grid, bf, s);
-    case 16: return launch_pc_ns<Conv, 16, F16>(p, a, gt, lds, grid, bf, s);
-    case 20: return launch_pc_ns<Conv, 20, F16>(p, a, gt, lds, grid, bf, s);
-    case 25: return launch_pc_ns<Conv, 25, F16>(p, a, gt, lds, grid, bf, s);
-    default: return set_error(MELT_E_UNSUPPORTED, "12-wave producer/consumer kernel: no register tile for this frame length");
+    case 10: return launch_pc_ns<Conv, 10, X3, F16>(p, a, gt, lds, grid, bf, rg, s);
+    case 16: return launch_pc_ns<Conv, 16, X3, F16>(p, a, gt, lds, grid, bf, rg, s);
+    case 20: return launch_pc_ns<Conv, 20, X3, F16>(p, a, gt, lds, grid, bf, rg, s);
+    case 25: return launch_pc_ns<Conv, 25, X3, F16>(p, a, gt, lds, grid, bf, rg, s);
+    default: return set_error(MELT_E_UNSUPPORTED, "producer/consumer kernel: no register tile for this frame length");
     }
 }
 
@@ -1001,14 +1018,16 @@ melt_status launch_melt_h16(Plan &p, const FwdTask &t, H16Kind kind, int bf, int
         return launch_ap<ConvBF16, false>(p, a, gt, lds, grid, bf, s);
     }
     if (kind == H16_PC12) {
-        if (x3 || !pc_fits(p)) return set_error(MELT_E_UNSUPPORTED, "12-wave producer/consumer kernel: unsupported geometry");
-        const size_t lds = pc_lds_bytes(p, bf);
+        if (!pc_fits(p)) return set_error(MELT_E_UNSUPPORTED, "producer/consumer kernel: unsupported geometry");
+        const size_t lds = x3 ? pc_x3_lds_bytes(p, bf) : pc_lds_bytes(p, bf);
         if (lds + 4 * sizeof(Chunk) > (size_t)kMaxLds) return set_error(MELT_E_UNSUPPORTED, "frame geometry exceeds LDS");
-        const int rg = row_groups(p);
+        const int rg = x3 ? pc_x3_row_groups(p) : row_groups(p);
         const int per_group = (int)std::max<int64_t>(1, std::min<int64_t>(t.est_chunks, ((int64_t)p.cu_count + rg - 1) / rg));
         const int grid = per_group * rg;
-        if (f16) return launch_pc<ConvF16, true>(p, a, gt, lds, grid, bf, s);
-        return launch_pc<ConvBF16, false>(p, a, gt, lds, grid, bf, s);
+        if (x3 && f16) return launch_pc<ConvF16X3, true, true>(p, a, gt, lds, grid, bf, rg, s);
+        if (x3) return launch_pc<ConvBF16X3, true, false>(p, a, gt, lds, grid, bf, rg, s);
+        if (f16) return launch_pc<ConvF16, false, true>(p, a, gt, lds, grid, bf, rg, s);
+        return launch_pc<ConvBF16, false, false>(p, a, gt, lds, grid, bf, rg, s);
     }
     if (kind == H16_PIPELINED) {
         if (!pp_fits(p)) return set_error(MELT_E_UNSUPPORTED, "producer/consumer kernel: no producer waves");

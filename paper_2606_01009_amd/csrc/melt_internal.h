@@ -145,6 +145,7 @@ melt_status launch_stft_main(Plan &p, const float *d_wave, float *d_out, hipStre
 melt_status launch_melt_table(Plan &p, int variant, const Chunk *tab, const int *n_tab, int64_t est_chunks,
                               int64_t n_frames, const float *d_wave, float *d_out, float *d_proj, hipStream_t s);
 void init_variants(Plan &p);             // melt_fwd.hip: fills the plan's variant table
+size_t pc_x3_lds_bytes(const Plan &p, int bf);   // melt_h16.hip: split-precision producer/consumer LDS
 int forward_variants(const Plan &p);
 void apply_tune_cache(Plan &p);          // stream.hip: apply a MELT_AUTOTUNE_CACHE entry
 const char *forward_variant_name(const Plan &p, int variant);
