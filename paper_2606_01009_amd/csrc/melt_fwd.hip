@@ -431,9 +431,12 @@ static std::vector<Variant> variant_list(const Plan &p) {
                     break;
                 }
         // the split precisions' producer/consumer form (8 waves, hi and lo rows; 64-frame
-        // chunks): their default where it fits
-        if (x3 && pc_fits(p) && pc_x3_lds_bytes(p, 64) + 4 * sizeof(Chunk) <= (size_t)kMaxLds)
-            v.push_back({V_H16_PC, 64});
+        // chunks, row groups of at most 5 tiles): their default where it fits with at most 4
+        // row groups (each group converts every chunk again: at 32 row tiles, 7 groups, the
+        // row-split kernel is faster), the last variant otherwise
+        const bool pc_x3 = x3 && pc_fits(p) && pc_x3_lds_bytes(p, 64) + 4 * sizeof(Chunk) <= (size_t)kMaxLds;
+        const bool pc_x3_first = pc_x3 && (p.row_tiles + 4) / 5 <= 4;
+        if (pc_x3_first) v.push_back({V_H16_PC, 64});
         if (!x3 && ap_fits(p) && as_lds_bytes(p, 128) + kRingBytes <= (size_t)kMaxLds) v.push_back({V_H16_AP, 128});
         if (as_fits(p)) {
             // one span buffer (128 then 64 frames per chunk; 96 then 64 for BF16X3), then two
@@ -468,6 +471,7 @@ static std::vector<Variant> variant_list(const Plan &p) {
                     v.push_back({V_H16_KS, bf});
                     break;
                 }
+        if (pc_x3 && !pc_x3_first) v.push_back({V_H16_PC, 64});
         // frame-split: the fallback for every 16-bit precision (the split ones only where no
         // register-tile kernel applies)
         if (!x3 || v.empty()) v.push_back({V_H16_FS, kBF32});
