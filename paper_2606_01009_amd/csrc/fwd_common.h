@@ -521,6 +521,12 @@ __device__ __forceinline__ void convert_span(const FwdArgs &a, const Chunk &ch, 
                                              typename Conv::elem_t *rows, int lo_off) {
     const int span = (ch.n_frames + a.J - 1) * a.H;
     const int valid = span_valid(a, ch);
+    // the thread index made opaque, so that the addresses derived from it are formed here on
+    // every call: hoisted out of a kernel's chunk loop they stay live across its multiply
+    // phase, where register-heavy kernels spill them, and the reload's wait for the wave's
+    // memory counter then also waits for its output stores in flight
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
     if ((a.H & 3) == 0) {
         // Vectors of 4 samples, thread-strided by step = 4 nt; four per thread and pass, so
         // their LDS reads are in flight together.  The row and column advance by (dr, dc)
@@ -528,11 +534,11 @@ __device__ __forceinline__ void convert_span(const FwdArgs &a, const Chunk &ch, 
         const int nt = blockDim.x, step = 4 * nt;
         const int dr = step / a.H, dc = step - dr * a.H;
         const int dad = dr * a.S + dc, wrap = a.S - a.H;
-        int c = 4 * (int)threadIdx.x;
+        int c = 4 * tid;
         const int r0 = span_row(a, c);
         c -= r0 * a.H;
         int ad = r0 * a.S + c;
-        for (int o0 = 4 * (int)threadIdx.x; o0 < span; o0 += 4 * step) {
+        for (int o0 = 4 * tid; o0 < span; o0 += 4 * step) {
             f32x4 v[4];
             int at[4];
 #pragma unroll
@@ -562,7 +568,7 @@ __device__ __forceinline__ void convert_span(const FwdArgs &a, const Chunk &ch, 
         }
         return;
     }
-    for (int o = threadIdx.x; o < span; o += blockDim.x) {
+    for (int o = tid; o < span; o += blockDim.x) {
         const float v = o < valid ? scratch[o] : 0.0f;
         const int r = span_row(a, o);
         Conv::store(rows, r * a.S + (o - r * a.H), v, lo_off);
