@@ -313,14 +313,16 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WPE)
     constexpr int FP4 = FPW == 3 ? 4 : FPW;
     constexpr int PST = 2 * FP4;                  // floats per bin
     static_assert(NB * PST <= 2 * FPW * BUF, "power spectra must fit in the FFT rows");
+    // LDS: the twiddles [k1][n2] in an array of their own, so that the compiler knows the
+    // stores into the FFT rows cannot change them (in one array with the rows, every twiddle
+    // read of step 1 waited for the store before it); then, dynamic, every wave's FFT rows,
+    // the window, the filter weights (pre-scaled, see below), first bins and offsets
+    __shared__ cf tw[N];
     extern __shared__ float smem[];
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // LDS: twiddles [N1][N2] and every wave's FFT rows (8-byte values first), then the window,
-    // the filter weights (pre-scaled, see below), first bins and offsets
-    cf *tw = reinterpret_cast<cf *>(smem);
-    cf *buf = tw + N + wid * FPW * BUF;
-    float *wl = reinterpret_cast<float *>(tw + N + WAVES * FPW * BUF);
+    cf *buf = reinterpret_cast<cf *>(smem) + wid * FPW * BUF;
+    float *wl = reinterpret_cast<float *>(reinterpret_cast<cf *>(smem) + WAVES * FPW * BUF);
     float *fbw = wl + N;
     int *fbs = reinterpret_cast<int *>(fbw + a.fb_nnz);
     int *fbo = fbs + a.M;
@@ -543,7 +545,8 @@ constexpr int kStftWaves = 4;
 size_t stft_lds_bytes(const StftShape &s, int M, int nnz) {
     const int N = s.N1 * s.N2;
     const int BUF = std::max(s.N1 * (s.N2 + 1), N);
-    // twiddles and FFT rows (the power spectra reuse the rows), window, weights, starts, offsets
+    // twiddles (static) and FFT rows (the power spectra reuse the rows), window, weights,
+    // starts, offsets
     return (size_t)N * 8 + (size_t)kStftWaves * s.FPW * BUF * 8 + (size_t)N * 4 + (size_t)nnz * 4 +
            (size_t)(2 * M + 1) * 4;
 }
@@ -553,9 +556,10 @@ size_t stft_lds_bytes(const StftShape &s, int M, int nnz) {
 template <int N1, int N2, int SUB, int KIND>
 melt_status launch_kind(const StftArgs &a, size_t lds, int grid, hipStream_t s) {
     constexpr int WPE = (N1 * N2 >= 1200) ? 1 : 3;
+    constexpr size_t kStatic = (size_t)N1 * N2 * sizeof(cf);   // the twiddle array
     (void)hipFuncSetAttribute((const void *)k_stft_mel<N1, N2, kStftWaves, SUB, WPE, KIND>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    k_stft_mel<N1, N2, kStftWaves, SUB, WPE, KIND><<<grid, 64 * kStftWaves, lds, s>>>(a);
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(160 * 1024 - kStatic));
+    k_stft_mel<N1, N2, kStftWaves, SUB, WPE, KIND><<<grid, 64 * kStftWaves, lds - kStatic, s>>>(a);
     return hip_check(hipGetLastError(), "stft_mel launch");
 }
 
