@@ -468,7 +468,7 @@ def main():
                          "duration, Mel-bin and batch sweeps) as JSON lines to this file and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported (the frames of a batch "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported (the frames of a batch "
               f"are independent, so N GPUs would each take 1/N of the clips with no communication)",
               file=sys.stderr)
         return 2
