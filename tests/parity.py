@@ -64,10 +64,18 @@ def check_log_power(L_gpu, R, I, A_r, A_i, n_terms, eps, extra_rel=1.0, label=""
                  for t, m in idx]
         raise AssertionError(f"{label}: {int(bad.sum())} of {bad.size} bins beyond the FP32 bound\n" + "\n".join(lines))
     if np.any(vac):
-        lo = np.log(eps * (1 - 2 * U32)) - 1e-6
-        hi = np.log(S + dS + eps) + 1e-6
+        # the log is evaluated and stored in FP32: the same 4 ulps of |L| as the active-bin bound
+        lo0 = np.log(eps * (1 - 2 * U32))
+        lo = lo0 - 4 * np.spacing(np.float32(abs(lo0))) - 1e-6
+        hi = np.log(S + dS + eps)
+        hi = hi + 4 * np.spacing(np.abs(hi).astype(np.float32)) + 1e-6
         inside = (L_gpu[vac] >= lo) & (L_gpu[vac] <= hi[vac])
-        assert np.all(inside), f"{label}: noise-floor bins outside [ln eps, ln(S+dS+eps)]"
+        if not np.all(inside):
+            out = np.argwhere(vac)[~inside][:8]
+            lines = [f"t={t} m={m} gpu={L_gpu[t, m]:.9g} S={S[t, m]:.3g} dS={dS[t, m]:.3g} lo={lo:.9g} "
+                     f"hi={hi[t, m]:.9g}" for t, m in out]
+            raise AssertionError(f"{label}: {int((~inside).sum())} noise-floor bins outside "
+                                 f"[ln eps, ln(S+dS+eps)]\n" + "\n".join(lines))
     return db_stats(L_gpu, L, S)
 
 
@@ -203,8 +211,12 @@ def check_stft_log(L_gpu, P, F, pair_norm2, n_fft, eps, c_fft=4.0, label=""):
                  for t, m in idx]
         raise AssertionError(f"{label}: {int(bad.sum())} of {bad.size} bins beyond the FFT bound\n" + "\n".join(lines))
     if np.any(vac):
-        hi = np.log(mel + dmel + eps) + 1e-6
-        assert np.all(L_gpu[vac] <= hi[vac]) and np.all(L_gpu[vac] >= np.log(eps * (1 - 2 * U32)) - 1e-6), label
+        # the log is evaluated and stored in FP32: the same 4 ulps of |L| as the active-bin bound
+        lo0 = np.log(eps * (1 - 2 * U32))
+        lo = lo0 - 4 * np.spacing(np.float32(abs(lo0))) - 1e-6
+        hi = np.log(mel + dmel + eps)
+        hi = hi + 4 * np.spacing(np.abs(hi).astype(np.float32)) + 1e-6
+        assert np.all(L_gpu[vac] <= hi[vac]) and np.all(L_gpu[vac] >= lo), label
     return db_stats(L_gpu, L, mel)
 
 

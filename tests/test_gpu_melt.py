@@ -383,6 +383,36 @@ def test_config2_full_size_sampled(torch, melt, orc, prec):
     _check(orc, melt, plan, L[ids], sub, off, prec, label=f"config2 full sampled {prec}")
 
 
+_CONFIG4 = {}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
+@pytest.mark.parametrize("variant", ["16k", "22k"])
+def test_config4_full_size_sampled(torch, melt, orc, variant, prec):
+    """The ragged systems batch at full size, as the systems benchmark launches it: 512 clips of
+    U[0.5, 30] s (16 kHz, N 512, H 128, or 22.05 kHz, N 1024, H 256; 128 Mel bins up to the
+    Nyquist frequency).  The first and last frame of every clip and 128 random frames are
+    checked against the oracle evaluated on exactly those frames."""
+    if variant not in _CONFIG4:
+        _CONFIG4.clear()                                  # one batch in host memory at a time
+        _CONFIG4[variant] = workloads.config4(variant)
+    cfg = _CONFIG4[variant]
+    N, H, sr = cfg["n_fft"], cfg["hop"], cfg["sr"]
+    plan = melt.MeltPlan(sample_rate=sr, n_fft=N, hop=H, n_mels=128, fmin=0.0, fmax=sr / 2, precision=prec)
+    L, _ = _gpu_forward(torch, melt, plan, cfg["wave"], cfg["offsets"])
+    off = np.asarray(cfg["offsets"], np.int64)
+    lens = off[1:] - off[:-1]
+    T_c = np.where(lens >= N, 1 + (lens - N) // H, 0)
+    fo = np.concatenate([[0], np.cumsum(T_c)])
+    assert L.shape == (fo[-1], 128)
+    assert np.all(np.isfinite(L))
+    has = T_c > 0
+    rng = np.random.default_rng(4040)
+    ids = np.unique(np.concatenate([fo[:-1][has], fo[1:][has] - 1, rng.integers(0, fo[-1], 128)]))
+    sub, soff = parity.frames_as_clips(cfg["wave"], off, N, H, ids)
+    _check(orc, melt, plan, L[ids], sub, soff, prec, label=f"config4 {variant} full sampled {prec}")
+
+
 # ------------------------------------------------------------------ centres, basis and options
 # Eq. mel_scale, Eq. inverse_mel and the filter-centre placement are checked against the
 # oracle's own computation, never against values read back from the plan.
