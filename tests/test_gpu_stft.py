@@ -122,6 +122,50 @@ def test_full_size_sampled(torch, melt, orc):
     parity.check_stft_log(L[ids], P, F, pn, 400, 1e-10, label="stft full sampled")
 
 
+_CONFIG4 = {}
+
+
+@pytest.mark.parametrize("variant", ["16k", "22k"])
+def test_config4_full_size_sampled(torch, melt, orc, variant):
+    """The ragged systems batch at full size (512 clips of U[0.5, 30] s; 16 kHz / N 512 / H 128
+    or 22.05 kHz / N 1024 / H 256; 128 Mel bins up to the Nyquist frequency), as the systems
+    benchmark launches the comparator.  The first and last frame of every clip and 128 random
+    frames are checked against the oracle on those frames; the FFT bound takes each frame's
+    own energy plus that of the frame sharing its complex FFT (clip-local index l ^ 1, none past
+    the clip's last frame)."""
+    if variant not in _CONFIG4:
+        _CONFIG4.clear()
+        _CONFIG4[variant] = workloads.config4(variant)
+    cfg = _CONFIG4[variant]
+    N, H, sr = cfg["n_fft"], cfg["hop"], cfg["sr"]
+    plan = melt.MeltPlan(sample_rate=sr, n_fft=N, hop=H, n_mels=128, fmin=0.0, fmax=sr / 2)
+    wave = cfg["wave"]
+    off = np.asarray(cfg["offsets"], np.int64)
+    L = _run(torch, melt, plan, wave, off)
+    lens = off[1:] - off[:-1]
+    T_c = np.where(lens >= N, 1 + (lens - N) // H, 0)
+    fo = np.concatenate([[0], np.cumsum(T_c)])
+    assert L.shape == (fo[-1], 128) and np.all(np.isfinite(L))
+    has = T_c > 0
+    rng = np.random.default_rng(4041)
+    ids = np.unique(np.concatenate([fo[:-1][has], fo[1:][has] - 1, rng.integers(0, fo[-1], 128)]))
+    clip = np.searchsorted(fo, ids, side="right") - 1
+    loc = ids - fo[clip]
+    w = orc.window(N)
+
+    def energy(c, l):
+        s0 = off[c] + l * H
+        return float(np.sum((w * wave[s0:s0 + N].astype(np.float64)) ** 2))
+
+    pn = np.array([energy(c, l) + (energy(c, l ^ 1) if (l ^ 1) < T_c[c] else 0.0) for c, l in zip(clip, loc)])
+    sub, soff = parity.frames_as_clips(wave, off, N, H, ids)
+    P = orc.power_spectrum(sub, soff, n_fft=N, hop=H)
+    F = orc.mel_filterbank(n_fft=N, sr=sr, n_mels=128, fmin=0.0, fmax=sr / 2)
+    st = parity.check_stft_log(L[ids], P, F, pn, N, 1e-10, label=f"stft config4 {variant} full sampled")
+    print(f"stft config4 {variant}: dB error vs FP64 oracle on active bins: max {st['max_db']:.3g} "
+          f"rms {st['rms_db']:.3g}")
+
+
 def _many_lengths(n, N, H, seed):
     """n clip lengths from 0 to N + 12 H samples (empty, sub-frame and short clips), so the
     chunk schedule runs over several blocks of 1024 clips."""
