@@ -43,6 +43,12 @@ def _melt_case(torch, melt, orc, wave, off, sr, N, H, M, K, prec, fmin=0.0, fmax
                          output=melt.MELT_OUT_MFCC, n_mfcc=K)
     assert plan.out_cols == K
     C = _gpu(torch, melt, plan, wave, off)
+    _check_mfcct(orc, plan, C, wave, off, prec)
+    return C
+
+
+def _check_mfcct(orc, plan, C, wave, off, prec, label=""):
+    N, H, M, K = plan.n_fft, plan.hop, plan.n_mels, plan.out_cols
     _, Wr, Wi = parity.oracle_basis(orc, plan.cfg)     # the oracle's own centres and basis
     eps = 1e-10
     if prec == "fp32":
@@ -60,9 +66,31 @@ def _melt_case(torch, melt, orc, wave, off, sr, N, H, M, K, prec, fmin=0.0, fmax
         bL, L = parity.log_error_radius(R, I, Ar, Ai, N, eps, extra_rel=4.0 if prec in ("fp8", "fp8b") else 0.0)
     D = orc.dct2_ortho(K, M)
     # after a 16-bit or FP8 projection the cepstrum runs as a split binary16 product
-    st = parity.check_cepstrum(C, L, bL, D, label=f"MFCCT {prec} N={N} M={M} K={K}", split=prec != "fp32")
-    print(f"MFCCT {prec} N={N} M={M} K={K}: max |dC| {st['max_abs']:.3g} (bound up to {st['max_bound']:.3g})")
-    return C
+    label = label or f"MFCCT {prec} N={N} M={M} K={K}"
+    st = parity.check_cepstrum(C, L, bL, D, label=label, split=prec != "fp32")
+    print(f"{label}: max |dC| {st['max_abs']:.3g} (bound up to {st['max_bound']:.3g})")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mfcct_cepstral_full_size_sampled(torch, melt, orc, prec):
+    """The cepstral workload at full size, as the workload sweep launches it: 64 clips x 30 s,
+    N = 1200, H = 160, M = 128, K = 40 (191 552 frames; the K-split projection, then the
+    cepstrum).  The first and last frame of every clip and 128 random frames are checked
+    against the oracle evaluated on exactly those frames."""
+    cfg = workloads.config2(n_mels=128)
+    N, H = 1200, 160
+    plan = melt.MeltPlan(sample_rate=16000.0, n_fft=N, hop=H, n_mels=128, fmin=0.0, fmax=8000.0, precision=prec,
+                         output=melt.MELT_OUT_MFCC, n_mfcc=40)
+    C = _gpu(torch, melt, plan, cfg["wave"], cfg["offsets"])
+    off = np.asarray(cfg["offsets"], np.int64)
+    lens = off[1:] - off[:-1]
+    T_c = np.where(lens >= N, 1 + (lens - N) // H, 0)
+    fo = np.concatenate([[0], np.cumsum(T_c)])
+    assert C.shape == (fo[-1], 40) and fo[-1] == 191552 and np.all(np.isfinite(C))
+    rng = np.random.default_rng(1200)
+    ids = np.unique(np.concatenate([fo[:-1], fo[1:] - 1, rng.integers(0, fo[-1], 128)]))
+    sub, soff = parity.frames_as_clips(cfg["wave"], off, N, H, ids)
+    _check_mfcct(orc, plan, C[ids], sub, soff, prec, label=f"MFCCT {prec} cepstral full sampled")
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "fp8", "fp8b"])
