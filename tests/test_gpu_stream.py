@@ -72,6 +72,19 @@ def test_stream_equals_batch_16k(torch, melt, prec):
         assert np.array_equal(got[s], ref[s])
 
 
+def test_stream_systems_configuration(torch, melt):
+    """The streaming systems row at its size: 512 streams at 16 kHz, 10 ms chunks (160 samples),
+    N 512, H 128, 128 Mel bins; 40 pushes equal the batch forward of the same streams bit for
+    bit."""
+    plan = melt.MeltPlan(sample_rate=16000.0, n_fft=512, hop=128, n_mels=128, fmin=0.0, fmax=8000.0)
+    X = _streams(512, 160 * 40, seed=5)
+    ref = _batch_reference(torch, melt, plan, X)
+    got, _ = _run_eager(torch, melt, plan, X, [160] * 40, 160)
+    for s in range(512):
+        assert got[s].shape == ref[s].shape
+        assert np.array_equal(got[s], ref[s])
+
+
 def test_stream_22k_alternating_chunks(torch, melt):
     """22.05 kHz, N=1024, H=256: 10 ms is 220.5 samples, so chunks alternate 220 and 221."""
     plan = melt.MeltPlan(sample_rate=22050, n_fft=1024, hop=256, n_mels=128)
