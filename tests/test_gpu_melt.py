@@ -386,7 +386,7 @@ def test_config2_full_size_sampled(torch, melt, orc, prec):
 _CONFIG4 = {}
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16", "bf16x3", "fp16x3", "fp8", "fp8b"])
 @pytest.mark.parametrize("variant", ["16k", "22k"])
 def test_config4_full_size_sampled(torch, melt, orc, variant, prec):
     """The ragged systems batch at full size, as the systems benchmark launches it: 512 clips of
